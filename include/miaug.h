@@ -1,0 +1,295 @@
+/*
+ * miaug.h -- C ABI of libmiaug, an MI355X (gfx950) implementation of the
+ * batched image-augmentation hot path of Buslaev et al., "Albumentations:
+ * fast and flexible image augmentations" (arXiv:1809.06839).
+ *
+ * The paper describes augmentation as label-preserving transforms applied to
+ * images together with their masks and boxes (Abstract; Sec. I; Sec. II-A to
+ * II-C) and times the single ops of Table I.  It gives no formulas; the exact
+ * arithmetic of every op below is a stated reading (integer fixed point with
+ * round-half-even and saturation for u8 data, IEEE double for per-sample
+ * setup), so that results are reproducible bit for bit.
+ *
+ * Conventions for every entry point:
+ *  - Return value: MIAUG_OK (0) or a negative status; nothing throws.  The
+ *    text of the last error of the calling thread is miaug_last_error().
+ *  - Memory: every tensor is owned by the caller.  Arguments documented as
+ *    "device" are HIP device pointers; "host" are ordinary host pointers.  The
+ *    library never keeps a caller pointer after the enqueued work.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls enqueue work and return; validation errors are reported
+ *    synchronously; launch failures are reported as MIAUG_EDEVICE.
+ *  - Layouts: u8 images are HWC with dense rows (C = 3 unless stated); masks
+ *    are HW u8; float images are CHW float32; boxes are xyxy float32 in
+ *    continuous pixel coordinates (pixel (i, j) covers [j, j+1) x [i, i+1)).
+ *  - Fixed point: sub-pixel positions carry 10 fraction bits (Q10).
+ *    rdiv_he(n, d) is n/d rounded to nearest, ties to even, with floor
+ *    division; sat8 clamps to [0, 255].
+ */
+#ifndef MIAUG_H
+#define MIAUG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+enum {
+    MIAUG_OK = 0,
+    MIAUG_EINVAL = -1,       /* null pointer or out-of-range scalar argument   */
+    MIAUG_ESHAPE = -2,       /* inconsistent or unsupported sizes              */
+    MIAUG_EUNSUPPORTED = -3, /* valid request the library does not implement   */
+    MIAUG_EDEVICE = -4,      /* HIP runtime error (launch, copy, no device)    */
+    MIAUG_ENOMEM = -5,       /* device or host allocation failed               */
+    MIAUG_ECAPACITY = -6     /* workspace smaller than required                */
+};
+
+/* Library version as 10000*major + 100*minor + patch. */
+int miaug_version(void);
+/* Static text of a status code. */
+const char *miaug_status_str(int status);
+/* Text of the calling thread's last error; valid until its next miaug call. */
+const char *miaug_last_error(void);
+
+/* ---------------------------------------------------------------- sampler
+ * Per-sample transform parameters from a counter-based generator
+ * (Philox4x64-10, Salmon et al., SC'11): draw d of global sample index g is
+ * word 0 of Philox(counter = {d, g, 0, 0}, key = {seed, 0}).  A uniform is
+ * (word >> 11) * 2^-53; a Bernoulli(p) is uniform < p; an integer in
+ * {0..m-1} is ((word >> 32) * m) >> 32; a float in [lo, hi] is
+ * (float)(lo + (hi - lo) * uniform) in double.  Results depend only on
+ * (seed, g), never on batch composition.  All outputs are host arrays of n
+ * records; the functions never touch the GPU.
+ */
+
+/* Random Dih4 element + brightness/contrast (Sec. II-B Dih4; Table I
+ * HorizontalFlip, VerticalFlip, Brightness).  flags[4i..4i+3] = {hflip p=.5,
+ * vflip p=.5, rot90 k in {0..3}, transpose p=.5}; ab[2i..2i+1] = {alpha in
+ * [0.8,1.2], beta in [-51,51]} (draws 0..5). */
+int miaug_sample_d4bc(uint64_t seed, uint64_t first_index, int n, int32_t *flags, float *ab);
+
+/* Shift-scale-rotate + crop + hue/saturation + gamma + blur (Table I Rotate,
+ * ShiftScaleRotate, RandomCrop64, ShiftHSV, Gamma).  f[5i..] = {angle_deg in
+ * [-45,45], scale in [0.9,1.1], dx, dy in [-0.0625,0.0625], gamma in
+ * [0.8,1.2]}; k[5i..] = {crop_x, crop_y in {0..crop_range}, dh = rint(U[-20,20])
+ * (hue, 2-degree units), ds = rint(U[-30,30]) (saturation, 0..255 scale),
+ * blur p=0.3}. */
+int miaug_sample_c2(uint64_t seed, uint64_t first_index, int n, int crop_range, float *f, int32_t *k);
+
+/* Differentiable warp + colour parameters: f[7i..] = {angle_deg in [-45,45],
+ * scale in [0.9,1.1], tx, ty in [-0.0625,0.0625] (fractions of W, H), alpha
+ * in [0.8,1.2], beta in [-0.2,0.2], gamma in [0.8,1.2]}. */
+int miaug_sample_wc(uint64_t seed, uint64_t first_index, int n, float *f);
+
+/* Grid distortion (Sec. II-C): f[10i..] = {x factors d_0..d_4, y factors
+ * d_0..d_4}, each 1 + (double)(float)U[-limit, limit]. */
+int miaug_sample_grid(uint64_t seed, uint64_t first_index, int n, double limit, double *f);
+
+/* ---------------------------------------------------------------- context
+ * A context holds per-device state: queue counters of the persistent ragged
+ * kernel, the tuned launch choice and device properties.  One context per
+ * host thread/stream; calls on one context must not overlap in time on
+ * different streams. */
+typedef struct miaug_ctx miaug_ctx;
+/* Creates a context on HIP device `device` (allocates 4 KiB of device memory). */
+int miaug_ctx_create(int device, miaug_ctx **out);
+int miaug_ctx_destroy(miaug_ctx *ctx);
+
+/* ---------------------------------------------------------------- plain Dih4 + brightness/contrast
+ * Sec. II-B (random transformation from Dih4) and Table I (HorizontalFlip,
+ * VerticalFlip, Brightness).  For each image i of a dense batch:
+ * out_i = LUT_i[d4_i(in_i)] with d4_i = hflip -> vflip -> rot90^k ->
+ * transpose as selected by flags[4i..4i+3] (rot90 is counter-clockwise,
+ * out[r][c] = in[c][W-1-r]) and LUT_i[v] = sat8(rint((double)alpha*v +
+ * (double)beta)).
+ *   in     device u8 [n][H][W][C], C in {1, 3, 4}
+ *   flags  device int32 [n][4]; ab device float [n][2]
+ *   out    device u8, n*H*W*C bytes; image i occupies bytes
+ *          [i*H*W*C, (i+1)*H*W*C) with shape (H, W, C), or (W, H, C) when its
+ *          element swaps the axes (odd k xor transpose).
+ * Errors: EINVAL on null pointers or n, H, W < 0 (n == 0 is a no-op);
+ * ESHAPE if C is not 1, 3 or 4; EDEVICE on launch failure. */
+int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
+                   uint8_t *out, void *stream);
+
+/* ---------------------------------------------------------------- full u8 pipeline
+ * Table I ShiftScaleRotate -> RandomCrop -> resize -> ShiftHSV -> Gamma, then
+ * a 3x3 binomial blur with probability 0.3, per RGB image, each op rounding
+ * to u8 before the next:
+ *  1. warp: forward map p' = s R(theta)(p - c) + c + (dx W, dy H), R(theta) =
+ *     [[cos, sin], [-sin, cos]], c = ((W-1)/2, (H-1)/2); the inverse is
+ *     formed in double and quantised to Q32; source position
+ *     q = rdiv_he(a0 x + a1 y + a2, 2^22) (Q10); bilinear with weights
+ *     (1024 - f, f) per axis, value rdiv_he(sum w_y w_x p, 2^20), reflect-101
+ *     border per tap;
+ *  2. crop crop x crop at (crop_x, crop_y);
+ *  3. resize to outsz x outsz, half-pixel centres
+ *     q_j = rdiv_he(((2j+1) Ws - Wd) 2^10, 2 Wd), replicate border;
+ *  4. integer hexcone HSV (H8 in 2-degree units 0..179, S8, V8 0..255):
+ *     H8' = (H8 + dh) mod 180, S8' = sat8(S8 + ds), back to RGB;
+ *  5. gamma LUT[v] = sat8(rint(255 (v/255)^gamma)) in double;
+ *  6. if the blur flag is set: [1,2,1]x[1,2,1]/16, one rdiv_he, reflect-101.
+ *   in   device u8 [n][H][W][3];  f device float [n][5];  k device int32 [n][5]
+ *        (layouts as produced by miaug_sample_c2)
+ *   out  device u8 [n][outsz][outsz][3]
+ * Errors: EINVAL null pointers; ESHAPE unless 1 <= crop, crop + max crop
+ * offset fits (checked per image on the device: offsets are clamped into
+ * [0, H - crop] and [0, W - crop]) and 1 <= outsz <= 4096. */
+int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const float *f,
+                                            const int32_t *k, int crop, int outsz, uint8_t *out,
+                                            void *stream);
+
+/* ---------------------------------------------------------------- ragged batch
+ * Sec. II-A: images of a detection / segmentation set (uneven sizes) are
+ * transformed together with their masks and boxes.  Per image i: Dih4 element
+ * (flags) -> brightness/contrast LUT (ab) -> bilinear resize to out_h x
+ * out_w (half-pixel centres, replicate border) -> per-channel normalisation
+ * (float)(((double)v/255 - mean_c) / std_c) into float32 CHW.  The mask takes
+ * the same Dih4 element and a nearest resize (source index
+ * (q + 512) >> 10 of the same Q10 position).  Boxes take the Dih4 element
+ * (hflip (W-x2, y1, W-x1, y2), vflip, rot90 (y1, W-x2, y2, W-x1), transpose
+ * (y1, x1, y2, x2)) and the scale (out_w/W', out_h/H'), in double, stored as
+ * float.
+ */
+typedef struct {
+    int32_t n;               /* number of images (0 allowed)                      */
+    int32_t out_h, out_w;    /* output size, 1..4096                               */
+    const uint8_t *img;      /* device: packed HWC u8 images                       */
+    const int64_t *img_off;  /* device: [n] byte offset of image i in img          */
+    const int32_t *hw;       /* device: [n][2] = {H_i, W_i}, 1..65535              */
+    const int32_t *flags;    /* device: [n][4] Dih4 flags (miaug_sample_d4bc)      */
+    const float *ab;         /* device: [n][2] alpha, beta                         */
+    const uint8_t *mask;     /* device or NULL: packed HW u8 masks                 */
+    const int64_t *mask_off; /* device: [n] byte offsets (when mask != NULL)       */
+    const float *boxes;      /* device or NULL: [nbox][4] xyxy                     */
+    const int32_t *box_off;  /* device: [n+1] CSR offsets (when boxes != NULL)     */
+    float mean[3], stdv[3];  /* normalisation constants                            */
+    float *out;              /* device: [n][3][out_h][out_w] float32               */
+    uint8_t *out_mask;       /* device: [n][out_h][out_w] (when mask != NULL)      */
+    float *out_boxes;        /* device: [nbox][4] (when boxes != NULL)             */
+} miaug_ragged_args;
+
+/* Batched form: one persistent launch.  Work items are (image, output tile);
+ * images are spread over per-XCD queues, workgroups pop tiles with atomics and
+ * steal from other queues when their own is empty.  The queue counters live in
+ * the context and are cleared by a fill kernel enqueued before the main
+ * kernel, so the call is stream-ordered and graph-capturable.
+ * Errors: EINVAL null ctx/args/pointers; ESHAPE bad sizes; EDEVICE launch. */
+int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *args, void *stream);
+
+/* Comparison form: the same kernels launched once per image (n launches, no
+ * persistence, no queue).  Output is bit-identical to miaug_ragged_apply. */
+int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *args, void *stream);
+
+/* hipGraph form: captures miaug_ragged_apply for fixed args (pointers, n,
+ * sizes) on `stream`; miaug_graph_launch replays it (reading whatever the
+ * argument buffers hold at replay time). */
+typedef struct miaug_graph miaug_graph;
+int miaug_ragged_graph_create(miaug_ctx *ctx, const miaug_ragged_args *args, void *stream, miaug_graph **out);
+int miaug_graph_launch(miaug_graph *g, void *stream);
+int miaug_graph_destroy(miaug_graph *g);
+
+/* Autotuner for the batched form: times each launch variant (output tile
+ * shape, workgroups per CU) on `args` `reps` times, keeps only variants whose
+ * output is bit-identical to the per-image form, and stores the fastest in the
+ * context (used by later miaug_ragged_apply calls).  Writes the chosen
+ * variant index to *chosen and its mean time in ms to *ms (either may be
+ * NULL).  Synchronises `stream`.  `args->out*` are overwritten. */
+int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *args, int reps, void *stream, int *chosen,
+                          float *ms);
+/* Number of variants and a variant's description ("tile 32x32, 4 wg/CU"). */
+int miaug_ragged_variant_count(void);
+const char *miaug_ragged_variant_name(int v);
+/* Forces a variant (-1 restores the default). */
+int miaug_ragged_set_variant(miaug_ctx *ctx, int v);
+
+/* ---------------------------------------------------------------- differentiable warp + colour
+ * Float32 form for training-time augmentation with gradients.  Per image i
+ * and channel c, with p_i = {angle_deg, scale, tx, ty, alpha, beta, gamma}:
+ *   (sx, sy) = inverse of the shift-scale-rotate map above (tx, ty are
+ *   fractions of W, H) evaluated in float at output pixel (x, y);
+ *   w = bilinear(x_i[c], sx, sy), taps outside the image read 0;
+ *   z = alpha w + beta; y1 = clamp(z, 0, 1); y = y1^gamma (0^gamma = 0).
+ *   x, y: device float [n][C][H][W]; params: device float [n][7].
+ * Errors: EINVAL null pointers; ESHAPE n, C, H, W out of range. */
+int miaug_warpcolor_fwd(const float *x, int n, int C, int H, int W, const float *params, float *y,
+                        void *stream);
+
+/* Backward of miaug_warpcolor_fwd given gy = dL/dy.  grad_x (may be NULL)
+ * receives dL/dx (the adjoint of the bilinear warp, accumulated per source
+ * tile without global atomics); grad_params receives dL/dparams [n][7].
+ * Conventions at kinks: the clamp derivative is 0 outside the open interval
+ * (0, 1); at y1 = 0 every derivative is 0; the bilinear derivative uses the
+ * cell floor(s).  workspace: device memory of miaug_warpcolor_workspace_bytes
+ * bytes (contents need not be initialised). */
+size_t miaug_warpcolor_workspace_bytes(int n, int C, int H, int W);
+int miaug_warpcolor_bwd(const float *x, int n, int C, int H, int W, const float *params, const float *gy,
+                        float *grad_x, float *grad_params, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* ---------------------------------------------------------------- elastic + grid distortion
+ * Sec. II-C and Fig. 4 (grid distortion and elastic transform; the elastic
+ * distortion of Simard et al. 2003 cited in Sec. I).
+ *
+ * Fields: for image i (global index first_index + i) and field f (0: x,
+ * 1: y), noise n_f(y, x) = (16-bit word (e mod 4) of word ((e mod 16)/4) of
+ * Philox(counter = {e/16, g, f, 4}, key = {seed, 0})) - 32768, e = y W + x.
+ * Taps t_k = rint(2^15 g_k / sum g), g_k = exp(-k^2 / (2 sigma^2)),
+ * |k| <= radius.  h = rdiv_he(sum_k t_k n(y, refl(x+k)), 2^15);
+ * v = sum_k t_k h(refl(y+k), x); off = rdiv_he(alpha v, 2^20) (Q10 px);
+ * refl = reflect-101.
+ *   off  device int32 [n][2][H][W] (written)
+ *   workspace device, miaug_elastic_workspace_bytes bytes (int16 pass data).
+ * Errors: EINVAL; ESHAPE unless 1 <= radius <= 512 and H, W >= 1;
+ * ECAPACITY small workspace. */
+size_t miaug_elastic_workspace_bytes(int n, int H, int W);
+int miaug_elastic_fields(uint64_t seed, uint64_t first_index, int n, int H, int W, double sigma, int alpha,
+                         int radius, int32_t *off, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Grid tables: for each image, 5 cells per axis of width cw = W/5, knots
+ * S_0 = 0, S_{k+1} = S_k + cw d_k (not renormalised); pixel x maps to
+ * src = S_k + (x + 1/2 - k cw) d_k - 1/2 with k = min(floor((x+1/2)/cw), 4),
+ * in double, q = rint(src 2^10).
+ *   grid device double [n][10] (miaug_sample_grid layout); mapx device int32
+ *   [n][W]; mapy device int32 [n][H]. */
+int miaug_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, void *stream);
+
+/* u8 chain: e = elastic remap of the image by off (source position
+ * ((x<<10) + off_x, (y<<10) + off_y), bilinear, reflect-101), rounded to u8;
+ * out = grid remap of e (source (mapx[x], mapy[y]), bilinear, reflect-101).
+ * The mask (optional) takes the same two remaps with nearest sampling.
+ *   img device u8 [n][H][W][C] (C in {1,3,4}); mask device u8 [n][H][W] or NULL
+ *   out device u8 like img; out_mask like mask.
+ * per_image != 0 launches the kernel once per image (comparison form). */
+int miaug_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
+                          const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
+                          uint8_t *out_mask, int per_image, void *stream);
+
+/* Float copy of the chain without u8 rounding (same Q10 positions, dyadic
+ * weights), CHW float32, and its adjoint w.r.t. the image (fields and grid
+ * are random draws, not parameters).  The backward accumulates with float
+ * atomics into grad_x, which it zeroes first; workspace holds the
+ * intermediate gradient (miaug_chain_f32_workspace_bytes). */
+int miaug_elastic_grid_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off,
+                               const int32_t *mapx, const int32_t *mapy, float *y, void *workspace,
+                               size_t workspace_bytes, void *stream);
+size_t miaug_chain_f32_workspace_bytes(int n, int C, int H, int W);
+int miaug_elastic_grid_f32_bwd(const float *gy, int n, int C, int H, int W, const int32_t *off,
+                               const int32_t *mapx, const int32_t *mapy, float *grad_x, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- image statistics
+ * Per image and channel: sum (uint64), min, max (int32) and a 256-bin
+ * histogram (uint32), reduced with wavefront and workgroup reductions.
+ *   img device u8 [n][npix][C]; sum device uint64 [n][C]; mn, mx device
+ *   int32 [n][C]; hist device uint32 [n][C][256] (any of the four may be NULL). */
+int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_t *sum, int32_t *mn,
+                         int32_t *mx, uint32_t *hist, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIAUG_H */

@@ -1,0 +1,114 @@
+"""Pins of the oracle's elastic transform and grid distortion (Sec. II-C and
+Fig. 4; the Simard et al. 2003 elastic distortion cited in Sec. I).
+
+References: scipy.ndimage.correlate1d with mirror borders (= reflect-101) on
+exact int64 data, numpy Philox, closed-form shifts and piecewise-linear maps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def test_gauss_taps_are_symmetric_normalised_q15():
+    t = oracle.gauss_taps_q15(50.0, 150)
+    assert len(t) == 301
+    assert np.array_equal(t, t[::-1])
+    assert abs(int(t.sum()) - 32768) <= 150  # per-tap rounding, at most 1/2 each
+    k = np.arange(-150, 151)
+    g = np.exp(-k.astype(np.float64) ** 2 / (2 * 50.0 ** 2))
+    assert np.abs(t - 32768 * g / g.sum()).max() <= 0.5 + 1e-9
+
+
+def test_hpass_equals_scipy_mirror_correlation_then_rshr():
+    ndimage = pytest.importorskip("scipy.ndimage")
+    H, W, r = 5, 37, 9
+    taps = oracle.gauss_taps_q15(3.0, r)
+    h = np.zeros((H, W), np.int32)
+    oracle.lib().or_elastic_hpass(11, 2, 0, H, W, taps, r, 0, H, h)
+    noise = np.array([[oracle.noise16(11, 2, 0, y * W + x) for x in range(W)] for y in range(H)], np.int64)
+    ref = ndimage.correlate1d(noise, taps.astype(np.int64), axis=1, mode="mirror")
+    ref = np.vectorize(lambda v: oracle.rshr_he(int(v), 15))(ref)
+    assert np.array_equal(h, ref)
+
+
+def test_field_equals_scipy_separable_reference_and_pointwise_definition():
+    ndimage = pytest.importorskip("scipy.ndimage")
+    H, W, r, sigma, alpha = 23, 29, 7, 2.5, 40
+    ox, oy = oracle.elastic_field(3, 1, H, W, sigma, alpha, r)
+    taps = oracle.gauss_taps_q15(sigma, r).astype(np.int64)
+    for field, off in ((0, ox), (1, oy)):
+        noise = np.array([[oracle.noise16(3, 1, field, y * W + x) for x in range(W)] for y in range(H)], np.int64)
+        h = ndimage.correlate1d(noise, taps, axis=1, mode="mirror")
+        h = np.vectorize(lambda v: oracle.rshr_he(int(v), 15))(h).astype(np.int64)
+        v = ndimage.correlate1d(h, taps, axis=0, mode="mirror")
+        ref = np.vectorize(lambda t: oracle.rshr_he(alpha * int(t), 20))(v)
+        assert np.array_equal(off, ref)
+    for (y, x) in [(0, 0), (5, 28), (22, 13)]:
+        assert oracle.elastic_field_at(3, 1, H, W, y, x, sigma, alpha, r) == (ox[y, x], oy[y, x])
+
+
+def test_field_statistics_at_the_large_tile_setting():
+    # sigma = 50, alpha = 1000: displacement std ~ alpha * std(U[-1,1]) / (2 sqrt(pi) sigma) ~ 3.3 px
+    H = W = 256
+    ox, oy = oracle.elastic_field(1809068395, 0, H, W, 50.0, 1000, 150)
+    sd = np.concatenate([ox.ravel(), oy.ravel()]).std() / 1024
+    assert 1.0 < sd < 8.0
+
+
+def test_zero_alpha_is_identity_and_constant_field_is_a_shift():
+    rng = np.random.default_rng(30)
+    img = rng.integers(0, 256, (16, 20, 3), dtype=np.uint8)
+    ox, oy = oracle.elastic_field(9, 0, 16, 20, 3.0, 0, 5)
+    assert not ox.any() and not oy.any()
+    assert np.array_equal(oracle.remap_field(img, ox, oy), img)
+    sx, sy = 3, -2
+    fx = np.full((16, 20), sx * 1024, np.int32)
+    fy = np.full((16, 20), sy * 1024, np.int32)
+    out = oracle.remap_field(img, fx, fy)
+    ys = [oracle.reflect101(y + sy, 16) for y in range(16)]
+    xs = [oracle.reflect101(x + sx, 20) for x in range(20)]
+    assert np.array_equal(out, img[np.ix_(ys, xs)])
+    outn = oracle.remap_field(img, fx, fy, oracle.NEAREST)
+    assert np.array_equal(outn, img[np.ix_(ys, xs)])
+
+
+def test_grid_identity_table_and_monotone_and_single_cell_closed_form():
+    for n in (7, 100, 4096):
+        q = oracle.grid_table(np.ones(5), n)
+        assert np.array_equal(q, np.arange(n) * 1024)
+    rng = np.random.default_rng(31)
+    d = 1 + rng.uniform(-0.3, 0.3, 5)
+    q = oracle.grid_table(d, 500)
+    assert np.all(np.diff(q) > 0)
+    # only cell 2 stretched: inside it, src = S_2 + (u - 2 cw) d_2 - 1/2 with S_2 = 2 cw
+    d = np.array([1.0, 1.0, 1.25, 1.0, 1.0])
+    q = oracle.grid_table(d, 100)
+    for x in range(40, 60):
+        u = x + 0.5
+        assert q[x] == round((40 + (u - 40) * 1.25 - 0.5) * 1024)
+    for x in range(0, 40):
+        assert q[x] == x * 1024
+    for x in range(60, 100):  # later cells are shifted by the stretch of cell 2 (not renormalised)
+        assert q[x] == (x + 5) * 1024
+
+
+def test_grid_remap_identity_tables_are_identity():
+    rng = np.random.default_rng(32)
+    img = rng.integers(0, 256, (9, 13, 3), dtype=np.uint8)
+    assert np.array_equal(oracle.grid_remap(img, np.arange(13) * 1024, np.arange(9) * 1024), img)
+
+
+def test_elastic_grid_pipeline_composes_the_two_ops():
+    rng = np.random.default_rng(33)
+    img = rng.integers(0, 256, (40, 36, 3), dtype=np.uint8)
+    mask = rng.integers(0, 8, (40, 36), dtype=np.uint8)
+    g = oracle.sample_grid(7, 3, 1)[0]
+    out, om = oracle.pipe_elastic_grid_one(img, mask, 7, 3, g, sigma=4.0, alpha=60, radius=12)
+    ox, oy = oracle.elastic_field(7, 3, 40, 36, 4.0, 60, 12)
+    mx, my = oracle.grid_table(g[:5], 36), oracle.grid_table(g[5:], 40)
+    e = oracle.remap_field(img, ox, oy)
+    assert np.array_equal(out, oracle.grid_remap(e, mx, my))
+    em = oracle.remap_field(mask, ox, oy, oracle.NEAREST)
+    assert np.array_equal(om, oracle.grid_remap(em, mx, my, oracle.NEAREST))
+    assert set(np.unique(om)) <= set(np.unique(mask))
