@@ -1,0 +1,297 @@
+"""MI355X (gfx950) batched image augmentation: a thin Python binding of
+libmiaug, the HIP implementation of the augmentation hot path of
+Buslaev et al., "Albumentations: fast and flexible image augmentations"
+(arXiv:1809.06839).
+
+Every function marshals torch tensors (device memory) and the current HIP
+stream into the C ABI declared in ``include/miaug.h``; all image work runs in
+the library's HIP kernels.  There is no CPU fallback: if ``libmiaug.so`` is
+not built, loading raises ``RuntimeError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first so that libmiaug binds to the HIP runtime torch uses
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmiaug.so")
+
+OK, EINVAL, ESHAPE, EUNSUPPORTED, EDEVICE, ENOMEM, ECAPACITY = 0, -1, -2, -3, -4, -5, -6
+
+IMAGENET_MEAN = (0.485, 0.456, 0.406)
+IMAGENET_STD = (0.229, 0.224, 0.225)
+
+
+class MiaugError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("miaug status %d (%s): %s" % (status, _status_str(status), msg))
+        self.status = status
+
+
+_vp, _i, _i64, _u64, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+
+
+class RaggedArgs(ctypes.Structure):
+    """Mirror of miaug_ragged_args (include/miaug.h)."""
+    _fields_ = [("n", ctypes.c_int32), ("out_h", ctypes.c_int32), ("out_w", ctypes.c_int32),
+                ("img", _vp), ("img_off", _vp), ("hw", _vp), ("flags", _vp), ("ab", _vp),
+                ("mask", _vp), ("mask_off", _vp), ("boxes", _vp), ("box_off", _vp),
+                ("mean", ctypes.c_float * 3), ("stdv", ctypes.c_float * 3),
+                ("out", _vp), ("out_mask", _vp), ("out_boxes", _vp)]
+
+
+_SIGS = {
+    "miaug_version": (_i, []),
+    "miaug_status_str": (ctypes.c_char_p, [_i]),
+    "miaug_last_error": (ctypes.c_char_p, []),
+    "miaug_sample_d4bc": (_i, [_u64, _u64, _i, _vp, _vp]),
+    "miaug_sample_c2": (_i, [_u64, _u64, _i, _i, _vp, _vp]),
+    "miaug_sample_wc": (_i, [_u64, _u64, _i, _vp]),
+    "miaug_sample_grid": (_i, [_u64, _u64, _i, _d, _vp]),
+    "miaug_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
+    "miaug_ctx_destroy": (_i, [_vp]),
+    "miaug_d4_bc_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
+    "miaug_ssr_crop_resize_hsv_gamma_blur_u8": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp]),
+    "miaug_ragged_apply": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
+    "miaug_ragged_apply_per_image": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
+    "miaug_ragged_graph_create": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp, ctypes.POINTER(_vp)]),
+    "miaug_graph_launch": (_i, [_vp, _vp]),
+    "miaug_graph_destroy": (_i, [_vp]),
+    "miaug_ragged_autotune": (_i, [_vp, ctypes.POINTER(RaggedArgs), _i, _vp, ctypes.POINTER(_i),
+                                   ctypes.POINTER(ctypes.c_float)]),
+    "miaug_ragged_variant_count": (_i, []),
+    "miaug_ragged_variant_name": (ctypes.c_char_p, [_i]),
+    "miaug_ragged_set_variant": (_i, [_vp, _i]),
+    "miaug_warpcolor_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp]),
+    "miaug_warpcolor_workspace_bytes": (_sz, [_i, _i, _i, _i]),
+    "miaug_warpcolor_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "miaug_elastic_workspace_bytes": (_sz, [_i, _i, _i]),
+    "miaug_elastic_fields": (_i, [_u64, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _sz, _vp]),
+    "miaug_grid_tables": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "miaug_elastic_grid_u8": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp]),
+    "miaug_chain_f32_workspace_bytes": (_sz, [_i, _i, _i, _i]),
+    "miaug_elastic_grid_f32_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "miaug_elastic_grid_f32_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "miaug_image_stats_u8": (_i, [_vp, _i, _i64, _i, _vp, _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libmiaug (raises RuntimeError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmiaug.so is not built (%s); run __graft_entry__.build() or "
+                               "python paper_1809_06839_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_str(s):
+    try:
+        return lib().miaug_status_str(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(status):
+    if status != OK:
+        raise MiaugError(status, lib().miaug_last_error().decode())
+    return status
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+# ---------------------------------------------------------------- sampler (host)
+def sample_d4bc(seed: int, first: int, n: int):
+    flags = np.zeros((n, 4), np.int32); ab = np.zeros((n, 2), np.float32)
+    _check(lib().miaug_sample_d4bc(seed, first, n, flags.ctypes.data, ab.ctypes.data))
+    return flags, ab
+
+
+def sample_c2(seed: int, first: int, n: int, crop_range: int = 64):
+    f = np.zeros((n, 5), np.float32); k = np.zeros((n, 5), np.int32)
+    _check(lib().miaug_sample_c2(seed, first, n, crop_range, f.ctypes.data, k.ctypes.data))
+    return f, k
+
+
+def sample_wc(seed: int, first: int, n: int):
+    f = np.zeros((n, 7), np.float32)
+    _check(lib().miaug_sample_wc(seed, first, n, f.ctypes.data))
+    return f
+
+
+def sample_grid(seed: int, first: int, n: int, limit: float = 0.3):
+    f = np.zeros((n, 10), np.float64)
+    _check(lib().miaug_sample_grid(seed, first, n, limit, f.ctypes.data))
+    return f
+
+
+# ---------------------------------------------------------------- context
+class Context:
+    """Per-device state (queue counters, tuned variant) of the ragged kernels."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().miaug_ctx_create(device, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().miaug_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_variant(self, v: int):
+        _check(lib().miaug_ragged_set_variant(self.handle, v))
+
+
+def ragged_variants():
+    L = lib()
+    return [L.miaug_ragged_variant_name(i).decode() for i in range(L.miaug_ragged_variant_count())]
+
+
+# ---------------------------------------------------------------- plain Dih4 + brightness/contrast
+def d4_bc_u8(img, flags, ab, out=None, stream=None):
+    """img [n, H, W, C] u8 -> out (same byte size; image i has shape (H, W, C) or (W, H, C))."""
+    _dev(img, torch.uint8, "img"); _dev(flags, torch.int32, "flags"); _dev(ab, torch.float32, "ab")
+    n, H, W, C = img.shape
+    if out is None:
+        out = torch.empty_like(img)
+    _dev(out, torch.uint8, "out")
+    _check(lib().miaug_d4_bc_u8(_p(img), n, H, W, C, _p(flags), _p(ab), _p(out), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- full u8 pipeline
+def ssr_crop_resize_hsv_gamma_blur_u8(img, f, k, crop=448, outsz=224, out=None, stream=None):
+    _dev(img, torch.uint8, "img"); _dev(f, torch.float32, "f"); _dev(k, torch.int32, "k")
+    n, H, W, C = img.shape
+    if C != 3:
+        raise ValueError("RGB images expected")
+    if out is None:
+        out = torch.empty((n, outsz, outsz, 3), dtype=torch.uint8, device=img.device)
+    _check(lib().miaug_ssr_crop_resize_hsv_gamma_blur_u8(_p(img), n, H, W, _p(f), _p(k), crop, outsz, _p(out),
+                                                         _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- ragged batch
+class Ragged:
+    """Device-side ragged batch + outputs, packed into one miaug_ragged_args."""
+
+    def __init__(self, img, img_off, hw, flags, ab, out_h=224, out_w=224, mask=None, mask_off=None, boxes=None,
+                 box_off=None, mean=IMAGENET_MEAN, std=IMAGENET_STD, out=None, out_mask=None, out_boxes=None):
+        n = hw.shape[0]
+        dev = img.device
+        _dev(img, torch.uint8, "img"); _dev(img_off, torch.int64, "img_off"); _dev(hw, torch.int32, "hw")
+        _dev(flags, torch.int32, "flags"); _dev(ab, torch.float32, "ab")
+        self.out = out if out is not None else torch.empty((n, 3, out_h, out_w), dtype=torch.float32, device=dev)
+        self.out_mask = None
+        self.out_boxes = None
+        if mask is not None:
+            _dev(mask, torch.uint8, "mask"); _dev(mask_off, torch.int64, "mask_off")
+            self.out_mask = out_mask if out_mask is not None else torch.empty((n, out_h, out_w), dtype=torch.uint8,
+                                                                              device=dev)
+        if boxes is not None:
+            _dev(boxes, torch.float32, "boxes"); _dev(box_off, torch.int32, "box_off")
+            self.out_boxes = out_boxes if out_boxes is not None else torch.empty_like(boxes)
+        self.keep = (img, img_off, hw, flags, ab, mask, mask_off, boxes, box_off)
+        a = RaggedArgs()
+        a.n, a.out_h, a.out_w = n, out_h, out_w
+        a.img, a.img_off, a.hw, a.flags, a.ab = (t.data_ptr() for t in (img, img_off, hw, flags, ab))
+        a.mask = mask.data_ptr() if mask is not None else None
+        a.mask_off = mask_off.data_ptr() if mask is not None else None
+        a.boxes = boxes.data_ptr() if boxes is not None and boxes.numel() > 0 else None
+        a.box_off = box_off.data_ptr() if a.boxes else None
+        a.mean = (ctypes.c_float * 3)(*mean)
+        a.stdv = (ctypes.c_float * 3)(*std)
+        a.out = self.out.data_ptr()
+        a.out_mask = self.out_mask.data_ptr() if self.out_mask is not None else None
+        a.out_boxes = self.out_boxes.data_ptr() if a.boxes else None
+        self.args = a
+
+    @classmethod
+    def from_host(cls, batch, flags, ab, device="cuda", **kw):
+        """Uploads a synth.RaggedBatch-like host batch and host parameters."""
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dt).to(device)
+        has_mask = batch.mask is not None
+        has_boxes = batch.boxes is not None and len(batch.boxes) > 0
+        return cls(t(batch.img, torch.uint8), t(batch.img_off, torch.int64), t(batch.hw, torch.int32),
+                   t(flags, torch.int32), t(ab, torch.float32),
+                   mask=t(batch.mask, torch.uint8) if has_mask else None,
+                   mask_off=t(batch.mask_off, torch.int64) if has_mask else None,
+                   boxes=t(batch.boxes, torch.float32) if has_boxes else None,
+                   box_off=t(batch.box_off, torch.int32) if has_boxes else None, **kw)
+
+
+def ragged_apply(ctx: Context, r: Ragged, stream=None):
+    _check(lib().miaug_ragged_apply(ctx.handle, ctypes.byref(r.args), _stream(stream)))
+    return r
+
+
+def ragged_apply_per_image(ctx: Context, r: Ragged, stream=None):
+    _check(lib().miaug_ragged_apply_per_image(ctx.handle, ctypes.byref(r.args), _stream(stream)))
+    return r
+
+
+def ragged_autotune(ctx: Context, r: Ragged, reps: int = 3, stream=None):
+    v, ms = ctypes.c_int(), ctypes.c_float()
+    _check(lib().miaug_ragged_autotune(ctx.handle, ctypes.byref(r.args), reps, _stream(stream), ctypes.byref(v),
+                                       ctypes.byref(ms)))
+    return v.value, ms.value
+
+
+class Graph:
+    """A captured hipGraph of ragged_apply for fixed buffers."""
+
+    def __init__(self, ctx: Context, r: Ragged, stream):
+        h = ctypes.c_void_p()
+        _check(lib().miaug_ragged_graph_create(ctx.handle, ctypes.byref(r.args), _stream(stream), ctypes.byref(h)))
+        self.handle, self.r = h, r
+
+    def launch(self, stream=None):
+        _check(lib().miaug_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().miaug_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,406 @@
+// api.cpp -- the C ABI of libmiaug: argument validation, error reporting,
+// contexts, graphs and the ragged-batch autotuner.  Every image operation is
+// executed by the HIP kernels behind the launch_* functions.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace miaug {
+namespace {
+thread_local char g_err[512] = "";
+}
+
+int set_error(int status, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+int hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return MIAUG_OK;
+    return set_error(e == hipErrorOutOfMemory ? MIAUG_ENOMEM : MIAUG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace miaug
+
+using namespace miaug;
+
+struct miaug_ctx {
+    int device;
+    int num_cu;
+    int variant;
+    int *counters;  // device, 256 ints
+};
+
+struct miaug_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+int begin_call() {
+    g_err[0] = 0;
+    return MIAUG_OK;
+}
+
+// Status of a ragged argument block (sizes of each image are validated on
+// the device side only through clamping; H, W must be >= 1 by contract).
+int ragged_check(const miaug_ragged_args *a) {
+    if (!a) return set_error(MIAUG_EINVAL, "ragged: args is NULL");
+    if (a->n < 0) return set_error(MIAUG_EINVAL, "ragged: n < 0");
+    if (a->out_h < 1 || a->out_w < 1 || a->out_h > 4096 || a->out_w > 4096)
+        return set_error(MIAUG_ESHAPE, "ragged: output size %dx%d outside 1..4096", a->out_h, a->out_w);
+    if (a->n == 0) return MIAUG_OK;
+    if (!a->img || !a->img_off || !a->hw || !a->flags || !a->ab || !a->out)
+        return set_error(MIAUG_EINVAL, "ragged: a required pointer is NULL");
+    if (a->mask && (!a->mask_off || !a->out_mask)) return set_error(MIAUG_EINVAL, "ragged: mask without offsets/output");
+    if (a->boxes && (!a->box_off || !a->out_boxes)) return set_error(MIAUG_EINVAL, "ragged: boxes without offsets/output");
+    for (int c = 0; c < 3; ++c)
+        if (!(a->stdv[c] != 0.0f)) return set_error(MIAUG_EINVAL, "ragged: std[%d] is zero", c);
+    return MIAUG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int miaug_version(void) { return 10000; }
+
+const char *miaug_status_str(int s) {
+    switch (s) {
+    case MIAUG_OK: return "ok";
+    case MIAUG_EINVAL: return "invalid argument";
+    case MIAUG_ESHAPE: return "invalid or unsupported shape";
+    case MIAUG_EUNSUPPORTED: return "unsupported";
+    case MIAUG_EDEVICE: return "device error";
+    case MIAUG_ENOMEM: return "out of memory";
+    case MIAUG_ECAPACITY: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+const char *miaug_last_error(void) { return g_err; }
+
+int miaug_ctx_create(int device, miaug_ctx **out) {
+    begin_call();
+    if (!out) return set_error(MIAUG_EINVAL, "ctx_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return set_error(MIAUG_EDEVICE, "ctx_create: no HIP device");
+    if (device < 0 || device >= ndev) return set_error(MIAUG_EINVAL, "ctx_create: device %d of %d", device, ndev);
+    int prev = 0;
+    hipGetDevice(&prev);
+    int st = hip_status(hipSetDevice(device), "hipSetDevice");
+    if (st) return st;
+    hipDeviceProp_t prop;
+    st = hip_status(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    miaug_ctx *c = nullptr;
+    if (!st) {
+        c = new (std::nothrow) miaug_ctx{device, prop.multiProcessorCount, ragged_default_variant(), nullptr};
+        if (!c) st = set_error(MIAUG_ENOMEM, "ctx_create: host allocation");
+    }
+    if (!st) {
+        st = hip_status(hipMalloc((void **)&c->counters, 256 * sizeof(int)), "hipMalloc counters");
+        if (!st) st = hip_status(hipMemset(c->counters, 0, 256 * sizeof(int)), "hipMemset counters");
+    }
+    hipSetDevice(prev);
+    if (st) {
+        if (c && c->counters) hipFree(c->counters);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MIAUG_OK;
+}
+
+int miaug_ctx_destroy(miaug_ctx *c) {
+    begin_call();
+    if (!c) return MIAUG_OK;
+    if (c->counters) hipFree(c->counters);
+    delete c;
+    return MIAUG_OK;
+}
+
+int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
+                   uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "d4_bc_u8: negative size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "d4_bc_u8: C=%d (1, 3 or 4)", C);
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!in || !flags || !ab || !out) return set_error(MIAUG_EINVAL, "d4_bc_u8: NULL pointer");
+    if ((long long)H * W * C > (1ll << 31) - 1) return set_error(MIAUG_ESHAPE, "d4_bc_u8: image too large");
+    return hip_status(launch_d4_bc_u8(in, n, H, W, C, flags, ab, out, as_stream(stream)), "d4_bc_u8 launch");
+}
+
+int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const float *f, const int32_t *k,
+                                            int crop, int outsz, uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "c2: negative size");
+    if (n == 0) return MIAUG_OK;
+    if (!in || !f || !k || !out) return set_error(MIAUG_EINVAL, "c2: NULL pointer");
+    if (H < 1 || W < 1 || crop < 1 || crop > H || crop > W || outsz < 1 || outsz > 4096 || H > 16384 || W > 16384)
+        return set_error(MIAUG_ESHAPE, "c2: H=%d W=%d crop=%d outsz=%d", H, W, crop, outsz);
+    return hip_status(launch_c2(in, n, H, W, f, k, crop, outsz, out, as_stream(stream)), "c2 launch");
+}
+
+int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream) {
+    begin_call();
+    if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply: ctx is NULL");
+    if (int st = ragged_check(a)) return st;
+    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
+    return hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply launch");
+}
+
+int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream) {
+    begin_call();
+    if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply_per_image: ctx is NULL");
+    if (int st = ragged_check(a)) return st;
+    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
+    return hip_status(launch_ragged(a, L, 1, as_stream(stream)), "ragged_apply_per_image launch");
+}
+
+int miaug_ragged_graph_create(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream, miaug_graph **out) {
+    begin_call();
+    if (!ctx || !out) return set_error(MIAUG_EINVAL, "graph_create: NULL ctx or out");
+    *out = nullptr;
+    if (int st = ragged_check(a)) return st;
+    if (!stream) return set_error(MIAUG_EINVAL, "graph_create: capture needs a non-null stream");
+    hipStream_t s = as_stream(stream);
+    int st = hip_status(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (st) return st;
+    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
+    hipError_t le = launch_ragged(a, L, 0, s);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_status(le != hipSuccess ? le : ee, "graph capture");
+    }
+    hipGraphExec_t ex = nullptr;
+    st = hip_status(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (st) {
+        hipGraphDestroy(g);
+        return st;
+    }
+    miaug_graph *G = new (std::nothrow) miaug_graph{g, ex};
+    if (!G) {
+        hipGraphExecDestroy(ex);
+        hipGraphDestroy(g);
+        return set_error(MIAUG_ENOMEM, "graph_create: host allocation");
+    }
+    *out = G;
+    return MIAUG_OK;
+}
+
+int miaug_graph_launch(miaug_graph *g, void *stream) {
+    begin_call();
+    if (!g) return set_error(MIAUG_EINVAL, "graph_launch: NULL graph");
+    return hip_status(hipGraphLaunch(g->exec, as_stream(stream)), "hipGraphLaunch");
+}
+
+int miaug_graph_destroy(miaug_graph *g) {
+    begin_call();
+    if (!g) return MIAUG_OK;
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    delete g;
+    return MIAUG_OK;
+}
+
+int miaug_ragged_variant_count(void) { return ragged_variant_count(); }
+const char *miaug_ragged_variant_name(int v) { return ragged_variant_name(v); }
+
+int miaug_ragged_set_variant(miaug_ctx *ctx, int v) {
+    begin_call();
+    if (!ctx) return set_error(MIAUG_EINVAL, "set_variant: NULL ctx");
+    if (v < -1 || v >= ragged_variant_count()) return set_error(MIAUG_EINVAL, "set_variant: %d out of range", v);
+    ctx->variant = v < 0 ? ragged_default_variant() : v;
+    return MIAUG_OK;
+}
+
+int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, void *stream, int *chosen, float *ms) {
+    begin_call();
+    if (!ctx) return set_error(MIAUG_EINVAL, "autotune: NULL ctx");
+    if (int st = ragged_check(a)) return st;
+    if (reps < 1) return set_error(MIAUG_EINVAL, "autotune: reps < 1");
+    if (a->n == 0) {
+        if (chosen) *chosen = ctx->variant;
+        if (ms) *ms = 0.f;
+        return MIAUG_OK;
+    }
+    hipStream_t s = as_stream(stream);
+    const size_t out_bytes = (size_t)a->n * 3 * a->out_h * a->out_w * sizeof(float);
+    const size_t mask_bytes = a->mask ? (size_t)a->n * a->out_h * a->out_w : 0;
+    std::vector<char> ref(out_bytes), got(out_bytes), mref(mask_bytes), mgot(mask_bytes);
+    RaggedLaunch L{0, ctx->num_cu, ctx->counters};
+    int st = hip_status(launch_ragged(a, L, 1, s), "autotune reference");
+    if (!st) st = hip_status(hipMemcpyAsync(ref.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
+    if (!st && mask_bytes)
+        st = hip_status(hipMemcpyAsync(mref.data(), a->out_mask, mask_bytes, hipMemcpyDeviceToHost, s), "copy");
+    if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+    if (st) return st;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    int best = -1;
+    float best_ms = 0.f;
+    for (int v = 0; v < ragged_variant_count() && !st; ++v) {
+        L.variant = v;
+        st = hip_status(hipMemsetAsync(a->out, 0, out_bytes, s), "clear");
+        if (!st) st = hip_status(launch_ragged(a, L, 0, s), "autotune candidate");
+        if (!st) st = hip_status(hipMemcpyAsync(got.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
+        if (!st && mask_bytes)
+            st = hip_status(hipMemcpyAsync(mgot.data(), a->out_mask, mask_bytes, hipMemcpyDeviceToHost, s), "copy");
+        if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+        if (st) break;
+        if (memcmp(ref.data(), got.data(), out_bytes) != 0 || memcmp(mref.data(), mgot.data(), mask_bytes) != 0)
+            continue;  // parity gate: only variants identical to the per-image form compete
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !st; ++r) st = hip_status(launch_ragged(a, L, 0, s), "autotune timing");
+        hipEventRecord(e1, s);
+        if (!st) st = hip_status(hipEventSynchronize(e1), "sync");
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        t /= reps;
+        if (best < 0 || t < best_ms) {
+            best = v;
+            best_ms = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st) return st;
+    if (best < 0) return set_error(MIAUG_EDEVICE, "autotune: no variant matched the per-image output");
+    ctx->variant = best;
+    if (chosen) *chosen = best;
+    if (ms) *ms = best_ms;
+    return MIAUG_OK;
+}
+
+int miaug_warpcolor_fwd(const float *x, int n, int C, int H, int W, const float *params, float *y, void *stream) {
+    begin_call();
+    if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "warpcolor_fwd: negative size");
+    if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!x || !params || !y) return set_error(MIAUG_EINVAL, "warpcolor_fwd: NULL pointer");
+    if (H > 16384 || W > 16384) return set_error(MIAUG_ESHAPE, "warpcolor_fwd: %dx%d too large", H, W);
+    return hip_status(launch_wc_fwd(x, n, C, H, W, params, y, as_stream(stream)), "warpcolor_fwd launch");
+}
+
+size_t miaug_warpcolor_workspace_bytes(int n, int C, int H, int W) {
+    if (n <= 0 || C <= 0 || H <= 0 || W <= 0) return 0;
+    return wc_workspace_bytes(n, C, H, W);
+}
+
+int miaug_warpcolor_bwd(const float *x, int n, int C, int H, int W, const float *params, const float *gy,
+                        float *grad_x, float *grad_params, void *ws, size_t ws_bytes, void *stream) {
+    begin_call();
+    if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "warpcolor_bwd: negative size");
+    if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!x || !params || !gy || !grad_params) return set_error(MIAUG_EINVAL, "warpcolor_bwd: NULL pointer");
+    if (H > 16384 || W > 16384) return set_error(MIAUG_ESHAPE, "warpcolor_bwd: %dx%d too large", H, W);
+    size_t need = wc_workspace_bytes(n, C, H, W);
+    if (!ws || ws_bytes < need)
+        return set_error(MIAUG_ECAPACITY, "warpcolor_bwd: workspace %zu < %zu bytes", ws_bytes, need);
+    return hip_status(launch_wc_bwd(x, n, C, H, W, params, gy, grad_x, grad_params, ws, as_stream(stream)),
+                      "warpcolor_bwd launch");
+}
+
+size_t miaug_elastic_workspace_bytes(int n, int H, int W) {
+    if (n <= 0 || H <= 0 || W <= 0) return 0;
+    return elastic_workspace_bytes(n, H, W);
+}
+
+int miaug_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha, int radius,
+                         int32_t *off, void *ws, size_t ws_bytes, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "elastic_fields: negative size");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!off) return set_error(MIAUG_EINVAL, "elastic_fields: NULL off");
+    if (radius < 1 || radius > 512 || !(sigma > 0.0) || alpha < 0 || alpha > 65535)
+        return set_error(MIAUG_ESHAPE, "elastic_fields: radius=%d sigma=%g alpha=%d", radius, sigma, alpha);
+    if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "elastic_fields: image too large");
+    size_t need = elastic_workspace_bytes(n, H, W);
+    if (!ws || ws_bytes < need)
+        return set_error(MIAUG_ECAPACITY, "elastic_fields: workspace %zu < %zu bytes", ws_bytes, need);
+    return hip_status(launch_elastic_fields(seed, first, n, H, W, sigma, alpha, radius, off, ws, as_stream(stream)),
+                      "elastic_fields launch");
+}
+
+int miaug_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "grid_tables: negative size");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!grid || !mapx || !mapy) return set_error(MIAUG_EINVAL, "grid_tables: NULL pointer");
+    if (H > 1000000 || W > 1000000) return set_error(MIAUG_ESHAPE, "grid_tables: size too large");
+    return hip_status(launch_grid_tables(grid, n, H, W, mapx, mapy, as_stream(stream)), "grid_tables launch");
+}
+
+int miaug_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C, const int32_t *off,
+                          const int32_t *mapx, const int32_t *mapy, uint8_t *out, uint8_t *out_mask, int per_image,
+                          void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "elastic_grid_u8: negative size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "elastic_grid_u8: C=%d", C);
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!img || !off || !mapx || !mapy || !out || (mask && !out_mask))
+        return set_error(MIAUG_EINVAL, "elastic_grid_u8: NULL pointer");
+    if ((long long)H * W * C > (1ll << 31) - 1) return set_error(MIAUG_ESHAPE, "elastic_grid_u8: image too large");
+    return hip_status(launch_elastic_grid_u8(img, mask, n, H, W, C, off, mapx, mapy, out, out_mask, per_image,
+                                             as_stream(stream)),
+                      "elastic_grid_u8 launch");
+}
+
+size_t miaug_chain_f32_workspace_bytes(int n, int C, int H, int W) {
+    if (n <= 0 || C <= 0 || H <= 0 || W <= 0) return 0;
+    return chain_f32_workspace_bytes(n, C, H, W);
+}
+
+int miaug_elastic_grid_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                               const int32_t *mapy, float *y, void *ws, size_t ws_bytes, void *stream) {
+    begin_call();
+    if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "chain_f32_fwd: negative size");
+    if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!x || !off || !mapx || !mapy || !y) return set_error(MIAUG_EINVAL, "chain_f32_fwd: NULL pointer");
+    if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "chain_f32_fwd: image too large");
+    size_t need = chain_f32_workspace_bytes(n, C, H, W);
+    if (!ws || ws_bytes < need)
+        return set_error(MIAUG_ECAPACITY, "chain_f32_fwd: workspace %zu < %zu bytes", ws_bytes, need);
+    return hip_status(launch_chain_f32_fwd(x, n, C, H, W, off, mapx, mapy, y, ws, as_stream(stream)),
+                      "chain_f32_fwd launch");
+}
+
+int miaug_elastic_grid_f32_bwd(const float *gy, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                               const int32_t *mapy, float *gx, void *ws, size_t ws_bytes, void *stream) {
+    begin_call();
+    if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "chain_f32_bwd: negative size");
+    if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!gy || !off || !mapx || !mapy || !gx) return set_error(MIAUG_EINVAL, "chain_f32_bwd: NULL pointer");
+    if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "chain_f32_bwd: image too large");
+    size_t need = chain_f32_workspace_bytes(n, C, H, W);
+    if (!ws || ws_bytes < need)
+        return set_error(MIAUG_ECAPACITY, "chain_f32_bwd: workspace %zu < %zu bytes", ws_bytes, need);
+    return hip_status(launch_chain_f32_bwd(gy, n, C, H, W, off, mapx, mapy, gx, ws, as_stream(stream)),
+                      "chain_f32_bwd launch");
+}
+
+int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_t *sum, int32_t *mn, int32_t *mx,
+                         uint32_t *hist, void *stream) {
+    begin_call();
+    if (n < 0 || npix < 0) return set_error(MIAUG_EINVAL, "image_stats: negative size");
+    if (C < 1 || C > 4) return set_error(MIAUG_ESHAPE, "image_stats: C=%d", C);
+    if (n == 0) return MIAUG_OK;
+    if (!img && npix > 0) return set_error(MIAUG_EINVAL, "image_stats: NULL image");
+    if (npix > (1ll << 40)) return set_error(MIAUG_ESHAPE, "image_stats: too many pixels");
+    return hip_status(launch_image_stats(img, n, npix, C, sum, mn, mx, hist, as_stream(stream)), "image_stats launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// internal.h -- host-side internals of libmiaug shared by the C ABI layer and
+// the kernel launchers.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/miaug.h"
+
+namespace miaug {
+
+// Records a formatted message as the calling thread's last error; returns status.
+int set_error(int status, const char *fmt, ...);
+// Maps a HIP error to MIAUG_EDEVICE with context text (MIAUG_OK on success).
+int hip_status(hipError_t e, const char *what);
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- launchers (each returns the hipError_t of its launches)
+hipError_t launch_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
+                           uint8_t *out, hipStream_t s);
+
+struct RaggedLaunch {
+    int variant;      // index into the variant table
+    int num_cu;       // compute units of the device
+    int *counters;    // device: queue counters (8 + 8 padding ints)
+};
+hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s);
+int ragged_variant_count();
+const char *ragged_variant_name(int v);
+int ragged_default_variant();
+
+hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const float *f, const int32_t *k, int crop, int outsz,
+                     uint8_t *out, hipStream_t s);
+
+hipError_t launch_wc_fwd(const float *x, int n, int C, int H, int W, const float *p, float *y, hipStream_t s);
+size_t wc_workspace_bytes(int n, int C, int H, int W);
+hipError_t launch_wc_bwd(const float *x, int n, int C, int H, int W, const float *p, const float *gy, float *gx,
+                         float *gp, void *ws, hipStream_t s);
+
+size_t elastic_workspace_bytes(int n, int H, int W);
+hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
+                                 int radius, int32_t *off, void *ws, hipStream_t s);
+hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, hipStream_t s);
+hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
+                                  const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
+                                  uint8_t *out_mask, int per_image, hipStream_t s);
+size_t chain_f32_workspace_bytes(int n, int C, int H, int W);
+hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                                const int32_t *mapy, float *y, void *ws, hipStream_t s);
+hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                                const int32_t *mapy, float *gx, void *ws, hipStream_t s);
+
+hipError_t launch_image_stats(const uint8_t *img, int n, int64_t npix, int C, uint64_t *sum, int32_t *mn, int32_t *mx,
+                              uint32_t *hist, hipStream_t s);
+
+}  // namespace miaug
