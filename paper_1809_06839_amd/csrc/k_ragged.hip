@@ -30,18 +30,24 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kQueues = 8;
 constexpr int kCounterStride = 16;  // ints between counters (one 64-byte line each)
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
-__device__ __forceinline__ int64_t floordiv64(int64_t n, int64_t d) {
-    int64_t q = n / d, r = n - q * d;
-    return (r < 0) ? q - 1 : q;
-}
-
-// Half-pixel-centre position of output index j (Q10): rdiv_he(((2j+1) Ls - Lo) 2^10, 2 Lo).
+// Half-pixel-centre position of output index j (Q10):
+// rdiv_he(((2j+1) Ls - Lo) 2^10, 2 Lo), evaluated with two 32-bit floor
+// divisions: A = (2j+1) Ls - Lo = qa D + ra (D = 2 Lo), then ra 2^10 = qb D + rb.
 __device__ __forceinline__ int32_t resize_q(int j, int Ls, int Lo) {
-    int64_t n = ((int64_t)(2 * j + 1) * Ls - Lo) * kFOne, d = 2 * (int64_t)Lo;
-    int64_t q = floordiv64(n, d), r = n - q * d;
-    return (int32_t)(q + ((2 * r > d) | ((2 * r == d) & (q & 1))));
+    const int D = 2 * Lo;
+    const int A = (2 * j + 1) * Ls - Lo;
+    int qa = A / D, ra = A - qa * D;
+    if (ra < 0) { qa -= 1; ra += D; }
+    const int B = ra << kFBits;
+    const int qb = B / D, rb = B - qb * D;
+    const int q = (qa << kFBits) + qb;
+    return q + ((2 * rb > D) | ((2 * rb == D) & (q & 1)));
 }
+
+// Round-half-even of acc / 2^20 for acc >= 0.
+__device__ __forceinline__ int rhe20(int acc) { return (acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20; }
 
 template <int T>
 struct Cfg {
@@ -55,17 +61,19 @@ struct Cfg {
 
 template <int T>
 struct __align__(16) Smem {
-    uint8_t img[2 * T][Cfg<T>::kStride];
-    uint8_t msk[T][Cfg<T>::kMStride];
+    // staging buffer: image slot s at byte 16*s*nchi, mask slot s at byte
+    // 16*(2*nl*nchi + s*nchm) (nchi, nchm: 16-byte chunks per slot of the tile)
+    uint8_t stage[2 * T * Cfg<T>::kStride + T * Cfg<T>::kMStride];
     float nlut[3][256];
     int32_t qline[T], qspan[T];
-    int32_t ph[2 * T], mph[T];
+    int4 line[T];  // per output line: LDS offsets of the two tap rows and the nearest mask row, weight
+    int4 col[T];   // per span position: byte offsets of the two taps in a row, weight, mask offset
     uint8_t bclut[256];
     int item;
 };
 
 template <int T>
-__device__ void build_norm_lut(const miaug_ragged_args &a, Smem<T> &S) {
+__device__ __forceinline__ void build_norm_lut(const miaug_ragged_args &a, Smem<T> &S) {
     for (int e = threadIdx.x; e < 3 * 256; e += kThreads) {
         int c = e >> 8, v = e & 255;
         S.nlut[c][v] = (float)((((double)v / 255.0) - (double)a.mean[c]) / (double)a.stdv[c]);
@@ -73,7 +81,7 @@ __device__ void build_norm_lut(const miaug_ragged_args &a, Smem<T> &S) {
 }
 
 template <int T>
-__device__ void build_bc_lut(const miaug_ragged_args &a, int img, Smem<T> &S) {
+__device__ __forceinline__ void build_bc_lut(const miaug_ragged_args &a, int img, Smem<T> &S) {
     int v = threadIdx.x;
     if (v < 256) {
         double t = (double)a.ab[2 * img] * (double)v + (double)a.ab[2 * img + 1];
@@ -83,7 +91,7 @@ __device__ void build_bc_lut(const miaug_ragged_args &a, int img, Smem<T> &S) {
 
 // Boxes of one image: Dih4 ops one after the other, then the scale to the
 // output size, in double.
-__device__ void ragged_boxes(const miaug_ragged_args &a, int img) {
+__device__ __forceinline__ void ragged_boxes(const miaug_ragged_args &a, int img) {
     int b0 = a.box_off[img], b1 = a.box_off[img + 1];
     const int32_t *fl = a.flags + 4 * img;
     for (int b = b0 + (int)threadIdx.x; b < b1; b += kThreads) {
@@ -113,7 +121,7 @@ __device__ void ragged_boxes(const miaug_ragged_args &a, int img) {
 // synchronise before LDS is reused.  `lut_img` is the image whose
 // brightness/contrast LUT is currently in LDS (-1: none).
 template <int T>
-__device__ void ragged_tile(const miaug_ragged_args &a, int img, int tile, Smem<T> &S, int &lut_img) {
+__device__ __forceinline__ void ragged_tile(const miaug_ragged_args &a, int img, int tile, Smem<T> &S, int &lut_img) {
     using C = Cfg<T>;
     const int tid = threadIdx.x;
     const int H = a.hw[2 * img], W = a.hw[2 * img + 1];
@@ -138,8 +146,13 @@ __device__ void ragged_tile(const miaug_ragged_args &a, int img, int tile, Smem<
     }
     if (tid < nl) S.qline[tid] = resize_q(l0 + tid, Ll, OL);
     if (tid >= 64 && tid - 64 < ns) S.qspan[tid - 64] = resize_q(s0 + tid - 64, Ls, OS);
+    const uint8_t *ibase = a.img + a.img_off[img];
+    const uint8_t *mbase = a.mask ? a.mask + a.mask_off[img] : nullptr;
+    if (tile == 0 && a.boxes) ragged_boxes(a, img);
+    __syncthreads();
 
-    const int32_t qs_first = resize_q(s0, Ls, OS), qs_last = resize_q(s0 + ns - 1, Ls, OS);
+    // source column span of the tile (bilinear taps) and of its nearest taps
+    const int32_t qs_first = S.qspan[0], qs_last = S.qspan[ns - 1];
     const int dlo = clampi(qs_first >> kFBits, Ls), dhi = clampi((qs_last >> kFBits) + 1, Ls);
     const int xa = ks * dlo + m.cx, xb = ks * dhi + m.cx;
     const int sxlo = min(xa, xb), nsx = abs(xb - xa) + 1;
@@ -147,33 +160,94 @@ __device__ void ragged_tile(const miaug_ragged_args &a, int img, int tile, Smem<
     const int mxa = ks * nlo + m.cx, mxb = ks * nhi + m.cx;
     const int mxlo = min(mxa, mxb), nmx = abs(mxb - mxa) + 1;
     const bool staged = nsx <= C::kMaxSpanPx;
-    const uint8_t *ibase = a.img + a.img_off[img];
-    const uint8_t *mbase = a.mask ? a.mask + a.mask_off[img] : nullptr;
-    __syncthreads();
 
-    if (staged) {
-        for (int it = tid; it < 2 * nl * C::kChunks; it += kThreads) {
-            int slot = it / C::kChunks, ch = it - slot * C::kChunks;
-            int q = S.qline[slot >> 1];
-            int d = clampi((q >> kFBits) + (slot & 1), Ll);
-            const uint8_t *g = ibase + ((size_t)(kl * d + m.cy) * W + sxlo) * 3;
-            if (ch == 0) S.ph[slot] = span_phase(g);
-            if (ch < span_chunks(g, nsx * 3)) load_span16_chunk(g, ch, S.img[slot]);
-        }
-        if (mbase) {
-            for (int it = tid; it < nl * C::kMChunks; it += kThreads) {
-                int slot = it / C::kMChunks, ch = it - slot * C::kMChunks;
-                int d = clampi((S.qline[slot] + kFOne / 2) >> kFBits, Ll);
-                const uint8_t *g = mbase + (size_t)(kl * d + m.cy) * W + mxlo;
-                if (ch == 0) S.mph[slot] = span_phase(g);
-                if (ch < span_chunks(g, nmx)) load_span16_chunk(g, ch, S.msk[slot]);
-            }
-        }
-    }
-    if (tile == 0 && a.boxes) ragged_boxes(a, img);
-    __syncthreads();
-
+    // Staging: item `it` (a 16-byte chunk of an image or mask slot) is copied
+    // straight from HBM to LDS byte 16*it with global_load_lds_dwordx4.  The 64
+    // lanes of a wave take 64 consecutive items, which is the DMA's lane layout
+    // (LDS base in M0 + 16 * lane), so no registers hold the data and a
+    // workgroup has its whole footprint in flight at once.
+    const int nchi = (nsx * 3 + 30) >> 4, nchm = mbase ? (nmx + 30) >> 4 : 0;
+    const int img_items = 2 * nl * nchi, total = img_items + nl * nchm;
     const size_t plane = (size_t)OH * OW;
+    if (staged) {
+        const uint32_t inv_i = ((1u << 20) + nchi - 1) / nchi;            // it / nchi = (it * inv) >> 20
+        const uint32_t inv_m = nchm ? ((1u << 20) + nchm - 1) / nchm : 0;  // (exact for it < 4096)
+        const int lane = tid & 63;
+        for (int base = tid - lane; base < total; base += kThreads) {
+            const int it = base + lane;
+            const uint8_t *src = nullptr;
+            if (it < total) {
+                const uint8_t *g;
+                int len, ch;
+                if (it < img_items) {
+                    const int slot = (int)(((uint32_t)it * inv_i) >> 20);
+                    ch = it - slot * nchi;
+                    const int d = clampi((S.qline[slot >> 1] >> kFBits) + (slot & 1), Ll);
+                    g = ibase + ((size_t)(kl * d + m.cy) * W + sxlo) * 3;
+                    len = nsx * 3;
+                } else {
+                    const int it2 = it - img_items, slot = (int)(((uint32_t)it2 * inv_m) >> 20);
+                    ch = it2 - slot * nchm;
+                    const int d = clampi((S.qline[slot] + kFOne / 2) >> kFBits, Ll);
+                    g = mbase + (size_t)(kl * d + m.cy) * W + mxlo;
+                    len = nmx;
+                }
+                if (ch < span_chunks(g, len)) src = (const uint8_t *)((uintptr_t)g & ~(uintptr_t)15) + 16 * ch;
+            }
+            if (src)
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr_t)(S.stage + 16 * base), 16, 0, 0);
+        }
+        // per-line and per-column tables (the same addresses, from the registers of phase A)
+        if (tid < nl) {
+            const int q = S.qline[tid];
+            const int d0 = clampi(q >> kFBits, Ll), d1 = clampi((q >> kFBits) + 1, Ll);
+            const uint8_t *g0 = ibase + ((size_t)(kl * d0 + m.cy) * W + sxlo) * 3;
+            const uint8_t *g1 = ibase + ((size_t)(kl * d1 + m.cy) * W + sxlo) * 3;
+            int mb = 0;
+            if (mbase) {
+                const int dn = clampi((q + kFOne / 2) >> kFBits, Ll);
+                mb = 16 * (img_items + tid * nchm) + span_phase(mbase + (size_t)(kl * dn + m.cy) * W + mxlo);
+            }
+            S.line[tid] = make_int4(16 * (2 * tid) * nchi + span_phase(g0), 16 * (2 * tid + 1) * nchi + span_phase(g1),
+                                    q & (kFOne - 1), mb);
+        }
+        if (tid >= 64 && tid - 64 < ns) {
+            const int si = tid - 64, q = S.qspan[si];
+            const int e0 = clampi(q >> kFBits, Ls), e1 = clampi((q >> kFBits) + 1, Ls);
+            const int en = clampi((q + kFOne / 2) >> kFBits, Ls);
+            S.col[si] = make_int4(3 * (ks * e0 + m.cx - sxlo), 3 * (ks * e1 + m.cx - sxlo), q & (kFOne - 1),
+                                  ks * en + m.cx - mxlo);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
+        __syncthreads();
+
+#pragma unroll
+        for (int k = 0; k < C::kPix; ++k) {
+            const int p = tid + k * kThreads;
+            const int jj = p / T, ii = p - jj * T;
+            if (p >= T * T || jj >= th || ii >= tw) continue;
+            const int4 L = S.line[swap ? ii : jj];
+            const int4 Cc = S.col[swap ? jj : ii];
+            const uint8_t *r0 = S.stage + L.x, *r1 = S.stage + L.y;
+            const int wl1 = L.z, ws1 = Cc.z;
+            float *o = a.out + (size_t)img * 3 * plane + (size_t)(j0 + jj) * OW + (i0 + ii);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int p00 = S.bclut[r0[Cc.x + c]], p01 = S.bclut[r0[Cc.y + c]];
+                const int p10 = S.bclut[r1[Cc.x + c]], p11 = S.bclut[r1[Cc.y + c]];
+                // (1024-ws1) p00 + ws1 p01 = 1024 p00 + ws1 (p01 - p00), exactly; same for rows
+                const int t0 = (p00 << kFBits) + ws1 * (p01 - p00);
+                const int t1 = (p10 << kFBits) + ws1 * (p11 - p10);
+                o[c * plane] = S.nlut[c][rhe20((t0 << kFBits) + wl1 * (t1 - t0))];
+            }
+            if (mbase) a.out_mask[(size_t)img * plane + (size_t)(j0 + jj) * OW + (i0 + ii)] = S.stage[L.w + Cc.w];
+        }
+        return;
+    }
+
+    // Fallback for spans wider than the staging buffer (source more than 4.6x
+    // the output along the span axis): the same arithmetic on direct loads.
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < C::kPix; ++k) {
         const int p = tid + k * kThreads;
@@ -181,44 +255,23 @@ __device__ void ragged_tile(const miaug_ragged_args &a, int img, int tile, Smem<
         if (p >= T * T || jj >= th || ii >= tw) continue;
         const int l = swap ? ii : jj, si = swap ? jj : ii;
         const int32_t ql = S.qline[l], qs = S.qspan[si];
-        const int wl1 = ql & (kFOne - 1), wl0 = kFOne - wl1;
-        const int ws1 = qs & (kFOne - 1), ws0 = kFOne - ws1;
-        const int e0 = clampi(qs >> kFBits, Ls), e1 = clampi((qs >> kFBits) + 1, Ls);
-        const int x0 = ks * e0 + m.cx - sxlo, x1 = ks * e1 + m.cx - sxlo;
-        int v[3];
-        if (staged) {
-            const uint8_t *r0 = S.img[2 * l] + S.ph[2 * l], *r1 = S.img[2 * l + 1] + S.ph[2 * l + 1];
+        const int wl1 = ql & (kFOne - 1), ws1 = qs & (kFOne - 1);
+        const int x0 = ks * clampi(qs >> kFBits, Ls) + m.cx, x1 = ks * clampi((qs >> kFBits) + 1, Ls) + m.cx;
+        const int y0 = kl * clampi(ql >> kFBits, Ll) + m.cy, y1 = kl * clampi((ql >> kFBits) + 1, Ll) + m.cy;
+        const uint8_t *r0 = ibase + (size_t)y0 * W * 3, *r1 = ibase + (size_t)y1 * W * 3;
+        float *o = a.out + (size_t)img * 3 * plane + (size_t)(j0 + jj) * OW + (i0 + ii);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int p00 = S.bclut[r0[3 * x0 + c]], p01 = S.bclut[r0[3 * x1 + c]];
-                int p10 = S.bclut[r1[3 * x0 + c]], p11 = S.bclut[r1[3 * x1 + c]];
-                v[c] = rshr_he(wl0 * (ws0 * p00 + ws1 * p01) + wl1 * (ws0 * p10 + ws1 * p11), 2 * kFBits);
-            }
-        } else {
-            const int y0 = kl * clampi(ql >> kFBits, Ll) + m.cy, y1 = kl * clampi((ql >> kFBits) + 1, Ll) + m.cy;
-            const uint8_t *r0 = ibase + ((size_t)y0 * W + sxlo) * 3, *r1 = ibase + ((size_t)y1 * W + sxlo) * 3;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int p00 = S.bclut[r0[3 * x0 + c]], p01 = S.bclut[r0[3 * x1 + c]];
-                int p10 = S.bclut[r1[3 * x0 + c]], p11 = S.bclut[r1[3 * x1 + c]];
-                v[c] = rshr_he(wl0 * (ws0 * p00 + ws1 * p01) + wl1 * (ws0 * p10 + ws1 * p11), 2 * kFBits);
-            }
+        for (int c = 0; c < 3; ++c) {
+            const int p00 = S.bclut[r0[3 * x0 + c]], p01 = S.bclut[r0[3 * x1 + c]];
+            const int p10 = S.bclut[r1[3 * x0 + c]], p11 = S.bclut[r1[3 * x1 + c]];
+            const int t0 = (p00 << kFBits) + ws1 * (p01 - p00);
+            const int t1 = (p10 << kFBits) + ws1 * (p11 - p10);
+            o[c * plane] = S.nlut[c][rhe20((t0 << kFBits) + wl1 * (t1 - t0))];
         }
-        const int j = j0 + jj, i = i0 + ii;
-        float *o = a.out + (size_t)img * 3 * plane + (size_t)j * OW + i;
-        o[0] = S.nlut[0][v[0]];
-        o[plane] = S.nlut[1][v[1]];
-        o[2 * plane] = S.nlut[2][v[2]];
         if (mbase) {
-            const int mx = ks * clampi((qs + kFOne / 2) >> kFBits, Ls) + m.cx - mxlo;
-            uint8_t mv;
-            if (staged) {
-                mv = S.msk[l][S.mph[l] + mx];
-            } else {
-                const int my = kl * clampi((ql + kFOne / 2) >> kFBits, Ll) + m.cy;
-                mv = mbase[(size_t)my * W + mxlo + mx];
-            }
-            a.out_mask[(size_t)img * plane + (size_t)j * OW + i] = mv;
+            const int mx = ks * clampi((qs + kFOne / 2) >> kFBits, Ls) + m.cx;
+            const int my = kl * clampi((ql + kFOne / 2) >> kFBits, Ll) + m.cy;
+            a.out_mask[(size_t)img * plane + (size_t)(j0 + jj) * OW + (i0 + ii)] = mbase[(size_t)my * W + mx];
         }
     }
 }
