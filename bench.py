@@ -153,7 +153,157 @@ def bench_ragged(args, torch, m):
     return res
 
 
-WORKLOADS = {"ragged": bench_ragged}
+def time_on_stream(torch, fn, steps, warmup, s):
+    """Average ms of fn(s) over `steps` calls on stream s, HIP events around the loop."""
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            fn(s)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        for _ in range(steps):
+            fn(s)
+        e1.record(s)
+        s.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def line(metric, n, ms, args, dtype, config, roofline, extra=None):
+    res = {"metric": metric, "value": n / (ms * 1e-3), "unit": "images/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
+    if extra:
+        res.update(extra)
+    return res
+
+
+def hbm_roof(alg_bytes, ms, kernel):
+    a = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kernel, "algorithmic_bytes_per_launch": alg_bytes}
+
+
+def bench_d4bc(args, torch, m):
+    """64 RGB 256x256 u8 images: random Dih4 element + brightness/contrast."""
+    import synth
+    n, H, W = 64, 256, 256
+    img = synth.uniform_u8(1809068391, n, H, W).cuda()
+    flags, ab = m.sample_d4bc(1809068391, 0, n)
+    fl, abt = torch.from_numpy(flags).cuda(), torch.from_numpy(ab).cuda()
+    out = torch.empty_like(img)
+    s = torch.cuda.Stream()
+    ms = time_on_stream(torch, lambda st: m.d4_bc_u8(img, fl, abt, out, st), args.steps, args.warmup, s)
+    alg = 2 * n * H * W * 3
+    res = line("images/sec and HBM GB/s (% peak), plain Dih4 + brightness/contrast", n, ms, args, "u8",
+               {"workload": "d4_brightness_contrast_64x256x256x3"}, hbm_roof(alg, ms, "k_d4_bc<3>"))
+    if not args.no_cpu_baseline:
+        import oracle, time as _t
+        x = img.cpu().numpy()
+        t0 = _t.perf_counter(); done = 0
+        while done < n and _t.perf_counter() - t0 < args.cpu_seconds:
+            oracle.pipe_d4bc(x[done:done + 1], flags[done:done + 1], ab[done:done + 1]); done += 1
+        dt = _t.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of the 64 images, single-threaded C oracle" % done}
+    return res
+
+
+def bench_c2(args, torch, m):
+    """256 smooth-noise RGB 512x512 u8 images: shift-scale-rotate -> crop 448 -> 224 -> HSV -> gamma -> blur."""
+    import synth
+    n = 256
+    img = synth.smooth_u8_hwc(1809068392, n, 512, 512, device="cuda")
+    f, k = m.sample_c2(1809068392, 0, n)
+    rec = torch.from_numpy(m.compile_c2(f, k, 512, 512, 448)).cuda()
+    out = torch.empty((n, 224, 224, 3), dtype=torch.uint8, device="cuda")
+    s = torch.cuda.Stream()
+    ms = time_on_stream(torch, lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec, 448, 224, out, st),
+                        args.steps, args.warmup, s)
+    alg = n * (512 * 512 * 3 + 224 * 224 * 3)
+    res = line("images/sec and HBM GB/s (% peak), full u8 pipeline", n, ms, args, "u8",
+               {"workload": "ssr_crop448_resize224_hsv_gamma_blur_256x512x512x3"}, hbm_roof(alg, ms, "k_c2"))
+    if not args.no_cpu_baseline:
+        import oracle, time as _t
+        x = img.cpu().numpy()
+        t0 = _t.perf_counter(); done = 0
+        while done < n and _t.perf_counter() - t0 < args.cpu_seconds:
+            oracle.pipe_c2_one(x[done], f[done], k[done]); done += 1
+        dt = _t.perf_counter() - t0
+        res["cpu_baseline"] = {"value": done / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d of the 256 images, single-threaded C oracle" % done}
+    return res
+
+
+def bench_wc(args, torch, m):
+    """128 x 3 x 224 x 224 float32: differentiable warp + colour, forward + backward."""
+    import synth
+    n, C, H, W = 128, 3, 224, 224
+    x = synth.smooth_noise(1809068394, n, H, W, C, device="cuda")
+    p = torch.from_numpy(m.sample_wc(1809068394, 0, n)).cuda()
+    g = torch.Generator().manual_seed(5)
+    w = (torch.rand((n, C, H, W), generator=g) * 2 - 1).cuda()
+    y = torch.empty_like(x)
+    gx = torch.empty_like(x)
+    gp = torch.empty_like(p)
+    ws = torch.empty(m.lib().miaug_warpcolor_workspace_bytes(n, C, H, W), dtype=torch.uint8, device="cuda")
+    L = m.lib()
+
+    def step(st):
+        m._check(L.miaug_warpcolor_fwd(m._p(x), n, C, H, W, m._p(p), m._p(y), m._stream(st)))
+        m._check(L.miaug_warpcolor_bwd(m._p(x), n, C, H, W, m._p(p), m._p(w), m._p(gx), m._p(gp), m._p(ws),
+                                       ws.numel(), m._stream(st)))
+
+    s = torch.cuda.Stream()
+    ms = time_on_stream(torch, step, args.steps, args.warmup, s)
+    plane = n * C * H * W * 4
+    alg = 2 * plane + 3 * plane  # forward x, y; backward gy, x, grad_x
+    return line("images/sec and HBM GB/s (% peak), differentiable warp + colour fwd+bwd", n, ms, args, "f32",
+                {"workload": "warpcolor_fwd_bwd_128x3x224x224_f32"}, hbm_roof(alg, ms, "k_wc_* (fwd + bwd)"))
+
+
+def bench_elastic(args, torch, m):
+    """16 RGB 4096x4096 u8 images + 8-label masks: elastic (sigma 50, alpha 1000) + 5x5 grid (0.3)."""
+    import synth
+    n, H, W = 16, 4096, 4096
+    img = torch.cat([synth.smooth_u8_hwc(1809068395 + i, 1, H, W, 3, device="cuda") for i in range(n)])
+    mask = torch.cat([synth.blob_masks(1809068396 + i, 1, H, W, 8, 512, device="cuda") for i in range(n)])
+    grid = torch.from_numpy(m.sample_grid(1809068395, 0, n)).cuda()
+    off = torch.empty((n, 2, H, W), dtype=torch.int32, device="cuda")
+    ws = torch.empty(m.lib().miaug_elastic_workspace_bytes(n, H, W), dtype=torch.uint8, device="cuda")
+    mapx = torch.empty((n, W), dtype=torch.int32, device="cuda")
+    mapy = torch.empty((n, H), dtype=torch.int32, device="cuda")
+    out = torch.empty_like(img)
+    om = torch.empty_like(mask)
+    L = m.lib()
+
+    def fields(st):
+        m._check(L.miaug_elastic_fields(1809068395, 0, n, H, W, 50.0, 1000, 150, m._p(off), m._p(ws), ws.numel(),
+                                         m._stream(st)))
+        m._check(L.miaug_grid_tables(m._p(grid), n, H, W, m._p(mapx), m._p(mapy), m._stream(st)))
+
+    def remap(st, per_image=0):
+        m._check(L.miaug_elastic_grid_u8(m._p(img), m._p(mask), n, H, W, 3, m._p(off), m._p(mapx), m._p(mapy),
+                                         m._p(out), m._p(om), per_image, m._stream(st)))
+
+    s = torch.cuda.Stream()
+    steps = max(1, args.steps // 4)
+    ms_f = time_on_stream(torch, fields, steps, 1, s)
+    ms_r = time_on_stream(torch, remap, args.steps, args.warmup, s)
+    ms_ri = time_on_stream(torch, lambda st: remap(st, 1), steps, 1, s)
+    macs = n * 2 * H * W * 301 * 2
+    alg = n * H * W * (3 + 1) * 2
+    ms = ms_f + ms_r
+    res = line("images/sec, large-tile elastic + grid distortion (fields + remap)", n, ms, args, "u8",
+               {"workload": "elastic_grid_16x4096x4096x3_masks"}, hbm_roof(alg, ms_r, "k_remap_chain_u8"),
+               {"field_ms": ms_f, "remap_ms": ms_r, "remap_per_image_launch_ms": ms_ri,
+                "field_roofline": {"bound": "alu", "achieved": macs / (ms_f * 1e-3) / 1e12,
+                                   "peak": 256 * 64 * 2.4e9 / 1e12, "unit": "Tmac/s (int32 VALU)",
+                                   "frac": macs / (ms_f * 1e-3) / (256 * 64 * 2.4e9)}})
+    return res
+
+
+WORKLOADS = {"ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
 
 
 def main():

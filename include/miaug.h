@@ -120,27 +120,47 @@ int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t 
  * a 3x3 binomial blur with probability 0.3, per RGB image, each op rounding
  * to u8 before the next:
  *  1. warp: forward map p' = s R(theta)(p - c) + c + (dx W, dy H), R(theta) =
- *     [[cos, sin], [-sin, cos]], c = ((W-1)/2, (H-1)/2); the inverse is
- *     formed in double and quantised to Q32; source position
- *     q = rdiv_he(a0 x + a1 y + a2, 2^22) (Q10); bilinear with weights
- *     (1024 - f, f) per axis, value rdiv_he(sum w_y w_x p, 2^20), reflect-101
- *     border per tap;
+ *     [[cos, sin], [-sin, cos]], c = ((W-1)/2, (H-1)/2).  Its inverse
+ *     a = {cos/s, -sin/s, cx - a0 (cx + dx W) - a1 (cy + dy H),
+ *          sin/s,  cos/s, cy - a3 (cx + dx W) - a4 (cy + dy H)}
+ *     (theta in radians = angle_deg * (pi/180), every expression evaluated
+ *     left to right in IEEE double) is quantised aq_i = llrint(a_i 2^32); the
+ *     source position of output pixel (x, y) is
+ *     q = rdiv_he(aq0 x + aq1 y + aq2, 2^22) (Q10, same for y with aq3..5);
+ *     bilinear with weights (1024 - f, f) per axis, value
+ *     rdiv_he(sum w_y w_x p, 2^20), reflect-101 border per tap;
  *  2. crop crop x crop at (crop_x, crop_y);
  *  3. resize to outsz x outsz, half-pixel centres
  *     q_j = rdiv_he(((2j+1) Ws - Wd) 2^10, 2 Wd), replicate border;
  *  4. integer hexcone HSV (H8 in 2-degree units 0..179, S8, V8 0..255):
- *     H8' = (H8 + dh) mod 180, S8' = sat8(S8 + ds), back to RGB;
- *  5. gamma LUT[v] = sat8(rint(255 (v/255)^gamma)) in double;
+ *     H8' = (H8 + dh) mod 180, S8' = sat8(S8 + ds), V8' = sat8(V8 + dv), back
+ *     to RGB;
+ *  5. gamma LUT[v] = sat8(rint(255 * pow(v / 255.0, gamma))) in double;
  *  6. if the blur flag is set: [1,2,1]x[1,2,1]/16, one rdiv_he, reflect-101.
- *   in   device u8 [n][H][W][3];  f device float [n][5];  k device int32 [n][5]
- *        (layouts as produced by miaug_sample_c2)
+ * Per-image setup (the Q32 matrix, crop offsets, the gamma LUT) is compiled
+ * on the host by miaug_compile_c2, so transcendental functions are evaluated
+ * once, in host double precision; the kernel is integer-only.
+ */
+typedef struct {
+    int64_t aq[6];          /* Q32 inverse affine matrix                          */
+    int32_t crop_x, crop_y; /* clamped into [0, W - crop] x [0, H - crop]         */
+    int32_t dh, ds, dv;     /* HSV8 shifts                                        */
+    int32_t blur;           /* 0 or 1                                             */
+    uint8_t gamma_lut[256]; /* LUT of step 5                                      */
+} miaug_c2_record;
+
+/* Host-side parameter compile: f[5i..] = {angle_deg, scale, dx, dy, gamma},
+ * k[5i..] = {crop_x, crop_y, dh, ds, blur} (miaug_sample_c2 layout) ->
+ * out[i] (host array of n records); dv = 0.  Errors: EINVAL, ESHAPE unless
+ * 1 <= crop <= min(H, W) and scale != 0. */
+int miaug_compile_c2(const float *f, const int32_t *k, int n, int H, int W, int crop, miaug_c2_record *out);
+
+/*   in   device u8 [n][H][W][3]; rec device miaug_c2_record [n]
  *   out  device u8 [n][outsz][outsz][3]
- * Errors: EINVAL null pointers; ESHAPE unless 1 <= crop, crop + max crop
- * offset fits (checked per image on the device: offsets are clamped into
- * [0, H - crop] and [0, W - crop]) and 1 <= outsz <= 4096. */
-int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const float *f,
-                                            const int32_t *k, int crop, int outsz, uint8_t *out,
-                                            void *stream);
+ * Errors: EINVAL null pointers or negative sizes (n == 0 is a no-op);
+ * ESHAPE unless 1 <= crop <= min(H, W), 1 <= outsz <= 4096, H, W <= 16384. */
+int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec,
+                                            int crop, int outsz, uint8_t *out, void *stream);
 
 /* ---------------------------------------------------------------- ragged batch
  * Sec. II-A: images of a detection / segmentation set (uneven sizes) are
@@ -224,7 +244,7 @@ int miaug_warpcolor_fwd(const float *x, int n, int C, int H, int W, const float 
  * Conventions at kinks: the clamp derivative is 0 outside the open interval
  * (0, 1); at y1 = 0 every derivative is 0; the bilinear derivative uses the
  * cell floor(s).  workspace: device memory of miaug_warpcolor_workspace_bytes
- * bytes (contents need not be initialised). */
+ * bytes (contents need not be initialised).  ESHAPE if C > 4. */
 size_t miaug_warpcolor_workspace_bytes(int n, int C, int H, int W);
 int miaug_warpcolor_bwd(const float *x, int n, int C, int H, int W, const float *params, const float *gy,
                         float *grad_x, float *grad_params, void *workspace, size_t workspace_bytes,
@@ -243,7 +263,7 @@ int miaug_warpcolor_bwd(const float *x, int n, int C, int H, int W, const float 
  * refl = reflect-101.
  *   off  device int32 [n][2][H][W] (written)
  *   workspace device, miaug_elastic_workspace_bytes bytes (int16 pass data).
- * Errors: EINVAL; ESHAPE unless 1 <= radius <= 512 and H, W >= 1;
+ * Errors: EINVAL; ESHAPE unless 1 <= radius <= 200, sigma > 0, 0 <= alpha <= 65535;
  * ECAPACITY small workspace. */
 size_t miaug_elastic_workspace_bytes(int n, int H, int W);
 int miaug_elastic_fields(uint64_t seed, uint64_t first_index, int n, int H, int W, double sigma, int alpha,

@@ -43,7 +43,15 @@ class RaggedArgs(ctypes.Structure):
                 ("out", _vp), ("out_mask", _vp), ("out_boxes", _vp)]
 
 
+class C2Record(ctypes.Structure):
+    """Mirror of miaug_c2_record (include/miaug.h)."""
+    _fields_ = [("aq", ctypes.c_int64 * 6), ("crop_x", ctypes.c_int32), ("crop_y", ctypes.c_int32),
+                ("dh", ctypes.c_int32), ("ds", ctypes.c_int32), ("dv", ctypes.c_int32), ("blur", ctypes.c_int32),
+                ("gamma_lut", ctypes.c_uint8 * 256)]
+
+
 _SIGS = {
+    "miaug_compile_c2": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
     "miaug_version": (_i, []),
     "miaug_status_str": (ctypes.c_char_p, [_i]),
     "miaug_last_error": (ctypes.c_char_p, []),
@@ -54,7 +62,7 @@ _SIGS = {
     "miaug_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
     "miaug_ctx_destroy": (_i, [_vp]),
     "miaug_d4_bc_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
-    "miaug_ssr_crop_resize_hsv_gamma_blur_u8": (_i, [_vp, _i, _i, _i, _vp, _vp, _i, _i, _vp, _vp]),
+    "miaug_ssr_crop_resize_hsv_gamma_blur_u8": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
     "miaug_ragged_apply": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
     "miaug_ragged_apply_per_image": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
     "miaug_ragged_graph_create": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp, ctypes.POINTER(_vp)]),
@@ -196,14 +204,26 @@ def d4_bc_u8(img, flags, ab, out=None, stream=None):
 
 
 # ---------------------------------------------------------------- full u8 pipeline
-def ssr_crop_resize_hsv_gamma_blur_u8(img, f, k, crop=448, outsz=224, out=None, stream=None):
-    _dev(img, torch.uint8, "img"); _dev(f, torch.float32, "f"); _dev(k, torch.int32, "k")
+def compile_c2(f, k, H, W, crop=448):
+    """Host parameter compile: returns an (n, 328) uint8 array of miaug_c2_record."""
+    f = np.ascontiguousarray(f, np.float32); k = np.ascontiguousarray(k, np.int32)
+    n = len(f)
+    rec = (C2Record * max(n, 1))()
+    _check(lib().miaug_compile_c2(f.ctypes.data, k.ctypes.data, n, H, W, crop, ctypes.addressof(rec)))
+    return np.frombuffer(bytes(rec), dtype=np.uint8).reshape(max(n, 1), ctypes.sizeof(C2Record))[:n].copy()
+
+
+def ssr_crop_resize_hsv_gamma_blur_u8(img, rec, crop=448, outsz=224, out=None, stream=None):
+    """img [n, H, W, 3] u8; rec: device uint8 [n, sizeof(miaug_c2_record)] from compile_c2."""
+    _dev(img, torch.uint8, "img"); _dev(rec, torch.uint8, "rec")
     n, H, W, C = img.shape
     if C != 3:
         raise ValueError("RGB images expected")
+    if rec.numel() != n * ctypes.sizeof(C2Record):
+        raise ValueError("rec must hold n records")
     if out is None:
         out = torch.empty((n, outsz, outsz, 3), dtype=torch.uint8, device=img.device)
-    _check(lib().miaug_ssr_crop_resize_hsv_gamma_blur_u8(_p(img), n, H, W, _p(f), _p(k), crop, outsz, _p(out),
+    _check(lib().miaug_ssr_crop_resize_hsv_gamma_blur_u8(_p(img), n, H, W, _p(rec), crop, outsz, _p(out),
                                                          _stream(stream)))
     return out
 
@@ -295,3 +315,130 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- differentiable warp + colour
+def warpcolor_fwd(x, params, out=None, stream=None):
+    """x [n, C, H, W] float32, params [n, 7] float32 -> y."""
+    _dev(x, torch.float32, "x"); _dev(params, torch.float32, "params")
+    n, C, H, W = x.shape
+    y = out if out is not None else torch.empty_like(x)
+    _check(lib().miaug_warpcolor_fwd(_p(x), n, C, H, W, _p(params), _p(y), _stream(stream)))
+    return y
+
+
+def warpcolor_bwd(x, params, gy, want_gx=True, stream=None):
+    _dev(x, torch.float32, "x"); _dev(params, torch.float32, "params"); _dev(gy, torch.float32, "gy")
+    n, C, H, W = x.shape
+    ws = torch.empty(max(1, lib().miaug_warpcolor_workspace_bytes(n, C, H, W)), dtype=torch.uint8, device=x.device)
+    gx = torch.empty_like(x) if want_gx else None
+    gp = torch.empty_like(params)
+    _check(lib().miaug_warpcolor_bwd(_p(x), n, C, H, W, _p(params), _p(gy), _p(gx), _p(gp), _p(ws), ws.numel(),
+                                     _stream(stream)))
+    return gx, gp
+
+
+class WarpColor(torch.autograd.Function):
+    """y = clamp(alpha * warp(x; angle, scale, tx, ty) + beta, 0, 1) ** gamma with
+    hand-written HIP backward kernels for x and the [n, 7] parameters."""
+
+    @staticmethod
+    def forward(ctx, x, params):
+        x = x.contiguous(); params = params.contiguous()
+        ctx.save_for_backward(x, params)
+        return warpcolor_fwd(x, params)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, params = ctx.saved_tensors
+        gx, gp = warpcolor_bwd(x, params, gy.contiguous(), want_gx=ctx.needs_input_grad[0])
+        return gx, gp
+
+
+def warp_color(x, params):
+    return WarpColor.apply(x, params)
+
+
+# ---------------------------------------------------------------- elastic + grid distortion
+def elastic_fields(seed, first, n, H, W, sigma=50.0, alpha=1000, radius=150, device="cuda", stream=None):
+    """Q10 displacement fields [n, 2, H, W] int32 (field 0: x, field 1: y)."""
+    off = torch.empty((n, 2, H, W), dtype=torch.int32, device=device)
+    ws = torch.empty(max(1, lib().miaug_elastic_workspace_bytes(n, H, W)), dtype=torch.uint8, device=device)
+    _check(lib().miaug_elastic_fields(seed, first, n, H, W, sigma, alpha, radius, _p(off), _p(ws), ws.numel(),
+                                      _stream(stream)))
+    return off
+
+
+def grid_tables(grid, H, W, stream=None):
+    """grid: device float64 [n, 10] -> (mapx [n, W], mapy [n, H]) int32 Q10 tables."""
+    _dev(grid, torch.float64, "grid")
+    n = grid.shape[0]
+    mapx = torch.empty((n, W), dtype=torch.int32, device=grid.device)
+    mapy = torch.empty((n, H), dtype=torch.int32, device=grid.device)
+    _check(lib().miaug_grid_tables(_p(grid), n, H, W, _p(mapx), _p(mapy), _stream(stream)))
+    return mapx, mapy
+
+
+def elastic_grid_u8(img, off, mapx, mapy, mask=None, per_image=False, stream=None):
+    """img [n, H, W, C] u8 (+ mask [n, H, W] u8) -> elastic then grid distortion."""
+    _dev(img, torch.uint8, "img"); _dev(off, torch.int32, "off")
+    _dev(mapx, torch.int32, "mapx"); _dev(mapy, torch.int32, "mapy")
+    n, H, W, C = img.shape
+    out = torch.empty_like(img)
+    om = torch.empty_like(mask) if mask is not None else None
+    if mask is not None:
+        _dev(mask, torch.uint8, "mask")
+    _check(lib().miaug_elastic_grid_u8(_p(img), _p(mask), n, H, W, C, _p(off), _p(mapx), _p(mapy), _p(out), _p(om),
+                                       int(per_image), _stream(stream)))
+    return out, om
+
+
+def elastic_grid_f32_fwd(x, off, mapx, mapy, stream=None):
+    _dev(x, torch.float32, "x")
+    n, C, H, W = x.shape
+    y = torch.empty_like(x)
+    ws = torch.empty(max(1, lib().miaug_chain_f32_workspace_bytes(n, C, H, W)), dtype=torch.uint8, device=x.device)
+    _check(lib().miaug_elastic_grid_f32_fwd(_p(x), n, C, H, W, _p(off), _p(mapx), _p(mapy), _p(y), _p(ws),
+                                            ws.numel(), _stream(stream)))
+    return y
+
+
+def elastic_grid_f32_bwd(gy, off, mapx, mapy, stream=None):
+    _dev(gy, torch.float32, "gy")
+    n, C, H, W = gy.shape
+    gx = torch.empty_like(gy)
+    ws = torch.empty(max(1, lib().miaug_chain_f32_workspace_bytes(n, C, H, W)), dtype=torch.uint8, device=gy.device)
+    _check(lib().miaug_elastic_grid_f32_bwd(_p(gy), n, C, H, W, _p(off), _p(mapx), _p(mapy), _p(gx), _p(ws),
+                                            ws.numel(), _stream(stream)))
+    return gx
+
+
+class ElasticGridF32(torch.autograd.Function):
+    """Float copy of the elastic + grid chain; gradient w.r.t. the image only
+    (the fields and grid tables are random draws, not parameters)."""
+
+    @staticmethod
+    def forward(ctx, x, off, mapx, mapy):
+        ctx.save_for_backward(off, mapx, mapy)
+        return elastic_grid_f32_fwd(x.contiguous(), off, mapx, mapy)
+
+    @staticmethod
+    def backward(ctx, gy):
+        off, mapx, mapy = ctx.saved_tensors
+        return elastic_grid_f32_bwd(gy.contiguous(), off, mapx, mapy), None, None, None
+
+
+# ---------------------------------------------------------------- statistics
+def image_stats_u8(img, C=None, stream=None):
+    """img [n, ..., C] u8 -> (sum [n, C] uint64 as int64, min, max [n, C] int32, hist [n, C, 256] int32)."""
+    _dev(img, torch.uint8, "img")
+    n = img.shape[0]
+    C = C or img.shape[-1]
+    npix = img[0].numel() // C
+    dev = img.device
+    s = torch.empty((n, C), dtype=torch.int64, device=dev)
+    mn = torch.empty((n, C), dtype=torch.int32, device=dev)
+    mx = torch.empty((n, C), dtype=torch.int32, device=dev)
+    h = torch.empty((n, C, 256), dtype=torch.int32, device=dev)
+    _check(lib().miaug_image_stats_u8(_p(img), n, npix, C, _p(s), _p(mn), _p(mx), _p(h), _stream(stream)))
+    return s, mn, mx, h

@@ -141,15 +141,15 @@ int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t 
     return hip_status(launch_d4_bc_u8(in, n, H, W, C, flags, ab, out, as_stream(stream)), "d4_bc_u8 launch");
 }
 
-int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const float *f, const int32_t *k,
+int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec,
                                             int crop, int outsz, uint8_t *out, void *stream) {
     begin_call();
     if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "c2: negative size");
     if (n == 0) return MIAUG_OK;
-    if (!in || !f || !k || !out) return set_error(MIAUG_EINVAL, "c2: NULL pointer");
+    if (!in || !rec || !out) return set_error(MIAUG_EINVAL, "c2: NULL pointer");
     if (H < 1 || W < 1 || crop < 1 || crop > H || crop > W || outsz < 1 || outsz > 4096 || H > 16384 || W > 16384)
         return set_error(MIAUG_ESHAPE, "c2: H=%d W=%d crop=%d outsz=%d", H, W, crop, outsz);
-    return hip_status(launch_c2(in, n, H, W, f, k, crop, outsz, out, as_stream(stream)), "c2 launch");
+    return hip_status(launch_c2(in, n, H, W, rec, crop, outsz, out, as_stream(stream)), "c2 launch");
 }
 
 int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream) {
@@ -306,6 +306,7 @@ int miaug_warpcolor_bwd(const float *x, int n, int C, int H, int W, const float 
     if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "warpcolor_bwd: negative size");
     if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
     if (!x || !params || !gy || !grad_params) return set_error(MIAUG_EINVAL, "warpcolor_bwd: NULL pointer");
+    if (C > 4) return set_error(MIAUG_ESHAPE, "warpcolor_bwd: C=%d (at most 4 channels)", C);
     if (H > 16384 || W > 16384) return set_error(MIAUG_ESHAPE, "warpcolor_bwd: %dx%d too large", H, W);
     size_t need = wc_workspace_bytes(n, C, H, W);
     if (!ws || ws_bytes < need)
@@ -325,7 +326,7 @@ int miaug_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, dou
     if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "elastic_fields: negative size");
     if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
     if (!off) return set_error(MIAUG_EINVAL, "elastic_fields: NULL off");
-    if (radius < 1 || radius > 512 || !(sigma > 0.0) || alpha < 0 || alpha > 65535)
+    if (radius < 1 || radius > 200 || !(sigma > 0.0) || alpha < 0 || alpha > 65535)
         return set_error(MIAUG_ESHAPE, "elastic_fields: radius=%d sigma=%g alpha=%d", radius, sigma, alpha);
     if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "elastic_fields: image too large");
     size_t need = elastic_workspace_bytes(n, H, W);

@@ -30,7 +30,7 @@ int ragged_variant_count();
 const char *ragged_variant_name(int v);
 int ragged_default_variant();
 
-hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const float *f, const int32_t *k, int crop, int outsz,
+hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
                      uint8_t *out, hipStream_t s);
 
 hipError_t launch_wc_fwd(const float *x, int n, int C, int H, int W, const float *p, float *y, hipStream_t s);

@@ -1,0 +1,444 @@
+// k_elastic.hip -- elastic transform and grid distortion (Sec. II-C, Fig. 4;
+// the elastic distortion of Simard et al. 2003 cited in Sec. I).
+//
+// Fields: per image and field, 16-bit Philox noise is smoothed by a separable
+// integer Gaussian (Q15 taps, reflect-101):
+//   k_field_h  one workgroup per (row segment of 1024, field, image): noise of
+//              the segment and its +-radius halo is generated into LDS, each
+//              thread produces 4 consecutive outputs with a sliding window (one
+//              noise read and one tap read per 4 multiply-adds);
+//   k_field_v  one workgroup per (32-column strip x 64 rows, field, image): the
+//              strip of the H-pass result with its +-radius halo is staged in
+//              LDS, each thread produces 8 consecutive rows of one column the
+//              same way, then offsets off = rdiv_he(alpha v, 2^20) (Q10 px).
+// Remap chain (u8): one workgroup per 32 x 32 output tile.  The grid tables
+// are monotone, so the tile's grid taps read a contiguous (before reflection)
+// block of rows and columns of the elastic result e; the tile computes that
+// block of e in LDS (each e pixel: displaced Q10 position -> 4 source taps ->
+// u8, reflect-101) and then blends the grid taps from LDS.  The mask takes the
+// same two maps with nearest sampling.  Float copy: the same maps without
+// rounding; its adjoint scatters with float atomics.
+#include "dev_common.h"
+#include "internal.h"
+
+namespace miaug {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxRadius = 200;  // V-pass strip (64 + 2 radius rows x 32 columns) stays below 64 KiB of LDS
+
+// ---------------------------------------------------------------- Philox4x64-10 (device copy)
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
+        const uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
+        const uint64_t o0 = h1 ^ c[1] ^ k0, o2 = h0 ^ c[3] ^ k1;
+        c[0] = o0; c[1] = l1; c[2] = o2; c[3] = l0;
+        k0 += W0; k1 += W1;
+    }
+}
+
+// ---------------------------------------------------------------- H pass
+constexpr int kHSeg = 1024;  // outputs per workgroup (4 per thread)
+
+__global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t first, int H, int W, int radius,
+                                                      const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
+    __shared__ int32_t noise[kHSeg + 2 * kMaxRadius + 16];
+    __shared__ int32_t tp[2 * kMaxRadius + 1];
+    const int segs = (W + kHSeg - 1) / kHSeg;
+    const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kHSeg;
+    const int field = blockIdx.y, img = blockIdx.z;
+    const uint64_t g = first + (uint64_t)img;
+    for (int k = threadIdx.x; k < 2 * radius + 1; k += kThreads) tp[k] = taps[k];
+    // noise at reflected columns x0 - radius .. x0 + kHSeg + radius - 1 (as far as needed)
+    const int n_need = min(kHSeg, W - x0) + 2 * radius;
+    for (int i = threadIdx.x; i < n_need; i += kThreads) {
+        const int xs = reflect101(x0 - radius + i, W);
+        const int64_t e = (int64_t)y * W + xs;
+        uint64_t c[4] = {(uint64_t)(e >> 4), g, (uint64_t)field, 4};
+        philox4x64_10(c, seed, 0);
+        const uint64_t word = c[(e & 15) >> 2];
+        noise[i] = (int32_t)((word >> (16 * (e & 3))) & 0xFFFFu) - 32768;
+    }
+    __syncthreads();
+    const int xl = 4 * threadIdx.x;  // first of this thread's 4 outputs, relative to x0
+    if (x0 + xl >= W) return;
+    int32_t acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    int32_t t0 = 0, t1 = 0, t2 = 0;  // taps k = j-1, j-2, j-3 (sliding)
+    const int nt = 2 * radius + 1;
+    for (int j = 0; j < nt + 3; ++j) {
+        // noise[xl + j] pairs with tap j for output 0, tap j-1 for output 1, ...
+        const int32_t v = noise[xl + j];
+        const int32_t tj = j < nt ? tp[j] : 0;
+        // operands fit 24 bits (|noise| <= 2^15, taps <= 2^15): full-rate v_mad_i32_i24
+        acc0 += __mul24(tj, v);
+        acc1 += __mul24(t0, v);
+        acc2 += __mul24(t1, v);
+        acc3 += __mul24(t2, v);
+        t2 = t1; t1 = t0; t0 = tj;
+    }
+    int32_t *row = hout + (((size_t)img * 2 + field) * H + y) * W + x0 + xl;
+    row[0] = rshr_he(acc0, 15);
+    if (x0 + xl + 1 < W) row[1] = rshr_he(acc1, 15);
+    if (x0 + xl + 2 < W) row[2] = rshr_he(acc2, 15);
+    if (x0 + xl + 3 < W) row[3] = rshr_he(acc3, 15);
+}
+
+// ---------------------------------------------------------------- V pass
+constexpr int kVCols = 32, kVRows = 64, kVPer = 8;  // 32 columns x (8 threads x 8 rows)
+
+__global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, int alpha,
+                                                      const int32_t *__restrict__ taps,
+                                                      const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
+    extern __shared__ int32_t smem[];
+    int32_t *tp = smem;                                   // 2 radius + 1
+    int32_t *strip = smem + ((2 * radius + 1 + 3) & ~3);  // (kVRows + 2 radius) x kVCols
+    const int strips_x = (W + kVCols - 1) / kVCols;
+    const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kVRows;
+    const int field = blockIdx.y, img = blockIdx.z;
+    const int32_t *hb = hin + ((size_t)img * 2 + field) * H * W;
+    for (int k = threadIdx.x; k < 2 * radius + 1; k += kThreads) tp[k] = taps[k];
+    const int rows = min(kVRows, H - y0) + 2 * radius;
+    for (int e = threadIdx.x; e < rows * kVCols; e += kThreads) {
+        const int r = e / kVCols, c = e - r * kVCols;
+        const int yy = reflect101(y0 - radius + r, H), xx = min(xs0 + c, W - 1);
+        strip[e] = hb[(size_t)yy * W + xx];
+    }
+    __syncthreads();
+    const int col = threadIdx.x % kVCols, grp = threadIdx.x / kVCols;
+    const int x = xs0 + col, yl = grp * kVPer;
+    if (x >= W || y0 + yl >= H) return;
+    int32_t acc[kVPer];
+    int32_t tw[kVPer - 1];
+#pragma unroll
+    for (int o = 0; o < kVPer; ++o) acc[o] = 0;
+#pragma unroll
+    for (int o = 0; o < kVPer - 1; ++o) tw[o] = 0;
+    const int nt = 2 * radius + 1;
+    for (int j = 0; j < nt + kVPer - 1; ++j) {
+        const int32_t v = strip[(yl + j) * kVCols + col];
+        const int32_t tj = j < nt ? tp[j] : 0;
+        // |h| <= 2^15 (1 + 150 / 2^15) and taps <= 2^15 fit 24 bits
+        acc[0] += __mul24(tj, v);
+#pragma unroll
+        for (int o = 1; o < kVPer; ++o) acc[o] += __mul24(tw[o - 1], v);
+#pragma unroll
+        for (int o = kVPer - 2; o > 0; --o) tw[o] = tw[o - 1];
+        tw[0] = tj;
+    }
+    int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
+#pragma unroll
+    for (int o = 0; o < kVPer; ++o)
+        if (y0 + yl + o < H) ob[(size_t)(y0 + yl + o) * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc[o], 30 - kFBits);
+}
+
+// ---------------------------------------------------------------- grid tables
+__global__ void k_grid_tables(const double *__restrict__ grid, int H, int W, int32_t *__restrict__ mapx,
+                              int32_t *__restrict__ mapy) {
+    const int img = blockIdx.y;
+    const int axis = blockIdx.z;  // 0: x (W entries), 1: y (H entries)
+    const int n = axis ? H : W;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *d = grid + 10 * img + 5 * axis;
+    const double cw = (double)n / 5;
+    const double u = i + 0.5;
+    int k = (int)floor(u / cw);
+    if (k > 4) k = 4;
+    double S = 0.0;
+    for (int j = 0; j < k; ++j) S = S + cw * d[j];
+    const double src = S + (u - k * cw) * d[k] - 0.5;
+    (axis ? mapy + (size_t)img * H : mapx + (size_t)img * W)[i] = (int32_t)llrint(src * kFOne);
+}
+
+// ---------------------------------------------------------------- u8 remap chain
+constexpr int kRT = 32;       // output tile
+constexpr int kRE = 64;       // max e-block side held in LDS (grid factors up to ~1.9)
+
+__device__ __forceinline__ uint32_t load_px(const uint8_t *p, int C) {
+    if (C == 1) return p[0];
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *w = (const uint32_t *)(a & ~(uintptr_t)3);
+    const int sh = (int)(a & 3);
+    const uint32_t lo = w[0];
+    if (sh + C <= 4) return lo >> (8 * sh);
+    return __builtin_amdgcn_alignbyte(w[1], lo, sh);
+}
+
+__device__ __forceinline__ uint32_t blend_u8(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, int ax, int ay,
+                                             int C) {
+    uint32_t out = 0;
+    for (int c = 0; c < C; ++c) {
+        const int a00 = (p00 >> (8 * c)) & 255, a01 = (p01 >> (8 * c)) & 255;
+        const int a10 = (p10 >> (8 * c)) & 255, a11 = (p11 >> (8 * c)) & 255;
+        const int t0 = (a00 << kFBits) + ax * (a01 - a00);
+        const int t1 = (a10 << kFBits) + ax * (a11 - a10);
+        const int acc = (t0 << kFBits) + ay * (t1 - t0);
+        out |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
+    }
+    return out;
+}
+
+// Elastic result at pixel (Y, X) (already inside the image).
+__device__ __forceinline__ uint32_t elastic_px(const uint8_t *img, int H, int W, int C, const int32_t *ox,
+                                               const int32_t *oy, int Y, int X) {
+    const size_t e = (size_t)Y * W + X;
+    const int qx = (X << kFBits) + ox[e], qy = (Y << kFBits) + oy[e];
+    int x0 = qx >> kFBits, y0 = qy >> kFBits;
+    const int ax = qx & (kFOne - 1), ay = qy & (kFOne - 1);
+    int x1 = x0 + 1, y1 = y0 + 1;
+    if (x0 < 0 || x1 >= W) { x0 = reflect101(x0, W); x1 = reflect101(x1, W); }
+    if (y0 < 0 || y1 >= H) { y0 = reflect101(y0, H); y1 = reflect101(y1, H); }
+    return blend_u8(load_px(img + ((size_t)y0 * W + x0) * C, C), load_px(img + ((size_t)y0 * W + x1) * C, C),
+                    load_px(img + ((size_t)y1 * W + x0) * C, C), load_px(img + ((size_t)y1 * W + x1) * C, C), ax, ay,
+                    C);
+}
+
+__device__ __forceinline__ uint8_t elastic_mask(const uint8_t *m, int H, int W, const int32_t *ox, const int32_t *oy,
+                                                int Y, int X) {
+    const size_t e = (size_t)Y * W + X;
+    const int qx = (X << kFBits) + ox[e], qy = (Y << kFBits) + oy[e];
+    return m[(size_t)reflect101((qy + kFOne / 2) >> kFBits, H) * W + reflect101((qx + kFOne / 2) >> kFBits, W)];
+}
+
+__global__ __launch_bounds__(kThreads) void k_remap_chain_u8(const uint8_t *__restrict__ img,
+                                                             const uint8_t *__restrict__ mask, int H, int W, int C,
+                                                             const int32_t *__restrict__ off,
+                                                             const int32_t *__restrict__ mapx,
+                                                             const int32_t *__restrict__ mapy,
+                                                             uint8_t *__restrict__ out, uint8_t *__restrict__ out_mask,
+                                                             int img_index) {
+    __shared__ uint32_t eb[kRE][kRE];
+    __shared__ uint8_t em[kRE][kRE];
+    __shared__ int32_t qx[kRT], qy[kRT];
+    const int im = img_index >= 0 ? img_index : (int)blockIdx.y;
+    const int tiles_x = (W + kRT - 1) / kRT;
+    const int x0 = (blockIdx.x % tiles_x) * kRT, y0 = (blockIdx.x / tiles_x) * kRT;
+    const int tw = min(kRT, W - x0), th = min(kRT, H - y0);
+    const size_t plane = (size_t)H * W;
+    const uint8_t *src = img + (size_t)im * plane * C;
+    const uint8_t *msrc = mask ? mask + (size_t)im * plane : nullptr;
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    const int32_t *mx = mapx + (size_t)im * W, *my = mapy + (size_t)im * H;
+    if (threadIdx.x < tw) qx[threadIdx.x] = mx[x0 + threadIdx.x];
+    if (threadIdx.x >= 64 && threadIdx.x - 64 < th) qy[threadIdx.x - 64] = my[y0 + threadIdx.x - 64];
+    __syncthreads();
+    // e rows/columns the tile's grid taps read (pre-reflection ranges; the
+    // extremes are taken over every entry, so any table is handled)
+    int c_lo = qx[0] >> kFBits, c_hi = c_lo, r_lo = qy[0] >> kFBits, r_hi = r_lo;
+    for (int i = 1; i < tw; ++i) { c_lo = min(c_lo, qx[i] >> kFBits); c_hi = max(c_hi, qx[i] >> kFBits); }
+    for (int i = 1; i < th; ++i) { r_lo = min(r_lo, qy[i] >> kFBits); r_hi = max(r_hi, qy[i] >> kFBits); }
+    c_hi += 1;
+    r_hi += 1;
+    const int ew = c_hi - c_lo + 1, eh = r_hi - r_lo + 1;
+    const bool staged = ew <= kRE && eh <= kRE;
+    if (staged) {
+        for (int e = threadIdx.x; e < ew * eh; e += kThreads) {
+            const int r = e / ew, c = e - r * ew;
+            const int Y = reflect101(r_lo + r, H), X = reflect101(c_lo + c, W);
+            eb[r][c] = elastic_px(src, H, W, C, ox, oy, Y, X);
+            if (msrc) em[r][c] = elastic_mask(msrc, H, W, ox, oy, Y, X);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < tw * th; e += kThreads) {
+        const int r = e / tw, c = e - r * tw;
+        const int gx = qx[c], gy = qy[r];
+        const int cx = gx >> kFBits, cy = gy >> kFBits;
+        const int ax = gx & (kFOne - 1), ay = gy & (kFOne - 1);
+        uint32_t v;
+        uint8_t mv = 0;
+        if (staged) {
+            v = blend_u8(eb[cy - r_lo][cx - c_lo], eb[cy - r_lo][cx + 1 - c_lo], eb[cy + 1 - r_lo][cx - c_lo],
+                         eb[cy + 1 - r_lo][cx + 1 - c_lo], ax, ay, C);
+            if (msrc) mv = em[((gy + kFOne / 2) >> kFBits) - r_lo][((gx + kFOne / 2) >> kFBits) - c_lo];
+        } else {
+            const int X0 = reflect101(cx, W), X1 = reflect101(cx + 1, W);
+            const int Y0 = reflect101(cy, H), Y1 = reflect101(cy + 1, H);
+            v = blend_u8(elastic_px(src, H, W, C, ox, oy, Y0, X0), elastic_px(src, H, W, C, ox, oy, Y0, X1),
+                         elastic_px(src, H, W, C, ox, oy, Y1, X0), elastic_px(src, H, W, C, ox, oy, Y1, X1), ax, ay, C);
+            if (msrc)
+                mv = elastic_mask(msrc, H, W, ox, oy, reflect101((gy + kFOne / 2) >> kFBits, H),
+                                  reflect101((gx + kFOne / 2) >> kFBits, W));
+        }
+        uint8_t *o = out + ((size_t)im * plane + (size_t)(y0 + r) * W + x0 + c) * C;
+        for (int ch = 0; ch < C; ++ch) o[ch] = (uint8_t)(v >> (8 * ch));
+        if (msrc) out_mask[(size_t)im * plane + (size_t)(y0 + r) * W + x0 + c] = mv;
+    }
+}
+
+// ---------------------------------------------------------------- float copy of the chain
+__device__ __forceinline__ void taps_q(int qx, int qy, int H, int W, int xs[2], int ys[2], float wx[2], float wy[2]) {
+    const int x0 = qx >> kFBits, y0 = qy >> kFBits;
+    const int ax = qx & (kFOne - 1), ay = qy & (kFOne - 1);
+    xs[0] = reflect101(x0, W); xs[1] = reflect101(x0 + 1, W);
+    ys[0] = reflect101(y0, H); ys[1] = reflect101(y0 + 1, H);
+    wx[0] = (float)(kFOne - ax) * (1.0f / kFOne); wx[1] = (float)ax * (1.0f / kFOne);
+    wy[0] = (float)(kFOne - ay) * (1.0f / kFOne); wy[1] = (float)ay * (1.0f / kFOne);
+}
+
+// e = elastic(x) for every pixel (workspace), then y = grid(e).
+__global__ void k_chain_f_elastic(const float *__restrict__ x, int C, int H, int W, const int32_t *__restrict__ off,
+                                  float *__restrict__ e) {
+    const size_t plane = (size_t)H * W;
+    const int im = blockIdx.y;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= plane) return;
+    const int Y = (int)(p / W), X = (int)(p % W);
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    int xs[2], ys[2];
+    float wx[2], wy[2];
+    taps_q((X << kFBits) + ox[p], (Y << kFBits) + oy[p], H, W, xs, ys, wx, wy);
+    for (int c = 0; c < C; ++c) {
+        const float *xc = x + ((size_t)im * C + c) * plane;
+        const float v = wy[0] * (wx[0] * xc[(size_t)ys[0] * W + xs[0]] + wx[1] * xc[(size_t)ys[0] * W + xs[1]]) +
+                        wy[1] * (wx[0] * xc[(size_t)ys[1] * W + xs[0]] + wx[1] * xc[(size_t)ys[1] * W + xs[1]]);
+        e[((size_t)im * C + c) * plane + p] = v;
+    }
+}
+
+__global__ void k_chain_f_grid(const float *__restrict__ e, int C, int H, int W, const int32_t *__restrict__ mapx,
+                               const int32_t *__restrict__ mapy, float *__restrict__ y) {
+    const size_t plane = (size_t)H * W;
+    const int im = blockIdx.y;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= plane) return;
+    const int r = (int)(p / W), c0 = (int)(p % W);
+    int xs[2], ys[2];
+    float wx[2], wy[2];
+    taps_q(mapx[(size_t)im * W + c0], mapy[(size_t)im * H + r], H, W, xs, ys, wx, wy);
+    for (int c = 0; c < C; ++c) {
+        const float *ec = e + ((size_t)im * C + c) * plane;
+        y[((size_t)im * C + c) * plane + p] =
+            wy[0] * (wx[0] * ec[(size_t)ys[0] * W + xs[0]] + wx[1] * ec[(size_t)ys[0] * W + xs[1]]) +
+            wy[1] * (wx[0] * ec[(size_t)ys[1] * W + xs[0]] + wx[1] * ec[(size_t)ys[1] * W + xs[1]]);
+    }
+}
+
+__global__ void k_fill_zero(float *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
+}
+
+// adjoint of the grid step: ge += w * gy (scatter)
+__global__ void k_chain_f_grid_adj(const float *__restrict__ gy, int C, int H, int W, const int32_t *__restrict__ mapx,
+                                   const int32_t *__restrict__ mapy, float *__restrict__ ge) {
+    const size_t plane = (size_t)H * W;
+    const int im = blockIdx.y;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= plane) return;
+    const int r = (int)(p / W), c0 = (int)(p % W);
+    int xs[2], ys[2];
+    float wx[2], wy[2];
+    taps_q(mapx[(size_t)im * W + c0], mapy[(size_t)im * H + r], H, W, xs, ys, wx, wy);
+    for (int c = 0; c < C; ++c) {
+        const float g = gy[((size_t)im * C + c) * plane + p];
+        float *gc = ge + ((size_t)im * C + c) * plane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicAdd(&gc[(size_t)ys[k >> 1] * W + xs[k & 1]], wy[k >> 1] * wx[k & 1] * g);
+    }
+}
+
+// adjoint of the elastic step: gx += w * ge (scatter)
+__global__ void k_chain_f_elastic_adj(const float *__restrict__ ge, int C, int H, int W,
+                                      const int32_t *__restrict__ off, float *__restrict__ gx) {
+    const size_t plane = (size_t)H * W;
+    const int im = blockIdx.y;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= plane) return;
+    const int Y = (int)(p / W), X = (int)(p % W);
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    int xs[2], ys[2];
+    float wx[2], wy[2];
+    taps_q((X << kFBits) + ox[p], (Y << kFBits) + oy[p], H, W, xs, ys, wx, wy);
+    for (int c = 0; c < C; ++c) {
+        const float g = ge[((size_t)im * C + c) * plane + p];
+        float *gc = gx + ((size_t)im * C + c) * plane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicAdd(&gc[(size_t)ys[k >> 1] * W + xs[k & 1]], wy[k >> 1] * wx[k & 1] * g);
+    }
+}
+
+}  // namespace
+
+size_t elastic_workspace_bytes(int n, int H, int W) {
+    return (size_t)n * 2 * H * W * sizeof(int32_t) + (2 * kMaxRadius + 1 + 15) * sizeof(int32_t);
+}
+
+hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
+                                 int radius, int32_t *off, void *ws, hipStream_t s) {
+    // Q15 taps t_k = rint(2^15 g_k / sum g), g_k = exp(-k^2 / (2 sigma^2)), on the host in double
+    int32_t taps[2 * kMaxRadius + 1];
+    double sum = 0.0;
+    for (int k = -radius; k <= radius; ++k) sum += exp(-(double)k * k / (2.0 * sigma * sigma));
+    for (int k = -radius; k <= radius; ++k)
+        taps[k + radius] = (int32_t)rint(32768.0 * exp(-(double)k * k / (2.0 * sigma * sigma)) / sum);
+    int32_t *hbuf = (int32_t *)ws;
+    int32_t *dtaps = hbuf + (size_t)n * 2 * H * W;
+    hipError_t e = hipMemcpyAsync(dtaps, taps, sizeof(int32_t) * (2 * radius + 1), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const int segs = (W + kHSeg - 1) / kHSeg;
+    hipLaunchKernelGGL(k_field_h, dim3((unsigned)H * segs, 2, n), dim3(kThreads), 0, s, seed, first, H, W, radius,
+                       dtaps, hbuf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int strips = ((W + kVCols - 1) / kVCols) * ((H + kVRows - 1) / kVRows);
+    const size_t lds = sizeof(int32_t) * ((((2 * radius + 1) + 3) & ~3) + (size_t)(kVRows + 2 * radius) * kVCols);
+    hipLaunchKernelGGL(k_field_v, dim3(strips, 2, n), dim3(kThreads), lds, s, H, W, radius, alpha, dtaps, hbuf, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, hipStream_t s) {
+    const int m = max(H, W);
+    hipLaunchKernelGGL(k_grid_tables, dim3((m + 255) / 256, n, 2), dim3(256), 0, s, grid, H, W, mapx, mapy);
+    return hipGetLastError();
+}
+
+hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
+                                  const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
+                                  uint8_t *out_mask, int per_image, hipStream_t s) {
+    const int tiles = ((W + kRT - 1) / kRT) * ((H + kRT - 1) / kRT);
+    if (per_image) {
+        for (int i = 0; i < n; ++i) {
+            hipLaunchKernelGGL(k_remap_chain_u8, dim3(tiles, 1), dim3(kThreads), 0, s, img, mask, H, W, C, off, mapx,
+                               mapy, out, out_mask, i);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(k_remap_chain_u8, dim3(tiles, n), dim3(kThreads), 0, s, img, mask, H, W, C, off, mapx, mapy, out,
+                       out_mask, -1);
+    return hipGetLastError();
+}
+
+size_t chain_f32_workspace_bytes(int n, int C, int H, int W) { return (size_t)n * C * H * W * sizeof(float); }
+
+hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                                const int32_t *mapy, float *y, void *ws, hipStream_t s) {
+    const size_t plane = (size_t)H * W;
+    const dim3 grid((unsigned)((plane + 255) / 256), n);
+    float *e = (float *)ws;
+    hipLaunchKernelGGL(k_chain_f_elastic, grid, dim3(256), 0, s, x, C, H, W, off, e);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_f_grid, grid, dim3(256), 0, s, e, C, H, W, mapx, mapy, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
+                                const int32_t *mapy, float *gx, void *ws, hipStream_t s) {
+    const size_t plane = (size_t)H * W, total = (size_t)n * C * plane;
+    const dim3 grid((unsigned)((plane + 255) / 256), n);
+    float *ge = (float *)ws;
+    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, ge, total);
+    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, gx, total);
+    hipLaunchKernelGGL(k_chain_f_grid_adj, grid, dim3(256), 0, s, gy, C, H, W, mapx, mapy, ge);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_f_elastic_adj, grid, dim3(256), 0, s, ge, C, H, W, off, gx);
+    return hipGetLastError();
+}
+
+}  // namespace miaug

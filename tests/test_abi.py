@@ -95,3 +95,14 @@ def test_ctx_create_reports_a_missing_device(miaug):
     h = ctypes.c_void_p()
     st = miaug.lib().miaug_ctx_create(0, ctypes.byref(h))
     assert st == miaug.EDEVICE and not h.value
+
+
+def test_c2_compile_matches_the_oracle_setup(miaug):
+    import oracle
+    m = miaug
+    f, k = m.sample_c2(5, 0, 64)
+    rec = m.compile_c2(f, k, 512, 512, 448)
+    for i in range(64):
+        aq = np.frombuffer(rec[i, :48].tobytes(), np.int64)
+        assert np.array_equal(aq, oracle.ssr_matrix_q32(*f[i][:4], 512, 512))
+        assert np.array_equal(rec[i, 72:], oracle.gamma_lut(f[i][4]))

@@ -1,0 +1,127 @@
+"""GPU parity of the elastic + grid-distortion path: fields and grid tables
+bit-exact, the u8 chain (images and masks) bit-exact, batched == per-image,
+and the float copy forward (<= 1e-6) and adjoint (<= 1e-5 of max) against the
+fp64 oracle, including sampled pixels of a 4096 x 4096 image."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m(dev):
+    import paper_1809_06839_amd as m
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("H,W,sigma,alpha,radius", [(40, 36, 4.0, 60, 12), (1, 50, 3.0, 100, 7), (67, 1, 2.0, 30, 5),
+                                                    (130, 1100, 50.0, 1000, 150), (3, 3, 1.0, 500, 1)])
+def test_fields_bit_exact(m, H, W, sigma, alpha, radius):
+    off = m.elastic_fields(7, 3, 2, H, W, sigma, alpha, radius).cpu().numpy()
+    for i in range(2):
+        ox, oy = oracle.elastic_field(7, 3 + i, H, W, sigma, alpha, radius)
+        assert np.array_equal(off[i, 0], ox) and np.array_equal(off[i, 1], oy), i
+
+
+def test_grid_tables_bit_exact(m):
+    import torch
+    g = m.sample_grid(5, 0, 4)
+    mx, my = m.grid_tables(torch.from_numpy(g).cuda(), 77, 4096)
+    mx, my = mx.cpu().numpy(), my.cpu().numpy()
+    for i in range(4):
+        assert np.array_equal(mx[i], oracle.grid_table(g[i, :5], 4096))
+        assert np.array_equal(my[i], oracle.grid_table(g[i, 5:], 77))
+
+
+@pytest.mark.parametrize("H,W,C", [(64, 80, 3), (33, 47, 1), (100, 37, 4), (5, 300, 3)])
+def test_u8_chain_bit_exact_and_batched_equals_per_image(m, H, W, C):
+    import torch
+    n = 3
+    img = synth.smooth_u8_hwc(H * W + C, n, H, W, C)
+    mask = synth.blob_masks(H + W, n, H, W, 8, 16)
+    off = m.elastic_fields(3, 0, n, H, W, 4.0, 80, 12)
+    g = m.sample_grid(3, 0, n)
+    mx, my = m.grid_tables(torch.from_numpy(g).cuda(), H, W)
+    out, om = m.elastic_grid_u8(img.cuda(), off, mx, my, mask.cuda())
+    out2, om2 = m.elastic_grid_u8(img.cuda(), off, mx, my, mask.cuda(), per_image=True)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2) and torch.equal(om, om2)
+    out, om = out.cpu().numpy(), om.cpu().numpy()
+    for i in range(n):
+        ref, rm = oracle.pipe_elastic_grid_one(img[i].numpy(), mask[i].numpy(), 3, i, g[i], 4.0, 80, 12)
+        assert np.array_equal(out[i], ref), i
+        assert np.array_equal(om[i], rm), i
+
+
+def test_f32_chain_forward_and_adjoint(m):
+    import torch
+    n, C, H, W = 2, 3, 48, 40
+    x = synth.smooth_noise(4, n, H, W, C)
+    off = m.elastic_fields(4, 0, n, H, W, 4.0, 80, 12)
+    g = m.sample_grid(4, 0, n)
+    mx, my = m.grid_tables(torch.from_numpy(g).cuda(), H, W)
+    y = m.elastic_grid_f32_fwd(x.cuda(), off, mx, my).cpu().numpy()
+    gy = np.random.default_rng(3).uniform(-1, 1, (n, C, H, W)).astype(np.float32)
+    gx = m.elastic_grid_f32_bwd(torch.from_numpy(gy).cuda(), off, mx, my).cpu().numpy()
+    o, mxx, myy = off.cpu().numpy(), mx.cpu().numpy(), my.cpu().numpy()
+    for i in range(n):
+        yr = oracle.chain_f_forward(x[i].numpy(), o[i, 0], o[i, 1], mxx[i], myy[i])
+        assert np.abs(y[i] - yr).max() <= 1e-6
+        gr = oracle.chain_f_backward(gy[i].astype(np.float64), o[i, 0], o[i, 1], mxx[i], myy[i])
+        assert np.abs(gx[i] - gr).max() <= 1e-5 * np.abs(gr).max()
+
+
+def test_large_tile_sampled_pixels_against_the_definition(m):
+    # one 4096 x 4096 image (sigma 50, alpha 1000, radius 150, 5x5 grid with limit 0.3):
+    # sampled field values and output pixels recomputed by the oracle one by one
+    import torch
+    H = W = 4096
+    img = synth.smooth_u8_hwc(1809068395, 1, H, W, 3, device="cuda")
+    mask = synth.blob_masks(1809068396, 1, H, W, 8, 512, device="cuda")
+    off = m.elastic_fields(1809068395, 0, 1, H, W)
+    g = m.sample_grid(1809068395, 0, 1)
+    mx, my = m.grid_tables(torch.from_numpy(g).cuda(), H, W)
+    out, om = m.elastic_grid_u8(img, off, mx, my, mask)
+    torch.cuda.synchronize()
+    offn, imgn, mxn, myn = off.cpu().numpy()[0], img.cpu().numpy()[0], mx.cpu().numpy()[0], my.cpu().numpy()[0]
+    rng = np.random.default_rng(6)
+    pts = [(0, 0), (H - 1, W - 1), (0, W - 1)] + [tuple(v) for v in rng.integers(0, H, (5, 2))]
+    for (yy, xx) in pts:
+        assert oracle.elastic_field_at(1809068395, 0, H, W, yy, xx) == (offn[0, yy, xx], offn[1, yy, xx]), (yy, xx)
+    # output pixels: grid taps of e, each e pixel from its own displaced taps
+    assert np.array_equal(mxn, oracle.grid_table(g[0, :5], W)) and np.array_equal(myn, oracle.grid_table(g[0, 5:], H))
+    outn = out.cpu().numpy()[0]
+    for (yy, xx) in [tuple(v) for v in rng.integers(0, H, (200, 2))]:
+        qx, qy = int(mxn[xx]), int(myn[yy])
+        x0, y0, ax, ay = qx >> 10, qy >> 10, qx & 1023, qy & 1023
+        e = {}
+        for dy in (0, 1):
+            for dx in (0, 1):
+                Y, X = oracle.reflect101(y0 + dy, H), oracle.reflect101(x0 + dx, W)
+                ex, ey = (X << 10) + int(offn[0, Y, X]), (Y << 10) + int(offn[1, Y, X])
+                bx, by, fx, fy = ex >> 10, ey >> 10, ex & 1023, ey & 1023
+                taps = [[imgn[oracle.reflect101(by + j, H), oracle.reflect101(bx + i, W)].astype(np.int64)
+                         for i in (0, 1)] for j in (0, 1)]
+                acc = (1024 - fy) * ((1024 - fx) * taps[0][0] + fx * taps[0][1]) + fy * ((1024 - fx) * taps[1][0] + fx * taps[1][1])
+                e[(dy, dx)] = np.array([oracle.rshr_he(int(v), 20) for v in acc], np.int64)
+        acc = (1024 - ay) * ((1024 - ax) * e[(0, 0)] + ax * e[(0, 1)]) + ay * ((1024 - ax) * e[(1, 0)] + ax * e[(1, 1)])
+        ref = np.array([oracle.rshr_he(int(v), 20) for v in acc], np.uint8)
+        assert np.array_equal(outn[yy, xx], ref), (yy, xx)
+
+
+def test_image_stats_match_oracle(m):
+    import torch
+    img = synth.uniform_u8(3, 5, 70, 90, 3)
+    s, mn, mx, h = m.image_stats_u8(img.cuda())
+    for i in range(5):
+        rs, rmn, rmx, rh = oracle.image_stats(img[i].numpy())
+        assert s[i].cpu().numpy().astype(np.uint64).tolist() == rs.tolist()
+        assert mn[i].tolist() == rmn.tolist() and mx[i].tolist() == rmx.tolist()
+        assert np.array_equal(h[i].cpu().numpy().astype(np.uint32), rh)
+    empty = torch.zeros((2, 0, 3), dtype=torch.uint8, device="cuda")
+    s, mn, mx, h = m.image_stats_u8(empty)
+    assert s.sum().item() == 0 and (mn == 255).all() and (mx == 0).all() and h.sum().item() == 0
