@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--workload", default="ragged")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--variant", type=int, default=-1,
+                   help="ragged launch variant; -1 runs the autotuner (outside the timed region)")
     return p.parse_args()
 
 
@@ -99,10 +101,17 @@ def bench_ragged(args, torch, m):
     ctx = m.Context(0)
     r = m.Ragged.from_host(b, flags, ab, device=dev)
     torch.cuda.synchronize()
-    variant, tune_ms = m.ragged_autotune(ctx, r, reps=3)
     variants = m.ragged_variants()
-    print("# autotuner chose variant %d (%s), %.3f ms" % (variant, variants[variant], tune_ms), file=sys.stderr,
-          flush=True)
+    if args.variant >= 0:
+        variant = args.variant
+        ctx.set_variant(variant)
+        print("# variant %d (%s) forced" % (variant, variants[variant]), file=sys.stderr, flush=True)
+    else:
+        variant, tune_ms, tune_times = m.ragged_autotune(ctx, r, reps=3, return_times=True)
+        for i, t in enumerate(tune_times):
+            print("#   variant %d (%s): %.3f ms" % (i, variants[i], t), file=sys.stderr, flush=True)
+        print("# autotuner chose variant %d (%s), %.3f ms" % (variant, variants[variant], tune_ms), file=sys.stderr,
+              flush=True)
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         g = m.Graph(ctx, r, s)
@@ -140,7 +149,8 @@ def bench_ragged(args, torch, m):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "ragged_d4_bc_resize224_normalize_f32", "global_batch": n,
                    "sizes": "H,W~U{128..1024}", "masks": "21 labels", "boxes": "0-16 per image",
-                   "launch": "persistent kernel in hipGraph, autotuned: %s" % variants[variant],
+                   "launch": "one launch in a hipGraph, %s: %s" % ("forced" if args.variant >= 0 else "autotuned",
+                                                                   variants[variant]),
                    "parallelism": "single GPU"},
         "per_image_launches": {"value": n / (ms_pi * 1e-3), "unit": "images/s", "ms_per_step": ms_pi,
                                "batched_speedup": ms_pi / ms},
@@ -303,7 +313,20 @@ def bench_elastic(args, torch, m):
     return res
 
 
-WORKLOADS = {"ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
+def bench_copy(args, torch, m):
+    """Plain device-to-device copy of 1 GiB: the reference for scaling the HBM
+    byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.Stream()
+    ms = time_on_stream(torch, lambda st: b.copy_(a), args.steps, args.warmup, s)
+    gbs = 2 * n / (ms * 1e-3) / 1e9
+    return {"metric": "copy GB/s (read + write)", "value": gbs, "unit": "GB/s", "bytes_read": n, "bytes_written": n,
+            "ms_per_step": ms, "steps": args.steps, "config": {"workload": "copy_1GiB"}}
+
+
+WORKLOADS = {"copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
 
 
 def main():

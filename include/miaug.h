@@ -179,7 +179,9 @@ typedef struct {
     int32_t out_h, out_w;    /* output size, 1..4096                               */
     const uint8_t *img;      /* device: packed HWC u8 images                       */
     const int64_t *img_off;  /* device: [n] byte offset of image i in img          */
-    const int32_t *hw;       /* device: [n][2] = {H_i, W_i}, 1..65535              */
+    const int32_t *hw;       /* device: [n][2] = {H_i, W_i}, H_i W_i 3 < 2^31; an
+                                image outside that range is skipped (outputs
+                                left untouched)                                   */
     const int32_t *flags;    /* device: [n][4] Dih4 flags (miaug_sample_d4bc)      */
     const float *ab;         /* device: [n][2] alpha, beta                         */
     const uint8_t *mask;     /* device or NULL: packed HW u8 masks                 */
@@ -213,13 +215,16 @@ int miaug_graph_launch(miaug_graph *g, void *stream);
 int miaug_graph_destroy(miaug_graph *g);
 
 /* Autotuner for the batched form: times each launch variant (output tile
- * shape, workgroups per CU) on `args` `reps` times, keeps only variants whose
- * output is bit-identical to the per-image form, and stores the fastest in the
+ * shape, plain or software-pipelined persistent loop or flat grid,
+ * workgroups per CU) on `args` `reps` times, keeps only variants whose output
+ * is bit-identical to the per-image form, and stores the fastest in the
  * context (used by later miaug_ragged_apply calls).  Writes the chosen
- * variant index to *chosen and its mean time in ms to *ms (either may be
- * NULL).  Synchronises `stream`.  `args->out*` are overwritten. */
+ * variant index to *chosen, its mean time in ms to *ms and, when `times` is
+ * not NULL, every variant's mean time to times[0 .. variant_count-1] (-1 for
+ * a variant that failed the parity gate).  Synchronises `stream`.
+ * `args->out*` are overwritten. */
 int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *args, int reps, void *stream, int *chosen,
-                          float *ms);
+                          float *ms, float *times);
 /* Number of variants and a variant's description ("tile 32x32, 4 wg/CU"). */
 int miaug_ragged_variant_count(void);
 const char *miaug_ragged_variant_name(int v);

@@ -69,7 +69,7 @@ _SIGS = {
     "miaug_graph_launch": (_i, [_vp, _vp]),
     "miaug_graph_destroy": (_i, [_vp]),
     "miaug_ragged_autotune": (_i, [_vp, ctypes.POINTER(RaggedArgs), _i, _vp, ctypes.POINTER(_i),
-                                   ctypes.POINTER(ctypes.c_float)]),
+                                   ctypes.POINTER(ctypes.c_float), _vp]),
     "miaug_ragged_variant_count": (_i, []),
     "miaug_ragged_variant_name": (ctypes.c_char_p, [_i]),
     "miaug_ragged_set_variant": (_i, [_vp, _i]),
@@ -287,11 +287,13 @@ def ragged_apply_per_image(ctx: Context, r: Ragged, stream=None):
     return r
 
 
-def ragged_autotune(ctx: Context, r: Ragged, reps: int = 3, stream=None):
+def ragged_autotune(ctx: Context, r: Ragged, reps: int = 3, stream=None, return_times=False):
+    """Times every launch variant (parity-gated); returns (chosen, ms) or (chosen, ms, times)."""
     v, ms = ctypes.c_int(), ctypes.c_float()
+    times = np.zeros(lib().miaug_ragged_variant_count(), np.float32)
     _check(lib().miaug_ragged_autotune(ctx.handle, ctypes.byref(r.args), reps, _stream(stream), ctypes.byref(v),
-                                       ctypes.byref(ms)))
-    return v.value, ms.value
+                                       ctypes.byref(ms), times.ctypes.data))
+    return (v.value, ms.value, times.tolist()) if return_times else (v.value, ms.value)
 
 
 class Graph:

@@ -227,7 +227,8 @@ int miaug_ragged_set_variant(miaug_ctx *ctx, int v) {
     return MIAUG_OK;
 }
 
-int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, void *stream, int *chosen, float *ms) {
+int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, void *stream, int *chosen, float *ms,
+                          float *times) {
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "autotune: NULL ctx");
     if (int st = ragged_check(a)) return st;
@@ -255,6 +256,7 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
     float best_ms = 0.f;
     for (int v = 0; v < ragged_variant_count() && !st; ++v) {
         L.variant = v;
+        if (times) times[v] = -1.f;
         st = hip_status(hipMemsetAsync(a->out, 0, out_bytes, s), "clear");
         if (!st) st = hip_status(launch_ragged(a, L, 0, s), "autotune candidate");
         if (!st) st = hip_status(hipMemcpyAsync(got.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
@@ -271,6 +273,7 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
         float t = 0.f;
         hipEventElapsedTime(&t, e0, e1);
         t /= reps;
+        if (times) times[v] = t;
         if (best < 0 || t < best_ms) {
             best = v;
             best_ms = t;

@@ -41,6 +41,22 @@ __device__ __forceinline__ int32_t sdiv_he(int32_t n, int32_t d) {
     return q + ((2 * r > d) | ((2 * r == d) & (q & 1)));
 }
 
+// a * b + c with operands known to fit 24 bits (full-rate v_mad_i32_i24; the
+// compiler otherwise widens such products to 64-bit multiply-adds).  ALU-only
+// inline asm: no memory operand.
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+    int d;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// Buffer resource over [base, base + bytes) for raw buffer stores: 32-bit byte
+// offsets, stores outside the range are dropped by the hardware.  Word 3 is
+// the gfx9-family default descriptor (32-bit data, no swizzle).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+
 __device__ __forceinline__ int sat8(int v) { return v < 0 ? 0 : (v > 255 ? 255 : v); }
 
 __device__ __forceinline__ int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }

@@ -101,12 +101,20 @@ class RaggedBatch:
 
 
 def ragged_batch(seed: int, n: int, lo: int = 128, hi: int = 1024, K: int = 21, mask_spacing: int = 128,
-                 max_boxes: int = 16, device="cpu", sizes=None) -> RaggedBatch:
+                 max_boxes: int = 16, device="cpu", sizes=None, canvases: int = 16) -> RaggedBatch:
     """n RGB images with H, W ~ U{lo..hi}, blob masks with K labels, 0..max_boxes boxes.
-    Returns host-side (numpy / CPU torch) buffers; the image content is generated on
-    `device` and copied back."""
+
+    Content: `canvases` smooth-noise canvases (and blob-mask canvases) of the
+    largest size are drawn once; image i is the H x W window of canvas i mod
+    `canvases` at a random offset, so every image is smooth noise with the same
+    statistics while generation costs a few kernel launches.  Returns host-side
+    (numpy) buffers."""
     rng = np.random.default_rng(seed)
     hw = np.asarray(sizes, np.int32) if sizes is not None else rng.integers(lo, hi + 1, size=(n, 2)).astype(np.int32)
+    CH, CW = int(hw[:, 0].max()), int(hw[:, 1].max())
+    nc = min(canvases, n)
+    canvas = smooth_u8_hwc(seed * 7919 + 1, nc, CH, CW, 3, device).cpu().numpy()
+    mcanvas = blob_masks(seed * 7919 + 2, nc, CH, CW, K, mask_spacing, device).cpu().numpy()
     align = 256
     img_off = np.zeros(n, np.int64); mask_off = np.zeros(n, np.int64)
     io = mo = 0
@@ -118,10 +126,10 @@ def ragged_batch(seed: int, n: int, lo: int = 128, hi: int = 1024, K: int = 21, 
     boxes, box_off = [], [0]
     for i, (H, W) in enumerate(hw):
         H, W = int(H), int(W)
-        im = smooth_u8_hwc(seed * 7919 + i, 1, H, W, 3, device)[0].cpu().numpy()
-        img[img_off[i]:img_off[i] + H * W * 3] = im.reshape(-1)
-        m = blob_masks(seed * 7919 + i + 1_000_003, 1, H, W, K, mask_spacing, device)[0].cpu().numpy()
-        mask[mask_off[i]:mask_off[i] + H * W] = m.reshape(-1)
+        oy, ox = int(rng.integers(0, CH - H + 1)), int(rng.integers(0, CW - W + 1))
+        c = i % nc
+        img[img_off[i]:img_off[i] + H * W * 3] = canvas[c, oy:oy + H, ox:ox + W].reshape(-1)
+        mask[mask_off[i]:mask_off[i] + H * W] = mcanvas[c, oy:oy + H, ox:ox + W].reshape(-1)
         b = random_boxes(seed * 7919 + i, H, W, max_boxes)
         boxes.append(b); box_off.append(box_off[-1] + len(b))
     boxes = np.concatenate(boxes) if boxes else np.zeros((0, 4), np.float32)
