@@ -50,6 +50,13 @@ __device__ __forceinline__ int mad24(int a, int b, int c) {
     return d;
 }
 
+// Unsigned form: a * b + c for a, b < 2^24 (v_mad_u32_u24).
+__device__ __forceinline__ uint32_t umad24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // Buffer resource over [base, base + bytes) for raw buffer stores: 32-bit byte
 // offsets, stores outside the range are dropped by the hardware.  Word 3 is
 // the gfx9-family default descriptor (32-bit data, no swizzle).

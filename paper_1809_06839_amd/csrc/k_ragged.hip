@@ -4,23 +4,33 @@
 // transformed together with masks and boxes; Sec. II-B Dih4; Table I
 // Brightness).
 //
-// Work item = (image, output tile of T x T).  The separable resize needs two
-// source lines per output line along one output axis (the "line" axis: output
-// rows, or output columns when the Dih4 element swaps axes) and a contiguous
-// span of source columns along the other.  A tile therefore stages 2*T
-// source row segments into LDS with 16-byte loads (only the rows the taps
-// touch, so downscaled images skip rows in HBM), then every output pixel reads
-// its 4 taps from LDS, applies the brightness/contrast LUT per tap, blends
-// with Q10 weights, rounds once and looks the result up in the normalisation
-// LUT.  Output stores are float rows of T (coalesced per channel plane).
+// Work item = (image, output tile of TL lines x TS span positions).  The
+// separable resize needs two source rows per output line along the "line"
+// axis (output rows, or output columns when the Dih4 element swaps axes) and a
+// contiguous span of source columns along the other.  A pass stages the 2 TL
+// source row segments of its lines (only the rows the taps touch, so
+// downscaled images skip rows in HBM) and TL nearest mask row segments into
+// LDS with global_load_lds_dwordx4, then every output pixel reads its 4 taps
+// from LDS, applies the brightness/contrast LUT per tap, blends with Q10
+// weights, rounds once and looks the result up in the normalisation LUT.
+// A tile whose staged footprint does not fit the staging buffer runs as two
+// passes over the halves of its span positions; a half that still does not
+// fit reads its taps straight from global memory.
 //
-// Scheduling: the batched form is one persistent launch.  Images are dealt to
-// 8 queues (image i -> queue i mod 8); workgroup b starts on queue b mod 8,
-// which is the XCD the hardware dispatches it to, so the tiles of one image
-// share that XCD's L2.  A workgroup pops tiles with an atomic counter and,
-// when its queue is empty, moves on to the next queue; every workgroup ends
-// after at most 8 empty pops.  Counters are cleared by a one-block fill kernel
-// enqueued just before, so the pair can be captured in a hipGraph.
+// The streaming form is a persistent launch in which every workgroup runs a
+// three-stage software pipeline over its passes: in one iteration it builds
+// the tables of pass k+2, issues the LDS-DMA of pass k+1 into one staging
+// buffer and blends pass k from the other.  The two staging buffers are
+// distinct LDS variables, so the compiler can tell the DMA in flight from the
+// LDS reads of the blend and does not wait for it there.
+//
+// Scheduling: images are dealt to 8 queues (image i -> queue i mod 8);
+// workgroup b starts on queue b mod 8, which is the XCD the hardware dispatches
+// it to, so the tiles of one image share that XCD's L2.  A workgroup pops
+// tiles with an atomic counter and, when its queue is empty, moves on to the
+// next queue; every workgroup ends after at most 8 empty pops.  Counters are
+// cleared by a one-block fill kernel enqueued just before, so the pair can be
+// captured in a hipGraph.
 #include "dev_common.h"
 #include "internal.h"
 
@@ -30,18 +40,63 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kQueues = 8;
 constexpr int kCounterStride = 16;  // ints between counters (one 64-byte line each)
+constexpr int kMaxSide = 1 << 20;   // images with a side this long or longer are skipped
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
+// Load of read-only kernel input through the constant address space: with a
+// uniform address it becomes a scalar load (counted by lgkmcnt, so it never
+// waits behind LDS-DMA traffic counted by vmcnt).
+template <class T>
+__device__ __forceinline__ T ldc(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
+// floor(A / D) and the remainder for 0 <= A < 2^23, 1 <= D < 2^23, given
+// rD = v_rcp_f32(D) (relative error below 2^-22).  The float quotient is
+// within 2/D <= 1 of A / D for D >= 2 (exact for D = 1), so its truncation is
+// off by at most one (and q D < 2^24 for the full-rate multiply).
+__device__ __forceinline__ int fdiv_small(int A, int D, float rD, int &r) {
+    int q = (int)((float)A * rD);
+    r = A - (int)__umul24(q, D);
+    if (r < 0) { q -= 1; r += D; }
+    else if (r >= D) { q += 1; r -= D; }
+    return q;
+}
+
+// floor(A / D) and the remainder for 0 <= A, 1 <= D < 2^23: the float form
+// below 2^23, the compiler's integer division above.
+__device__ __forceinline__ int udiv_small(int A, int D, int &r) {
+    if (A < (1 << 23)) return fdiv_small(A, D, __builtin_amdgcn_rcpf((float)D), r);
+    const int q = A / D;
+    r = A - q * D;
+    return q;
+}
+
+// floor(A / D) and the remainder for 2^23 <= A < 2^34 (sides of at least
+// about 2^13 pixels); out of line, since it is rarely taken.
+__device__ __noinline__ int2 div_wide(int64_t A, int D) {
+    const int q = (int)(A / D);
+    return make_int2(q, (int)(A - (int64_t)q * D));
+}
+
 // Half-pixel-centre position of output index j (Q10):
-// rdiv_he(((2j+1) Ls - Lo) 2^10, 2 Lo), evaluated with two 32-bit floor
-// divisions: A = (2j+1) Ls - Lo = qa D + ra (D = 2 Lo), then ra 2^10 = qb D + rb.
+// rdiv_he(((2j+1) Ls - Lo) 2^10, 2 Lo) for 0 <= j < Lo <= 4096, 1 <= Ls < 2^20.
+// A + D = (2j+1) Ls + Lo > 0 is split as qa D + ra, then ra 2^10 = qb D + rb.
 __device__ __forceinline__ int32_t resize_q(int j, int Ls, int Lo) {
     const int D = 2 * Lo;
-    const int A = (2 * j + 1) * Ls - Lo;
-    int qa = A / D, ra = A - qa * D;
-    if (ra < 0) { qa -= 1; ra += D; }
-    const int B = ra << kFBits;
-    const int qb = B / D, rb = B - qb * D;
+    const float rD = __builtin_amdgcn_rcpf((float)D);
+    const int64_t A = (int64_t)(2 * j + 1) * Ls + Lo;
+    int qa, ra;
+    if (A < (1 << 23)) {
+        qa = fdiv_small((int)A, D, rD, ra);
+    } else {
+        const int2 qr = div_wide(A, D);
+        qa = qr.x;
+        ra = qr.y;
+    }
+    qa -= 1;
+    int rb;
+    const int qb = fdiv_small(ra << kFBits, D, rD, rb);
     const int q = (qa << kFBits) + qb;
     return q + ((2 * rb > D) | ((2 * rb == D) & (q & 1)));
 }
@@ -49,18 +104,12 @@ __device__ __forceinline__ int32_t resize_q(int j, int Ls, int Lo) {
 // Round-half-even of acc / 2^20 for acc >= 0.
 __device__ __forceinline__ int rhe20(int acc) { return (acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20; }
 
-// A tile covers TL output lines (the axis whose taps select source rows) by
-// TS span positions (the axis whose taps select source columns).
-template <int TL, int TS>
-struct Cfg {
-    static constexpr int kMaxSpanPx = (TS - 1) * 46 / 10 + 4;        // staged span: scale factors up to 4.6
-    static constexpr int kChunks = (kMaxSpanPx * 3 + 30) / 16;       // 16-byte chunks per image slot
-    static constexpr int kStride = kChunks * 16;
-    static constexpr int kMChunks = (kMaxSpanPx + 30) / 16;
-    static constexpr int kMStride = kMChunks * 16;
-    static constexpr int kPix = (TL * TS + kThreads - 1) / kThreads;  // output pixels per thread
-    static_assert(TL <= 64 && TS <= 64 && TL % 8 == 0 && TS % 8 == 0, "tile sides are multiples of 8, at most 64");
-};
+// Staging buffer of CAP 16-byte chunks plus slack: a tap's two-dword read may
+// reach a few bytes past the last chunk.
+constexpr int stage_bytes(int cap) { return cap * 16 + 16; }
+
+template <int TS>
+constexpr int log2_of() { return TS == 64 ? 6 : TS == 32 ? 5 : TS == 16 ? 4 : 3; }
 
 // Work items per image: the tile grid in line x span coordinates depends on
 // whether the element swaps axes, so the queue reserves the larger count.
@@ -71,44 +120,44 @@ __host__ __device__ __forceinline__ int tiles_per_image(int OH, int OW) {
     return a > b ? a : b;
 }
 
-// LDS of a workgroup with NB staging buffers (1: plain, 2: pipelined).
-template <int TL, int TS, int NB>
-struct __align__(16) Smem {
-    // staging buffer b: image slot s at byte 16*s*nchi, mask slot s at byte
-    // 16*(2*nl*nchi + s*nchm) (nchi, nchm: 16-byte chunks per slot of the tile)
-    uint8_t stage[NB][2 * TL * Cfg<TL, TS>::kStride + TL * Cfg<TL, TS>::kMStride + 16];
-    int4 line[NB][TL];  // per output line: LDS offsets of the two tap rows and the nearest mask row, weight
-    int4 col[NB][TS];   // per span position: byte offsets of the two taps in a row, weight, mask offset
-    int32_t qline[NB][TL], qspan[NB][TS];
-    float nlut[3][256];
-    uint8_t bclut[NB][256];
-    int item[4];
-};
+// Largest staged footprint (16-byte chunks) of a whole TL x TS tile whose
+// source extent along the span axis is up to 4.6 times the output's.
+template <int TL, int TS>
+constexpr int full_cap() {
+    return 2 * TL * ((((TS - 1) * 46 / 10 + 4) * 3 + 30) / 16) + TL * ((((TS - 1) * 46 / 10 + 4) + 30) / 16);
+}
 
-template <int TL, int TS, int NB>
-__device__ __forceinline__ void build_norm_lut(const miaug_ragged_args &a, Smem<TL, TS, NB> &S) {
-    for (int e = threadIdx.x; e < 3 * 256; e += kThreads) {
+__device__ __forceinline__ void build_norm_lut(const miaug_ragged_args &a, float (&nlut)[3][256]) {
+    for (int e = threadIdx.x; e < 3 * 256; e += blockDim.x) {
         int c = e >> 8, v = e & 255;
-        S.nlut[c][v] = (float)((((double)v / 255.0) - (double)a.mean[c]) / (double)a.stdv[c]);
+        nlut[c][v] = (float)((((double)v / 255.0) - (double)a.mean[c]) / (double)a.stdv[c]);
     }
+}
+
+__device__ __forceinline__ void build_bc_lut(float alpha, float beta, uint8_t *lut) {
+    const int tid = threadIdx.x;
+    const double v = (double)alpha * (double)tid + (double)beta;
+    lut[tid] = (uint8_t)sat8((int)rint(v));
 }
 
 // Boxes of one image: Dih4 ops one after the other, then the scale to the
 // output size, in double.
+template <int NT>
 __device__ __forceinline__ void ragged_boxes(const miaug_ragged_args &a, int img) {
-    int b0 = a.box_off[img], b1 = a.box_off[img + 1];
+    int b0 = ldc(a.box_off + img), b1 = ldc(a.box_off + img + 1);
     const int32_t *fl = a.flags + 4 * img;
-    for (int b = b0 + (int)threadIdx.x; b < b1; b += kThreads) {
+    const int f0 = ldc(fl), f1 = ldc(fl + 1), f2 = ldc(fl + 2), f3 = ldc(fl + 3);
+    for (int b = b0 + (int)threadIdx.x; b < b1; b += NT) {
         double x1 = a.boxes[4 * b], y1 = a.boxes[4 * b + 1], x2 = a.boxes[4 * b + 2], y2 = a.boxes[4 * b + 3];
-        double h = a.hw[2 * img], w = a.hw[2 * img + 1];
-        if (fl[0]) { double u = w - x2, v = w - x1; x1 = u; x2 = v; }
-        if (fl[1]) { double u = h - y2, v = h - y1; y1 = u; y2 = v; }
-        for (int t = 0; t < (fl[2] & 3); ++t) {
+        double h = ldc(a.hw + 2 * img), w = ldc(a.hw + 2 * img + 1);
+        if (f0) { double u = w - x2, v = w - x1; x1 = u; x2 = v; }
+        if (f1) { double u = h - y2, v = h - y1; y1 = u; y2 = v; }
+        for (int t = 0; t < (f2 & 3); ++t) {
             double nx1 = y1, ny1 = w - x2, nx2 = y2, ny2 = w - x1;
             x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
             double s = h; h = w; w = s;
         }
-        if (fl[3]) {
+        if (f3) {
             double nx1 = y1, ny1 = x1, nx2 = y2, ny2 = x2;
             x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
             double s = h; h = w; w = s;
@@ -121,549 +170,734 @@ __device__ __forceinline__ void ragged_boxes(const miaug_ragged_args &a, int img
     }
 }
 
-// Geometry of one work item, identical in every thread.
-struct Tile {
-    int img, tile;
+// ---------------------------------------------------------------- passes
+// Per-image inputs a pass plan needs.
+struct ImgInfo {
+    int H, W, f0, f1, f2, f3;
+    int64_t io, mo;  // byte offsets of the image and mask
+    float alpha, beta;
+};
+
+// Through scalar loads (uniform img).
+__device__ __forceinline__ ImgInfo info_scalar(const miaug_ragged_args &a, int img) {
+    ImgInfo r;
+    r.H = ldc(a.hw + 2 * img);
+    r.W = ldc(a.hw + 2 * img + 1);
+    const int32_t *fl = a.flags + 4 * img;
+    r.f0 = ldc(fl);
+    r.f1 = ldc(fl + 1);
+    r.f2 = ldc(fl + 2);
+    r.f3 = ldc(fl + 3);
+    r.io = ldc(a.img_off + img);
+    r.mo = a.mask ? ldc(a.mask_off + img) : 0;
+    r.alpha = ldc(a.ab + 2 * img);
+    r.beta = ldc(a.ab + 2 * img + 1);
+    return r;
+}
+
+// Asynchronous form for a whole wave: lane l < 12 loads field l of image img
+// with one vector load (counted by vmcnt, so it can stay in flight across LDS
+// work); info_gather() assembles the fields once the load has completed.
+__device__ __forceinline__ int info_issue(const miaug_ragged_args &a, int img) {
+    const int l = threadIdx.x & 63;
+    const int32_t *p = nullptr;
+    if (l < 2) p = a.hw + 2 * img + l;
+    else if (l < 6) p = a.flags + 4 * img + (l - 2);
+    else if (l < 8) p = (const int32_t *)(a.img_off + img) + (l - 6);
+    else if (l < 10 && a.mask) p = (const int32_t *)(a.mask_off + img) + (l - 8);
+    else if (l >= 10 && l < 12) p = (const int32_t *)(a.ab + 2 * img) + (l - 10);
+    return p ? *p : 0;
+}
+
+__device__ __forceinline__ ImgInfo info_gather(int v) {
+    ImgInfo r;
+    r.H = __builtin_amdgcn_readlane(v, 0);
+    r.W = __builtin_amdgcn_readlane(v, 1);
+    r.f0 = __builtin_amdgcn_readlane(v, 2);
+    r.f1 = __builtin_amdgcn_readlane(v, 3);
+    r.f2 = __builtin_amdgcn_readlane(v, 4);
+    r.f3 = __builtin_amdgcn_readlane(v, 5);
+    r.io = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 7) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(v, 6));
+    r.mo = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(v, 9) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(v, 8));
+    r.alpha = __int_as_float(__builtin_amdgcn_readlane(v, 10));
+    r.beta = __int_as_float(__builtin_amdgcn_readlane(v, 11));
+    return r;
+}
+
+// Geometry of one pass, identical in every thread.
+struct Pass {
+    int img, tile, part;  // part 0: whole tile; 1 / 2: first / second half of its span positions
+    bool valid;           // false: end of the work stream
+    bool empty;           // image skipped or spare item: nothing to do
+    bool staged;          // footprint fits the staging buffer
+    bool swap;
     int H, W;
     D4Map m;
-    bool swap, staged, empty;
-    int j0, i0, th, tw, nl, ns, Ll, Ls, kl, ks;
-    int nchi, nchm, img_items;
-    int sxlo, nsx, mxlo, nmx;  // source column span of the bilinear taps / of the nearest taps
+    int l0, s0, nl, ns;  // first output line / span position, counts
+    int OL, OS, Ll, Ls, kl, ks;
+    int sxlo, nsx, mxlo, nmx;          // source column spans of the bilinear / nearest taps
+    int nchi, nchm, img_items, total;  // staging layout in 16-byte chunks
+    int64_t io, mo;
+    float alpha, beta;
 };
 
+template <int TL, int TS, int CAP>
+__device__ __forceinline__ Pass make_pass(const miaug_ragged_args &a, const ImgInfo &in, int img, int tile,
+                                          int part) {
+    Pass p;
+    p.img = img;
+    p.tile = tile;
+    p.part = part;
+    p.valid = true;
+    p.H = in.H;
+    p.W = in.W;
+    p.io = in.io;
+    p.mo = in.mo;
+    p.alpha = in.alpha;
+    p.beta = in.beta;
+    p.empty = p.H < 1 || p.W < 1 || p.H >= kMaxSide || p.W >= kMaxSide || (int64_t)p.H * p.W * 3 >= ((int64_t)1 << 31);
+    p.m = make_d4(p.empty ? 1 : p.H, p.empty ? 1 : p.W, in.f0, in.f1, in.f2, in.f3);
+    p.swap = p.m.swaps();
+    p.OL = p.swap ? a.out_w : a.out_h;
+    p.OS = p.swap ? a.out_h : a.out_w;
+    const int n_sb = (p.OS + TS - 1) / TS;
+    int sb;
+    p.l0 = udiv_small(tile, n_sb, sb) * TL;
+    p.s0 = sb * TS;
+    if (p.l0 >= p.OL) p.empty = true;  // spare item of the larger tile grid
+    p.nl = min(TL, p.OL - p.l0);
+    int ns = min(TS, p.OS - p.s0);
+    if (part == 1) {
+        ns = min(ns, TS / 2);
+    } else if (part == 2) {
+        p.s0 += TS / 2;
+        ns -= TS / 2;
+    }
+    p.ns = ns;
+    if (p.nl < 1 || ns < 1) p.empty = true;
+    p.Ll = p.swap ? p.m.ow : p.m.oh;
+    p.Ls = p.swap ? p.m.oh : p.m.ow;
+    p.kl = p.swap ? p.m.by : p.m.ay;
+    p.ks = p.swap ? p.m.ax : p.m.bx;
+    p.staged = false;
+    p.sxlo = p.nsx = p.mxlo = p.nmx = p.nchi = p.nchm = p.img_items = p.total = 0;
+    if (p.empty) return p;
+    const int32_t qf = resize_q(p.s0, p.Ls, p.OS), ql = resize_q(p.s0 + ns - 1, p.Ls, p.OS);
+    const int dlo = clampi(qf >> kFBits, p.Ls), dhi = clampi((ql >> kFBits) + 1, p.Ls);
+    const int xa = p.ks * dlo + p.m.cx, xb = p.ks * dhi + p.m.cx;
+    p.sxlo = min(xa, xb);
+    p.nsx = abs(xb - xa) + 1;
+    const int nlo = clampi((qf + kFOne / 2) >> kFBits, p.Ls), nhi = clampi((ql + kFOne / 2) >> kFBits, p.Ls);
+    const int mxa = p.ks * nlo + p.m.cx, mxb = p.ks * nhi + p.m.cx;
+    p.mxlo = min(mxa, mxb);
+    p.nmx = abs(mxb - mxa) + 1;
+    p.nchi = (3 * p.nsx + 30) >> 4;  // most chunks a row segment of 3 nsx bytes can touch
+    p.nchm = a.mask ? (p.nmx + 30) >> 4 : 0;
+    p.img_items = 2 * p.nl * p.nchi;
+    p.total = p.img_items + p.nl * p.nchm;
+    p.staged = p.total <= CAP;
+    return p;
+}
+
+// Pass `part` of tile (img, tile); part 0 becomes part 1 when the whole tile's
+// footprint does not fit the staging buffer (one call site of make_pass).
+template <int TL, int TS, int CAP>
+__device__ __forceinline__ Pass plan_pass(const miaug_ragged_args &a, const ImgInfo &in, int img, int tile,
+                                          int part) {
+    Pass p;
+    for (;;) {
+        p = make_pass<TL, TS, CAP>(a, in, img, tile, part);
+        if (part != 0 || p.empty || p.staged || p.ns <= TS / 2) break;
+        part = 1;
+    }
+    return p;
+}
+
+// What later stages of a pass read back from LDS (one int each).
+enum { M_VALID, M_EMPTY, M_STAGED, M_IMG, M_TILE, M_PART, M_SWAP, M_J0, M_I0, M_NL, M_NS, M_NCHI, M_NCHM,
+       M_ITEMS, M_TOTAL, M_W, M_LL, M_LS, M_KL, M_KS, M_CX, M_CY, M_OL, M_OS, M_L0, M_S0, M_IOFF,
+       M_MOFF = M_IOFF + 2, M_ALPHA = M_MOFF + 2, M_BETA, M_N = (M_BETA + 1 + 3) / 4 * 4 };
+
+struct Meta {
+    int valid, empty, staged, img, tile, part, swap, j0, i0, nl, ns, nchi, nchm, items, total;
+    int W, Ll, Ls, kl, ks, cx, cy, OL, OS, l0, s0;  // geometry for the direct path
+    int64_t img_off, mask_off;  // byte offsets of the image and mask in the packed batch
+    float alpha, beta;          // brightness/contrast parameters
+};
+
+__device__ __forceinline__ Meta read_meta(const int *s) {
+    Meta m;
+    m.valid = __builtin_amdgcn_readfirstlane(s[M_VALID]);
+    m.empty = __builtin_amdgcn_readfirstlane(s[M_EMPTY]);
+    m.staged = __builtin_amdgcn_readfirstlane(s[M_STAGED]);
+    m.img = __builtin_amdgcn_readfirstlane(s[M_IMG]);
+    m.tile = __builtin_amdgcn_readfirstlane(s[M_TILE]);
+    m.part = __builtin_amdgcn_readfirstlane(s[M_PART]);
+    m.swap = __builtin_amdgcn_readfirstlane(s[M_SWAP]);
+    m.j0 = __builtin_amdgcn_readfirstlane(s[M_J0]);
+    m.i0 = __builtin_amdgcn_readfirstlane(s[M_I0]);
+    m.nl = __builtin_amdgcn_readfirstlane(s[M_NL]);
+    m.ns = __builtin_amdgcn_readfirstlane(s[M_NS]);
+    m.nchi = __builtin_amdgcn_readfirstlane(s[M_NCHI]);
+    m.nchm = __builtin_amdgcn_readfirstlane(s[M_NCHM]);
+    m.items = __builtin_amdgcn_readfirstlane(s[M_ITEMS]);
+    m.total = __builtin_amdgcn_readfirstlane(s[M_TOTAL]);
+    m.W = __builtin_amdgcn_readfirstlane(s[M_W]);
+    m.Ll = __builtin_amdgcn_readfirstlane(s[M_LL]);
+    m.Ls = __builtin_amdgcn_readfirstlane(s[M_LS]);
+    m.kl = __builtin_amdgcn_readfirstlane(s[M_KL]);
+    m.ks = __builtin_amdgcn_readfirstlane(s[M_KS]);
+    m.cx = __builtin_amdgcn_readfirstlane(s[M_CX]);
+    m.cy = __builtin_amdgcn_readfirstlane(s[M_CY]);
+    m.OL = __builtin_amdgcn_readfirstlane(s[M_OL]);
+    m.OS = __builtin_amdgcn_readfirstlane(s[M_OS]);
+    m.l0 = __builtin_amdgcn_readfirstlane(s[M_L0]);
+    m.s0 = __builtin_amdgcn_readfirstlane(s[M_S0]);
+    m.img_off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(s[M_IOFF + 1]) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane(s[M_IOFF]));
+    m.mask_off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(s[M_MOFF + 1]) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane(s[M_MOFF]));
+    m.alpha = __int_as_float(__builtin_amdgcn_readfirstlane(s[M_ALPHA]));
+    m.beta = __int_as_float(__builtin_amdgcn_readfirstlane(s[M_BETA]));
+    return m;
+}
+
+__device__ __forceinline__ const uint8_t *align16(const uint8_t *g) {
+    return (const uint8_t *)((uintptr_t)g & ~(uintptr_t)15);
+}
+
+// Tables of a pass, built by wave 0 alone (the other waves only read them
+// after a barrier):
+//   ln[l]  = LDS byte offsets of the two tap rows of line l, its Q10 weight and
+//            the LDS byte offset of its nearest mask row;
+//   cl[s]  = byte offsets of the two taps of span position s inside a staged
+//            row, its weight, and the nearest mask tap's offset;
+//   rw[r]  = per staged row r (2 per line, then 1 mask row per line): offset of
+//            its first 16-byte chunk from the image's (mask's) aligned base,
+//            and its chunk count;
+//   meta   = what the DMA and blend stages need.
+// Lane l < TL builds line l, lane TL + s span position s, with one shared
+// evaluation of the resize position.
 template <int TL, int TS>
-__device__ __forceinline__ Tile tile_geometry(const miaug_ragged_args &a, int img, int tile) {
-    Tile t;
-    t.img = img;
-    t.tile = tile;
-    t.H = a.hw[2 * img];
-    t.W = a.hw[2 * img + 1];
-    // images that are empty or not addressable with 32-bit byte offsets are
-    // skipped (their outputs are left untouched)
-    t.empty = t.H < 1 || t.W < 1 || (int64_t)t.H * t.W * 3 >= ((int64_t)1 << 31);
-    const int32_t *fl = a.flags + 4 * img;
-    t.m = make_d4(max(t.H, 1), max(t.W, 1), fl[0], fl[1], fl[2], fl[3]);
-    t.swap = t.m.swaps();
-    // line axis: output rows, or output columns when the element swaps axes
-    const int OL = t.swap ? a.out_w : a.out_h, OS = t.swap ? a.out_h : a.out_w;
-    const int n_sb = (OS + TS - 1) / TS;
-    const int l0 = (tile / n_sb) * TL, s0 = (tile % n_sb) * TS;
-    if (l0 >= OL) t.empty = true;  // spare item of the larger tile grid
-    t.nl = min(TL, OL - l0);
-    t.ns = min(TS, OS - s0);
-    t.j0 = t.swap ? s0 : l0;
-    t.i0 = t.swap ? l0 : s0;
-    t.th = t.swap ? t.ns : t.nl;
-    t.tw = t.swap ? t.nl : t.ns;
-    t.Ll = t.swap ? t.m.ow : t.m.oh;
-    t.Ls = t.swap ? t.m.oh : t.m.ow;
-    t.kl = t.swap ? t.m.by : t.m.ay;
-    t.ks = t.swap ? t.m.ax : t.m.bx;
-    return t;
+__device__ __forceinline__ void pass_tables(const miaug_ragged_args &a, const Pass &p, int4 *ln, int4 *cl, int2 *rw,
+                                            int *meta) {
+    static_assert(TL + TS <= 64, "one wave builds the tables");
+    const int lane = threadIdx.x & 63;
+    const bool live = p.valid && !p.empty;
+    const int64_t io = live ? p.io : 0;
+    const int64_t mo = live && a.mask ? p.mo : 0;
+    if (lane == 0) {
+        meta[M_VALID] = p.valid;
+        meta[M_EMPTY] = p.empty;
+        meta[M_STAGED] = p.staged;
+        meta[M_IMG] = p.img;
+        meta[M_TILE] = p.tile;
+        meta[M_PART] = p.part;
+        meta[M_SWAP] = p.swap;
+        meta[M_J0] = p.swap ? p.s0 : p.l0;
+        meta[M_I0] = p.swap ? p.l0 : p.s0;
+        meta[M_NL] = p.nl;
+        meta[M_NS] = p.ns;
+        meta[M_NCHI] = p.nchi;
+        meta[M_NCHM] = p.nchm;
+        meta[M_ITEMS] = p.img_items;
+        meta[M_TOTAL] = p.total;
+        meta[M_W] = p.W;
+        meta[M_LL] = p.Ll;
+        meta[M_LS] = p.Ls;
+        meta[M_KL] = p.kl;
+        meta[M_KS] = p.ks;
+        meta[M_CX] = p.m.cx;
+        meta[M_CY] = p.m.cy;
+        meta[M_OL] = p.OL;
+        meta[M_OS] = p.OS;
+        meta[M_L0] = p.l0;
+        meta[M_S0] = p.s0;
+        meta[M_IOFF] = (int)(uint32_t)io;
+        meta[M_IOFF + 1] = (int)(uint32_t)((uint64_t)io >> 32);
+        meta[M_MOFF] = (int)(uint32_t)mo;
+        meta[M_MOFF + 1] = (int)(uint32_t)((uint64_t)mo >> 32);
+        meta[M_ALPHA] = __float_as_int(p.alpha);
+        meta[M_BETA] = __float_as_int(p.beta);
+    }
+    if (!live || !p.staged) return;
+    const D4Map &m = p.m;
+    const bool isl = lane < TL;  // lanes 0..TL-1: lines; TL..TL+TS-1: span positions
+    const int idx = isl ? lane : lane - TL;
+    if (idx >= (isl ? p.nl : p.ns) || lane >= TL + TS) return;
+    const int Lsrc = isl ? p.Ll : p.Ls;
+    const int q = resize_q(isl ? p.l0 + idx : p.s0 + idx, Lsrc, isl ? p.OL : p.OS);
+    const int d0 = clampi(q >> kFBits, Lsrc), d1 = clampi((q >> kFBits) + 1, Lsrc);
+    const int dn = clampi((q + kFOne / 2) >> kFBits, Lsrc);
+    if (isl) {
+        // rows are < 2^31 bytes into the image: 32-bit offsets from its aligned base
+        const int ph = (int)((uintptr_t)(a.img + io) & 15);
+        const int r0 = ph + ((p.kl * d0 + m.cy) * p.W + p.sxlo) * 3;
+        const int r1 = ph + ((p.kl * d1 + m.cy) * p.W + p.sxlo) * 3;
+        rw[2 * idx] = make_int2(r0 & ~15, ((r0 & 15) + 3 * p.nsx + 15) >> 4);
+        rw[2 * idx + 1] = make_int2(r1 & ~15, ((r1 & 15) + 3 * p.nsx + 15) >> 4);
+        int mof = 0;
+        if (a.mask) {
+            const int mph = (int)((uintptr_t)(a.mask + mo) & 15);
+            const int rm = mph + (p.kl * dn + m.cy) * p.W + p.mxlo;
+            rw[2 * p.nl + idx] = make_int2(rm & ~15, ((rm & 15) + p.nmx + 15) >> 4);
+            mof = 16 * (p.img_items + idx * p.nchm) + (rm & 15);
+        }
+        ln[idx] = make_int4(16 * (2 * idx) * p.nchi + (r0 & 15), 16 * (2 * idx + 1) * p.nchi + (r1 & 15),
+                            q & (kFOne - 1), mof);
+    } else {
+        cl[idx] = make_int4(3 * (p.ks * d0 + m.cx - p.sxlo), 3 * (p.ks * d1 + m.cx - p.sxlo), q & (kFOne - 1),
+                            p.ks * dn + m.cx - p.mxlo);
+    }
 }
 
-// Phase 1 of a work item into buffer b: resize positions of its lines and
-// span positions, the brightness/contrast LUT, the boxes (first tile of an
-// image), then -- after one barrier -- the LDS-DMA of the source rows and the
-// per-line / per-column tables.  The DMA completes asynchronously (vmcnt);
-// compute_tile may read buffer b only after s_waitcnt vmcnt(0) + a barrier.
-template <int TL, int TS, int NB>
-__device__ __forceinline__ void prepare_tile(const miaug_ragged_args &a, Tile &t, int b, Smem<TL, TS, NB> &S,
-                                             int &lut_img) {
-    using C = Cfg<TL, TS>;
+// Issues the LDS-DMA of a staged pass: chunk `it` of the pass (image rows
+// first, 2 nl slots of nchi chunks, then nl mask slots of nchm chunks) lands
+// at stage byte 16 it.  The 64 lanes of a wave take 64 consecutive chunks,
+// which is the DMA's lane layout (LDS base in M0 + 16 * lane); threads
+// 0..NT-1 take part.  All row-table reads come first, then the DMAs, so their
+// LDS latencies overlap.  Completion is counted by vmcnt.
+template <int NT, int CAP, int N>
+__device__ __forceinline__ void pass_dma(const miaug_ragged_args &a, const Meta &mt, const int2 *rw,
+                                         uint8_t (&st)[N]) {
+    constexpr int kIt = (CAP + NT - 1) / NT;
+    if (!mt.valid || mt.empty || !mt.staged) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint8_t *ib = align16(a.img + mt.img_off);
+    const uint8_t *mb = a.mask ? align16(a.mask + mt.mask_off) : ib;
+    const int nchi = mt.nchi, nchm = mt.nchm, items = mt.items, total = mt.total;
+    const float ri = __builtin_amdgcn_rcpf((float)nchi), rm = __builtin_amdgcn_rcpf((float)max(nchm, 1));
+    const int mslot0 = 2 * mt.nl;
+    const uint8_t *src[kIt];
+#pragma unroll
+    for (int u = 0; u < kIt; ++u) {
+        src[u] = nullptr;
+        if (tid - lane + u * NT >= total) break;  // uniform per wave
+        const int it = tid + u * NT;
+        const bool im = it < items;
+        int ch;
+        const int slot = fdiv_small(im ? it : it - items, im ? nchi : max(nchm, 1), im ? ri : rm, ch) +
+                         (im ? 0 : mslot0);
+        const int2 r = rw[min(max(slot, 0), 3 * mslot0 / 2 - 1)];
+        src[u] = (it < total && ch < r.y) ? (im ? ib : mb) + r.x + 16 * ch : nullptr;
+    }
+#pragma unroll
+    for (int u = 0; u < kIt; ++u) {
+        const int base = tid - lane + u * NT;
+        if (base >= total) break;
+        if (src[u]) __builtin_amdgcn_global_load_lds((const void *)src[u], (lds_ptr_t)(st + 16 * base), 16, 0, 0);
+    }
+}
+
+// Blend, normalise and store a staged pass.  Each tap byte is one ds_read_u8
+// (the channel is the instruction's immediate offset) whose result indexes
+// the brightness/contrast LUT directly.  The separable blend uses full-rate
+// 24-bit multiplies (weights <= 1024, partial sums < 2^18, total < 2^28).
+// Stores take per-channel scalar offsets.  Lanes take output row segments
+// when the element keeps the axes (consecutive lanes read consecutive columns
+// of the same two staged rows), and 8 x 8 blocks when it swaps them
+// (consecutive lanes would otherwise read the same column of many staged rows,
+// which share few LDS banks).
+template <int TL, int TS, int NT, bool SWAP, int N>
+__device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta &mt, const uint8_t (&st)[N],
+                                         const int4 *ln, const int4 *cl, const uint8_t *bc,
+                                         const float (&nlut)[3][256]) {
+    constexpr int kPix = (TL * TS + NT - 1) / NT;
+    static_assert(NT % 64 == 0 && (TL * TS) % NT == 0, "whole waves, whole tiles");
     const int tid = threadIdx.x;
-    if (t.empty) {
-        __syncthreads();
-        t.staged = false;
-        return;
-    }
-    const int OL = t.swap ? a.out_w : a.out_h, OS = t.swap ? a.out_h : a.out_w;
-    const int l0 = t.swap ? t.i0 : t.j0, s0 = t.swap ? t.j0 : t.i0;
-    static_assert(TL <= 64 && TS <= 64, "line and span positions are computed by threads 0..63 and 64..127");
-    if (lut_img != t.img) {
-        if (tid < 256) {
-            const double v = (double)a.ab[2 * t.img] * (double)tid + (double)a.ab[2 * t.img + 1];
-            S.bclut[b][tid] = (uint8_t)sat8((int)rint(v));
-        }
-        lut_img = t.img;
-    }
-    if (tid < t.nl) S.qline[b][tid] = resize_q(l0 + tid, t.Ll, OL);
-    if (tid >= 64 && tid - 64 < t.ns) S.qspan[b][tid - 64] = resize_q(s0 + tid - 64, t.Ls, OS);
-    if (t.tile == 0 && a.boxes) ragged_boxes(a, t.img);
-    __syncthreads();
-
-    // source column span of the tile (bilinear taps) and of its nearest taps
-    const D4Map &m = t.m;
-    const int W = t.W, Ll = t.Ll, Ls = t.Ls, kl = t.kl, ks = t.ks, nl = t.nl;
-    const int32_t qs_first = S.qspan[b][0], qs_last = S.qspan[b][t.ns - 1];
-    const int dlo = clampi(qs_first >> kFBits, Ls), dhi = clampi((qs_last >> kFBits) + 1, Ls);
-    const int xa = ks * dlo + m.cx, xb = ks * dhi + m.cx;
-    const int sxlo = min(xa, xb), nsx = abs(xb - xa) + 1;
-    const int nlo = clampi((qs_first + kFOne / 2) >> kFBits, Ls), nhi = clampi((qs_last + kFOne / 2) >> kFBits, Ls);
-    const int mxa = ks * nlo + m.cx, mxb = ks * nhi + m.cx;
-    const int mxlo = min(mxa, mxb), nmx = abs(mxb - mxa) + 1;
-    t.staged = nsx <= C::kMaxSpanPx;
-    const uint8_t *ibase = a.img + a.img_off[t.img];
-    const uint8_t *mbase = a.mask ? a.mask + a.mask_off[t.img] : nullptr;
-
-    // Staging: item `it` (a 16-byte chunk of an image or mask slot) is copied
-    // straight from HBM to LDS byte 16*it with global_load_lds_dwordx4.  The 64
-    // lanes of a wave take 64 consecutive items, which is the DMA's lane layout
-    // (LDS base in M0 + 16 * lane), so no registers hold the data and a
-    // workgroup has its whole footprint in flight at once.
-    t.nchi = (nsx * 3 + 30) >> 4;
-    t.nchm = mbase ? (nmx + 30) >> 4 : 0;
-    t.img_items = 2 * nl * t.nchi;
-    if (!t.staged) return;
-    const int nchi = t.nchi, nchm = t.nchm, img_items = t.img_items;
-    const int total = img_items + nl * nchm;
-    const uint32_t inv_i = ((1u << 20) + nchi - 1) / nchi;            // it / nchi = (it * inv) >> 20
-    const uint32_t inv_m = nchm ? ((1u << 20) + nchm - 1) / nchm : 0;  // (exact for it < 4096)
-    const int lane = tid & 63;
-    uint8_t *stage = S.stage[b];
-    for (int base = tid - lane; base < total; base += kThreads) {
-        const int it = base + lane;
-        const uint8_t *src = nullptr;
-        if (it < total) {
-            const uint8_t *g;
-            int len, ch;
-            if (it < img_items) {
-                const int slot = (int)(((uint32_t)it * inv_i) >> 20);
-                ch = it - slot * nchi;
-                const int d = clampi((S.qline[b][slot >> 1] >> kFBits) + (slot & 1), Ll);
-                g = ibase + (uint32_t)(((kl * d + m.cy) * W + sxlo) * 3);  // images are < 2^31 bytes
-                len = nsx * 3;
-            } else {
-                const int it2 = it - img_items, slot = (int)(((uint32_t)it2 * inv_m) >> 20);
-                ch = it2 - slot * nchm;
-                const int d = clampi((S.qline[b][slot] + kFOne / 2) >> kFBits, Ll);
-                g = mbase + (uint32_t)((kl * d + m.cy) * W + mxlo);
-                len = nmx;
-            }
-            if (ch < span_chunks(g, len)) src = (const uint8_t *)((uintptr_t)g & ~(uintptr_t)15) + 16 * ch;
-        }
-        if (src) __builtin_amdgcn_global_load_lds((const void *)src, (lds_ptr_t)(stage + 16 * base), 16, 0, 0);
-    }
-    // per-line and per-column tables
-    if (tid < nl) {
-        const int q = S.qline[b][tid];
-        const int d0 = clampi(q >> kFBits, Ll), d1 = clampi((q >> kFBits) + 1, Ll);
-        const uint8_t *g0 = ibase + ((size_t)(kl * d0 + m.cy) * W + sxlo) * 3;
-        const uint8_t *g1 = ibase + ((size_t)(kl * d1 + m.cy) * W + sxlo) * 3;
-        int mb = 0;
-        if (mbase) {
-            const int dn = clampi((q + kFOne / 2) >> kFBits, Ll);
-            mb = 16 * (img_items + tid * nchm) + span_phase(mbase + (size_t)(kl * dn + m.cy) * W + mxlo);
-        }
-        S.line[b][tid] = make_int4(16 * (2 * tid) * nchi + span_phase(g0), 16 * (2 * tid + 1) * nchi + span_phase(g1),
-                                   q & (kFOne - 1), mb);
-    }
-    if (tid >= 64 && tid - 64 < t.ns) {
-        const int si = tid - 64, q = S.qspan[b][si];
-        const int e0 = clampi(q >> kFBits, Ls), e1 = clampi((q >> kFBits) + 1, Ls);
-        const int en = clampi((q + kFOne / 2) >> kFBits, Ls);
-        S.col[b][si] = make_int4(3 * (ks * e0 + m.cx - sxlo), 3 * (ks * e1 + m.cx - sxlo), q & (kFOne - 1),
-                                 ks * en + m.cx - mxlo);
-    }
-}
-
-// Phase 2: blend, normalise and store the tile from buffer b (staged), or
-// from global memory when the span was too wide for the staging buffer.
-// Three bytes of a staged pixel at LDS byte offset o (any alignment): one
-// ds_read2_b32 of the two dwords that hold it, then a byte-aligned funnel shift.
-__device__ __forceinline__ uint32_t lds_rgb(const uint8_t *st, int o) {
-    const uint32_t *w = (const uint32_t *)(st + (o & ~3));
-    return __builtin_amdgcn_alignbyte(w[1], w[0], o & 3);
-}
-
-template <int TL, int TS, int NB>
-__device__ __forceinline__ void compute_tile(const miaug_ragged_args &a, const Tile &t, int b,
-                                             Smem<TL, TS, NB> &S) {
-    using C = Cfg<TL, TS>;
-    if (t.empty) return;
-    const int tid = threadIdx.x;
-    const size_t plane = (size_t)a.out_h * a.out_w;
+    const int plane = a.out_h * a.out_w;  // outputs are at most 4096 x 4096
     const int OW = a.out_w;
     const bool has_mask = a.mask != nullptr;
-    if (t.staged) {
-        // Uniform per-channel bases + 32-bit per-pixel offsets keep address
-        // arithmetic scalar.  Lanes take a 32-wide output row segment when the
-        // element keeps the axes (consecutive lanes read consecutive columns of
-        // the same two staged rows), and an 8 x 8 block when it swaps them
-        // (consecutive lanes would otherwise read the same column of 32
-        // different staged rows, which share few LDS banks).
-        const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(a.out + (size_t)t.img * 3 * plane, (uint32_t)(12 * plane));
-        const __amdgpu_buffer_rsrc_t rm =
-            buffer_rsrc(has_mask ? a.out_mask + (size_t)t.img * plane : a.out_mask, (uint32_t)plane);
-        const int base = t.j0 * OW + t.i0;
-        const uint8_t *st = S.stage[b];
+    const int wlog = mt.part ? log2_of<TS>() - 1 : log2_of<TS>();
+    const int npx = TL << wlog;
+    const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(a.out + (size_t)mt.img * 3 * plane, (uint32_t)(12 * plane));
+    const __amdgpu_buffer_rsrc_t rm =
+        buffer_rsrc(has_mask ? a.out_mask + (size_t)mt.img * plane : a.out_mask, (uint32_t)plane);
+    const int base = mt.j0 * OW + mt.i0;
 #pragma unroll
-        for (int k = 0; k < C::kPix; ++k) {
-            const int p = tid + k * kThreads;
-            int l, si;  // line and span position within the tile
-            if (!t.swap) {
-                l = p / TS;
-                si = p - l * TS;
-            } else {
-                const int lane = p & 63, blk = p >> 6;  // 8 x 8 blocks
-                l = 8 * (blk % (TL / 8)) + (lane & 7);
-                si = 8 * (blk / (TL / 8)) + (lane >> 3);
-            }
-            if (p >= TL * TS || l >= t.nl || si >= t.ns) continue;
-            const int jj = t.swap ? si : l, ii = t.swap ? l : si;
-            const int4 L = S.line[b][l];
-            const int4 Cc = S.col[b][si];
-            const uint32_t q00 = lds_rgb(st, L.x + Cc.x), q01 = lds_rgb(st, L.x + Cc.y);
-            const uint32_t q10 = lds_rgb(st, L.y + Cc.x), q11 = lds_rgb(st, L.y + Cc.y);
-            const int wl1 = L.z, ws1 = Cc.z;
-            int v[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int p00 = S.bclut[b][(q00 >> (8 * c)) & 255], p01 = S.bclut[b][(q01 >> (8 * c)) & 255];
-                const int p10 = S.bclut[b][(q10 >> (8 * c)) & 255], p11 = S.bclut[b][(q11 >> (8 * c)) & 255];
-                // (1024-ws1) p00 + ws1 p01 = 1024 p00 + ws1 (p01 - p00), exactly; same for rows.
-                // Every product has operands below 2^24 in magnitude: full-rate 24-bit multiplies.
-                const int t0 = mad24(ws1, p01 - p00, p00 << kFBits);
-                const int t1 = mad24(ws1, p11 - p10, p10 << kFBits);
-                v[c] = rhe20(mad24(wl1, t1 - t0, t0 << kFBits));
-            }
-            const int off = base + jj * OW + ii;
-            // the b32 store takes the bit pattern: pass the float's bits, not its value
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S.nlut[0][v[0]]), ro, 4 * off, 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S.nlut[1][v[1]]), ro, 4 * (off + (int)plane), 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(S.nlut[2][v[2]]), ro, 4 * (off + 2 * (int)plane), 0,
-                                                  0);
-            if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(st[L.w + Cc.w], rm, off, 0, 0);
+    for (int k = 0; k < kPix; ++k) {
+        const int p = tid + k * NT;
+        if (p >= npx) break;
+        int l, si;  // line and span position within the pass
+        if (!SWAP) {
+            l = p >> wlog;
+            si = p & ((1 << wlog) - 1);
+        } else {
+            const int lane = p & 63, blk = p >> 6;  // 8 x 8 blocks
+            l = 8 * (blk % (TL / 8)) + (lane & 7);
+            si = 8 * (blk / (TL / 8)) + (lane >> 3);
         }
-        return;
-    }
-    // Fallback for spans wider than the staging buffer (source more than 4.6x
-    // the output along the span axis): the same arithmetic on direct loads.
-    const D4Map &m = t.m;
-    const uint8_t *ibase = a.img + a.img_off[t.img];
-    const uint8_t *mbase = has_mask ? a.mask + a.mask_off[t.img] : nullptr;
-#pragma unroll
-    for (int k = 0; k < C::kPix; ++k) {
-        const int p = tid + k * kThreads;
-        const int l = p / TS, si = p - l * TS;
-        if (p >= TL * TS || l >= t.nl || si >= t.ns) continue;
-        const int jj = t.swap ? si : l, ii = t.swap ? l : si;
-        const int32_t ql = S.qline[b][l], qs = S.qspan[b][si];
-        const int wl1 = ql & (kFOne - 1), ws1 = qs & (kFOne - 1);
-        const int x0 = t.ks * clampi(qs >> kFBits, t.Ls) + m.cx, x1 = t.ks * clampi((qs >> kFBits) + 1, t.Ls) + m.cx;
-        const int y0 = t.kl * clampi(ql >> kFBits, t.Ll) + m.cy, y1 = t.kl * clampi((ql >> kFBits) + 1, t.Ll) + m.cy;
-        const uint8_t *r0 = ibase + (size_t)y0 * t.W * 3, *r1 = ibase + (size_t)y1 * t.W * 3;
-        float *o = a.out + (size_t)t.img * 3 * plane + (size_t)(t.j0 + jj) * OW + (t.i0 + ii);
+        if (l >= mt.nl || si >= mt.ns) continue;
+        const int4 L = ln[l];
+        const int4 C = cl[si];
+        const uint32_t ws1 = C.z, ws0 = kFOne - ws1, wl1 = L.z, wl0 = kFOne - wl1;
+        const int o00 = L.x + C.x, o01 = L.x + C.y, o10 = L.y + C.x, o11 = L.y + C.y;
+        const int off = base + (SWAP ? umad24(si, OW, l) : umad24(l, OW, si));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int p00 = S.bclut[b][r0[3 * x0 + c]], p01 = S.bclut[b][r0[3 * x1 + c]];
-            const int p10 = S.bclut[b][r1[3 * x0 + c]], p11 = S.bclut[b][r1[3 * x1 + c]];
+            const uint32_t p00 = bc[st[o00 + c]], p01 = bc[st[o01 + c]];
+            const uint32_t p10 = bc[st[o10 + c]], p11 = bc[st[o11 + c]];
+            const uint32_t t0 = umad24(p01, ws1, __umul24(p00, ws0));
+            const uint32_t t1 = umad24(p11, ws1, __umul24(p10, ws0));
+            const int v = rhe20((int)umad24(t1, wl1, __umul24(t0, wl0)));
+            // the b32 store takes the bit pattern: pass the float's bits, not its value
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(nlut[c][v]), ro, 4 * off, 4 * c * plane, 0);
+        }
+        if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(st[L.w + C.w], rm, off, 0, 0);
+    }
+}
+
+template <int TL, int TS, int NT, int N>
+__device__ __forceinline__ void pass_blend(const miaug_ragged_args &a, const Meta &mt, const uint8_t (&st)[N],
+                                           const int4 *ln, const int4 *cl, const uint8_t *bc,
+                                           const float (&nlut)[3][256]) {
+    if (mt.swap) blend_px<TL, TS, NT, true>(a, mt, st, ln, cl, bc, nlut);
+    else blend_px<TL, TS, NT, false>(a, mt, st, ln, cl, bc, nlut);
+}
+
+// A pass whose footprint does not fit the staging buffer (the source is more
+// than about 4.6 / 9 times the output along the span axis for a whole / half
+// tile): the same arithmetic on direct global loads.
+template <int NT>
+__device__ __forceinline__ void pass_direct(const miaug_ragged_args &a, const Meta &p, const uint8_t *bc,
+                                            const float (&nlut)[3][256]) {
+    const int tid = threadIdx.x;
+    const size_t plane = (size_t)a.out_h * a.out_w;
+    const uint8_t *ib = a.img + p.img_off;
+    const uint8_t *mb = a.mask ? a.mask + p.mask_off : nullptr;
+    for (int e = tid; e < p.nl * p.ns; e += NT) {
+        const int l = e / p.ns, si = e - l * p.ns;
+        const int jj = p.swap ? p.s0 + si : p.l0 + l, ii = p.swap ? p.l0 + l : p.s0 + si;
+        const int32_t ql = resize_q(p.l0 + l, p.Ll, p.OL), qs = resize_q(p.s0 + si, p.Ls, p.OS);
+        const int wl1 = ql & (kFOne - 1), ws1 = qs & (kFOne - 1);
+        const int x0 = p.ks * clampi(qs >> kFBits, p.Ls) + p.cx, x1 = p.ks * clampi((qs >> kFBits) + 1, p.Ls) + p.cx;
+        const int y0 = p.kl * clampi(ql >> kFBits, p.Ll) + p.cy, y1 = p.kl * clampi((ql >> kFBits) + 1, p.Ll) + p.cy;
+        const uint8_t *r0 = ib + (size_t)y0 * p.W * 3, *r1 = ib + (size_t)y1 * p.W * 3;
+        float *o = a.out + (size_t)p.img * 3 * plane + (size_t)jj * a.out_w + ii;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int p00 = bc[r0[3 * x0 + c]], p01 = bc[r0[3 * x1 + c]];
+            const int p10 = bc[r1[3 * x0 + c]], p11 = bc[r1[3 * x1 + c]];
             const int t0 = (p00 << kFBits) + ws1 * (p01 - p00);
             const int t1 = (p10 << kFBits) + ws1 * (p11 - p10);
-            o[c * plane] = S.nlut[c][rhe20((t0 << kFBits) + wl1 * (t1 - t0))];
+            o[c * plane] = nlut[c][rhe20((t0 << kFBits) + wl1 * (t1 - t0))];
         }
-        if (mbase) {
-            const int mx = t.ks * clampi((qs + kFOne / 2) >> kFBits, t.Ls) + m.cx;
-            const int my = t.kl * clampi((ql + kFOne / 2) >> kFBits, t.Ll) + m.cy;
-            a.out_mask[(size_t)t.img * plane + (size_t)(t.j0 + jj) * OW + (t.i0 + ii)] = mbase[(size_t)my * t.W + mx];
+        if (mb) {
+            const int mx = p.ks * clampi((qs + kFOne / 2) >> kFBits, p.Ls) + p.cx;
+            const int my = p.kl * clampi((ql + kFOne / 2) >> kFBits, p.Ll) + p.cy;
+            a.out_mask[(size_t)p.img * plane + (size_t)jj * a.out_w + ii] = mb[(size_t)my * p.W + mx];
         }
     }
 }
 
-// One work item, not pipelined.
-template <int TL, int TS, int NB>
-__device__ __forceinline__ void run_tile(const miaug_ragged_args &a, int img, int tile, Smem<TL, TS, NB> &S,
-                                         int &lut_img) {
-    Tile t = tile_geometry<TL, TS>(a, img, tile);
-    prepare_tile<TL, TS, NB>(a, t, 0, S, lut_img);
-    __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
-    __syncthreads();
-    compute_tile<TL, TS, NB>(a, t, 0, S);
-}
-
-// Work-item queue: images are dealt to 8 queues (image i -> queue i mod 8);
-// pop() hands out (image, tile) items of queue q in order and moves on to the
-// next queue when q is empty.  Returns -1 once all 8 queues are exhausted.
-__device__ __forceinline__ int pop_item(const miaug_ragged_args &a, int *counters, int tiles, int &q, int &tries) {
-    while (tries < kQueues) {
-        const int nq = (a.n - q + kQueues - 1) / kQueues;  // images i with i mod 8 == q
-        const int idx = atomicAdd(&counters[q * kCounterStride], 1);
-        if (idx < nq * tiles) return ((idx / tiles) * kQueues + q) * tiles + idx % tiles;
-        q = (q + 1) % kQueues;
-        ++tries;
+// One work item, its passes one after the other (single staging buffer).
+// One wave plans the pass and builds its tables; after a barrier every wave
+// reads the plan back.
+template <int TL, int TS, int CAP, int N>
+__device__ __forceinline__ void run_item(const miaug_ragged_args &a, int item, int tiles, uint8_t (&st)[N], int4 *ln,
+                                         int4 *cl, int2 *rw, int *meta, uint8_t *bc, int &bc_img,
+                                         const float (&nlut)[3][256], int &planner) {
+    int tile;
+    const int img = udiv_small(item, tiles, tile);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int part = 0;
+    for (;;) {
+        if (wave == (planner++ & 3)) {  // the planning wave rotates, so no SIMD gets all of it
+            const Pass p = plan_pass<TL, TS, CAP>(a, info_scalar(a, img), img, tile, part);
+            pass_tables<TL, TS>(a, p, ln, cl, rw, meta);
+        }
+        __syncthreads();
+        const Meta mt = read_meta(meta);
+        if (!mt.empty) {
+            if (bc_img != mt.img) {
+                build_bc_lut(mt.alpha, mt.beta, bc);
+                bc_img = mt.img;
+            }
+            if (mt.tile == 0 && mt.part <= 1 && a.boxes) ragged_boxes<kThreads>(a, mt.img);
+        }
+        pass_dma<kThreads, CAP>(a, mt, rw, st);
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
+        __syncthreads();
+        if (!mt.empty) {
+            if (mt.staged) pass_blend<TL, TS, kThreads>(a, mt, st, ln, cl, bc, nlut);
+            else pass_direct<kThreads>(a, mt, bc, nlut);
+        }
+        __syncthreads();  // tables and stage are rewritten next
+        if (mt.part != 1) break;
+        part = 2;
     }
-    return -1;
 }
 
-// ---------------------------------------------------------------- register-prefetch pipeline
-// The next tile's source rows are loaded into registers (ordinary 16-byte
-// global loads) while the current tile is blended from LDS; after a barrier
-// the registers are written to the single LDS stage.  Unlike an LDS-DMA into
-// a second buffer, register loads do not make the compiler wait for them
-// before the current tile's LDS reads, so load latency overlaps compute while
-// the workgroup keeps one stage buffer (4 workgroups per CU at 32 x 32).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// Chunked work claiming (thread 0 of a workgroup): one atomic claims K
+// consecutive positions of a queue (position u of queue q is tile u mod tiles
+// of image (u / tiles) * 8 + q), and the atomic for the next chunk is issued
+// as soon as the current one is known, so its latency hides behind a whole
+// chunk of tiles.
+template <int K>
+struct Claimer {
+    int tiles, q, tries, raw;
 
-template <int TL, int TS>
-struct Prefetch {
-    static constexpr int kPer = (2 * TL * Cfg<TL, TS>::kChunks + TL * Cfg<TL, TS>::kMChunks + kThreads - 1) / kThreads;
-    u32x4 v[kPer];
-    int d[kPer];  // LDS byte offset in the stage, -1: nothing
+    __device__ __forceinline__ void issue(int *counters) {
+        if (tries < kQueues) raw = atomicAdd(&counters[q * kCounterStride], K);
+    }
+    // Chunk from the atomic issued last: queue, first position and count
+    // (count 0 once every queue is exhausted).  Exhausted queues are skipped
+    // with further, synchronous atomics.
+    __device__ __forceinline__ int3 resolve(const miaug_ragged_args &a, int *counters) {
+        while (tries < kQueues) {
+            const int total = ((a.n - q + kQueues - 1) / kQueues) * tiles;  // images i with i mod 8 == q
+            if (raw < total) return make_int3(q, raw, min(K, total - raw));
+            q = (q + 1) % kQueues;
+            if (++tries < kQueues) raw = atomicAdd(&counters[q * kCounterStride], K);
+        }
+        return make_int3(0, 0, 0);
+    }
 };
 
-// Resize positions of a tile's lines and span positions into ql / qs, the
-// boxes of the image's first tile.  Readers need a barrier.
-template <int TL, int TS>
-__device__ __forceinline__ void tile_positions(const miaug_ragged_args &a, const Tile &t, int32_t *ql, int32_t *qs) {
-    if (t.empty) return;
-    const int tid = threadIdx.x;
-    const int OL = t.swap ? a.out_w : a.out_h, OS = t.swap ? a.out_h : a.out_w;
-    const int l0 = t.swap ? t.i0 : t.j0, s0 = t.swap ? t.j0 : t.i0;
-    if (tid < t.nl) ql[tid] = resize_q(l0 + tid, t.Ll, OL);
-    if (tid >= 64 && tid - 64 < t.ns) qs[tid - 64] = resize_q(s0 + tid - 64, t.Ls, OS);
-    if (t.tile == 0 && a.boxes) ragged_boxes(a, t.img);
-}
-
-// Source column spans of a tile from its span positions (uniform).
-template <int TL, int TS>
-__device__ __forceinline__ void tile_span(const miaug_ragged_args &a, Tile &t, const int32_t *qs) {
-    using C = Cfg<TL, TS>;
-    if (t.empty) {
-        t.staged = false;
-        return;
-    }
-    const D4Map &m = t.m;
-    const int32_t qs_first = qs[0], qs_last = qs[t.ns - 1];
-    const int dlo = clampi(qs_first >> kFBits, t.Ls), dhi = clampi((qs_last >> kFBits) + 1, t.Ls);
-    const int xa = t.ks * dlo + m.cx, xb = t.ks * dhi + m.cx;
-    t.sxlo = min(xa, xb);
-    t.nsx = abs(xb - xa) + 1;
-    const int nlo = clampi((qs_first + kFOne / 2) >> kFBits, t.Ls), nhi = clampi((qs_last + kFOne / 2) >> kFBits, t.Ls);
-    const int mxa = t.ks * nlo + m.cx, mxb = t.ks * nhi + m.cx;
-    t.mxlo = min(mxa, mxb);
-    t.nmx = abs(mxb - mxa) + 1;
-    t.staged = t.nsx <= C::kMaxSpanPx;
-    t.nchi = (t.nsx * 3 + 30) >> 4;
-    t.nchm = a.mask ? (t.nmx + 30) >> 4 : 0;
-    t.img_items = 2 * t.nl * t.nchi;
-}
-
-// Issues the 16-byte loads of a staged tile into registers (item it -> LDS
-// byte 16*it, the same layout as the DMA path).
-template <int TL, int TS>
-__device__ __forceinline__ void tile_loads(const miaug_ragged_args &a, const Tile &t, const int32_t *ql,
-                                           Prefetch<TL, TS> &pf) {
-    const int tid = threadIdx.x;
-    const bool on = !t.empty && t.staged;
-    const int total = on ? t.img_items + t.nl * t.nchm : 0;
-    const uint32_t inv_i = on ? ((1u << 20) + t.nchi - 1) / t.nchi : 0;
-    const uint32_t inv_m = t.nchm ? ((1u << 20) + t.nchm - 1) / t.nchm : 0;
-    const uint8_t *ibase = a.img + (on ? a.img_off[t.img] : 0);
-    const uint8_t *mbase = (on && a.mask) ? a.mask + a.mask_off[t.img] : nullptr;
-    const D4Map &m = t.m;
-#pragma unroll
-    for (int u = 0; u < Prefetch<TL, TS>::kPer; ++u) {
-        const int it = tid + u * kThreads;
-        pf.d[u] = -1;
-        if (it < total) {
-            const uint8_t *g;
-            int len, ch;
-            if (it < t.img_items) {
-                const int slot = (int)(((uint32_t)it * inv_i) >> 20);
-                ch = it - slot * t.nchi;
-                const int d = clampi((ql[slot >> 1] >> kFBits) + (slot & 1), t.Ll);
-                g = ibase + (uint32_t)(((t.kl * d + m.cy) * t.W + t.sxlo) * 3);
-                len = t.nsx * 3;
-            } else {
-                const int it2 = it - t.img_items, slot = (int)(((uint32_t)it2 * inv_m) >> 20);
-                ch = it2 - slot * t.nchm;
-                const int d = clampi((ql[slot] + kFOne / 2) >> kFBits, t.Ll);
-                g = mbase + (uint32_t)((t.kl * d + m.cy) * t.W + t.mxlo);
-                len = t.nmx;
-            }
-            if (ch < span_chunks(g, len)) {
-                pf.v[u] = *(const u32x4 *)((const uint8_t *)((uintptr_t)g & ~(uintptr_t)15) + 16 * ch);
-                pf.d[u] = 16 * it;
-            }
-        }
-    }
-}
-
-// Writes the prefetched registers to the stage and builds the tile's tables
-// and brightness/contrast LUT.  Readers need a barrier.
-template <int TL, int TS>
-__device__ __forceinline__ void tile_commit(const miaug_ragged_args &a, const Tile &t, const Prefetch<TL, TS> &pf,
-                                            const int32_t *ql, const int32_t *qs, Smem<TL, TS, 1> &S, int &lut_img) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < Prefetch<TL, TS>::kPer; ++u)
-        if (pf.d[u] >= 0) *(u32x4 *)(S.stage[0] + pf.d[u]) = pf.v[u];
-    if (t.empty) return;
-    if (lut_img != t.img) {
-        if (tid < 256) {
-            const double v = (double)a.ab[2 * t.img] * (double)tid + (double)a.ab[2 * t.img + 1];
-            S.bclut[0][tid] = (uint8_t)sat8((int)rint(v));
-        }
-        lut_img = t.img;
-    }
-    // positions for the fallback path, tables for the staged path
-    if (tid < t.nl) S.qline[0][tid] = ql[tid];
-    if (tid >= 64 && tid - 64 < t.ns) S.qspan[0][tid - 64] = qs[tid - 64];
-    if (!t.staged) return;
-    const D4Map &m = t.m;
-    const uint8_t *ibase = a.img + a.img_off[t.img];
-    const uint8_t *mbase = a.mask ? a.mask + a.mask_off[t.img] : nullptr;
-    if (tid < t.nl) {
-        const int q = ql[tid];
-        const int d0 = clampi(q >> kFBits, t.Ll), d1 = clampi((q >> kFBits) + 1, t.Ll);
-        const uint8_t *g0 = ibase + (uint32_t)(((t.kl * d0 + m.cy) * t.W + t.sxlo) * 3);
-        const uint8_t *g1 = ibase + (uint32_t)(((t.kl * d1 + m.cy) * t.W + t.sxlo) * 3);
-        int mb = 0;
-        if (mbase) {
-            const int dn = clampi((q + kFOne / 2) >> kFBits, t.Ll);
-            mb = 16 * (t.img_items + tid * t.nchm) + span_phase(mbase + (uint32_t)((t.kl * dn + m.cy) * t.W + t.mxlo));
-        }
-        S.line[0][tid] = make_int4(16 * (2 * tid) * t.nchi + span_phase(g0),
-                                   16 * (2 * tid + 1) * t.nchi + span_phase(g1), q & (kFOne - 1), mb);
-    }
-    if (tid >= 64 && tid - 64 < t.ns) {
-        const int si = tid - 64, q = qs[si];
-        const int e0 = clampi(q >> kFBits, t.Ls), e1 = clampi((q >> kFBits) + 1, t.Ls);
-        const int en = clampi((q + kFOne / 2) >> kFBits, t.Ls);
-        S.col[0][si] = make_int4(3 * (t.ks * e0 + m.cx - t.sxlo), 3 * (t.ks * e1 + m.cx - t.sxlo),
-                                 q & (kFOne - 1), t.ks * en + m.cx - t.mxlo);
-    }
-}
-
-template <int TL, int TS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_ragged_prefetch(miaug_ragged_args a, int *__restrict__ counters) {
-    __shared__ Smem<TL, TS, 1> S;
-    __shared__ int32_t pql[2][TL], pqs[2][TS];  // positions of the prefetched tile (alternating)
-    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
-    build_norm_lut(a, S);
-    int lut_img = -1;
-    int q = blockIdx.x % kQueues, tries = 0;  // thread 0 only
-    if (threadIdx.x == 0) {
-        S.item[0] = pop_item(a, counters, tiles, q, tries);
-        S.item[1] = pop_item(a, counters, tiles, q, tries);
-    }
-    __syncthreads();
-    int nxt = S.item[0], after = S.item[1];
-    if (nxt < 0) return;
-    Prefetch<TL, TS> pf;
-    Tile tn = tile_geometry<TL, TS>(a, nxt / tiles, nxt % tiles);
-    tile_positions<TL, TS>(a, tn, pql[0], pqs[0]);
-    __syncthreads();
-    tile_span<TL, TS>(a, tn, pqs[0]);
-    tile_loads<TL, TS>(a, tn, pql[0], pf);
-    int pb = 0;      // position buffer of the prefetched tile
-    int slot = 2;    // item ring slot the next pop writes
-    for (;;) {
-        // the prefetched tile becomes current
-        const Tile tc = tn;
-        tile_commit<TL, TS>(a, tc, pf, pql[pb], pqs[pb], S, lut_img);
-        const int cur_next = after;
-        if (cur_next >= 0) {
-            if (threadIdx.x == 0) S.item[slot] = pop_item(a, counters, tiles, q, tries);
-            tn = tile_geometry<TL, TS>(a, cur_next / tiles, cur_next % tiles);
-            tile_positions<TL, TS>(a, tn, pql[pb ^ 1], pqs[pb ^ 1]);
-        }
-        __syncthreads();  // stage, tables, LUT of tc; positions of tn; S.item[slot]
-        if (cur_next >= 0) {
-            after = S.item[slot];
-            slot = (slot + 1) & 3;
-            tile_span<TL, TS>(a, tn, pqs[pb ^ 1]);
-            tile_loads<TL, TS>(a, tn, pql[pb ^ 1], pf);
-        }
-        compute_tile<TL, TS, 1>(a, tc, 0, S);
-        if (cur_next < 0) break;
-        pb ^= 1;
-        __syncthreads();  // every thread is done reading the stage before it is overwritten
-    }
-}
-
-// Persistent form, not pipelined: one item at a time.
-template <int TL, int TS>
+// Persistent form: chunks of K tiles, one pass at a time.
+template <int TL, int TS, int CAP, int K>
 __global__ __launch_bounds__(kThreads) void k_ragged_persistent(miaug_ragged_args a, int *__restrict__ counters) {
-    __shared__ Smem<TL, TS, 1> S;
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[TL];
+    __shared__ int4 cl[TS];
+    __shared__ int2 rw[3 * TL];
+    __shared__ __align__(16) int meta[M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
+    __shared__ int3 chunk_s;
     const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
-    build_norm_lut(a, S);
-    int lut_img = -1;
-    int q = blockIdx.x % kQueues, tries = 0;  // thread 0 only
-    for (;;) {
-        if (threadIdx.x == 0) S.item[0] = pop_item(a, counters, tiles, q, tries);
-        __syncthreads();
-        const int item = S.item[0];
-        if (item < 0) break;
-        run_tile<TL, TS, 1>(a, item / tiles, item % tiles, S, lut_img);
-        __syncthreads();
-    }
-}
-
-// Persistent, software-pipelined form: while tile k is blended from LDS
-// buffer k mod 2, the rows of tile k+1 are already streaming into the other
-// buffer and the index of tile k+2 is being fetched, so the HBM and atomic
-// latencies of one item hide behind the arithmetic of the previous one.
-template <int TL, int TS>
-__global__ __launch_bounds__(kThreads) void k_ragged_pipe(miaug_ragged_args a, int *__restrict__ counters) {
-    __shared__ Smem<TL, TS, 2> S;
-    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
-    build_norm_lut(a, S);
-    int lut0 = -1, lut1 = -1;  // image whose brightness/contrast LUT sits in buffer 0 / 1
-    int q = blockIdx.x % kQueues, tries = 0;  // thread 0 only
+    Claimer<K> C{tiles, (int)(blockIdx.x % kQueues), 0, 0};  // meaningful in thread 0
     if (threadIdx.x == 0) {
-        S.item[0] = pop_item(a, counters, tiles, q, tries);
-        S.item[1] = pop_item(a, counters, tiles, q, tries);
+        C.issue(counters);
+        chunk_s = C.resolve(a, counters);
+        C.issue(counters);  // next chunk, in flight
     }
+    build_norm_lut(a, nlut);
+    int bc_img = -1, planner = 0;
     __syncthreads();
-    int cur = S.item[0], nxt = S.item[1];
-    if (cur < 0) return;
-    Tile tc = tile_geometry<TL, TS>(a, cur / tiles, cur % tiles);
-    prepare_tile<TL, TS, 2>(a, tc, 0, S, lut0);
-    int b = 0;
     for (;;) {
-        __builtin_amdgcn_s_waitcnt(0);  // tile `cur` is in buffer b (LDS-DMA counted by vmcnt)
-        __syncthreads();
-        Tile tn = tc;
-        if (nxt >= 0) {
-            if (threadIdx.x == 0) S.item[2] = pop_item(a, counters, tiles, q, tries);
-            tn = tile_geometry<TL, TS>(a, nxt / tiles, nxt % tiles);
-            int li = b ? lut0 : lut1;
-            prepare_tile<TL, TS, 2>(a, tn, b ^ 1, S, li);  // its barrier publishes S.item[2]
-            if (b) lut0 = li; else lut1 = li;
+        const int cq = __builtin_amdgcn_readfirstlane(chunk_s.x);
+        const int cbase = __builtin_amdgcn_readfirstlane(chunk_s.y);
+        const int cn = __builtin_amdgcn_readfirstlane(chunk_s.z);
+        if (cn == 0) break;
+        for (int t = 0; t < cn; ++t) {
+            const int u = cbase + t;
+            int ut;
+            const int img = udiv_small(u, tiles, ut) * kQueues + cq;
+            run_item<TL, TS, CAP>(a, img * tiles + ut, tiles, st, ln, cl, rw, meta, bc, bc_img, nlut, planner);
         }
-        compute_tile<TL, TS, 2>(a, tc, b, S);
-        if (nxt < 0) break;
-        const int nn = S.item[2];
-        cur = nxt;
-        nxt = nn;
-        tc = tn;
-        b ^= 1;
+        if (threadIdx.x == 0) {  // run_item ended with a barrier: chunk_s is free
+            chunk_s = C.resolve(a, counters);
+            C.issue(counters);
+        }
+        __syncthreads();
     }
 }
 
 // Flat grid: one workgroup per item, XCD-aware: workgroup b runs on XCD b mod 8
 // and takes item b / 8 of queue b mod 8.
-template <int TL, int TS>
+template <int TL, int TS, int CAP>
 __global__ __launch_bounds__(kThreads) void k_ragged_flat(miaug_ragged_args a) {
-    __shared__ Smem<TL, TS, 1> S;
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[TL];
+    __shared__ int4 cl[TS];
+    __shared__ int2 rw[3 * TL];
+    __shared__ __align__(16) int meta[M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
     const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
     const int q = blockIdx.x % kQueues, idx = blockIdx.x / kQueues;
     const int img = (idx / tiles) * kQueues + q;
     if (img >= a.n) return;
-    build_norm_lut(a, S);
-    int lut_img = -1;
-    run_tile<TL, TS, 1>(a, img, idx % tiles, S, lut_img);
+    build_norm_lut(a, nlut);
+    int bc_img = -1;
+    int planner = 0;
+    run_item<TL, TS, CAP>(a, img * tiles + idx % tiles, tiles, st, ln, cl, rw, meta, bc, bc_img, nlut, planner);
 }
 
 // One image per launch (the comparison form): workgroup b = tile b.
-template <int TL, int TS>
+template <int TL, int TS, int CAP>
 __global__ __launch_bounds__(kThreads) void k_ragged_one(miaug_ragged_args a, int img) {
-    __shared__ Smem<TL, TS, 1> S;
-    build_norm_lut(a, S);
-    int lut_img = -1;
-    run_tile<TL, TS, 1>(a, img, blockIdx.x, S, lut_img);
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[TL];
+    __shared__ int4 cl[TS];
+    __shared__ int2 rw[3 * TL];
+    __shared__ __align__(16) int meta[M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
+    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    build_norm_lut(a, nlut);
+    int bc_img = -1;
+    int planner = 0;
+    run_item<TL, TS, CAP>(a, img * tiles + (int)blockIdx.x, tiles, st, ln, cl, rw, meta, bc, bc_img, nlut, planner);
+}
+
+// ---------------------------------------------------------------- streaming pipeline
+// Per-workgroup pass stream, followed by the planner wave.  Its first thread
+// (the owner) keeps items two ahead in a 4-entry ring: when a pass consumes an
+// item it issues the atomic for a later one and only reads the result after
+// the next s_waitcnt vmcnt(0), so the atomic's latency overlaps a whole
+// iteration.
+template <int TL, int TS, int CAP>
+struct Stream {
+    int tiles;
+    int r;                    // ring index of the next item (all threads of the planner wave)
+    int q, tries, raw, slot;  // owner thread: queue state, atomic in flight (slot < 0: none)
+
+    __device__ __forceinline__ void issue(int *counters) {
+        if (tries < kQueues) raw = atomicAdd(&counters[q * kCounterStride], 1);
+    }
+    // Item from the atomic issued last (owner, after its result arrived);
+    // exhausted queues are skipped with further, synchronous atomics.
+    __device__ __forceinline__ int resolve(const miaug_ragged_args &a, int *counters) {
+        while (tries < kQueues) {
+            const int nq = (a.n - q + kQueues - 1) / kQueues;  // images i with i mod 8 == q
+            if (raw < nq * tiles) return ((raw / tiles) * kQueues + q) * tiles + raw % tiles;
+            q = (q + 1) % kQueues;
+            if (++tries < kQueues) raw = atomicAdd(&counters[q * kCounterStride], 1);
+        }
+        return -1;
+    }
+    // Issues the atomic a consumed ring entry asked for (after the table
+    // stage's global loads, so that none of them waits for it).
+    __device__ __forceinline__ void issue_as_owner(int *counters) {
+        if (slot >= 0) issue(counters);
+    }
+    __device__ __forceinline__ void publish_as_owner(const miaug_ragged_args &a, int *counters, int *ring) {
+        if (slot >= 0) {
+            ring[slot] = resolve(a, counters);
+            slot = -1;
+        }
+    }
+    // The pass after `prev` (the last planned pass): its second half, or the
+    // first pass of the next item in the ring.  Every thread of the planner
+    // wave takes the same decision; valid = false at the end of the work.
+    __device__ __forceinline__ bool next_as(const Meta &prev, const int *ring, int &img, int &tile, int &part,
+                                            bool owner) {
+        if (!prev.valid) return false;
+        if (prev.part == 1) {
+            img = prev.img;
+            tile = prev.tile;
+            part = 2;
+            return true;
+        }
+        const int item = __builtin_amdgcn_readfirstlane(ring[r & 3]);
+        if (owner) slot = (r + 2) & 3;  // its atomic is issued by issue_as_owner()
+        ++r;
+        if (item < 0) return false;
+        img = udiv_small(item, tiles, tile);
+        part = 0;
+        return true;
+    }
+};
+
+// Boxes and brightness/contrast LUT of a pass about to be staged, by threads
+// 0..NT-1 (NT >= 256).  Their global loads come before the pass's DMA is
+// issued, so they never wait behind it.
+template <int NT>
+__device__ __forceinline__ void pass_side(const miaug_ragged_args &a, const Meta &m, uint8_t *bc, int &bc_img) {
+    if (!m.valid || m.empty) return;
+    if (m.tile == 0 && m.part <= 1 && a.boxes) ragged_boxes<NT>(a, m.img);
+    if (bc_img != m.img) {
+        if (threadIdx.x < 256) build_bc_lut(m.alpha, m.beta, bc);
+        bc_img = m.img;
+    }
+}
+
+// Streaming pipeline: NC waves stage and blend, one more wave plans.
+// Iteration k (pass P_k in staging buffer k mod 2, table set k mod 3), after
+// a barrier that publishes P_k's DMA, the tables of P_{k+1} and the item ring:
+//   planner wave: decide P_{k+2}, plan it and write its tables (set k+2);
+//                 thread 0 issues the queue atomic for a later item;
+//   other waves:  LUT and boxes of P_{k+1}, DMA of P_{k+1} into the other
+//                 buffer, blend of P_k (its LDS reads touch only variables the
+//                 DMA does not write, so they do not wait for it).
+// Two warm-up passes that do nothing fill the pipeline.
+template <int TL, int TS, int CAP, int NC>
+__global__ __launch_bounds__(64 * (NC + 1)) void k_ragged_stream(miaug_ragged_args a, int *__restrict__ counters) {
+    constexpr int NT = 64 * NC;  // staging and blending threads
+    __shared__ __align__(16) uint8_t st0[stage_bytes(CAP)];  // two distinct variables: see the file comment
+    __shared__ __align__(16) uint8_t st1[stage_bytes(CAP)];
+    __shared__ int4 ln[3][TL];
+    __shared__ int4 cl[3][TS];
+    __shared__ int2 rw[3][3 * TL];
+    __shared__ __align__(16) int meta[3][M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[2][256];
+    __shared__ int ring[4];
+    const int tid = threadIdx.x;
+    const bool planner = __builtin_amdgcn_readfirstlane(tid >> 6) == NC;
+    // The planner's serial chain sets the pace of every iteration: let the
+    // SIMD's arbiter prefer its instructions over the blend waves'.
+    if (planner) __builtin_amdgcn_s_setprio(3);
+    Stream<TL, TS, CAP> S;
+    S.tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    S.r = 0;
+    S.q = blockIdx.x % kQueues;
+    S.tries = 0;
+    S.raw = 0;
+    S.slot = -1;
+    if (tid == NT) {  // thread 0 of the planner wave owns the queue state
+        for (int i = 0; i < 2; ++i) {
+            S.slot = i;
+            S.issue(counters);
+            S.publish_as_owner(a, counters, ring);
+        }
+    }
+    if (tid < 2 * M_N) meta[tid / M_N][tid % M_N] = (tid % M_N == M_VALID || tid % M_N == M_EMPTY) ? 1 : 0;
+    build_norm_lut(a, nlut);
+    int bc_img[2] = {-1, -1};
+    int set = 0, B = 0;
+    int info_img = -1, info_raw = 0;  // planner wave: image whose record is in (or on its way to) info_raw
+    __syncthreads();
+    Meta mnext = read_meta(meta[0]);  // warm-up pass 0
+    for (;;) {
+        __builtin_amdgcn_s_waitcnt(0);  // P_k's LDS-DMA, the stores before it, the owner's atomic
+        if (tid == NT) S.publish_as_owner(a, counters, ring);
+        __syncthreads();
+        const int s1 = set == 2 ? 0 : set + 1, s2 = s1 == 2 ? 0 : s1 + 1;
+        const Meta mk = mnext;  // P_k's plan, read last iteration
+        if (!mk.valid) break;
+        const Meta m1 = read_meta(meta[s1]);
+        mnext = m1;
+        if (planner) {
+            int img2 = 0, tile2 = 0, part2 = 0;
+            const bool v2 = S.next_as(m1, ring, img2, tile2, part2, tid == NT);
+            if (v2 && img2 != info_img) {  // not prefetched: load now
+                info_raw = info_issue(a, img2);
+                info_img = img2;
+            }
+            const ImgInfo in = info_gather(info_raw);
+            Pass p2 = plan_pass<TL, TS, CAP>(a, in, img2, tile2, part2);
+            p2.valid = v2;
+            pass_tables<TL, TS>(a, p2, ln[s2], cl[s2], rw[s2], meta[s2]);
+            // prefetch the image of the next ring entry; it arrives by the next iteration's wait
+            const int nitem = v2 ? __builtin_amdgcn_readfirstlane(ring[S.r & 3]) : -1;
+            if (nitem >= 0) {
+                int t;
+                const int nimg = udiv_small(nitem, S.tiles, t);
+                if (nimg != info_img) {
+                    info_raw = info_issue(a, nimg);
+                    info_img = nimg;
+                }
+            }
+            if (tid == NT) S.issue_as_owner(counters);
+        } else {
+            pass_side<NT>(a, m1, bc[B ^ 1], bc_img[B ^ 1]);
+            if (B == 0) {
+                pass_dma<NT, CAP>(a, m1, rw[s1], st1);
+                if (!mk.empty && mk.staged) pass_blend<TL, TS, NT>(a, mk, st0, ln[set], cl[set], bc[0], nlut);
+            } else {
+                pass_dma<NT, CAP>(a, m1, rw[s1], st0);
+                if (!mk.empty && mk.staged) pass_blend<TL, TS, NT>(a, mk, st1, ln[set], cl[set], bc[1], nlut);
+            }
+            if (!mk.empty && !mk.staged) pass_direct<NT>(a, mk, bc[B], nlut);
+        }
+        set = s1;
+        B ^= 1;
+    }
 }
 
 __global__ void k_zero_counters(int *counters, int n) {
@@ -671,30 +905,37 @@ __global__ void k_zero_counters(int *counters, int n) {
 }
 
 struct Variant {
-    int tl, ts;     // lines x span positions per tile
-    int mode;       // 0 persistent, 1 persistent pipelined (LDS-DMA), 2 flat grid, 3 persistent register prefetch
+    int tl, ts;
+    int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid
     int wg_per_cu;  // workgroups per CU of the persistent modes
+    int chunk;      // tiles claimed per atomic (persistent mode)
     const char *name;
 };
 const Variant kVariants[] = {
-    {32, 32, 3, 4, "tile 32x32, register-prefetch persistent 4 wg/CU"},
-    {32, 32, 0, 4, "tile 32x32, persistent 4 wg/CU"},
-    {32, 32, 2, 0, "tile 32x32, flat grid"},
-    {16, 32, 3, 7, "tile 16x32, register-prefetch persistent 7 wg/CU"},
-    {16, 32, 0, 8, "tile 16x32, persistent 8 wg/CU"},
-    {16, 32, 2, 0, "tile 16x32, flat grid"},
-    {32, 32, 1, 2, "tile 32x32, LDS-DMA double-buffered persistent 2 wg/CU"},
-    {16, 16, 2, 0, "tile 16x16, flat grid"},
+    {32, 32, 1, 4, 1, "tile 32x32, persistent 4 wg/CU, chunks of 1"},
+    {32, 32, 1, 4, 4, "tile 32x32, persistent 4 wg/CU, chunks of 4"},
+    {32, 32, 1, 4, 8, "tile 32x32, persistent 4 wg/CU, chunks of 8"},
+    {16, 32, 1, 8, 8, "tile 16x32, persistent 8 wg/CU, chunks of 8"},
+    {32, 32, 2, 0, 1, "tile 32x32, flat grid"},
+    {32, 32, 0, 2, 1, "tile 32x32, streaming pipeline 8+1 waves, 2 wg/CU"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <int TL, int TS, int K>
+hipError_t launch_chunked(const miaug_ragged_args *a, int grid, int *counters, hipStream_t s) {
+    hipLaunchKernelGGL((k_ragged_persistent<TL, TS, full_cap<TL, TS>(), K>), dim3(grid), dim3(kThreads), 0, s, *a,
+                       counters);
+    return hipGetLastError();
+}
 
 template <int TL, int TS>
 hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLaunch &L, int per_image,
                     hipStream_t s) {
+    constexpr int kFull = full_cap<TL, TS>();
     const int tiles = tiles_per_image<TL, TS>(a->out_h, a->out_w);
     if (per_image) {
         for (int i = 0; i < a->n; ++i) {
-            hipLaunchKernelGGL((k_ragged_one<TL, TS>), dim3(tiles), dim3(kThreads), 0, s, *a, i);
+            hipLaunchKernelGGL((k_ragged_one<TL, TS, kFull>), dim3(tiles), dim3(kThreads), 0, s, *a, i);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -702,7 +943,7 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     }
     if (v.mode == 2) {
         const int per_q = (a->n + kQueues - 1) / kQueues;
-        hipLaunchKernelGGL((k_ragged_flat<TL, TS>), dim3(kQueues * per_q * tiles), dim3(kThreads), 0, s, *a);
+        hipLaunchKernelGGL((k_ragged_flat<TL, TS, kFull>), dim3(kQueues * per_q * tiles), dim3(kThreads), 0, s, *a);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, s, L.counters, kQueues * kCounterStride);
@@ -712,13 +953,13 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     const long items = (long)a->n * tiles;
     if (grid > items) grid = (int)items;
     grid = ((grid + kQueues - 1) / kQueues) * kQueues;
-    if (v.mode == 1)
-        hipLaunchKernelGGL((k_ragged_pipe<TL, TS>), dim3(grid), dim3(kThreads), 0, s, *a, L.counters);
-    else if (v.mode == 3)
-        hipLaunchKernelGGL((k_ragged_prefetch<TL, TS>), dim3(grid), dim3(kThreads), 0, s, *a, L.counters);
-    else
-        hipLaunchKernelGGL((k_ragged_persistent<TL, TS>), dim3(grid), dim3(kThreads), 0, s, *a, L.counters);
-    return hipGetLastError();
+    if (v.mode == 0) {
+        hipLaunchKernelGGL((k_ragged_stream<TL, TS, kFull, 8>), dim3(grid), dim3(64 * 9), 0, s, *a, L.counters);
+        return hipGetLastError();
+    }
+    if (v.chunk >= 8) return launch_chunked<TL, TS, 8>(a, grid, L.counters, s);
+    if (v.chunk >= 4) return launch_chunked<TL, TS, 4>(a, grid, L.counters, s);
+    return launch_chunked<TL, TS, 1>(a, grid, L.counters, s);
 }
 
 }  // namespace
@@ -731,7 +972,6 @@ hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int 
     if (a->n == 0) return hipSuccess;
     const Variant &v = kVariants[(L.variant >= 0 && L.variant < kNumVariants) ? L.variant : 0];
     if (v.tl == 32) return launch_t<32, 32>(a, v, L, per_image, s);
-    if (v.ts == 16) return launch_t<16, 16>(a, v, L, per_image, s);
     return launch_t<16, 32>(a, v, L, per_image, s);
 }
 

@@ -25,7 +25,7 @@ def ctx(m):
 
 SMALL_SIZES = [(1, 1), (1, 300), (300, 1), (2, 3), (128, 1024), (1024, 128), (224, 224), (223, 225), (57, 91),
                (449, 448), (1000, 999), (150, 700), (31, 17), (640, 480), (333, 77), (96, 96), (512, 900),
-               (129, 130), (7, 400), (260, 261)]
+               (129, 130), (7, 400), (260, 261), (40, 2500), (2500, 40)]
 
 
 def oracle_image(b, i, flags, ab, OH=224, OW=224):
@@ -56,6 +56,8 @@ def small(m):
 
 @pytest.mark.parametrize("variant", range(8))
 def test_small_ragged_all_variants_bit_exact(m, ctx, small, variant):
+    if variant >= len(m.ragged_variants()):
+        pytest.skip("the library has fewer variants")
     b, flags, ab = small
     ctx.set_variant(variant)
     r = m.Ragged.from_host(b, flags, ab)
