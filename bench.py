@@ -19,6 +19,7 @@ the oracle's CPU throughput on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +42,30 @@ def parse():
     p.add_argument("--variant", type=int, default=-1,
                    help="ragged launch variant; -1 runs the autotuner (outside the timed region)")
     return p.parse_args()
+
+
+def profiled_traffic(profile: str, variant_name: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary of
+    a kernel, or None when the kernel source or the launch variant has changed
+    since the counters were taken."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", profile)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1809_06839_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("k_ragged.hip", "dev_common.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    if fields.get("kernel_source_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    if fields.get("variant", "").strip() != variant_name:
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"].split()[0])
+    except (KeyError, ValueError):
+        return None
 
 
 def resize_rows_touched(L: int, out: int = 224) -> int:
@@ -155,7 +180,8 @@ def bench_ragged(args, torch, m):
         "per_image_launches": {"value": n / (ms_pi * 1e-3), "unit": "images/s", "ms_per_step": ms_pi,
                                "batched_speedup": ms_pi / ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic("k_ragged_persistent_2048img_ragged_to_224_f32.md", variants[variant]),
                      "kernel": "k_ragged_persistent", "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:

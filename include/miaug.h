@@ -179,9 +179,9 @@ typedef struct {
     int32_t out_h, out_w;    /* output size, 1..4096                               */
     const uint8_t *img;      /* device: packed HWC u8 images                       */
     const int64_t *img_off;  /* device: [n] byte offset of image i in img          */
-    const int32_t *hw;       /* device: [n][2] = {H_i, W_i}, H_i W_i 3 < 2^31; an
-                                image outside that range is skipped (outputs
-                                left untouched)                                   */
+    const int32_t *hw;       /* device: [n][2] = {H_i, W_i}; an image with a side
+                                < 1 or >= 2^20, or H_i W_i 3 >= 2^31, is skipped
+                                (its outputs are left untouched)                  */
     const int32_t *flags;    /* device: [n][4] Dih4 flags (miaug_sample_d4bc)      */
     const float *ab;         /* device: [n][2] alpha, beta                         */
     const uint8_t *mask;     /* device or NULL: packed HW u8 masks                 */
@@ -215,14 +215,14 @@ int miaug_graph_launch(miaug_graph *g, void *stream);
 int miaug_graph_destroy(miaug_graph *g);
 
 /* Autotuner for the batched form: times each launch variant (output tile
- * shape, plain or software-pipelined persistent loop or flat grid,
- * workgroups per CU) on `args` `reps` times, keeps only variants whose output
- * is bit-identical to the per-image form, and stores the fastest in the
- * context (used by later miaug_ragged_apply calls).  Writes the chosen
- * variant index to *chosen, its mean time in ms to *ms and, when `times` is
- * not NULL, every variant's mean time to times[0 .. variant_count-1] (-1 for
- * a variant that failed the parity gate).  Synchronises `stream`.
- * `args->out*` are overwritten. */
+ * shape; persistent loop claiming 1, 4 or 8 tiles per atomic, flat grid, or
+ * the streaming pipeline with a planner wave; workgroups per CU) on `args`
+ * `reps` times, keeps only variants whose output is bit-identical to the
+ * per-image form, and stores the fastest in the context (used by later
+ * miaug_ragged_apply calls).  Writes the chosen variant index to *chosen, its
+ * mean time in ms to *ms and, when `times` is not NULL, every variant's mean
+ * time to times[0 .. variant_count-1] (-1 for a variant that failed the
+ * parity gate).  Synchronises `stream`.  `args->out*` are overwritten. */
 int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *args, int reps, void *stream, int *chosen,
                           float *ms, float *times);
 /* Number of variants and a variant's description ("tile 32x32, 4 wg/CU"). */
@@ -235,7 +235,8 @@ int miaug_ragged_set_variant(miaug_ctx *ctx, int v);
  * Float32 form for training-time augmentation with gradients.  Per image i
  * and channel c, with p_i = {angle_deg, scale, tx, ty, alpha, beta, gamma}:
  *   (sx, sy) = inverse of the shift-scale-rotate map above (tx, ty are
- *   fractions of W, H) evaluated in float at output pixel (x, y);
+ *   fractions of W, H) evaluated in double at output pixel (x, y), its
+ *   fractional parts rounded to float for the bilinear weights;
  *   w = bilinear(x_i[c], sx, sy), taps outside the image read 0;
  *   z = alpha w + beta; y1 = clamp(z, 0, 1); y = y1^gamma (0^gamma = 0).
  *   x, y: device float [n][C][H][W]; params: device float [n][7].
