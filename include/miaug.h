@@ -315,6 +315,156 @@ int miaug_elastic_grid_f32_bwd(const float *gy, int n, int C, int H, int W, cons
 int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_t *sum, int32_t *mn,
                          int32_t *mx, uint32_t *hist, void *stream);
 
+/* ---------------------------------------------------------------- op-list pipelines
+ * The paper's usage pattern (Sec. I; Sec. II and the listings of its
+ * figures): a user lists transforms, each applied with its own probability
+ * and a parameter drawn from a range, and applies the composition to an image
+ * together with its masks and boxes.  A pipeline compiles such a list, by
+ * pattern, onto one of the fused chains above (brackets: optional; the ops
+ * must come in this order):
+ *   MIAUG_PIPE_DIH4      [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
+ *                        dense u8 images (and masks) -> u8, miaug_d4_bc_u8
+ *   MIAUG_PIPE_RAGGED    [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
+ *                        RESIZE [NORMALIZE]
+ *                        ragged RGB u8 + masks + boxes -> f32 NCHW, miaug_ragged_apply
+ *   MIAUG_PIPE_U8CHAIN   [SSR] CROP RESIZE [HSV] [GAMMA] [BLUR3]
+ *                        dense RGB u8 -> u8 (square crop and output),
+ *                        miaug_ssr_crop_resize_hsv_gamma_blur_u8
+ *   MIAUG_PIPE_DISTORT   ELASTIC [GRID] | GRID
+ *                        dense u8 images (and masks) -> u8, miaug_elastic_grid_u8
+ * Any other list is rejected with MIAUG_EUNSUPPORTED and a message naming
+ * the first op that does not fit.
+ *
+ * Op fields (p is the probability of applying the op; a skipped op takes
+ * its identity parameters):
+ *   HFLIP, VFLIP, TRANSPOSE   p.
+ *   ROT90             p; k uniform in {lo[0] .. hi[0]} (integers in 0..3).
+ *   BRIGHT_CONTRAST   p; alpha in [lo[0], hi[0]], beta in [lo[1], hi[1]]
+ *                     (pixel units); skipped: (1, 0).
+ *   SSR               p; angle_deg in [lo[0], hi[0]], scale in [lo[1], hi[1]],
+ *                     dx, dy in [lo[2], hi[2]], [lo[3], hi[3]] (fractions of
+ *                     W, H); bilinear, reflect-101 only; skipped: identity.
+ *   CROP              out_h x out_w window at offsets uniform in
+ *                     {0 .. H - out_h} x {0 .. W - out_w}; p must be 1.
+ *   RESIZE            to out_h x out_w; bilinear (masks: nearest).
+ *   HSV               p; dh = rint(U[lo[0], hi[0]]) (2-degree units),
+ *                     ds = rint(U[lo[1], hi[1]]), dv = rint(U[lo[2], hi[2]]).
+ *   GAMMA             p; gamma in [lo[0], hi[0]]; skipped: 1.
+ *   BLUR3             p (3x3 binomial).
+ *   ELASTIC           alpha = lo[0] (pixels, integer 0..65535), sigma = lo[1],
+ *                     radius = lo[2] (0: ceil(3 sigma), at most 200); p must be 1.
+ *   GRID              p; 5 cells per axis, factors 1 + U[-lo[0], lo[0]]
+ *                     (0 <= lo[0] < 1); skipped: all 1.
+ *   NORMALIZE         mean = lo[0..2], std = hi[0..2]; p must be 1.
+ * Draws: op number j of the list uses Philox draws 16 j (its Bernoulli gate,
+ * only when p < 1) and 16 j + 1, 16 j + 2, ... (its parameters, in the order
+ * listed above), with the generator of the sampler section. */
+enum {
+    MIAUG_OP_HFLIP = 1, MIAUG_OP_VFLIP = 2, MIAUG_OP_ROT90 = 3, MIAUG_OP_TRANSPOSE = 4, MIAUG_OP_SSR = 5,
+    MIAUG_OP_CROP = 6, MIAUG_OP_RESIZE = 7, MIAUG_OP_BRIGHT_CONTRAST = 8, MIAUG_OP_HSV = 9, MIAUG_OP_GAMMA = 10,
+    MIAUG_OP_BLUR3 = 11, MIAUG_OP_BLUR5 = 12, MIAUG_OP_ELASTIC = 13, MIAUG_OP_GRID = 14, MIAUG_OP_NORMALIZE = 15
+};
+enum { MIAUG_INTERP_BILINEAR = 0, MIAUG_INTERP_NEAREST = 1 };
+enum { MIAUG_BORDER_REFLECT101 = 0, MIAUG_BORDER_CONSTANT = 1 };
+enum { MIAUG_PIPE_DIH4 = 1, MIAUG_PIPE_RAGGED = 2, MIAUG_PIPE_U8CHAIN = 3, MIAUG_PIPE_DISTORT = 4 };
+
+typedef struct {
+    uint32_t kind;         /* MIAUG_OP_*                                          */
+    float p;               /* probability of applying the op                     */
+    float lo[4], hi[4];    /* parameter ranges (see above)                        */
+    uint32_t interp;       /* MIAUG_INTERP_*                                      */
+    uint32_t border;       /* MIAUG_BORDER_*                                      */
+    int32_t out_h, out_w;  /* CROP, RESIZE                                        */
+} miaug_op;
+
+/* Per-sample parameters (host record; what miaug_sample writes and
+ * miaug_apply consumes).  Fields an op list does not use keep identity
+ * values. */
+typedef struct {
+    uint64_t seed, index;           /* generator key and global sample index     */
+    int32_t flags[4];               /* hflip, vflip, rot90 k, transpose          */
+    float alpha, beta;              /* brightness/contrast                       */
+    float angle, scale, dx, dy;     /* shift-scale-rotate                        */
+    int32_t crop_x, crop_y;         /* crop offsets                              */
+    int32_t dh, ds, dv;             /* HSV shifts                                */
+    float gamma;                    /* gamma                                     */
+    int32_t blur;                   /* 3x3 blur flag                             */
+    int32_t pad;
+    double grid[10];                /* grid factors: x d_0..d_4, y d_0..d_4      */
+} miaug_params;
+
+typedef struct miaug_pipeline miaug_pipeline;
+/* Compiles `ops` (host array, copied).  ctx may be NULL for a pipeline that
+ * only samples.  Errors: EINVAL (NULL out, n_ops < 1, bad field values),
+ * EUNSUPPORTED (list fits no chain). */
+int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_pipeline **out);
+/* Frees the pipeline and its device buffers (synchronises the device). */
+int miaug_pipeline_destroy(miaug_pipeline *p);
+/* MIAUG_PIPE_* of a pipeline (or a negative status). */
+int miaug_pipeline_kind(const miaug_pipeline *p);
+/* Bytes of n parameter records: n * sizeof(miaug_params). */
+size_t miaug_param_bytes(const miaug_pipeline *p, int n);
+/* Draws the records of samples first_index .. first_index + n - 1.
+ *   hw  host int32 [n][2] source sizes (needed when the list has CROP; may be
+ *       NULL otherwise); params host [n] records (written).  Host only. */
+int miaug_sample(const miaug_pipeline *p, uint64_t seed, uint64_t first_index, int n, const int32_t *hw,
+                 miaug_params *params);
+
+/* A batch.  Dense pipelines (DIH4, U8CHAIN, DISTORT) read img as
+ * [n][H][W][channels] (mask [n][H][W]); the ragged pipeline reads the packed
+ * layout of miaug_ragged_args (img_off, hw, mask_off, box_off device arrays,
+ * channels = 3).  All pointers are device pointers. */
+typedef struct {
+    int32_t n, channels, H, W;
+    const uint8_t *img;
+    const int64_t *img_off;
+    const int32_t *hw;
+    const uint8_t *mask;      /* NULL: no masks                                   */
+    const int64_t *mask_off;
+    const float *boxes;       /* NULL: no boxes (ragged pipeline only)            */
+    const int32_t *box_off;
+} miaug_batch_in;
+/* Outputs (device): img u8 like the input (DIH4: image i keeps its byte range,
+ * with shape (W, H) when its element swaps axes; DISTORT: same shape), u8
+ * [n][s][s][3] (U8CHAIN, s = RESIZE size) or float32 [n][3][out_h][out_w]
+ * (RAGGED); mask and boxes as the chains above. */
+typedef struct {
+    void *img;
+    uint8_t *mask;
+    float *boxes;
+} miaug_batch_out;
+
+/* Applies the pipeline with host records `params` [in->n] (copied to the
+ * device through a pinned staging buffer owned by the pipeline; the call
+ * waits for the previous call's copy before reusing it).  Device buffers of
+ * the chain (parameter records, elastic fields and tables) are allocated on
+ * first use and grown when a larger batch comes.  Errors: EINVAL, ESHAPE,
+ * EUNSUPPORTED (mask or boxes the chain cannot take, records of a DISTORT
+ * batch that are not consecutive samples of one seed), EDEVICE. */
+int miaug_apply(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *params, miaug_batch_out *out,
+                void *stream);
+/* Comparison form: one launch per image; identical output. */
+int miaug_apply_per_image(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *params,
+                          miaug_batch_out *out, void *stream);
+
+/* hipGraph of miaug_apply for a fixed batch and outputs: the graph copies the
+ * records from its own pinned buffer, so each launch takes new records.
+ * miaug_pipeline_graph_launch waits for the previous launch's copy, fills
+ * the buffer from `params` and replays the graph on `stream`.  A DISTORT
+ * pipeline with ELASTIC is not capturable (EUNSUPPORTED): its noise stream is
+ * a launch argument. */
+typedef struct miaug_pipeline_graph miaug_pipeline_graph;
+int miaug_pipeline_graph_capture(miaug_pipeline *p, const miaug_batch_in *in, const miaug_batch_out *out,
+                                 void *stream, miaug_pipeline_graph **g);
+int miaug_pipeline_graph_launch(miaug_pipeline_graph *g, const miaug_params *params, void *stream);
+int miaug_pipeline_graph_destroy(miaug_pipeline_graph *g);
+
+/* Tunes the launch of the pipeline's chain on this batch (the ragged
+ * autotuner for MIAUG_PIPE_RAGGED; other chains have one launch form and
+ * return at once).  Overwrites the outputs; synchronises `stream`. */
+int miaug_pipeline_autotune(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *params,
+                            miaug_batch_out *out, int reps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,35 @@ class C2Record(ctypes.Structure):
                 ("gamma_lut", ctypes.c_uint8 * 256)]
 
 
+class Op(ctypes.Structure):
+    """Mirror of miaug_op (include/miaug.h)."""
+    _fields_ = [("kind", ctypes.c_uint32), ("p", ctypes.c_float), ("lo", ctypes.c_float * 4),
+                ("hi", ctypes.c_float * 4), ("interp", ctypes.c_uint32), ("border", ctypes.c_uint32),
+                ("out_h", ctypes.c_int32), ("out_w", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    """Mirror of miaug_params (include/miaug.h): one sample's parameters."""
+    _fields_ = [("seed", ctypes.c_uint64), ("index", ctypes.c_uint64), ("flags", ctypes.c_int32 * 4),
+                ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("angle", ctypes.c_float),
+                ("scale", ctypes.c_float), ("dx", ctypes.c_float), ("dy", ctypes.c_float),
+                ("crop_x", ctypes.c_int32), ("crop_y", ctypes.c_int32), ("dh", ctypes.c_int32),
+                ("ds", ctypes.c_int32), ("dv", ctypes.c_int32), ("gamma", ctypes.c_float),
+                ("blur", ctypes.c_int32), ("pad", ctypes.c_int32), ("grid", ctypes.c_double * 10)]
+
+
+class BatchIn(ctypes.Structure):
+    """Mirror of miaug_batch_in (include/miaug.h)."""
+    _fields_ = [("n", ctypes.c_int32), ("channels", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("img", _vp), ("img_off", _vp), ("hw", _vp), ("mask", _vp), ("mask_off", _vp), ("boxes", _vp),
+                ("box_off", _vp)]
+
+
+class BatchOut(ctypes.Structure):
+    """Mirror of miaug_batch_out (include/miaug.h)."""
+    _fields_ = [("img", _vp), ("mask", _vp), ("boxes", _vp)]
+
+
 _SIGS = {
     "miaug_compile_c2": (_i, [_vp, _vp, _i, _i, _i, _i, _vp]),
     "miaug_version": (_i, []),
@@ -84,6 +113,18 @@ _SIGS = {
     "miaug_elastic_grid_f32_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "miaug_elastic_grid_f32_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "miaug_image_stats_u8": (_i, [_vp, _i, _i64, _i, _vp, _vp, _vp, _vp, _vp]),
+    "miaug_pipeline_create": (_i, [_vp, ctypes.POINTER(Op), _i, ctypes.POINTER(_vp)]),
+    "miaug_pipeline_destroy": (_i, [_vp]),
+    "miaug_pipeline_kind": (_i, [_vp]),
+    "miaug_param_bytes": (_sz, [_vp, _i]),
+    "miaug_sample": (_i, [_vp, _u64, _u64, _i, _vp, _vp]),
+    "miaug_apply": (_i, [_vp, ctypes.POINTER(BatchIn), _vp, ctypes.POINTER(BatchOut), _vp]),
+    "miaug_apply_per_image": (_i, [_vp, ctypes.POINTER(BatchIn), _vp, ctypes.POINTER(BatchOut), _vp]),
+    "miaug_pipeline_graph_capture": (_i, [_vp, ctypes.POINTER(BatchIn), ctypes.POINTER(BatchOut), _vp,
+                                          ctypes.POINTER(_vp)]),
+    "miaug_pipeline_graph_launch": (_i, [_vp, _vp, _vp]),
+    "miaug_pipeline_graph_destroy": (_i, [_vp]),
+    "miaug_pipeline_autotune": (_i, [_vp, ctypes.POINTER(BatchIn), _vp, ctypes.POINTER(BatchOut), _i, _vp]),
 }
 
 _lib = None
@@ -444,3 +485,119 @@ def image_stats_u8(img, C=None, stream=None):
     h = torch.empty((n, C, 256), dtype=torch.int32, device=dev)
     _check(lib().miaug_image_stats_u8(_p(img), n, npix, C, _p(s), _p(mn), _p(mx), _p(h), _stream(stream)))
     return s, mn, mx, h
+
+
+# ---------------------------------------------------------------- op-list pipelines
+OP = {"HFLIP": 1, "VFLIP": 2, "ROT90": 3, "TRANSPOSE": 4, "SSR": 5, "CROP": 6, "RESIZE": 7, "BRIGHT_CONTRAST": 8,
+      "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15}
+PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT"}
+INTERP_BILINEAR, INTERP_NEAREST = 0, 1
+BORDER_REFLECT101, BORDER_CONSTANT = 0, 1
+
+
+def op(kind, p=1.0, lo=(0, 0, 0, 0), hi=(0, 0, 0, 0), interp=INTERP_BILINEAR, border=BORDER_REFLECT101,
+       out=(0, 0)):
+    """One miaug_op; `kind` is a name of OP or its value; lo, hi take up to 4 values."""
+    o = Op()
+    o.kind = OP[kind] if isinstance(kind, str) else int(kind)
+    o.p = p
+    lo = list(lo) + [0] * (4 - len(lo))
+    hi = list(hi) + [0] * (4 - len(hi))
+    for i in range(4):
+        o.lo[i] = lo[i]
+        o.hi[i] = hi[i]
+    o.interp, o.border = interp, border
+    o.out_h, o.out_w = out
+    return o
+
+
+class Pipeline:
+    """An op list compiled onto one fused chain (miaug_pipeline_create)."""
+
+    def __init__(self, ctx, ops):
+        self.ops = (Op * len(ops))(*ops)
+        h = _vp()
+        _check(lib().miaug_pipeline_create(ctx.handle if ctx is not None else None, self.ops, len(ops),
+                                           ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def kind(self):
+        return PIPE[lib().miaug_pipeline_kind(self.handle)]
+
+    def sample(self, seed, first, n, hw=None):
+        """n parameter records (a ctypes array of Params); hw: host int32 [n, 2] when the list has CROP."""
+        recs = (Params * max(n, 1))()
+        hwa = None if hw is None else np.ascontiguousarray(hw, dtype=np.int32)
+        _check(lib().miaug_sample(self.handle, seed, first, n, None if hwa is None else hwa.ctypes.data,
+                                  ctypes.byref(recs)))
+        return recs
+
+    @staticmethod
+    def batch(img=None, mask=None, ragged=None):
+        """miaug_batch_in / miaug_batch_out for a dense batch (img [n, H, W, C] u8, mask [n, H, W] u8) or a
+        Ragged (its packed inputs and outputs).  Returns (batch_in, batch_out, outputs)."""
+        bi, bo = BatchIn(), BatchOut()
+        if ragged is not None:
+            a = ragged.args
+            bi.n, bi.channels, bi.H, bi.W = a.n, 3, 0, 0
+            bi.img, bi.img_off, bi.hw = a.img, a.img_off, a.hw
+            bi.mask, bi.mask_off, bi.boxes, bi.box_off = a.mask, a.mask_off, a.boxes, a.box_off
+            bo.img, bo.mask, bo.boxes = a.out, a.out_mask, a.out_boxes
+            return bi, bo, ragged
+        _dev(img, torch.uint8, "img")
+        n, H, W = img.shape[:3]
+        bi.n, bi.channels, bi.H, bi.W = n, (img.shape[3] if img.dim() == 4 else 1), H, W
+        bi.img = img.data_ptr()
+        if mask is not None:
+            _dev(mask, torch.uint8, "mask")
+            bi.mask = mask.data_ptr()
+        return bi, bo, None
+
+    def apply(self, bi, bo, params, stream=None, per_image=False):
+        f = lib().miaug_apply_per_image if per_image else lib().miaug_apply
+        _check(f(self.handle, ctypes.byref(bi), ctypes.byref(params), ctypes.byref(bo), _stream(stream)))
+
+    def autotune(self, bi, bo, params, reps=3, stream=None):
+        _check(lib().miaug_pipeline_autotune(self.handle, ctypes.byref(bi), ctypes.byref(params), ctypes.byref(bo),
+                                             reps, _stream(stream)))
+
+    def graph(self, bi, bo, stream):
+        return PipelineGraph(self, bi, bo, stream)
+
+    def close(self):
+        if self.handle:
+            lib().miaug_pipeline_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PipelineGraph:
+    """miaug_pipeline_graph: a captured pipeline launch that takes new records at every replay."""
+
+    def __init__(self, pipe, bi, bo, stream):
+        self.pipe = pipe
+        h = _vp()
+        _check(lib().miaug_pipeline_graph_capture(pipe.handle, ctypes.byref(bi), ctypes.byref(bo),
+                                                  ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, params, stream):
+        _check(lib().miaug_pipeline_graph_launch(self.handle, ctypes.byref(params),
+                                                 ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self.handle:
+            lib().miaug_pipeline_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

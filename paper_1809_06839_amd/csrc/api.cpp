@@ -24,6 +24,8 @@ int set_error(int status, const char *fmt, ...) {
     return status;
 }
 
+void clear_error() { g_err[0] = 0; }
+
 int hip_status(hipError_t e, const char *what) {
     if (e == hipSuccess) return MIAUG_OK;
     return set_error(e == hipErrorOutOfMemory ? MIAUG_ENOMEM : MIAUG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -32,13 +34,6 @@ int hip_status(hipError_t e, const char *what) {
 }  // namespace miaug
 
 using namespace miaug;
-
-struct miaug_ctx {
-    int device;
-    int num_cu;
-    int variant;
-    int *counters;  // device, 256 ints
-};
 
 struct miaug_graph {
     hipGraph_t graph;

@@ -7,10 +7,19 @@
 
 #include "../../include/miaug.h"
 
+struct miaug_ctx {
+    int device;
+    int num_cu;
+    int variant;
+    int *counters;  // device, 256 ints
+};
+
 namespace miaug {
 
 // Records a formatted message as the calling thread's last error; returns status.
 int set_error(int status, const char *fmt, ...);
+// Clears the calling thread's last error (start of every entry point).
+void clear_error();
 // Maps a HIP error to MIAUG_EDEVICE with context text (MIAUG_OK on success).
 int hip_status(hipError_t e, const char *what);
 
@@ -41,6 +50,7 @@ hipError_t launch_wc_bwd(const float *x, int n, int C, int H, int W, const float
 size_t elastic_workspace_bytes(int n, int H, int W);
 hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
                                  int radius, int32_t *off, void *ws, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, hipStream_t s);
 hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
                                   const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,

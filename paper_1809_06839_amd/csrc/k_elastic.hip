@@ -318,6 +318,10 @@ __global__ void k_chain_f_grid(const float *__restrict__ e, int C, int H, int W,
     }
 }
 
+__global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_fill_zero(float *__restrict__ p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
@@ -438,6 +442,13 @@ hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, con
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_chain_f_elastic_adj, grid, dim3(256), 0, s, ge, C, H, W, off, gx);
+    return hipGetLastError();
+}
+
+// Fill of n 32-bit words with v (a kernel, so it can sit in a captured graph).
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
