@@ -3,15 +3,6 @@
 // -> gamma LUT -> 3x3 binomial blur (Table I ShiftScaleRotate, RandomCrop64,
 // ShiftHSV, Gamma; Sec. II colour transforms).
 //
-// One workgroup per (image, T x T output tile).  The blur needs the pre-blur
-// values of a 1-pixel halo, and the resize needs two warp samples per output
-// line along each axis, so the tile evaluates, in LDS:
-//   1. the resize positions of its (T+2) rows and columns (halo rows/columns
-//      reflected at the image border, as the blur reads them);
-//   2. the warp samples on the grid of the 2(T+2) x 2(T+2) crop lines those
-//      positions touch (each sample: Q32 affine position -> 4 taps -> u8);
-//   3. the (T+2)^2 pre-blur pixels: resize blend -> u8 -> HSV8 -> gamma LUT;
-//   4. the output: 3x3 blur (or copy) written as aligned dwords.
 // Every intermediate is rounded exactly as the sequential definition rounds
 // it; only the order of evaluation differs.
 #include "dev_common.h"
@@ -103,12 +94,51 @@ __device__ __forceinline__ uint32_t hsv_shift(uint32_t rgb, int dh, int ds, int 
     return o0 | (o1 << 8) | (o2 << 16);
 }
 
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+constexpr int kStageMax = 40 * 1024;  // bytes of staged source per tile
+constexpr int kMaxRows = 160;          // staged source rows per tile
+
+// Three bytes of a staged pixel at LDS byte offset o (any alignment).
+__device__ __forceinline__ uint32_t lds_rgb(const uint8_t *st, int o) {
+    const uint32_t *w = (const uint32_t *)(st + (o & ~3));
+    return __builtin_amdgcn_alignbyte(w[1], w[0], o & 3);
+}
+
+// Bilinear blend of four packed RGB taps with Q10 weights, one rounding.
+__device__ __forceinline__ uint32_t blend4(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, int ax, int ay) {
+    uint32_t out = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a00 = (p00 >> (8 * c)) & 255, a01 = (p01 >> (8 * c)) & 255;
+        const int a10 = (p10 >> (8 * c)) & 255, a11 = (p11 >> (8 * c)) & 255;
+        const int t0 = (a00 << kFBits) + ax * (a01 - a00);
+        const int t1 = (a10 << kFBits) + ax * (a11 - a10);
+        const int acc = (t0 << kFBits) + ay * (t1 - t0);
+        out |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
+    }
+    return out;
+}
+
+// One workgroup per (image, T x T output tile):
+//  1. resize positions of the (T+2) pre-blur rows and columns, and the affine
+//     terms of the crop lines their taps touch (a1 Y + a2, a0 X, ... in Q32);
+//  2. the source bounding box of every warp tap of the tile (the map is
+//     affine, so its extremes are at the corners of the crop-line ranges);
+//     when the box lies inside the image (no reflection needed) and fits,
+//     its rows are staged into LDS with 16-byte DMA loads;
+//  3. each pre-blur pixel evaluates its 2 x 2 warp samples (taps from LDS, or
+//     from global memory with reflect-101 for tiles near the border), the
+//     resize blend, the HSV shift and the gamma LUT;
+//  4. the output: 3x3 blur (or copy) written as aligned dwords.
 __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in, int H, int W,
                                                  const miaug_c2_record *__restrict__ recs, int crop, int outsz,
                                                  uint8_t *__restrict__ out) {
-    __shared__ uint32_t grid[kG][kG];
+    __shared__ __align__(16) uint8_t stage[kStageMax + 16];
     __shared__ uint32_t pre[kP][kP];
     __shared__ int32_t rq[kP], cq[kP];
+    __shared__ int64_t tyx[kG], tyy[kG], txx[kG], txy[kG];  // affine terms of crop rows / columns
+    __shared__ int32_t rowoff[kMaxRows];                       // LDS offset of staged row r's first pixel
+    __shared__ int32_t box[6];                                 // bx, by, bw, bh, nch, staged
     __shared__ uint8_t lut[256];
 
     const int img = blockIdx.y, tid = threadIdx.x;
@@ -117,41 +147,102 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
     const int y0 = (blockIdx.x / tiles_x) * kT, x0 = (blockIdx.x % tiles_x) * kT;
     const int th = min(kT, outsz - y0), tw = min(kT, outsz - x0);
     const uint8_t *src = in + (size_t)img * H * W * 3;
+    const int gh = 2 * (th + 2), gw = 2 * (tw + 2);
 
     lut[tid] = R.gamma_lut[tid];
     if (tid < th + 2) rq[tid] = resize_q(reflect101(y0 - 1 + tid, outsz), crop, outsz);
     if (tid >= 64 && tid - 64 < tw + 2) cq[tid - 64] = resize_q(reflect101(x0 - 1 + tid - 64, outsz), crop, outsz);
     __syncthreads();
-
-    // warp samples on the crop lines the resize taps touch
     const int64_t a0 = R.aq[0], a1 = R.aq[1], a2 = R.aq[2], a3 = R.aq[3], a4 = R.aq[4], a5 = R.aq[5];
-    const int gh = 2 * (th + 2), gw = 2 * (tw + 2);
-    for (int e = tid; e < gh * gw; e += kThreads) {
-        const int gi = e / gw, gj = e - gi * gw;
-        const int Y = R.crop_y + clampi((rq[gi >> 1] >> kFBits) + (gi & 1), crop);
-        const int X = R.crop_x + clampi((cq[gj >> 1] >> kFBits) + (gj & 1), crop);
-        const int64_t qx = rshr_he64(a0 * X + a1 * Y + a2, 32 - kFBits);
-        const int64_t qy = rshr_he64(a3 * X + a4 * Y + a5, 32 - kFBits);
-        grid[gi][gj] = warp_sample(src, H, W, qx, qy);
+    if (tid < gh) {
+        const int Y = R.crop_y + clampi((rq[tid >> 1] >> kFBits) + (tid & 1), crop);
+        tyx[tid] = a1 * Y + a2;
+        tyy[tid] = a4 * Y + a5;
+    }
+    if (tid >= 128 && tid - 128 < gw) {
+        const int c = tid - 128, X = R.crop_x + clampi((cq[c >> 1] >> kFBits) + (c & 1), crop);
+        txx[c] = a0 * X;
+        txy[c] = a3 * X;
+    }
+    __syncthreads();
+    // Source box of the taps.  A position is (row term) + (column term) and the
+    // rounding is monotone, so its extremes over the tile are the rounded sums
+    // of the extreme terms.  The crop lines grow with the pre-blur index except
+    // that a halo line reflected at the output border repeats an inner line, so
+    // the extreme terms are among the first and last four lines.
+    if (tid == 0) {
+        int64_t lo[4], hi[4];  // min / max of txx, tyx, txy, tyy
+        const int64_t *t[4] = {txx, tyx, txy, tyy};
+        const int len[4] = {gw, gh, gw, gh};
+        for (int a = 0; a < 4; ++a) {
+            lo[a] = hi[a] = t[a][0];
+            for (int k = 0; k < 4; ++k) {
+                const int64_t u = t[a][k], v = t[a][len[a] - 1 - k];
+                lo[a] = min(lo[a], min(u, v));
+                hi[a] = max(hi[a], max(u, v));
+            }
+        }
+        const int xmin = (int)(rshr_he64(lo[0] + lo[1], 32 - kFBits) >> kFBits);
+        const int xmax = (int)(rshr_he64(hi[0] + hi[1], 32 - kFBits) >> kFBits) + 1;
+        const int ymin = (int)(rshr_he64(lo[2] + lo[3], 32 - kFBits) >> kFBits);
+        const int ymax = (int)(rshr_he64(hi[2] + hi[3], 32 - kFBits) >> kFBits) + 1;
+        const int bw = xmax - xmin + 1, bh = ymax - ymin + 1;
+        const int nch = (3 * bw + 30) >> 4;
+        const bool inside = xmin >= 0 && xmax <= W - 1 && ymin >= 0 && ymax <= H - 1;
+        box[0] = xmin; box[1] = ymin; box[2] = bw; box[3] = bh; box[4] = nch;
+        box[5] = inside && bh <= kMaxRows && bh * nch * 16 <= kStageMax;
+    }
+    __syncthreads();
+    const int bx = box[0], by = box[1], bh = box[3], nch = box[4];
+    const bool staged = box[5] != 0;
+    if (staged) {
+        const int bw = box[2];
+        if (tid < bh) {
+            const uint8_t *g = src + ((size_t)(by + tid) * W + bx) * 3;
+            rowoff[tid] = 16 * tid * nch + (int)((uintptr_t)g & 15);
+        }
+        // chunk it of the box: row it / nch, chunk it % nch of that row's 16-byte aligned span
+        const int total = bh * nch, lane = tid & 63;
+        const float rn = __builtin_amdgcn_rcpf((float)nch);
+        for (int base = tid - lane; base < total; base += kThreads) {
+            const int it = base + lane;
+            const uint8_t *s = nullptr;
+            if (it < total) {
+                int r = (int)((float)it * rn), ch;
+                ch = it - r * nch;
+                if (ch < 0) { r -= 1; ch += nch; } else if (ch >= nch) { r += 1; ch -= nch; }
+                const uint8_t *g = src + ((size_t)(by + r) * W + bx) * 3;
+                if (ch < span_chunks(g, 3 * bw)) s = (const uint8_t *)((uintptr_t)g & ~(uintptr_t)15) + 16 * ch;
+            }
+            if (s) __builtin_amdgcn_global_load_lds((const void *)s, (lds_ptr_t)(stage + 16 * base), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
     }
     __syncthreads();
 
-    // pre-blur pixels: resize blend -> HSV shift -> gamma
+    // pre-blur pixels: 2 x 2 warp samples -> resize blend -> HSV shift -> gamma
     for (int e = tid; e < (th + 2) * (tw + 2); e += kThreads) {
         const int pi = e / (tw + 2), pj = e - pi * (tw + 2);
-        const int wy = rq[pi] & (kFOne - 1), wx = cq[pj] & (kFOne - 1);
-        const uint32_t g00 = grid[2 * pi][2 * pj], g01 = grid[2 * pi][2 * pj + 1];
-        const uint32_t g10 = grid[2 * pi + 1][2 * pj], g11 = grid[2 * pi + 1][2 * pj + 1];
-        uint32_t rgb = 0;
+        uint32_t g[2][2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int b00 = (g00 >> (8 * c)) & 255, b01 = (g01 >> (8 * c)) & 255;
-            const int b10 = (g10 >> (8 * c)) & 255, b11 = (g11 >> (8 * c)) & 255;
-            const int t0 = (b00 << kFBits) + wx * (b01 - b00);
-            const int t1 = (b10 << kFBits) + wx * (b11 - b10);
-            const int acc = (t0 << kFBits) + wy * (t1 - t0);
-            rgb |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
-        }
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int r = 2 * pi + u, c = 2 * pj + v;
+                const int64_t qx = rshr_he64(txx[c] + tyx[r], 32 - kFBits);
+                const int64_t qy = rshr_he64(txy[c] + tyy[r], 32 - kFBits);
+                if (staged) {
+                    const int sx = (int)(qx >> kFBits) - bx, sy = (int)(qy >> kFBits) - by;
+                    const int ax = (int)(qx & (kFOne - 1)), ay = (int)(qy & (kFOne - 1));
+                    const int o0 = rowoff[sy] + 3 * sx, o1 = rowoff[sy + 1] + 3 * sx;
+                    g[u][v] = blend4(lds_rgb(stage, o0), lds_rgb(stage, o0 + 3), lds_rgb(stage, o1),
+                                     lds_rgb(stage, o1 + 3), ax, ay);
+                } else {
+                    g[u][v] = warp_sample(src, H, W, qx, qy);
+                }
+            }
+        const int wy = rq[pi] & (kFOne - 1), wx = cq[pj] & (kFOne - 1);
+        const uint32_t rgb = blend4(g[0][0], g[0][1], g[1][0], g[1][1], wx, wy);
         const uint32_t h = hsv_shift(rgb, R.dh, R.ds, R.dv);
         pre[pi][pj] = (uint32_t)lut[h & 255] | ((uint32_t)lut[(h >> 8) & 255] << 8) | ((uint32_t)lut[(h >> 16) & 255] << 16);
     }
