@@ -322,8 +322,15 @@ def bench_elastic(args, torch, m):
         m._check(L.miaug_elastic_grid_u8(m._p(img), m._p(mask), n, H, W, 3, m._p(off), m._p(mapx), m._p(mapy),
                                          m._p(out), m._p(om), per_image, m._stream(st)))
 
+    ws_box = torch.empty(m.lib().miaug_elastic_box_workspace_bytes(n, H, W), dtype=torch.uint8, device="cuda")
+
+    def fields_box(st):
+        m._check(L.miaug_elastic_fields_box(1809068395, 0, n, H, W, 50.0, 1000, m._p(off), m._p(ws_box),
+                                             ws_box.numel(), m._stream(st)))
+
     s = torch.cuda.Stream()
     steps = max(1, args.steps // 4)
+    ms_fb = time_on_stream(torch, fields_box, steps, 1, s)
     ms_f = time_on_stream(torch, fields, steps, 1, s)
     ms_r = time_on_stream(torch, remap, args.steps, args.warmup, s)
     ms_ri = time_on_stream(torch, lambda st: remap(st, 1), steps, 1, s)
@@ -335,7 +342,9 @@ def bench_elastic(args, torch, m):
                {"field_ms": ms_f, "remap_ms": ms_r, "remap_per_image_launch_ms": ms_ri,
                 "field_roofline": {"bound": "alu", "achieved": macs / (ms_f * 1e-3) / 1e12,
                                    "peak": 256 * 64 * 2.4e9 / 1e12, "unit": "Tmac/s (int32 VALU)",
-                                   "frac": macs / (ms_f * 1e-3) / (256 * 64 * 2.4e9)}})
+                                   "frac": macs / (ms_f * 1e-3) / (256 * 64 * 2.4e9)},
+                "box_field_ms": ms_fb, "box_field_speedup": ms_f / ms_fb,
+                "box_field_roofline": hbm_roof(n * 2 * H * W * 4, ms_fb, "k_box_rows + 3 x k_box_cols")})
     return res
 
 

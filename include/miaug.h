@@ -275,6 +275,24 @@ size_t miaug_elastic_workspace_bytes(int n, int H, int W);
 int miaug_elastic_fields(uint64_t seed, uint64_t first_index, int n, int H, int W, double sigma, int alpha,
                          int radius, int32_t *off, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Approximate fields (opt-in): each axis's Gaussian is replaced by a cascade
+ * of three box filters (Wells, IEEE PAMI 1986), widths w_i from Kovesi
+ * ("Fast almost-Gaussian filtering", DICTA 2010): w_ideal = sqrt(4 sigma^2 +
+ * 1), wl = the largest odd integer <= w_ideal, wu = wl + 2, the first
+ * m = round((12 sigma^2 - 3 wl^2 - 12 wl - 9) / (-4 wl - 4)) passes use wl, the
+ * others wu.  A pass is pass(x) = rdiv_he(sum over |k| <= r of
+ * in[refl(x + k)], 2r + 1) with r = w / 2.  Per field: the noise of
+ * miaug_elastic_fields -> three passes along each row -> three passes along
+ * each column -> v; off = rdiv_he(alpha v, 2^5) (Q10 px, the scale of the
+ * exact field).  O(1) work per pixel and pass instead of 2 (2 radius + 1).
+ *   off  device int32 [n][2][H][W] (written)
+ *   workspace device, miaug_elastic_box_workspace_bytes bytes.
+ * Errors: EINVAL; ESHAPE unless sigma > 0 with every box radius <= 255,
+ * 0 <= alpha <= 65535, W <= 7168; ECAPACITY small workspace. */
+size_t miaug_elastic_box_workspace_bytes(int n, int H, int W);
+int miaug_elastic_fields_box(uint64_t seed, uint64_t first_index, int n, int H, int W, double sigma, int alpha,
+                             int32_t *off, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Grid tables: for each image, 5 cells per axis of width cw = W/5, knots
  * S_0 = 0, S_{k+1} = S_k + cw d_k (not renormalised); pixel x maps to
  * src = S_k + (x + 1/2 - k cw) d_k - 1/2 with k = min(floor((x+1/2)/cw), 4),
@@ -352,7 +370,9 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *   GAMMA             p; gamma in [lo[0], hi[0]]; skipped: 1.
  *   BLUR3             p (3x3 binomial).
  *   ELASTIC           alpha = lo[0] (pixels, integer 0..65535), sigma = lo[1],
- *                     radius = lo[2] (0: ceil(3 sigma), at most 200); p must be 1.
+ *                     radius = lo[2] (0: ceil(3 sigma), at most 200); p must be 1;
+ *                     hi[0] != 0 selects the box-cascade approximation
+ *                     (miaug_elastic_fields_box; radius unused).
  *   GRID              p; 5 cells per axis, factors 1 + U[-lo[0], lo[0]]
  *                     (0 <= lo[0] < 1); skipped: all 1.
  *   NORMALIZE         mean = lo[0..2], std = hi[0..2]; p must be 1.

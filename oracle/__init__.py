@@ -94,6 +94,9 @@ _SIGS = {
     "or_gauss_taps_q15": (None, [_d, _i, _i32p]),
     "or_elastic_hpass": (None, [_u64, _u64, _i, _i, _i, _i32p, _i, _i, _i, _i32p]),
     "or_elastic_field": (None, [_u64, _u64, _i, _i, _d, _i, _i, _i32p, _i32p]),
+    "or_box_widths": (None, [_d, _i32p]),
+    "or_box_pass": (None, [_i32p, _i, _i, _i32p]),
+    "or_elastic_field_box": (None, [_u64, _u64, _i, _i, _d, _i, _i32p, _i32p]),
     "or_elastic_field_at": (None, [_u64, _u64, _i, _i, _d, _i, _i, _i, _i, _ip, _ip]),
     "or_remap_field_u8": (None, [_u8p, _i, _i, _i, _i32p, _i32p, _i, _u8p]),
     "or_grid_table": (None, [_f64p, _i, _i, _i32p]),
@@ -342,6 +345,26 @@ def elastic_hpass(seed, index, field, H, W, sigma=50.0, radius=150, y0=0, y1=Non
 def elastic_field(seed, index, H, W, sigma=50.0, alpha=1000, radius=150):
     ox = np.zeros((H, W), np.int32); oy = np.zeros((H, W), np.int32)
     lib().or_elastic_field(seed, index, H, W, sigma, alpha, radius, ox, oy)
+    return ox, oy
+
+
+def box_widths(sigma):
+    w = np.zeros(3, np.int32)
+    lib().or_box_widths(sigma, w)
+    return tuple(int(v) for v in w)
+
+
+def box_pass(line, r):
+    line = _c(line, np.int32)
+    out = np.zeros_like(line)
+    lib().or_box_pass(line, len(line), r, out)
+    return out
+
+
+def elastic_field_box(seed, index, H, W, sigma=50.0, alpha=1000):
+    """Box-cascade approximation of the elastic field: (offx, offy) int32 [H, W]."""
+    ox = np.zeros((H, W), np.int32); oy = np.zeros((H, W), np.int32)
+    lib().or_elastic_field_box(seed, index, H, W, sigma, alpha, ox, oy)
     return ox, oy
 
 

@@ -572,6 +572,71 @@ void or_elastic_field(uint64_t seed, uint64_t index, int H, int W, double sigma,
     free(h); free(taps);
 }
 
+/* Approximate elastic field (opt-in): the Gaussian of each axis is replaced by
+ * a cascade of three box filters (Wells, IEEE PAMI 1986), with the widths of
+ * Kovesi ("Fast almost-Gaussian filtering", DICTA 2010): w_ideal =
+ * sqrt(12 sigma^2 / n + 1) for n = 3 passes, wl = the largest odd integer not
+ * above w_ideal, wu = wl + 2, m = round((12 sigma^2 - n wl^2 - 4 n wl - 3 n) /
+ * (-4 wl - 4)) (half away from zero); the first m passes use wl, the rest wu.
+ * widths[] receives the three widths. */
+void or_box_widths(double sigma, int *widths)
+{
+    const int n = 3;
+    double w_ideal = sqrt(12.0 * sigma * sigma / n + 1.0);
+    int wl = (int)floor(w_ideal);
+    if (wl % 2 == 0) wl -= 1;
+    int wu = wl + 2;
+    double m_ideal = (12.0 * sigma * sigma - n * wl * wl - 4.0 * n * wl - 3.0 * n) / (-4.0 * wl - 4.0);
+    int m = (int)round(m_ideal);
+    for (int i = 0; i < n; ++i) widths[i] = i < m ? wl : wu;
+}
+
+/* One box pass along a line of n values: out[i] = rdiv_he(sum over |k| <= r of
+ * in[reflect101(i + k)], 2r + 1). */
+void or_box_pass(const int32_t *in, int n, int r, int32_t *out)
+{
+    for (int i = 0; i < n; ++i) {
+        int64_t s = 0;
+        for (int k = -r; k <= r; ++k) s += in[or_reflect101(i + k, n)];
+        out[i] = (int32_t)or_rdiv_he(s, 2 * r + 1);
+    }
+}
+
+/* Per field: noise (as in the exact field) -> three box passes along each row
+ * -> three box passes along each column -> v (noise units) -> offset
+ * rshr_he(alpha v, 5), the Q10 scale of the exact field (whose v carries 15
+ * more fraction bits). */
+void or_elastic_field_box(uint64_t seed, uint64_t index, int H, int W, double sigma, int alpha,
+                          int32_t *offx, int32_t *offy)
+{
+    int widths[3];
+    or_box_widths(sigma, widths);
+    int L = H > W ? H : W;
+    int32_t *a = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+    int32_t *b = (int32_t *)malloc(sizeof(int32_t) * (size_t)L);
+    int32_t *f = (int32_t *)malloc(sizeof(int32_t) * (size_t)H * W);
+    for (int field = 0; field < 2; ++field) {
+        int32_t *off = field == 0 ? offx : offy;
+        for (int y = 0; y < H; ++y) {
+            for (int x = 0; x < W; ++x) a[x] = or_noise16(seed, index, field, (int64_t)y * W + x);
+            for (int p = 0; p < 3; ++p) {
+                or_box_pass(a, W, widths[p] / 2, b);
+                memcpy(a, b, sizeof(int32_t) * (size_t)W);
+            }
+            memcpy(f + (size_t)y * W, a, sizeof(int32_t) * (size_t)W);
+        }
+        for (int x = 0; x < W; ++x) {
+            for (int y = 0; y < H; ++y) a[y] = f[(size_t)y * W + x];
+            for (int p = 0; p < 3; ++p) {
+                or_box_pass(a, H, widths[p] / 2, b);
+                memcpy(a, b, sizeof(int32_t) * (size_t)H);
+            }
+            for (int y = 0; y < H; ++y) off[(size_t)y * W + x] = (int32_t)or_rshr_he((int64_t)alpha * a[y], 5);
+        }
+    }
+    free(a); free(b); free(f);
+}
+
 /* The same field value at one pixel, computed from the definition alone
  * (used to check sampled pixels of full-size images). */
 void or_elastic_field_at(uint64_t seed, uint64_t index, int H, int W, double sigma, int alpha,

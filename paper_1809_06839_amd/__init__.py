@@ -107,6 +107,8 @@ _SIGS = {
     "miaug_warpcolor_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "miaug_elastic_workspace_bytes": (_sz, [_i, _i, _i]),
     "miaug_elastic_fields": (_i, [_u64, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _sz, _vp]),
+    "miaug_elastic_box_workspace_bytes": (_sz, [_i, _i, _i]),
+    "miaug_elastic_fields_box": (_i, [_u64, _u64, _i, _i, _i, _d, _i, _vp, _vp, _sz, _vp]),
     "miaug_grid_tables": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "miaug_elastic_grid_u8": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _i, _vp]),
     "miaug_chain_f32_workspace_bytes": (_sz, [_i, _i, _i, _i]),
@@ -409,6 +411,15 @@ def elastic_fields(seed, first, n, H, W, sigma=50.0, alpha=1000, radius=150, dev
     ws = torch.empty(max(1, lib().miaug_elastic_workspace_bytes(n, H, W)), dtype=torch.uint8, device=device)
     _check(lib().miaug_elastic_fields(seed, first, n, H, W, sigma, alpha, radius, _p(off), _p(ws), ws.numel(),
                                       _stream(stream)))
+    return off
+
+
+def elastic_fields_box(seed, first, n, H, W, sigma=50.0, alpha=1000, device="cuda", stream=None):
+    """Box-cascade approximation of elastic_fields: Q10 offsets [n, 2, H, W] int32."""
+    off = torch.empty((n, 2, H, W), dtype=torch.int32, device=device)
+    ws = torch.empty(max(1, lib().miaug_elastic_box_workspace_bytes(n, H, W)), dtype=torch.uint8, device=device)
+    _check(lib().miaug_elastic_fields_box(seed, first, n, H, W, sigma, alpha, _p(off), _p(ws), ws.numel(),
+                                          _stream(stream)))
     return off
 
 

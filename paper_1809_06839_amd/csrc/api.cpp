@@ -334,6 +334,30 @@ int miaug_elastic_fields(uint64_t seed, uint64_t first, int n, int H, int W, dou
                       "elastic_fields launch");
 }
 
+size_t miaug_elastic_box_workspace_bytes(int n, int H, int W) {
+    return (n > 0 && H > 0 && W > 0) ? box_workspace_bytes(n, H, W) : 0;
+}
+
+int miaug_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
+                             int32_t *off, void *ws, size_t ws_bytes, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "elastic_fields_box: negative size");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!off) return set_error(MIAUG_EINVAL, "elastic_fields_box: NULL off");
+    if (!(sigma > 0.0) || alpha < 0 || alpha > 65535)
+        return set_error(MIAUG_ESHAPE, "elastic_fields_box: sigma=%g alpha=%d", sigma, alpha);
+    int r[3];
+    box_radii(sigma, r);
+    if (r[0] < 0 || r[2] > 255) return set_error(MIAUG_ESHAPE, "elastic_fields_box: sigma %g gives box radius %d > 255", sigma, r[2]);
+    if (W > 7168 || (long long)H * W > (1ll << 30))
+        return set_error(MIAUG_ESHAPE, "elastic_fields_box: rows longer than 7168 or image too large");
+    const size_t need = box_workspace_bytes(n, H, W);
+    if (!ws || ws_bytes < need)
+        return set_error(MIAUG_ECAPACITY, "elastic_fields_box: workspace %zu < %zu bytes", ws_bytes, need);
+    return hip_status(launch_elastic_fields_box(seed, first, n, H, W, sigma, alpha, off, ws, as_stream(stream)),
+                      "elastic_fields_box launch");
+}
+
 int miaug_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, void *stream) {
     begin_call();
     if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "grid_tables: negative size");

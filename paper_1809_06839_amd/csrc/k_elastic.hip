@@ -42,49 +42,75 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 }
 
 // ---------------------------------------------------------------- H pass
-constexpr int kHSeg = 1024;  // outputs per workgroup (4 per thread)
+constexpr int kHPer = 5;                   // consecutive outputs per thread (odd: no LDS bank sharing)
+constexpr int kHSeg = kHPer * kThreads;    // outputs per workgroup
 
 __global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t first, int H, int W, int radius,
                                                       const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
     __shared__ int32_t noise[kHSeg + 2 * kMaxRadius + 16];
-    __shared__ int32_t tp[2 * kMaxRadius + 1];
+    __shared__ int32_t tp[2 * kMaxRadius + 16];  // taps, zero-padded to a multiple of kHPer
     const int segs = (W + kHSeg - 1) / kHSeg;
     const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kHSeg;
     const int field = blockIdx.y, img = blockIdx.z;
     const uint64_t g = first + (uint64_t)img;
-    for (int k = threadIdx.x; k < 2 * radius + 1; k += kThreads) tp[k] = taps[k];
+    const int nt = 2 * radius + 1, ntp = (nt + kHPer - 1) / kHPer * kHPer;
+    for (int k = threadIdx.x; k < ntp; k += kThreads) tp[k] = k < nt ? taps[k] : 0;
     // noise at reflected columns x0 - radius .. x0 + kHSeg + radius - 1 (as far as needed)
     const int n_need = min(kHSeg, W - x0) + 2 * radius;
-    for (int i = threadIdx.x; i < n_need; i += kThreads) {
-        const int xs = reflect101(x0 - radius + i, W);
-        const int64_t e = (int64_t)y * W + xs;
-        uint64_t c[4] = {(uint64_t)(e >> 4), g, (uint64_t)field, 4};
+    // The segment's own columns x0 .. x0 + m - 1 (m <= kHSeg) first: one Philox block gives
+    // the 16 values of 16 consecutive stream positions.  Then the reflected halo columns,
+    // which are copies of columns already generated when the row is covered by this segment
+    // and are generated one by one otherwise.
+    const int m = min(kHSeg, W - x0);
+    const int64_t e0 = (int64_t)y * W + x0, e1 = e0 + m;
+    for (int64_t grp = (e0 >> 4) + threadIdx.x; grp <= ((e1 - 1) >> 4); grp += kThreads) {
+        uint64_t c[4] = {(uint64_t)grp, g, (uint64_t)field, 4};
         philox4x64_10(c, seed, 0);
-        const uint64_t word = c[(e & 15) >> 2];
-        noise[i] = (int32_t)((word >> (16 * (e & 3))) & 0xFFFFu) - 32768;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t e = grp * 16 + k;
+            if (e >= e0 && e < e1) noise[radius + (int)(e - e0)] = (int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768;
+        }
     }
     __syncthreads();
-    const int xl = 4 * threadIdx.x;  // first of this thread's 4 outputs, relative to x0
+    for (int i = threadIdx.x; i < n_need; i += kThreads) {
+        if (i >= radius && i < radius + m) continue;  // own column, generated above
+        const int xs = reflect101(x0 - radius + i, W);
+        if (xs >= x0 && xs < x0 + m) {
+            noise[i] = noise[radius + (xs - x0)];
+        } else {
+            const int64_t e = (int64_t)y * W + xs;
+            uint64_t c[4] = {(uint64_t)(e >> 4), g, (uint64_t)field, 4};
+            philox4x64_10(c, seed, 0);
+            const uint64_t word = c[(e & 15) >> 2];
+            noise[i] = (int32_t)((word >> (16 * (e & 3))) & 0xFFFFu) - 32768;
+        }
+    }
+    __syncthreads();
+    const int xl = kHPer * threadIdx.x;  // first of this thread's outputs, relative to x0
     if (x0 + xl >= W) return;
-    int32_t acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-    int32_t t0 = 0, t1 = 0, t2 = 0;  // taps k = j-1, j-2, j-3 (sliding)
-    const int nt = 2 * radius + 1;
-    for (int j = 0; j < nt + 3; ++j) {
-        // noise[xl + j] pairs with tap j for output 0, tap j-1 for output 1, ...
-        const int32_t v = noise[xl + j];
-        const int32_t tj = j < nt ? tp[j] : 0;
-        // operands fit 24 bits (|noise| <= 2^15, taps <= 2^15): full-rate v_mad_i32_i24
-        acc0 += __mul24(tj, v);
-        acc1 += __mul24(t0, v);
-        acc2 += __mul24(t1, v);
-        acc3 += __mul24(t2, v);
-        t2 = t1; t1 = t0; t0 = tj;
+    // Register-blocked correlation: per block of kHPer taps, 2 kHPer - 1 noise values and
+    // kHPer taps feed kHPer^2 multiply-adds with compile-time register indices.  Operands fit
+    // 24 bits (|noise| <= 2^15, taps <= 2^15): full-rate v_mad_i32_i24.  Reads past the noise
+    // of the segment meet zero taps.
+    int32_t acc[kHPer];
+#pragma unroll
+    for (int o = 0; o < kHPer; ++o) acc[o] = 0;
+    for (int j0 = 0; j0 < ntp; j0 += kHPer) {
+        int32_t xv[2 * kHPer - 1], tv[kHPer];
+#pragma unroll
+        for (int i = 0; i < 2 * kHPer - 1; ++i) xv[i] = noise[xl + j0 + i];
+#pragma unroll
+        for (int i = 0; i < kHPer; ++i) tv[i] = tp[j0 + i];
+#pragma unroll
+        for (int jj = 0; jj < kHPer; ++jj)
+#pragma unroll
+            for (int o = 0; o < kHPer; ++o) acc[o] += __mul24(tv[jj], xv[jj + o]);
     }
     int32_t *row = hout + (((size_t)img * 2 + field) * H + y) * W + x0 + xl;
-    row[0] = rshr_he(acc0, 15);
-    if (x0 + xl + 1 < W) row[1] = rshr_he(acc1, 15);
-    if (x0 + xl + 2 < W) row[2] = rshr_he(acc2, 15);
-    if (x0 + xl + 3 < W) row[3] = rshr_he(acc3, 15);
+#pragma unroll
+    for (int o = 0; o < kHPer; ++o)
+        if (x0 + xl + o < W) row[o] = rshr_he(acc[o], 15);
 }
 
 // ---------------------------------------------------------------- V pass
@@ -94,13 +120,14 @@ __global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, 
                                                       const int32_t *__restrict__ taps,
                                                       const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
     extern __shared__ int32_t smem[];
-    int32_t *tp = smem;                                   // 2 radius + 1
-    int32_t *strip = smem + ((2 * radius + 1 + 3) & ~3);  // (kVRows + 2 radius) x kVCols
+    const int nt = 2 * radius + 1, ntp = (nt + kVPer - 1) / kVPer * kVPer;
+    int32_t *tp = smem;          // taps, zero-padded to ntp
+    int32_t *strip = smem + ntp;  // (kVRows + 2 radius + kVPer) x kVCols
     const int strips_x = (W + kVCols - 1) / kVCols;
     const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kVRows;
     const int field = blockIdx.y, img = blockIdx.z;
     const int32_t *hb = hin + ((size_t)img * 2 + field) * H * W;
-    for (int k = threadIdx.x; k < 2 * radius + 1; k += kThreads) tp[k] = taps[k];
+    for (int k = threadIdx.x; k < ntp; k += kThreads) tp[k] = k < nt ? taps[k] : 0;
     const int rows = min(kVRows, H - y0) + 2 * radius;
     for (int e = threadIdx.x; e < rows * kVCols; e += kThreads) {
         const int r = e / kVCols, c = e - r * kVCols;
@@ -111,28 +138,141 @@ __global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, 
     const int col = threadIdx.x % kVCols, grp = threadIdx.x / kVCols;
     const int x = xs0 + col, yl = grp * kVPer;
     if (x >= W || y0 + yl >= H) return;
+    // register-blocked as in the H pass; rows past the strip meet zero taps
     int32_t acc[kVPer];
-    int32_t tw[kVPer - 1];
 #pragma unroll
     for (int o = 0; o < kVPer; ++o) acc[o] = 0;
+    for (int j0 = 0; j0 < ntp; j0 += kVPer) {
+        int32_t xv[2 * kVPer - 1], tv[kVPer];
 #pragma unroll
-    for (int o = 0; o < kVPer - 1; ++o) tw[o] = 0;
-    const int nt = 2 * radius + 1;
-    for (int j = 0; j < nt + kVPer - 1; ++j) {
-        const int32_t v = strip[(yl + j) * kVCols + col];
-        const int32_t tj = j < nt ? tp[j] : 0;
+        for (int i = 0; i < 2 * kVPer - 1; ++i) xv[i] = strip[(yl + j0 + i) * kVCols + col];
+#pragma unroll
+        for (int i = 0; i < kVPer; ++i) tv[i] = tp[j0 + i];
         // |h| <= 2^15 (1 + 150 / 2^15) and taps <= 2^15 fit 24 bits
-        acc[0] += __mul24(tj, v);
 #pragma unroll
-        for (int o = 1; o < kVPer; ++o) acc[o] += __mul24(tw[o - 1], v);
+        for (int jj = 0; jj < kVPer; ++jj)
 #pragma unroll
-        for (int o = kVPer - 2; o > 0; --o) tw[o] = tw[o - 1];
-        tw[0] = tj;
+            for (int o = 0; o < kVPer; ++o) acc[o] += __mul24(tv[jj], xv[jj + o]);
     }
     int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
 #pragma unroll
     for (int o = 0; o < kVPer; ++o)
         if (y0 + yl + o < H) ob[(size_t)(y0 + yl + o) * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc[o], 30 - kFBits);
+}
+
+// ---------------------------------------------------------------- box-cascade field (approximate, opt-in)
+// Each axis's Gaussian is replaced by three box filters (Wells 1986; widths
+// of Kovesi 2010), every pass rounding its mean: pass(x) = rdiv_he(sum over
+// |k| <= r of in[refl(x + k)], 2r + 1).  Rows: noise and the three passes in
+// LDS, one workgroup per row.  Columns: one pass per launch, each thread
+// sliding a window down kBoxSeg rows of one column; the last pass writes the
+// offsets rshr_he(alpha v, 5) (Q10 px).
+constexpr int kBoxSeg = 64;       // rows per thread in the column passes
+
+// rdiv_he(s, w) for odd w and |s| <= 32768 w (w values of the noise range):
+// A = s + 32768 w >= 0, A / w <= 65536, so the float quotient (rw = v_rcp_f32(w))
+// is within 1/64 of A / w and one correction step makes it exact; w is odd,
+// so 2r == w never happens.
+__device__ __forceinline__ int box_round(int s, int w, float rw) {
+    const int A = s + 32768 * w;
+    int q = (int)((float)A * rw);
+    int r = A - q * w;
+    if (r < 0) { q -= 1; r += w; }
+    else if (r >= w) { q += 1; r -= w; }
+    return q - 32768 + (2 * r > w);
+}
+
+// LDS (dynamic): two lines of W + 2 (r2 + 1) int32; the halo offset is hb = r2 + 1.
+__global__ __launch_bounds__(kThreads) void k_box_rows(uint64_t seed, uint64_t first, int H, int W, int r0, int r1,
+                                                       int r2, int16_t *__restrict__ out) {
+    extern __shared__ int32_t lines[];
+    const int hb = r2 + 1;  // halo of the widest pass
+    int32_t *bufa = lines, *bufb = lines + W + 2 * hb;
+    const int y = blockIdx.x, field = blockIdx.y, img = blockIdx.z;
+    const uint64_t g = first + (uint64_t)img;
+    const int64_t e0 = (int64_t)y * W, e1 = e0 + W;
+    // noise: one Philox block gives the 16 values of 16 consecutive stream positions
+    for (int64_t grp = (e0 >> 4) + threadIdx.x; grp <= ((e1 - 1) >> 4); grp += kThreads) {
+        uint64_t c[4] = {(uint64_t)grp, g, (uint64_t)field, 4};
+        philox4x64_10(c, seed, 0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t e = grp * 16 + k;
+            if (e >= e0 && e < e1)
+                bufa[hb + (int)(e - e0)] = (int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768;
+        }
+    }
+    int32_t *src = bufa, *dst = bufb;
+    // each thread slides over `chunk` consecutive outputs; an odd chunk puts the 64
+    // lanes of a wave in 64 different LDS banks (an even one would share few banks)
+    const int chunk = ((W + kThreads - 1) / kThreads) | 1, x0 = threadIdx.x * chunk;
+    for (int p = 0; p < 3; ++p) {
+        const int r = p == 0 ? r0 : (p == 1 ? r1 : r2), w = 2 * r + 1;
+        __syncthreads();
+        for (int k = threadIdx.x; k <= r; k += kThreads) {  // reflected ends (r left, r + 1 right)
+            if (k < r) src[hb - 1 - k] = src[hb + reflect101(-1 - k, W)];
+            src[hb + W + k] = src[hb + reflect101(W + k, W)];
+        }
+        __syncthreads();
+        if (x0 < W) {
+            const float rw = __builtin_amdgcn_rcpf((float)w);
+            int s = 0;
+            for (int k = -r; k <= r; ++k) s += src[hb + x0 + k];
+            const int xe = min(W, x0 + chunk);
+            for (int x = x0; x < xe; ++x) {
+                dst[hb + x] = box_round(s, w, rw);
+                s += src[hb + x + r + 1] - src[hb + x - r];
+            }
+        }
+        int32_t *t = src; src = dst; dst = t;
+    }
+    __syncthreads();
+    int16_t *o = out + (((size_t)img * 2 + field) * H + y) * W;
+    for (int x = threadIdx.x; x < W; x += kThreads) o[x] = (int16_t)src[hb + x];
+}
+
+// One column pass: in -> out16 (alpha < 0) or in -> offsets rshr_he(alpha v, 5).
+__global__ __launch_bounds__(kThreads) void k_box_cols(const int16_t *__restrict__ in, int H, int W, int r, int alpha,
+                                                       int16_t *__restrict__ out16, int32_t *__restrict__ off) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kBoxSeg;
+    const size_t plane = ((size_t)blockIdx.z) * H * W;  // (image, field) plane
+    if (x >= W || y0 >= H) return;
+    const int16_t *col = in + plane + x;
+    const int w = 2 * r + 1;
+    const float rw = __builtin_amdgcn_rcpf((float)w);
+    const int ye = min(H, y0 + kBoxSeg);
+    int s = 0;
+    auto emit = [&](int y, int v) {
+        if (alpha < 0) out16[plane + (size_t)y * W + x] = (int16_t)v;
+        else off[plane + (size_t)y * W + x] = (int32_t)rshr_he64((int64_t)alpha * v, 5);
+    };
+    if (y0 - r >= 0 && ye + r < H && ye - y0 == kBoxSeg) {  // every read inside the column: no reflection
+        const int16_t *c = col + (size_t)(y0 - r) * W;
+        for (int k = 0; k < w; ++k) s += c[(size_t)k * W];
+        const int16_t *add = col + (size_t)(y0 + r + 1) * W, *sub = col + (size_t)(y0 - r) * W;
+        for (int y = y0; y < ye; y += 8) {  // the 16 loads of 8 rows are issued together
+            int av[8], sv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                av[k] = add[(size_t)k * W];
+                sv[k] = sub[(size_t)k * W];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                emit(y + k, box_round(s, w, rw));
+                s += av[k] - sv[k];
+            }
+            add += (size_t)8 * W;
+            sub += (size_t)8 * W;
+        }
+        return;
+    }
+    for (int k = -r; k <= r; ++k) s += col[(size_t)reflect101(y0 + k, H) * W];
+    for (int y = y0; y < ye; ++y) {
+        emit(y, box_round(s, w, rw));
+        s += col[(size_t)reflect101(y + r + 1, H) * W] - col[(size_t)reflect101(y - r, H) * W];
+    }
 }
 
 // ---------------------------------------------------------------- grid tables
@@ -388,7 +528,8 @@ hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, in
                        dtaps, hbuf);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int strips = ((W + kVCols - 1) / kVCols) * ((H + kVRows - 1) / kVRows);
-    const size_t lds = sizeof(int32_t) * ((((2 * radius + 1) + 3) & ~3) + (size_t)(kVRows + 2 * radius) * kVCols);
+    const int ntp = (2 * radius + 1 + kVPer - 1) / kVPer * kVPer;
+    const size_t lds = sizeof(int32_t) * (ntp + (size_t)(kVRows + 2 * radius + kVPer) * kVCols);
     hipLaunchKernelGGL(k_field_v, dim3(strips, 2, n), dim3(kThreads), lds, s, H, W, radius, alpha, dtaps, hbuf, off);
     return hipGetLastError();
 }
@@ -449,6 +590,37 @@ hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, con
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// Box widths of a three-pass cascade for sigma (Kovesi 2010): w_ideal =
+// sqrt(4 sigma^2 + 1), wl = largest odd integer <= w_ideal, wu = wl + 2, and
+// m = round((12 sigma^2 - 3 wl^2 - 12 wl - 9) / (-4 wl - 4)) passes of wl.
+void box_radii(double sigma, int r[3]) {
+    const double wi = sqrt(12.0 * sigma * sigma / 3.0 + 1.0);
+    int wl = (int)floor(wi);
+    if (wl % 2 == 0) wl -= 1;
+    const int m = (int)round((12.0 * sigma * sigma - 3.0 * wl * wl - 12.0 * wl - 9.0) / (-4.0 * wl - 4.0));
+    for (int i = 0; i < 3; ++i) r[i] = ((i < m) ? wl : wl + 2) / 2;
+}
+
+size_t box_workspace_bytes(int n, int H, int W) { return (size_t)n * 2 * H * W * sizeof(int16_t) * 2; }
+
+hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
+                                     int32_t *off, void *ws, hipStream_t s) {
+    int r[3];
+    box_radii(sigma, r);
+    int16_t *a = (int16_t *)ws, *b = a + (size_t)n * 2 * H * W;
+    const size_t lds = sizeof(int32_t) * 2 * ((size_t)W + 2 * (r[2] + 1));
+    hipLaunchKernelGGL(k_box_rows, dim3(H, 2, n), dim3(kThreads), lds, s, seed, first, H, W, r[0], r[1], r[2], a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 grid((W + 63) / 64, (H + 4 * kBoxSeg - 1) / (4 * kBoxSeg), 2 * n);
+    hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr, off);
     return hipGetLastError();
 }
 

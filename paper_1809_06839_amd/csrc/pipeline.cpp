@@ -90,6 +90,7 @@ struct miaug_pipeline {
     float mean[3], stdv[3];  // NORMALIZE (RAGGED)
     int el_alpha, el_radius; // ELASTIC (DISTORT); el_alpha < 0: no elastic op
     double el_sigma;
+    bool el_box;             // box-cascade approximation of the field
     // pinned staging of packed records, device copies, chain buffers
     void *pinned = nullptr;
     size_t pinned_cap = 0;
@@ -338,7 +339,8 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
     // DISTORT: fields (or zero offsets), grid tables (from the records, or identity factors), remap chain
     const int H = in->H, W = in->W;
     const size_t field_bytes = (size_t)n * 2 * H * W * sizeof(int32_t);
-    const size_t ews = p->el_alpha >= 0 ? miaug_elastic_workspace_bytes(n, H, W) : 0;
+    const size_t ews = p->el_alpha < 0 ? 0
+                       : (p->el_box ? miaug_elastic_box_workspace_bytes(n, H, W) : miaug_elastic_workspace_bytes(n, H, W));
     const size_t tab_bytes = (size_t)n * (H + W) * sizeof(int32_t);
     char *w = (char *)p->dwork;
     int32_t *off = (int32_t *)w;
@@ -347,7 +349,9 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
     int32_t *mapy = mapx + (size_t)n * W;
     (void)tab_bytes;
     int st;
-    if (p->el_alpha >= 0)
+    if (p->el_alpha >= 0 && p->el_box)
+        st = miaug_elastic_fields_box(first->seed, first->index, n, H, W, p->el_sigma, p->el_alpha, off, ew, ews, s);
+    else if (p->el_alpha >= 0)
         st = miaug_elastic_fields(first->seed, first->index, n, H, W, p->el_sigma, p->el_alpha, p->el_radius, off, ew,
                                   ews, s);
     else
@@ -361,7 +365,8 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
 
 size_t distort_work_bytes(const miaug_pipeline *p, int n, int H, int W) {
     size_t b = (size_t)n * 2 * H * W * sizeof(int32_t) + (size_t)n * (H + W) * sizeof(int32_t);
-    if (p->el_alpha >= 0) b += miaug_elastic_workspace_bytes(n, H, W);
+    if (p->el_alpha >= 0)
+        b += p->el_box ? miaug_elastic_box_workspace_bytes(n, H, W) : miaug_elastic_workspace_bytes(n, H, W);
     return b + 256;
 }
 
@@ -479,6 +484,7 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     p->el_alpha = -1;
     p->el_radius = 0;
     p->el_sigma = 0.0;
+    p->el_box = false;
     for (const miaug_op &o : p->ops) {
         if (o.kind == MIAUG_OP_RESIZE) {
             p->out_h = o.out_h;
@@ -494,6 +500,7 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
         } else if (o.kind == MIAUG_OP_ELASTIC) {
             p->el_alpha = (int)o.lo[0];
             p->el_sigma = o.lo[1];
+            p->el_box = o.hi[0] != 0.f;
             p->el_radius = o.lo[2] > 0.f ? (int)o.lo[2] : (int)ceil(3.0 * o.lo[1]);
             if (p->el_radius < 1 || p->el_radius > 200) {
                 delete p;

@@ -27,6 +27,15 @@ def test_fields_bit_exact(m, H, W, sigma, alpha, radius):
         assert np.array_equal(off[i, 0], ox) and np.array_equal(off[i, 1], oy), i
 
 
+@pytest.mark.parametrize("n,H,W,sigma,alpha", [(2, 40, 36, 2.0, 60), (1, 1, 50, 3.0, 100), (1, 67, 1, 2.0, 30),
+                                               (2, 96, 130, 6.0, 300), (1, 3, 3, 5.0, 500), (1, 512, 2048, 50.0, 1000)])
+def test_box_fields_bit_exact(m, n, H, W, sigma, alpha):
+    off = m.elastic_fields_box(7, 3, n, H, W, sigma, alpha).cpu().numpy()
+    for i in range(n):
+        ox, oy = oracle.elastic_field_box(7, 3 + i, H, W, sigma, alpha)
+        assert np.array_equal(off[i, 0], ox) and np.array_equal(off[i, 1], oy), i
+
+
 def test_grid_tables_bit_exact(m):
     import torch
     g = m.sample_grid(5, 0, 4)

@@ -112,3 +112,61 @@ def test_elastic_grid_pipeline_composes_the_two_ops():
     em = oracle.remap_field(mask, ox, oy, oracle.NEAREST)
     assert np.array_equal(om, oracle.grid_remap(em, mx, my, oracle.NEAREST))
     assert set(np.unique(om)) <= set(np.unique(mask))
+
+
+# ---------------------------------------------------------------- box-cascade field (opt-in approximation)
+def _cascade_variance(widths):
+    return sum((w * w - 1) / 12.0 for w in widths)
+
+
+@pytest.mark.parametrize("sigma", [0.8, 1.0, 2.5, 6.0, 20.0, 50.0, 77.7])
+def test_box_widths_are_odd_and_give_the_closest_cascade_variance(sigma):
+    w = oracle.box_widths(sigma)
+    assert all(v % 2 == 1 for v in w) and w[0] <= w[1] <= w[2] and w[2] - w[0] in (0, 2)
+    wl = w[0] if w[2] != w[0] else None
+    # among cascades of three odd widths from {wl, wl + 2} (any split), the chosen one is nearest to sigma^2
+    base = w[0] if w[0] == w[2] else wl
+    cands = [[base] * k + [base + 2] * (3 - k) for k in range(4)] + [[base - 2] * k + [base] * (3 - k) for k in range(4)]
+    cands = [c for c in cands if min(c) >= 1]
+    best = min(abs(_cascade_variance(c) - sigma ** 2) for c in cands)
+    assert abs(_cascade_variance(w) - sigma ** 2) <= best + 1e-9
+
+
+def test_box_pass_equals_scipy_mirror_sum_then_rounded_division():
+    ndimage = pytest.importorskip("scipy.ndimage")
+    rng = np.random.default_rng(5)
+    for n, r in [(37, 4), (9, 6), (1, 3), (200, 50), (3, 1)]:
+        line = rng.integers(-32768, 32768, n).astype(np.int64)
+        s = ndimage.correlate1d(line, np.ones(2 * r + 1, np.int64), mode="mirror")
+        ref = np.array([oracle.rdiv_he(int(v), 2 * r + 1) for v in s], np.int32)
+        assert np.array_equal(oracle.box_pass(line.astype(np.int32), r), ref), (n, r)
+
+
+def test_box_field_is_the_row_then_column_cascade():
+    ndimage = pytest.importorskip("scipy.ndimage")
+    H, W, sigma, alpha = 19, 23, 2.0, 300
+    radii = [w // 2 for w in oracle.box_widths(sigma)]
+    ox, oy = oracle.elastic_field_box(9, 4, H, W, sigma, alpha)
+
+    def cascade(a, axis):
+        for r in radii:
+            s = ndimage.correlate1d(a, np.ones(2 * r + 1, np.int64), axis=axis, mode="mirror")
+            a = np.vectorize(lambda v, r=r: oracle.rdiv_he(int(v), 2 * r + 1))(s).astype(np.int64)
+        return a
+
+    for field, off in ((0, ox), (1, oy)):
+        noise = np.array([[oracle.noise16(9, 4, field, y * W + x) for x in range(W)] for y in range(H)], np.int64)
+        v = cascade(cascade(noise, 1), 0)
+        ref = np.vectorize(lambda t: oracle.rshr_he(alpha * int(t), 5))(v)
+        assert np.array_equal(off, ref), field
+
+
+def test_box_field_tracks_the_gaussian_field_and_zero_alpha_is_zero():
+    H, W, sigma, alpha = 64, 80, 6.0, 300
+    ex, ey = oracle.elastic_field(1, 0, H, W, sigma, alpha, 18)
+    bx, by = oracle.elastic_field_box(1, 0, H, W, sigma, alpha)
+    for e, b in ((ex, bx), (ey, by)):
+        assert np.corrcoef(e.ravel(), b.ravel())[0, 1] > 0.99
+        assert 0.9 < b.std() / e.std() < 1.1
+    zx, zy = oracle.elastic_field_box(1, 0, H, W, sigma, 0)
+    assert not zx.any() and not zy.any()

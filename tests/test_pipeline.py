@@ -279,3 +279,24 @@ def test_distortion_pipeline_matches_the_oracle_chain(ctx):
         d = np.array(list(recs[i].grid), np.float64)
         ref = oracle.grid_remap(imgs[i], oracle.grid_table(d[:5], W), oracle.grid_table(d[5:], H))
         assert np.array_equal(got[i], ref), i
+
+
+@pytest.mark.gpu
+def test_distortion_pipeline_with_the_box_field(ctx):
+    import torch
+    n, H, W = 2, 64, 90
+    p = m.Pipeline(ctx, [op("ELASTIC", 1, (300, 6, 0), (1, 0, 0)), op("GRID", 1, (0.3,))])
+    imgs = synth.smooth_u8_hwc(43, n, H, W).numpy()
+    recs = p.sample(78, 0, n)
+    x = torch.from_numpy(imgs).cuda()
+    out = torch.empty_like(x)
+    bi, bo, _ = p.batch(img=x)
+    bo.img = out.data_ptr()
+    p.apply(bi, bo, recs)
+    got = out.cpu().numpy()
+    for i in range(n):
+        d = np.array(list(recs[i].grid), np.float64)
+        ox, oy = oracle.elastic_field_box(78, i, H, W, 6.0, 300)
+        e = oracle.remap_field(imgs[i], ox, oy)
+        ref = oracle.grid_remap(e, oracle.grid_table(d[:5], W), oracle.grid_table(d[5:], H))
+        assert np.array_equal(got[i], ref), i
