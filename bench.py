@@ -101,6 +101,17 @@ def ragged_algorithmic_bytes(hw, nboxes, out=224):
     return total
 
 
+def ragged_kernel_name(variant_name: str) -> str:
+    """Kernel that a ragged launch variant runs."""
+    if "next pass planned" in variant_name:
+        return "k_ragged_pipe"
+    if "streaming" in variant_name:
+        return "k_ragged_stream"
+    if "flat" in variant_name:
+        return "k_ragged_flat"
+    return "k_ragged_persistent"
+
+
 def cpu_baseline_ragged(b, flags, ab, seconds):
     import oracle
     oracle.lib()
@@ -181,8 +192,8 @@ def bench_ragged(args, torch, m):
                                "batched_speedup": ms_pi / ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_ragged_persistent_2048img_ragged_to_224_f32.md", variants[variant]),
-                     "kernel": "k_ragged_persistent", "algorithmic_bytes_per_launch": alg},
+                     "traffic": profiled_traffic("k_ragged_2048img_ragged_to_224_f32.md", variants[variant]),
+                     "kernel": ragged_kernel_name(variants[variant]), "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_ragged(b, flags, ab, args.cpu_seconds)

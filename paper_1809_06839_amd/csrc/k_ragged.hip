@@ -17,6 +17,12 @@
 // passes over the halves of its span positions; a half that still does not
 // fit reads its taps straight from global memory.
 //
+// The default form is a persistent launch in which every workgroup plans its
+// next pass (one wave, tables double-buffered) while the LDS-DMA of the
+// current pass is in flight.  Other launch forms are kept as autotuner
+// candidates: one pass at a time with chunked claims, a flat grid, and a
+// streaming form.
+//
 // The streaming form is a persistent launch in which every workgroup runs a
 // three-stage software pipeline over its passes: in one iteration it builds
 // the tables of pass k+2, issues the LDS-DMA of pass k+1 into one staging
@@ -121,10 +127,11 @@ __host__ __device__ __forceinline__ int tiles_per_image(int OH, int OW) {
 }
 
 // Largest staged footprint (16-byte chunks) of a whole TL x TS tile whose
-// source extent along the span axis is up to 4.6 times the output's.
-template <int TL, int TS>
+// source extent along the span axis is up to R / 10 times the output's
+// (4.6 by default; 4.3 leaves room for a second table set in 40 KB).
+template <int TL, int TS, int R = 46>
 constexpr int full_cap() {
-    return 2 * TL * ((((TS - 1) * 46 / 10 + 4) * 3 + 30) / 16) + TL * ((((TS - 1) * 46 / 10 + 4) + 30) / 16);
+    return 2 * TL * ((((TS - 1) * R / 10 + 4) * 3 + 30) / 16) + TL * ((((TS - 1) * R / 10 + 4) + 30) / 16);
 }
 
 __device__ __forceinline__ void build_norm_lut(const miaug_ragged_args &a, float (&nlut)[3][256]) {
@@ -696,6 +703,91 @@ __global__ __launch_bounds__(kThreads) void k_ragged_persistent(miaug_ragged_arg
     }
 }
 
+// Next item of the claim stream of thread 0 (-1 once every queue is
+// exhausted); the atomic for the one after it is issued before returning.
+__device__ __forceinline__ int claim_item(Claimer<1> &C, const miaug_ragged_args &a, int *counters) {
+    const int3 c = C.resolve(a, counters);
+    if (c.z == 0) return -1;
+    int ut;
+    const int img = udiv_small(c.y, C.tiles, ut) * kQueues + c.x;
+    C.issue(counters);
+    return img * C.tiles + ut;
+}
+
+// Plans pass `part` of work item `item` (-1: end of the stream) into one set
+// of tables (one wave).
+template <int TL, int TS, int CAP>
+__device__ __forceinline__ void plan_item(const miaug_ragged_args &a, int item, int part, int tiles, int4 *ln,
+                                          int4 *cl, int2 *rw, int *meta) {
+    if (item < 0) {
+        if ((threadIdx.x & 63) == 0) meta[M_VALID] = 0;
+        return;
+    }
+    int tile;
+    const int img = udiv_small(item, tiles, tile);
+    const Pass p = plan_pass<TL, TS, CAP>(a, info_scalar(a, img), img, tile, part);
+    pass_tables<TL, TS>(a, p, ln, cl, rw, meta);
+}
+
+// Persistent form in which the next pass is planned while the current one's
+// LDS-DMA is in flight: the tables (and the plan) are double-buffered, the
+// staging buffer is not.  Per pass: every wave issues its share of the DMA,
+// one wave (rotating) then plans the next pass into the other table set, all
+// wait for their DMA, a barrier, blend, a barrier.  Thread 0 claims items one
+// ahead: `nx` holds the next unplanned item and is refilled after the barrier
+// that follows the planner's read of it.
+template <int TL, int TS, int CAP>
+__global__ __launch_bounds__(kThreads) void k_ragged_pipe(miaug_ragged_args a, int *__restrict__ counters) {
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[2][TL];
+    __shared__ int4 cl[2][TS];
+    __shared__ int2 rw[2][3 * TL];
+    __shared__ __align__(16) int meta[2][M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
+    __shared__ int nx;
+    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    Claimer<1> C{tiles, (int)(blockIdx.x % kQueues), 0, 0};  // meaningful in thread 0
+    int first = -1;
+    if (threadIdx.x == 0) {
+        C.issue(counters);
+        first = claim_item(C, a, counters);
+        nx = claim_item(C, a, counters);
+    }
+    first = __builtin_amdgcn_readfirstlane(first);  // lane 0 of wave 0
+    if (wave == 0) plan_item<TL, TS, CAP>(a, first, 0, tiles, ln[0], cl[0], rw[0], meta[0]);
+    build_norm_lut(a, nlut);
+    int bc_img = -1, planner = 1, b = 0;
+    __syncthreads();
+    for (;;) {
+        const Meta mt = read_meta(meta[b]);
+        if (!mt.valid) break;
+        if (!mt.empty) {
+            if (bc_img != mt.img) {
+                build_bc_lut(mt.alpha, mt.beta, bc);
+                bc_img = mt.img;
+            }
+            if (mt.tile == 0 && mt.part <= 1 && a.boxes) ragged_boxes<kThreads>(a, mt.img);
+        }
+        pass_dma<kThreads, CAP>(a, mt, rw[b], st);
+        const bool consume = mt.part != 1;  // the next pass starts a new item
+        if (wave == (planner++ & 3)) {
+            const int item = consume ? __builtin_amdgcn_readfirstlane(nx) : mt.img * tiles + mt.tile;
+            plan_item<TL, TS, CAP>(a, item, consume ? 0 : 2, tiles, ln[b ^ 1], cl[b ^ 1], rw[b ^ 1], meta[b ^ 1]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
+        __syncthreads();
+        if (threadIdx.x == 0 && consume) nx = claim_item(C, a, counters);
+        if (!mt.empty) {
+            if (mt.staged) pass_blend<TL, TS, kThreads>(a, mt, st, ln[b], cl[b], bc, nlut);
+            else pass_direct<kThreads>(a, mt, bc, nlut);
+        }
+        __syncthreads();  // the stage and this table set are rewritten next
+        b ^= 1;
+    }
+}
+
 // Flat grid: one workgroup per item, XCD-aware: workgroup b runs on XCD b mod 8
 // and takes item b / 8 of queue b mod 8.
 template <int TL, int TS, int CAP>
@@ -906,12 +998,14 @@ __global__ void k_zero_counters(int *counters, int n) {
 
 struct Variant {
     int tl, ts;
-    int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid
+    int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid, 3 persistent with
+                    // the next pass planned during the current pass's DMA
     int wg_per_cu;  // workgroups per CU of the persistent modes
     int chunk;      // tiles claimed per atomic (persistent mode)
     const char *name;
 };
 const Variant kVariants[] = {
+    {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
     {32, 32, 1, 4, 1, "tile 32x32, persistent 4 wg/CU, chunks of 1"},
     {32, 32, 1, 4, 4, "tile 32x32, persistent 4 wg/CU, chunks of 4"},
     {32, 32, 1, 4, 8, "tile 32x32, persistent 4 wg/CU, chunks of 8"},
@@ -955,6 +1049,11 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     grid = ((grid + kQueues - 1) / kQueues) * kQueues;
     if (v.mode == 0) {
         hipLaunchKernelGGL((k_ragged_stream<TL, TS, kFull, 8>), dim3(grid), dim3(64 * 9), 0, s, *a, L.counters);
+        return hipGetLastError();
+    }
+    if (v.mode == 3) {
+        hipLaunchKernelGGL((k_ragged_pipe<TL, TS, full_cap<TL, TS, 43>()>), dim3(grid), dim3(kThreads), 0, s,
+                           *a, L.counters);
         return hipGetLastError();
     }
     if (v.chunk >= 8) return launch_chunked<TL, TS, 8>(a, grid, L.counters, s);
