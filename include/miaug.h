@@ -165,14 +165,18 @@ int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int
 /* ---------------------------------------------------------------- ragged batch
  * Sec. II-A: images of a detection / segmentation set (uneven sizes) are
  * transformed together with their masks and boxes.  Per image i: Dih4 element
- * (flags) -> brightness/contrast LUT (ab) -> bilinear resize to out_h x
- * out_w (half-pixel centres, replicate border) -> per-channel normalisation
+ * (flags) -> optional crop window (crop: the random-sized crop of the
+ * paper's detection example, Fig. 2) -> brightness/contrast LUT (ab) ->
+ * bilinear resize of the window to out_h x out_w (half-pixel centres,
+ * replicate border at the window's edges) -> per-channel normalisation
  * (float)(((double)v/255 - mean_c) / std_c) into float32 CHW.  The mask takes
- * the same Dih4 element and a nearest resize (source index
+ * the same Dih4 element and window and a nearest resize (source index
  * (q + 512) >> 10 of the same Q10 position).  Boxes take the Dih4 element
  * (hflip (W-x2, y1, W-x1, y2), vflip, rot90 (y1, W-x2, y2, W-x1), transpose
- * (y1, x1, y2, x2)) and the scale (out_w/W', out_h/H'), in double, stored as
- * float.
+ * (y1, x1, y2, x2)), the window (shift by (-x0, -y0), clip to [0, w] x
+ * [0, h]: a box outside the window keeps its slot with zero width or height)
+ * and the scale (out_w/w', out_h/h') of the window (or the whole Dih4 image),
+ * in double, stored as float.
  */
 typedef struct {
     int32_t n;               /* number of images (0 allowed)                      */
@@ -184,6 +188,10 @@ typedef struct {
                                 (its outputs are left untouched)                  */
     const int32_t *flags;    /* device: [n][4] Dih4 flags (miaug_sample_d4bc)      */
     const float *ab;         /* device: [n][2] alpha, beta                         */
+    const int32_t *crop;     /* device or NULL: [n][4] = {y0, x0, h, w} crop window
+                                of the Dih4 image (h = 0: no window for that
+                                image); an image whose window is not inside its
+                                Dih4 image (or has w < 1) is skipped               */
     const uint8_t *mask;     /* device or NULL: packed HW u8 masks                 */
     const int64_t *mask_off; /* device: [n] byte offsets (when mask != NULL)       */
     const float *boxes;      /* device or NULL: [nbox][4] xyxy                     */
@@ -342,8 +350,8 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  * must come in this order):
  *   MIAUG_PIPE_DIH4      [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
  *                        dense u8 images (and masks) -> u8, miaug_d4_bc_u8
- *   MIAUG_PIPE_RAGGED    [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
- *                        RESIZE [NORMALIZE]
+ *   MIAUG_PIPE_RAGGED    [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [SIZED_CROP]
+ *                        [BRIGHT_CONTRAST] RESIZE [NORMALIZE]
  *                        ragged RGB u8 + masks + boxes -> f32 NCHW, miaug_ragged_apply
  *   MIAUG_PIPE_U8CHAIN   [SSR] CROP RESIZE [HSV] [GAMMA] [BLUR3]
  *                        dense RGB u8 -> u8 (square crop and output),
@@ -364,6 +372,20 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *                     W, H); bilinear, reflect-101 only; skipped: identity.
  *   CROP              out_h x out_w window at offsets uniform in
  *                     {0 .. H - out_h} x {0 .. W - out_w}; p must be 1.
+ *   SIZED_CROP        p; random-sized crop of the Dih4 image (H' x W'):
+ *                     area fraction in [lo[0], hi[0]] (0 < lo, hi <= 1),
+ *                     aspect ratio w/h log-uniform in [lo[1], hi[1]].  Try t
+ *                     (t < 10) reads the four words of Philox block 16 j + 1 + t:
+ *                     s = lo0 + (hi0 - lo0) u(word 0), r = exp(log lo1 +
+ *                     (log hi1 - log lo1) u(word 1)), A = H' W' s,
+ *                     w = floor(sqrt(A r) + 1/2), h = floor(sqrt(A / r) + 1/2);
+ *                     the first try with 1 <= w <= W', 1 <= h <= H' takes
+ *                     crop_y = below(word 2, H' - h + 1), crop_x = below(word 3,
+ *                     W' - w + 1).  No try fits: a centred window with
+ *                     h = max(1, floor(W' / lo1 + 1/2)) if W'/H' < lo1,
+ *                     w = max(1, floor(H' hi1 + 1/2)) if W'/H' > hi1, else the
+ *                     whole image.  u(x) = (x >> 11) 2^-53, below(x, m) =
+ *                     ((x >> 32) m) >> 32.  Skipped: crop_h = crop_w = 0.
  *   RESIZE            to out_h x out_w; bilinear (masks: nearest).
  *   HSV               p; dh = rint(U[lo[0], hi[0]]) (2-degree units),
  *                     ds = rint(U[lo[1], hi[1]]), dv = rint(U[lo[2], hi[2]]).
@@ -382,7 +404,8 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
 enum {
     MIAUG_OP_HFLIP = 1, MIAUG_OP_VFLIP = 2, MIAUG_OP_ROT90 = 3, MIAUG_OP_TRANSPOSE = 4, MIAUG_OP_SSR = 5,
     MIAUG_OP_CROP = 6, MIAUG_OP_RESIZE = 7, MIAUG_OP_BRIGHT_CONTRAST = 8, MIAUG_OP_HSV = 9, MIAUG_OP_GAMMA = 10,
-    MIAUG_OP_BLUR3 = 11, MIAUG_OP_BLUR5 = 12, MIAUG_OP_ELASTIC = 13, MIAUG_OP_GRID = 14, MIAUG_OP_NORMALIZE = 15
+    MIAUG_OP_BLUR3 = 11, MIAUG_OP_BLUR5 = 12, MIAUG_OP_ELASTIC = 13, MIAUG_OP_GRID = 14, MIAUG_OP_NORMALIZE = 15,
+    MIAUG_OP_SIZED_CROP = 16
 };
 enum { MIAUG_INTERP_BILINEAR = 0, MIAUG_INTERP_NEAREST = 1 };
 enum { MIAUG_BORDER_REFLECT101 = 0, MIAUG_BORDER_CONSTANT = 1 };
@@ -409,7 +432,8 @@ typedef struct {
     int32_t dh, ds, dv;             /* HSV shifts                                */
     float gamma;                    /* gamma                                     */
     int32_t blur;                   /* 3x3 blur flag                             */
-    int32_t pad;
+    int32_t crop_h, crop_w;         /* random-sized crop window size (0: none);
+                                       its offsets are crop_y, crop_x            */
     double grid[10];                /* grid factors: x d_0..d_4, y d_0..d_4      */
 } miaug_params;
 

@@ -20,6 +20,7 @@ not contain (parity unpinned against the original library).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -104,8 +105,9 @@ _SIGS = {
     "or_image_stats_u8": (None, [_u8p, _i64, _i, _u64p, _i32p, _i32p, _u32p]),
     "or_pipe_d4bc": (None, [_u8p, _i, _i, _i, _i, _i32p, _f32p, _u8p]),
     "or_pipe_c2_one": (None, [_u8p, _i, _i, _f32p, _i32p, _i, _i, _u8p]),
-    "or_pipe_ragged_one": (None, [_u8p, ctypes.c_void_p, _i, _i, _i32p, _f32p, ctypes.c_void_p, _i,
-                                  _f32p, _f32p, _i, _i, _f32p, ctypes.c_void_p, ctypes.c_void_p]),
+    "or_pipe_ragged_one": (None, [_u8p, ctypes.c_void_p, _i, _i, _i32p, _f32p, ctypes.c_void_p, ctypes.c_void_p,
+                                  _i, _f32p, _f32p, _i, _i, _f32p, ctypes.c_void_p, ctypes.c_void_p]),
+    "or_boxes_d4_crop_resize": (None, [_f32p, _i, _i, _i, _i, _i, _i, _i, ctypes.c_void_p, _i, _i, _f32p]),
     "or_pipe_elastic_grid_one": (None, [_u8p, ctypes.c_void_p, _i, _i, _i, _u64, _u64, _d, _i, _i,
                                         _f64p, _u8p, ctypes.c_void_p]),
     "or_wc_forward": (None, [_f32p, _i, _i, _i, _f64p, _f64p]),
@@ -192,6 +194,48 @@ def sample_grid(seed: int, first: int, n: int, limit: float = 0.3):
     return f
 
 
+def _unit(word) -> float:
+    return (int(word) >> 11) * 2.0 ** -53
+
+
+def _below(word, m: int) -> int:
+    return ((int(word) >> 32) * m) >> 32
+
+
+def sized_crop_window(seed, index, draw0, H, W, scale=(0.08, 1.0), ratio=(0.75, 4.0 / 3.0), attempts=10):
+    """Window {y0, x0, h, w} of the random-sized crop (Sec. II and Fig. 2's detection
+    pipeline name a random-sized crop; the sampler is the usual area / aspect-ratio
+    scheme, written out here as this library reads it).
+
+    Try t (0 <= t < attempts) reads the four words of Philox block
+    {draw0 + t, index, 0, 0} under key {seed, 0}: word 0 gives the area fraction
+    s = lo + (hi - lo) u0, word 1 the aspect ratio r = exp(log lo_r + (log hi_r - log lo_r) u1);
+    with A = H W s, w = floor(sqrt(A r) + 1/2) and h = floor(sqrt(A / r) + 1/2).  The first
+    try with 1 <= w <= W and 1 <= h <= H wins, at y0 = below(word 2, H - h + 1),
+    x0 = below(word 3, W - w + 1).  When no try fits, the window is centred and keeps the
+    image's aspect ratio clamped into [lo_r, hi_r] (the full image if it is inside)."""
+    lo_s, hi_s = float(scale[0]), float(scale[1])
+    lo_r, hi_r = float(ratio[0]), float(ratio[1])
+    llo, lhi = math.log(lo_r), math.log(hi_r)
+    for t in range(attempts):
+        w4 = philox4x64_10([draw0 + t, index, 0, 0], [seed, 0])
+        s = lo_s + (hi_s - lo_s) * _unit(w4[0])
+        r = math.exp(llo + (lhi - llo) * _unit(w4[1]))
+        area = float(H) * float(W) * s
+        w = int(math.floor(math.sqrt(area * r) + 0.5))
+        h = int(math.floor(math.sqrt(area / r) + 0.5))
+        if 1 <= w <= W and 1 <= h <= H:
+            return np.array([_below(w4[2], H - h + 1), _below(w4[3], W - w + 1), h, w], np.int32)
+    in_r = float(W) / float(H)
+    if in_r < lo_r:
+        w, h = W, max(1, int(math.floor(W / lo_r + 0.5)))
+    elif in_r > hi_r:
+        h, w = H, max(1, int(math.floor(H * hi_r + 0.5)))
+    else:
+        h, w = H, W
+    return np.array([(H - h) // 2, (W - w) // 2, h, w], np.int32)
+
+
 # ---------------------------------------------------------------- geometry
 def _hwc(img):
     img = _c(img, np.uint8)
@@ -236,6 +280,16 @@ def boxes_d4_resize(boxes, H, W, flags, Hd, Wd):
     if len(boxes):
         lib().or_boxes_d4_resize(boxes, len(boxes), H, W, int(flags[0]), int(flags[1]), int(flags[2]),
                                  int(flags[3]), Hd, Wd, out)
+    return out
+
+
+def boxes_d4_crop_resize(boxes, H, W, flags, win, Hd, Wd):
+    boxes = _c(boxes, np.float32).reshape(-1, 4)
+    out = np.zeros_like(boxes)
+    win = None if win is None else _c(win, np.int32)
+    if len(boxes):
+        lib().or_boxes_d4_crop_resize(boxes, len(boxes), H, W, int(flags[0]), int(flags[1]), int(flags[2]),
+                                      int(flags[3]), _ptr(win), Hd, Wd, out)
     return out
 
 
@@ -417,15 +471,18 @@ def pipe_c2_one(img, f, k, crop_=448, outsz=224):
     return out
 
 
-def pipe_ragged_one(img, mask, flags, ab, boxes=None, Hd=224, Wd=224, mean=IMAGENET_MEAN, std=IMAGENET_STD):
+def pipe_ragged_one(img, mask, flags, ab, boxes=None, Hd=224, Wd=224, mean=IMAGENET_MEAN, std=IMAGENET_STD,
+                    win=None):
+    """win: None or {y0, x0, h, w}, a crop window of the Dih4 image."""
     img = _c(img, np.uint8); H, W = img.shape[:2]
+    win = None if win is None else _c(win, np.int32)
     out = np.zeros((3, Hd, Wd), np.float32)
     om = np.zeros((Hd, Wd), np.uint8) if mask is not None else None
     mask = _c(mask, np.uint8) if mask is not None else None
     nb = 0 if boxes is None else len(boxes)
     boxes = _c(boxes, np.float32).reshape(-1, 4) if nb else None
     ob = np.zeros((nb, 4), np.float32) if nb else None
-    lib().or_pipe_ragged_one(img, _ptr(mask), H, W, _c(flags, np.int32), _c(ab, np.float32), _ptr(boxes), nb,
+    lib().or_pipe_ragged_one(img, _ptr(mask), H, W, _c(flags, np.int32), _c(ab, np.float32), _ptr(win), _ptr(boxes), nb,
                              _c(mean, np.float32), _c(std, np.float32), Hd, Wd, out, _ptr(om), _ptr(ob))
     return out, om, (ob if nb else np.zeros((0, 4), np.float32))
 

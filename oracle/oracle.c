@@ -266,23 +266,61 @@ void or_d4(const uint8_t *in, int H, int W, int C, int hflip, int vflip, int k, 
 
 /* Boxes (xyxy, continuous pixel coordinates) follow the same Dih4 ops and a
  * final resize to (Hd, Wd) (Sec. II-A: boxes follow spatial transforms). */
+/* One box (double xyxy, in place) under the Dih4 ops one after the other;
+ * (*h, *w) go from the source size to the Dih4 image's size. */
+static void box_d4(double *x1, double *y1, double *x2, double *y2, double *h, double *w, int hflip, int vflip,
+                   int k, int transpose)
+{
+    if (hflip) { double a = *w - *x2, b = *w - *x1; *x1 = a; *x2 = b; }
+    if (vflip) { double a = *h - *y2, b = *h - *y1; *y1 = a; *y2 = b; }
+    for (int r = 0; r < (k & 3); ++r) {
+        double nx1 = *y1, ny1 = *w - *x2, nx2 = *y2, ny2 = *w - *x1;
+        *x1 = nx1; *y1 = ny1; *x2 = nx2; *y2 = ny2;
+        double s = *h; *h = *w; *w = s;
+    }
+    if (transpose) {
+        double nx1 = *y1, ny1 = *x1, nx2 = *y2, ny2 = *x2;
+        *x1 = nx1; *y1 = ny1; *x2 = nx2; *y2 = ny2;
+        double s = *h; *h = *w; *w = s;
+    }
+}
+
 void or_boxes_d4_resize(const float *boxes, int nb, int H, int W, int hflip, int vflip, int k,
                         int transpose, int Hd, int Wd, float *out)
 {
     for (int i = 0; i < nb; ++i) {
         double x1 = boxes[4 * i + 0], y1 = boxes[4 * i + 1], x2 = boxes[4 * i + 2], y2 = boxes[4 * i + 3];
         double h = H, w = W;
-        if (hflip) { double a = w - x2, b = w - x1; x1 = a; x2 = b; }
-        if (vflip) { double a = h - y2, b = h - y1; y1 = a; y2 = b; }
-        for (int r = 0; r < (k & 3); ++r) {
-            double nx1 = y1, ny1 = w - x2, nx2 = y2, ny2 = w - x1;
-            x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
-            double s = h; h = w; w = s;
-        }
-        if (transpose) {
-            double nx1 = y1, ny1 = x1, nx2 = y2, ny2 = x2;
-            x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
-            double s = h; h = w; w = s;
+        box_d4(&x1, &y1, &x2, &y2, &h, &w, hflip, vflip, k, transpose);
+        double sx = (double)Wd / w, sy = (double)Hd / h;
+        out[4 * i + 0] = (float)(x1 * sx);
+        out[4 * i + 1] = (float)(y1 * sy);
+        out[4 * i + 2] = (float)(x2 * sx);
+        out[4 * i + 3] = (float)(y2 * sy);
+    }
+}
+
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Boxes under Dih4, then a crop window win = {y0, x0, h, w} of the Dih4 image
+ * (the random-sized crop of Fig. 2's detection pipeline), then a resize of the
+ * window to (Hd, Wd).  The crop shifts the box by (-x0, -y0) and clips it to
+ * the window; a box outside the window becomes one of zero width or height
+ * (it keeps its slot, so the box count per image is unchanged). */
+void or_boxes_d4_crop_resize(const float *boxes, int nb, int H, int W, int hflip, int vflip, int k,
+                             int transpose, const int32_t *win, int Hd, int Wd, float *out)
+{
+    for (int i = 0; i < nb; ++i) {
+        double x1 = boxes[4 * i + 0], y1 = boxes[4 * i + 1], x2 = boxes[4 * i + 2], y2 = boxes[4 * i + 3];
+        double h = H, w = W;
+        box_d4(&x1, &y1, &x2, &y2, &h, &w, hflip, vflip, k, transpose);
+        if (win) {
+            h = win[2];
+            w = win[3];
+            x1 = clampd(x1 - win[1], 0.0, w);
+            x2 = clampd(x2 - win[1], 0.0, w);
+            y1 = clampd(y1 - win[0], 0.0, h);
+            y2 = clampd(y2 - win[0], 0.0, h);
         }
         double sx = (double)Wd / w, sy = (double)Hd / h;
         out[4 * i + 0] = (float)(x1 * sx);
@@ -775,34 +813,48 @@ void or_pipe_c2_one(const uint8_t *img, int H, int W, const float *f, const int3
 }
 
 /* Ragged-batch pipeline for one image (Sec. II-A: image, masks and boxes
- * transformed together): Dih4 -> brightness/contrast -> resize (Hd x Wd,
- * bilinear) -> normalise to CHW f32; the mask takes Dih4 -> nearest resize;
- * boxes take Dih4 -> scale.  mask/boxes may be NULL. */
+ * transformed together): Dih4 -> [crop window] -> brightness/contrast ->
+ * resize (Hd x Wd, bilinear) -> normalise to CHW f32; the mask takes Dih4 ->
+ * [crop] -> nearest resize; boxes take Dih4 -> [crop: shift, clip] -> scale.
+ * win (NULL: none) = {y0, x0, h, w} inside the Dih4 image; mask/boxes may be
+ * NULL. */
 void or_pipe_ragged_one(const uint8_t *img, const uint8_t *mask, int H, int W, const int32_t *flags,
-                        const float *ab, const float *boxes, int nb, const float *mean, const float *stdv,
-                        int Hd, int Wd, float *out, uint8_t *out_mask, float *out_boxes)
+                        const float *ab, const int32_t *win, const float *boxes, int nb, const float *mean,
+                        const float *stdv, int Hd, int Wd, float *out, uint8_t *out_mask, float *out_boxes)
 {
     int ho, wo;
     uint8_t lut[256];
     float nlut[3 * 256];
     uint8_t *d = (uint8_t *)malloc((size_t)H * W * 3);
+    uint8_t *c = (uint8_t *)malloc((size_t)H * W * 3);
     uint8_t *l = (uint8_t *)malloc((size_t)H * W * 3);
     uint8_t *r = (uint8_t *)malloc((size_t)Hd * Wd * 3);
     or_d4(img, H, W, 3, flags[0], flags[1], flags[2], flags[3], d, &ho, &wo);
+    int hc = ho, wc = wo;
+    if (win) {  /* crop window {y0, x0, h, w} of the Dih4 image */
+        or_crop_u8(d, ho, wo, 3, win[1], win[0], win[2], win[3], c);
+        hc = win[2];
+        wc = win[3];
+    } else {
+        memcpy(c, d, (size_t)H * W * 3);
+    }
     or_bc_lut(ab[0], ab[1], lut);
-    or_apply_lut(d, (int64_t)H * W * 3, lut, l);
-    or_resize_u8(l, ho, wo, 3, r, Hd, Wd, OR_BILINEAR);
+    or_apply_lut(c, (int64_t)hc * wc * 3, lut, l);
+    or_resize_u8(l, hc, wc, 3, r, Hd, Wd, OR_BILINEAR);
     or_normalize_lut(mean, stdv, 3, nlut);
     or_normalize_chw(r, Hd, Wd, 3, nlut, out);
     if (mask && out_mask) {
         uint8_t *md = (uint8_t *)malloc((size_t)H * W);
+        uint8_t *mc = (uint8_t *)malloc((size_t)H * W);
         or_d4(mask, H, W, 1, flags[0], flags[1], flags[2], flags[3], md, &ho, &wo);
-        or_resize_u8(md, ho, wo, 1, out_mask, Hd, Wd, OR_NEAREST);
-        free(md);
+        if (win) or_crop_u8(md, ho, wo, 1, win[1], win[0], win[2], win[3], mc);
+        else memcpy(mc, md, (size_t)H * W);
+        or_resize_u8(mc, hc, wc, 1, out_mask, Hd, Wd, OR_NEAREST);
+        free(md); free(mc);
     }
     if (boxes && out_boxes && nb > 0)
-        or_boxes_d4_resize(boxes, nb, H, W, flags[0], flags[1], flags[2], flags[3], Hd, Wd, out_boxes);
-    free(d); free(l); free(r);
+        or_boxes_d4_crop_resize(boxes, nb, H, W, flags[0], flags[1], flags[2], flags[3], win, Hd, Wd, out_boxes);
+    free(d); free(c); free(l); free(r);
 }
 
 /* Large-tile pipeline for one image: elastic (bilinear image, nearest mask,

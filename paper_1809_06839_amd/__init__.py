@@ -37,7 +37,7 @@ _vp, _i, _i64, _u64, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ct
 class RaggedArgs(ctypes.Structure):
     """Mirror of miaug_ragged_args (include/miaug.h)."""
     _fields_ = [("n", ctypes.c_int32), ("out_h", ctypes.c_int32), ("out_w", ctypes.c_int32),
-                ("img", _vp), ("img_off", _vp), ("hw", _vp), ("flags", _vp), ("ab", _vp),
+                ("img", _vp), ("img_off", _vp), ("hw", _vp), ("flags", _vp), ("ab", _vp), ("crop", _vp),
                 ("mask", _vp), ("mask_off", _vp), ("boxes", _vp), ("box_off", _vp),
                 ("mean", ctypes.c_float * 3), ("stdv", ctypes.c_float * 3),
                 ("out", _vp), ("out_mask", _vp), ("out_boxes", _vp)]
@@ -64,7 +64,8 @@ class Params(ctypes.Structure):
                 ("scale", ctypes.c_float), ("dx", ctypes.c_float), ("dy", ctypes.c_float),
                 ("crop_x", ctypes.c_int32), ("crop_y", ctypes.c_int32), ("dh", ctypes.c_int32),
                 ("ds", ctypes.c_int32), ("dv", ctypes.c_int32), ("gamma", ctypes.c_float),
-                ("blur", ctypes.c_int32), ("pad", ctypes.c_int32), ("grid", ctypes.c_double * 10)]
+                ("blur", ctypes.c_int32), ("crop_h", ctypes.c_int32), ("crop_w", ctypes.c_int32),
+                ("grid", ctypes.c_double * 10)]
 
 
 class BatchIn(ctypes.Structure):
@@ -276,11 +277,14 @@ class Ragged:
     """Device-side ragged batch + outputs, packed into one miaug_ragged_args."""
 
     def __init__(self, img, img_off, hw, flags, ab, out_h=224, out_w=224, mask=None, mask_off=None, boxes=None,
-                 box_off=None, mean=IMAGENET_MEAN, std=IMAGENET_STD, out=None, out_mask=None, out_boxes=None):
+                 box_off=None, mean=IMAGENET_MEAN, std=IMAGENET_STD, out=None, out_mask=None, out_boxes=None,
+                 crop=None):
         n = hw.shape[0]
         dev = img.device
         _dev(img, torch.uint8, "img"); _dev(img_off, torch.int64, "img_off"); _dev(hw, torch.int32, "hw")
         _dev(flags, torch.int32, "flags"); _dev(ab, torch.float32, "ab")
+        if crop is not None:
+            _dev(crop, torch.int32, "crop")
         self.out = out if out is not None else torch.empty((n, 3, out_h, out_w), dtype=torch.float32, device=dev)
         self.out_mask = None
         self.out_boxes = None
@@ -291,10 +295,11 @@ class Ragged:
         if boxes is not None:
             _dev(boxes, torch.float32, "boxes"); _dev(box_off, torch.int32, "box_off")
             self.out_boxes = out_boxes if out_boxes is not None else torch.empty_like(boxes)
-        self.keep = (img, img_off, hw, flags, ab, mask, mask_off, boxes, box_off)
+        self.keep = (img, img_off, hw, flags, ab, mask, mask_off, boxes, box_off, crop)
         a = RaggedArgs()
         a.n, a.out_h, a.out_w = n, out_h, out_w
         a.img, a.img_off, a.hw, a.flags, a.ab = (t.data_ptr() for t in (img, img_off, hw, flags, ab))
+        a.crop = crop.data_ptr() if crop is not None else None
         a.mask = mask.data_ptr() if mask is not None else None
         a.mask_off = mask_off.data_ptr() if mask is not None else None
         a.boxes = boxes.data_ptr() if boxes is not None and boxes.numel() > 0 else None
@@ -307,8 +312,9 @@ class Ragged:
         self.args = a
 
     @classmethod
-    def from_host(cls, batch, flags, ab, device="cuda", **kw):
-        """Uploads a synth.RaggedBatch-like host batch and host parameters."""
+    def from_host(cls, batch, flags, ab, device="cuda", crop=None, **kw):
+        """Uploads a synth.RaggedBatch-like host batch and host parameters
+        (crop: optional host int32 [n][4] windows {y0, x0, h, w})."""
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dt).to(device)
         has_mask = batch.mask is not None
         has_boxes = batch.boxes is not None and len(batch.boxes) > 0
@@ -317,7 +323,8 @@ class Ragged:
                    mask=t(batch.mask, torch.uint8) if has_mask else None,
                    mask_off=t(batch.mask_off, torch.int64) if has_mask else None,
                    boxes=t(batch.boxes, torch.float32) if has_boxes else None,
-                   box_off=t(batch.box_off, torch.int32) if has_boxes else None, **kw)
+                   box_off=t(batch.box_off, torch.int32) if has_boxes else None,
+                   crop=t(crop, torch.int32) if crop is not None else None, **kw)
 
 
 def ragged_apply(ctx: Context, r: Ragged, stream=None):
@@ -500,7 +507,8 @@ def image_stats_u8(img, C=None, stream=None):
 
 # ---------------------------------------------------------------- op-list pipelines
 OP = {"HFLIP": 1, "VFLIP": 2, "ROT90": 3, "TRANSPOSE": 4, "SSR": 5, "CROP": 6, "RESIZE": 7, "BRIGHT_CONTRAST": 8,
-      "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15}
+      "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15,
+      "SIZED_CROP": 16}
 PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT"}
 INTERP_BILINEAR, INTERP_NEAREST = 0, 1
 BORDER_REFLECT101, BORDER_CONSTANT = 0, 1

@@ -147,8 +147,9 @@ __device__ __forceinline__ void build_bc_lut(float alpha, float beta, uint8_t *l
     lut[tid] = (uint8_t)sat8((int)rint(v));
 }
 
-// Boxes of one image: Dih4 ops one after the other, then the scale to the
-// output size, in double.
+// Boxes of one image: Dih4 ops one after the other, the shift into the crop
+// window and the clip to it (when there is one), then the scale to the output
+// size, in double.  Called only for images whose window is valid.
 template <int NT>
 __device__ __forceinline__ void ragged_boxes(const miaug_ragged_args &a, int img) {
     int b0 = ldc(a.box_off + img), b1 = ldc(a.box_off + img + 1);
@@ -169,6 +170,15 @@ __device__ __forceinline__ void ragged_boxes(const miaug_ragged_args &a, int img
             x1 = nx1; y1 = ny1; x2 = nx2; y2 = ny2;
             double s = h; h = w; w = s;
         }
+        if (a.crop && ldc(a.crop + 4 * img + 2) != 0) {  // shift into the crop window and clip to it
+            const double wy = ldc(a.crop + 4 * img), wx = ldc(a.crop + 4 * img + 1);
+            h = ldc(a.crop + 4 * img + 2);
+            w = ldc(a.crop + 4 * img + 3);
+            x1 = fmin(fmax(x1 - wx, 0.0), w);
+            x2 = fmin(fmax(x2 - wx, 0.0), w);
+            y1 = fmin(fmax(y1 - wy, 0.0), h);
+            y2 = fmin(fmax(y2 - wy, 0.0), h);
+        }
         double sx = (double)a.out_w / w, sy = (double)a.out_h / h;
         a.out_boxes[4 * b] = (float)(x1 * sx);
         a.out_boxes[4 * b + 1] = (float)(y1 * sy);
@@ -183,6 +193,7 @@ struct ImgInfo {
     int H, W, f0, f1, f2, f3;
     int64_t io, mo;  // byte offsets of the image and mask
     float alpha, beta;
+    int wy, wx, wh, ww;  // crop window of the Dih4 image (wh = 0: none)
 };
 
 // Through scalar loads (uniform img).
@@ -199,10 +210,17 @@ __device__ __forceinline__ ImgInfo info_scalar(const miaug_ragged_args &a, int i
     r.mo = a.mask ? ldc(a.mask_off + img) : 0;
     r.alpha = ldc(a.ab + 2 * img);
     r.beta = ldc(a.ab + 2 * img + 1);
+    r.wy = r.wx = r.wh = r.ww = 0;
+    if (a.crop) {
+        r.wy = ldc(a.crop + 4 * img);
+        r.wx = ldc(a.crop + 4 * img + 1);
+        r.wh = ldc(a.crop + 4 * img + 2);
+        r.ww = ldc(a.crop + 4 * img + 3);
+    }
     return r;
 }
 
-// Asynchronous form for a whole wave: lane l < 12 loads field l of image img
+// Asynchronous form for a whole wave: lane l < 16 loads field l of image img
 // with one vector load (counted by vmcnt, so it can stay in flight across LDS
 // work); info_gather() assembles the fields once the load has completed.
 __device__ __forceinline__ int info_issue(const miaug_ragged_args &a, int img) {
@@ -213,6 +231,7 @@ __device__ __forceinline__ int info_issue(const miaug_ragged_args &a, int img) {
     else if (l < 8) p = (const int32_t *)(a.img_off + img) + (l - 6);
     else if (l < 10 && a.mask) p = (const int32_t *)(a.mask_off + img) + (l - 8);
     else if (l >= 10 && l < 12) p = (const int32_t *)(a.ab + 2 * img) + (l - 10);
+    else if (l >= 12 && l < 16 && a.crop) p = a.crop + 4 * img + (l - 12);
     return p ? *p : 0;
 }
 
@@ -230,6 +249,10 @@ __device__ __forceinline__ ImgInfo info_gather(int v) {
                      (uint32_t)__builtin_amdgcn_readlane(v, 8));
     r.alpha = __int_as_float(__builtin_amdgcn_readlane(v, 10));
     r.beta = __int_as_float(__builtin_amdgcn_readlane(v, 11));
+    r.wy = __builtin_amdgcn_readlane(v, 12);
+    r.wx = __builtin_amdgcn_readlane(v, 13);
+    r.wh = __builtin_amdgcn_readlane(v, 14);
+    r.ww = __builtin_amdgcn_readlane(v, 15);
     return r;
 }
 
@@ -266,6 +289,19 @@ __device__ __forceinline__ Pass make_pass(const miaug_ragged_args &a, const ImgI
     p.beta = in.beta;
     p.empty = p.H < 1 || p.W < 1 || p.H >= kMaxSide || p.W >= kMaxSide || (int64_t)p.H * p.W * 3 >= ((int64_t)1 << 31);
     p.m = make_d4(p.empty ? 1 : p.H, p.empty ? 1 : p.W, in.f0, in.f1, in.f2, in.f3);
+    if (in.wh != 0 && !p.empty) {
+        // crop window (wy, wx, wh, ww) of the Dih4 image: output (r, c) of the
+        // window is (r + wy, c + wx) of that image; a window that is not inside
+        // it skips the image
+        if (in.wy < 0 || in.wx < 0 || in.wh < 1 || in.ww < 1 || in.wh > p.m.oh - in.wy || in.ww > p.m.ow - in.wx) {
+            p.empty = true;
+        } else {
+            p.m.cy += p.m.ay * in.wy + p.m.by * in.wx;
+            p.m.cx += p.m.ax * in.wy + p.m.bx * in.wx;
+            p.m.oh = in.wh;
+            p.m.ow = in.ww;
+        }
+    }
     p.swap = p.m.swaps();
     p.OL = p.swap ? a.out_w : a.out_h;
     p.OS = p.swap ? a.out_h : a.out_w;

@@ -24,17 +24,63 @@ inline U128 mul64(uint64_t a, uint64_t b) {
     unsigned __int128 p = (unsigned __int128)a * b;
     return {(uint64_t)(p >> 64), (uint64_t)p};
 }
-uint64_t philox_word0(uint64_t d, uint64_t g, uint64_t seed) {
+// All four words of the block with counter {d, g, 0, 0} and key {seed, 0}.
+void philox_block(uint64_t d, uint64_t g, uint64_t seed, uint64_t (&c)[4]) {
     const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
     const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-    uint64_t c[4] = {d, g, 0, 0}, k0 = seed, k1 = 0;
+    c[0] = d; c[1] = g; c[2] = 0; c[3] = 0;
+    uint64_t k0 = seed, k1 = 0;
     for (int r = 0; r < 10; ++r) {
         U128 p0 = mul64(M0, c[0]), p1 = mul64(M1, c[2]);
         uint64_t o0 = p1.hi ^ c[1] ^ k0, o2 = p0.hi ^ c[3] ^ k1;
         c[0] = o0; c[1] = p1.lo; c[2] = o2; c[3] = p0.lo;
         k0 += W0; k1 += W1;
     }
+}
+uint64_t philox_word0(uint64_t d, uint64_t g, uint64_t seed) {
+    uint64_t c[4];
+    philox_block(d, g, seed, c);
     return c[0];
+}
+double unit_of(uint64_t w) { return (double)(w >> 11) * 0x1.0p-53; }
+int below_of(uint64_t w, uint32_t m) { return (int)(((w >> 32) * (uint64_t)m) >> 32); }
+
+// Random-sized crop window {y0, x0, h, w} of an H x W image: up to 10 tries,
+// try t reading the four words of block d + t (area fraction, log aspect
+// ratio, row offset, column offset); the first window that fits wins, else a
+// centred window with the aspect ratio clamped into [rlo, rhi].
+void sized_crop(uint64_t seed, uint64_t g, uint64_t d, int H, int W, double slo, double shi, double rlo,
+                double rhi, int32_t (&win)[4]) {
+    const double llo = log(rlo), lhi = log(rhi);
+    for (int t = 0; t < 10; ++t) {
+        uint64_t c[4];
+        philox_block(d + (uint64_t)t, g, seed, c);
+        const double s = slo + (shi - slo) * unit_of(c[0]);
+        const double r = exp(llo + (lhi - llo) * unit_of(c[1]));
+        const double area = (double)H * (double)W * s;
+        const double wf = floor(sqrt(area * r) + 0.5), hf = floor(sqrt(area / r) + 0.5);
+        if (wf >= 1.0 && wf <= (double)W && hf >= 1.0 && hf <= (double)H) {
+            const int w = (int)wf, h = (int)hf;
+            win[0] = below_of(c[2], (uint32_t)(H - h + 1));
+            win[1] = below_of(c[3], (uint32_t)(W - w + 1));
+            win[2] = h;
+            win[3] = w;
+            return;
+        }
+    }
+    int h = H, w = W;
+    const double in_r = (double)W / (double)H;
+    if (in_r < rlo) {
+        h = (int)floor((double)W / rlo + 0.5);
+        h = h < 1 ? 1 : h;
+    } else if (in_r > rhi) {
+        w = (int)floor((double)H * rhi + 0.5);
+        w = w < 1 ? 1 : w;
+    }
+    win[0] = (H - h) / 2;
+    win[1] = (W - w) / 2;
+    win[2] = h;
+    win[3] = w;
 }
 struct Gen {
     uint64_t seed, g;
@@ -47,15 +93,16 @@ struct Gen {
 const char *op_name(uint32_t k) {
     static const char *names[] = {"?", "HFLIP", "VFLIP", "ROT90", "TRANSPOSE", "SSR", "CROP", "RESIZE",
                                   "BRIGHT_CONTRAST", "HSV", "GAMMA", "BLUR3", "BLUR5", "ELASTIC", "GRID",
-                                  "NORMALIZE"};
+                                  "NORMALIZE", "SIZED_CROP"};
     return k < sizeof(names) / sizeof(names[0]) ? names[k] : "?";
 }
 
 // Allowed op sequences per chain (each op at most once, in this order).
 const uint32_t kSeqDih4[] = {MIAUG_OP_HFLIP, MIAUG_OP_VFLIP, MIAUG_OP_ROT90, MIAUG_OP_TRANSPOSE,
                              MIAUG_OP_BRIGHT_CONTRAST};
-const uint32_t kSeqRagged[] = {MIAUG_OP_HFLIP,           MIAUG_OP_VFLIP,  MIAUG_OP_ROT90, MIAUG_OP_TRANSPOSE,
-                               MIAUG_OP_BRIGHT_CONTRAST, MIAUG_OP_RESIZE, MIAUG_OP_NORMALIZE};
+const uint32_t kSeqRagged[] = {MIAUG_OP_HFLIP,      MIAUG_OP_VFLIP,           MIAUG_OP_ROT90,
+                               MIAUG_OP_TRANSPOSE,  MIAUG_OP_SIZED_CROP,      MIAUG_OP_BRIGHT_CONTRAST,
+                               MIAUG_OP_RESIZE,     MIAUG_OP_NORMALIZE};
 const uint32_t kSeqU8[] = {MIAUG_OP_SSR, MIAUG_OP_CROP, MIAUG_OP_RESIZE, MIAUG_OP_HSV, MIAUG_OP_GAMMA, MIAUG_OP_BLUR3};
 const uint32_t kSeqDistort[] = {MIAUG_OP_ELASTIC, MIAUG_OP_GRID};
 
@@ -89,6 +136,7 @@ struct miaug_pipeline {
     int crop_h, crop_w;      // CROP size (U8CHAIN)
     float mean[3], stdv[3];  // NORMALIZE (RAGGED)
     int el_alpha, el_radius; // ELASTIC (DISTORT); el_alpha < 0: no elastic op
+    bool wcrop;              // SIZED_CROP (RAGGED): records carry a crop window
     double el_sigma;
     bool el_box;             // box-cascade approximation of the field
     // pinned staging of packed records, device copies, chain buffers
@@ -154,10 +202,14 @@ int op_check(const miaug_op &o, int i) {
         for (int c = 0; c < 3; ++c)
             if (!(o.hi[c] != 0.f)) return set_error(MIAUG_EINVAL, "pipeline: op %d (NORMALIZE): std[%d] is 0", i, c);
         break;
+    case MIAUG_OP_SIZED_CROP:
+        if (!(o.lo[0] > 0.f && o.hi[0] <= 1.f && o.lo[1] > 0.f))
+            return set_error(MIAUG_EINVAL, "pipeline: op %d (SIZED_CROP): need 0 < scale <= 1, ratio > 0", i);
+        break;
     case MIAUG_OP_BLUR5:
         return set_error(MIAUG_EUNSUPPORTED, "pipeline: op %d (BLUR5): no fused chain takes a 5x5 blur", i);
     default:
-        if (o.kind < MIAUG_OP_HFLIP || o.kind > MIAUG_OP_NORMALIZE)
+        if (o.kind < MIAUG_OP_HFLIP || o.kind > MIAUG_OP_SIZED_CROP)
             return set_error(MIAUG_EINVAL, "pipeline: op %d: unknown kind %u", i, o.kind);
     }
     return MIAUG_OK;
@@ -190,13 +242,14 @@ int grow_device(void **ptr, size_t *cap, size_t bytes, const char *what) {
 }
 
 // Packed device form of the records of one batch (host side), by chain:
-//   DIH4, RAGGED: int32 flags [n][4], then float ab [n][2]
+//   DIH4, RAGGED: int32 flags [n][4], then float ab [n][2] (RAGGED with
+//                 SIZED_CROP: then int32 windows [n][4])
 //   U8CHAIN:      miaug_c2_record [n]
 //   DISTORT:      double grid [n][10]
 size_t packed_bytes(const miaug_pipeline *p, int n) {
     switch (p->kind) {
-    case MIAUG_PIPE_DIH4:
-    case MIAUG_PIPE_RAGGED: return (size_t)n * 24;
+    case MIAUG_PIPE_DIH4: return (size_t)n * 24;
+    case MIAUG_PIPE_RAGGED: return (size_t)n * (p->wcrop ? 40 : 24);
     case MIAUG_PIPE_U8CHAIN: return (size_t)n * sizeof(miaug_c2_record);
     default: return (size_t)n * 10 * sizeof(double);
     }
@@ -210,6 +263,15 @@ int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, vo
             for (int k = 0; k < 4; ++k) fl[4 * i + k] = r[i].flags[k];
             ab[2 * i] = r[i].alpha;
             ab[2 * i + 1] = r[i].beta;
+        }
+        if (p->wcrop) {
+            int32_t *win = (int32_t *)((char *)dst + (size_t)n * 24);
+            for (int i = 0; i < n; ++i) {
+                win[4 * i] = r[i].crop_y;
+                win[4 * i + 1] = r[i].crop_x;
+                win[4 * i + 2] = r[i].crop_h;
+                win[4 * i + 3] = r[i].crop_w;
+            }
         }
         return MIAUG_OK;
     }
@@ -288,6 +350,7 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
             a.hw = in->hw;
             a.flags = fl;
             a.ab = ab;
+            a.crop = p->wcrop ? (const int32_t *)((char *)dp + (size_t)n * 24) : nullptr;
             a.mask = in->mask;
             a.mask_off = in->mask_off;
             a.boxes = in->boxes;
@@ -450,7 +513,7 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
         int kind;
         const uint32_t *seq;
         int nseq;
-    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 5}, {MIAUG_PIPE_RAGGED, kSeqRagged, 7}, {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},
+    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 5}, {MIAUG_PIPE_RAGGED, kSeqRagged, 8}, {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},
                  {MIAUG_PIPE_DISTORT, kSeqDistort, 2}};
     int kind = 0, worst = -1;
     for (const Cand &c : cands) {
@@ -485,7 +548,9 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     p->el_radius = 0;
     p->el_sigma = 0.0;
     p->el_box = false;
+    p->wcrop = false;
     for (const miaug_op &o : p->ops) {
+        if (o.kind == MIAUG_OP_SIZED_CROP) p->wcrop = true;
         if (o.kind == MIAUG_OP_RESIZE) {
             p->out_h = o.out_h;
             p->out_w = o.out_w;
@@ -540,8 +605,9 @@ int miaug_sample(const miaug_pipeline *p, uint64_t seed, uint64_t first_index, i
                  miaug_params *params) {
     clear_error();
     if (!p || n < 0 || (n > 0 && !params)) return set_error(MIAUG_EINVAL, "sample: bad arguments");
-    const bool crop = has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_CROP);
-    if (crop && n > 0 && !hw) return set_error(MIAUG_EINVAL, "sample: the op list has CROP: source sizes needed");
+    const bool crop = has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_CROP) ||
+                      has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_SIZED_CROP);
+    if (crop && n > 0 && !hw) return set_error(MIAUG_EINVAL, "sample: the op list crops: source sizes needed");
     for (int i = 0; i < n; ++i) {
         miaug_params &r = params[i];
         memset(&r, 0, sizeof(r));
@@ -585,6 +651,20 @@ int miaug_sample(const miaug_pipeline *p, uint64_t seed, uint64_t first_index, i
                 r.crop_x = G.below(d + 2, (uint32_t)(W - o.out_w + 1));
                 break;
             }
+            case MIAUG_OP_SIZED_CROP:
+                if (on) {
+                    // the window lives in the Dih4 image (drawn by the ops before this one)
+                    const bool swap = ((r.flags[2] & 1) != 0) != (r.flags[3] != 0);
+                    const int H = swap ? hw[2 * i + 1] : hw[2 * i], W = swap ? hw[2 * i] : hw[2 * i + 1];
+                    if (H < 1 || W < 1) return set_error(MIAUG_ESHAPE, "sample: sample %d: empty image", i);
+                    int32_t win[4];
+                    sized_crop(seed, r.index, d + 1, H, W, o.lo[0], o.hi[0], o.lo[1], o.hi[1], win);
+                    r.crop_y = win[0];
+                    r.crop_x = win[1];
+                    r.crop_h = win[2];
+                    r.crop_w = win[3];
+                }
+                break;
             case MIAUG_OP_HSV:
                 if (on) {
                     r.dh = (int32_t)rint((double)G.range(d + 1, o.lo[0], o.hi[0]));
@@ -710,6 +790,7 @@ int miaug_pipeline_autotune(miaug_pipeline *p, const miaug_batch_in *in, const m
     a.hw = in->hw;
     a.flags = (const int32_t *)p->dparams;
     a.ab = (const float *)((char *)p->dparams + (size_t)in->n * 16);
+    a.crop = p->wcrop ? (const int32_t *)((char *)p->dparams + (size_t)in->n * 24) : nullptr;
     a.mask = in->mask;
     a.mask_off = in->mask_off;
     a.boxes = in->boxes;

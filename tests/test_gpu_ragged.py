@@ -122,3 +122,76 @@ def test_full_size_batch_sampled_against_oracle(m, ctx):
     m.ragged_apply_per_image(ctx, r)
     torch.cuda.synchronize()
     assert torch.equal(out_b, r.out) and torch.equal(m_b, r.out_mask)
+
+
+# ---------------------------------------------------------------- crop windows (random-sized crop)
+def d4_shape(h, w, fl):
+    swap = (int(fl[2]) & 1) != int(fl[3] != 0)
+    return (w, h) if swap else (h, w)
+
+
+def crop_windows(b, flags, seed, scale=(0.08, 1.0), ratio=(0.75, 4 / 3)):
+    win = np.zeros((b.n, 4), np.int32)
+    for i in range(b.n):
+        H, W = d4_shape(int(b.hw[i][0]), int(b.hw[i][1]), flags[i])
+        win[i] = oracle.sized_crop_window(seed, i, 1, H, W, scale, ratio)
+    return win
+
+
+def check_crop_outputs(b, r, flags, ab, win, idx, OH=224, OW=224):
+    out, om = r.out.cpu().numpy(), r.out_mask.cpu().numpy()
+    ob = r.out_boxes.cpu().numpy() if r.out_boxes is not None else None
+    for i in idx:
+        ref, rm, rb = oracle.pipe_ragged_one(b.image(i), b.mask_of(i), flags[i], ab[i], b.boxes_of(i), OH, OW,
+                                             win=win[i])
+        assert np.array_equal(out[i].view(np.uint32), ref.view(np.uint32)), ("image", i, tuple(win[i]))
+        assert np.array_equal(om[i], rm), ("mask", i, tuple(win[i]))
+        if len(rb):
+            got = ob[b.box_off[i]:b.box_off[i + 1]]
+            assert np.all(np.abs(got - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), ("boxes", i)
+
+
+@pytest.mark.parametrize("variant", range(8))
+def test_crop_windows_all_variants_bit_exact(m, ctx, small, variant):
+    if variant >= len(m.ragged_variants()):
+        pytest.skip("the library has fewer variants")
+    b, flags, ab = small
+    win = crop_windows(b, flags, 77)
+    win[3] = (0, 0, *d4_shape(int(b.hw[3][0]), int(b.hw[3][1]), flags[3]))  # the whole image
+    ctx.set_variant(variant)
+    r = m.Ragged.from_host(b, flags, ab, crop=win)
+    m.ragged_apply(ctx, r)
+    check_crop_outputs(b, r, flags, ab, win, range(b.n))
+    ctx.set_variant(-1)
+
+
+def test_crop_window_per_image_form_and_skips(m, ctx, small):
+    import torch
+    b, flags, ab = small
+    win = crop_windows(b, flags, 78, scale=(0.3, 0.9))
+    win[5, 2] = 0          # h = 0: no window for image 5
+    bad = [1, 6]
+    win[1] = (0, 0, 2, 400)  # wider than the image
+    win[6] = (-1, 0, 1, 1)   # negative offset
+    r = m.Ragged.from_host(b, flags, ab, crop=win)
+    r.out.fill_(7.0); r.out_mask.fill_(9)
+    m.ragged_apply_per_image(ctx, r)
+    torch.cuda.synchronize()
+    full = [i for i in range(b.n) if i not in bad]
+    w2 = win.copy(); w2[5] = (0, 0, *d4_shape(int(b.hw[5][0]), int(b.hw[5][1]), flags[5]))
+    check_crop_outputs(b, r, flags, ab, w2, full)
+    out, om = r.out.cpu().numpy(), r.out_mask.cpu().numpy()
+    for i in bad:  # skipped images: outputs untouched
+        assert np.all(out[i] == 7.0) and np.all(om[i] == 9), i
+
+
+def test_full_size_batch_with_crop_windows_sampled_against_oracle(m, ctx):
+    import torch
+    b = synth.ragged_batch(1809068394, 2048, device="cuda")
+    flags, ab = m.sample_d4bc(1809068394, 0, 2048)
+    win = crop_windows(b, flags, 1809068394)
+    r = m.Ragged.from_host(b, flags, ab, crop=win)
+    m.ragged_apply(ctx, r)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6)
+    check_crop_outputs(b, r, flags, ab, win, sorted(rng.choice(2048, 32, replace=False)))

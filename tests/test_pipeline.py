@@ -126,7 +126,7 @@ def test_crop_needs_source_sizes_and_fitting_images():
 
 def test_param_record_size():
     p = m.Pipeline(None, [op("HFLIP")])
-    assert m.lib().miaug_param_bytes(p.handle, 3) == 3 * 168
+    assert m.lib().miaug_param_bytes(p.handle, 3) == 3 * 176
 
 
 # ---------------------------------------------------------------- GPU
@@ -300,3 +300,60 @@ def test_distortion_pipeline_with_the_box_field(ctx):
         e = oracle.remap_field(imgs[i], ox, oy)
         ref = oracle.grid_remap(e, oracle.grid_table(d[:5], W), oracle.grid_table(d[5:], H))
         assert np.array_equal(got[i], ref), i
+
+
+# ---------------------------------------------------------------- random-sized crop
+def test_sized_crop_sampler_matches_the_oracle_windows():
+    seed = 1809068395
+    scale, ratio = (0.08, 1.0), (0.75, 4 / 3)
+    ops = [op("HFLIP", 0.5), op("ROT90", 1, (0,), (3,)), op("TRANSPOSE", 0.5),
+           op("SIZED_CROP", 0.9, (scale[0], ratio[0]), (scale[1], ratio[1])),
+           op("RESIZE", out=(224, 224))]
+    p = m.Pipeline(None, ops)
+    assert p.kind == "RAGGED"
+    rng = np.random.default_rng(3)
+    n = 200
+    hw = np.stack([rng.integers(1, 1025, n), rng.integers(1, 1025, n)], 1).astype(np.int32)
+    recs = p.sample(seed, 50, n, hw)
+    f32 = lambda v: float(np.float32(v))
+    for i in range(n):
+        r, g = recs[i], 50 + i
+        on = uniform(seed, g, 48) < 0.9                                   # op 3 gate: draw 48
+        if not on:
+            assert (r.crop_h, r.crop_w) == (0, 0)
+            continue
+        swap = (r.flags[2] & 1) != (r.flags[3] != 0)
+        H, W = (hw[i][1], hw[i][0]) if swap else (hw[i][0], hw[i][1])
+        ref = oracle.sized_crop_window(seed, g, 48 + 1, int(H), int(W), (f32(scale[0]), f32(scale[1])),
+                                       (f32(ratio[0]), f32(ratio[1])))
+        assert (r.crop_y, r.crop_x, r.crop_h, r.crop_w) == tuple(int(v) for v in ref), i
+    with pytest.raises(m.MiaugError):
+        p.sample(seed, 0, 2)  # source sizes are needed
+
+
+@pytest.mark.gpu
+def test_ragged_pipeline_with_sized_crop_matches_the_oracle(ctx):
+    import torch
+    sizes = [(1, 1), (300, 41), (129, 1000), (224, 224), (57, 91), (640, 480), (1024, 128)]
+    b = synth.ragged_batch(23, len(sizes), sizes=sizes)
+    p = m.Pipeline(ctx, [op("HFLIP", 0.5), op("VFLIP", 0.5), op("ROT90", 1, (0,), (3,)), op("TRANSPOSE", 0.5),
+                         op("SIZED_CROP", 0.8, (0.08, 0.75), (1.0, 4 / 3)),
+                         op("BRIGHT_CONTRAST", 1, (0.8, -51), (1.2, 51)), op("RESIZE", out=(96, 128)),
+                         op("NORMALIZE", 1, m.IMAGENET_MEAN, m.IMAGENET_STD)])
+    recs = p.sample(9, 0, b.n, np.asarray(b.hw, np.int32))
+    flags, ab = host_flags(recs, b.n)
+    r = m.Ragged.from_host(b, flags, ab, out_h=96, out_w=128)
+    bi, bo, _ = p.batch(ragged=r)
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    out, om = r.out.cpu().numpy(), r.out_mask.cpu().numpy()
+    ob = r.out_boxes.cpu().numpy() if r.out_boxes is not None else None
+    for i in range(b.n):
+        win = None if recs[i].crop_h == 0 else (recs[i].crop_y, recs[i].crop_x, recs[i].crop_h, recs[i].crop_w)
+        ref, rm, rb = oracle.pipe_ragged_one(b.image(i), b.mask_of(i), flags[i], ab[i], b.boxes_of(i), 96, 128,
+                                             win=win)
+        assert np.array_equal(out[i].view(np.uint32), ref.view(np.uint32)), i
+        assert np.array_equal(om[i], rm), i
+        if len(rb):
+            got = ob[b.box_off[i]:b.box_off[i + 1]]
+            assert np.all(np.abs(got - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), i
