@@ -14,7 +14,7 @@ launch form for comparison, the roofline of the dominant kernel (algorithmic
 bytes per launch / average launch time, HIP events on the launch stream), and
 the oracle's CPU throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged|d4bc|c2|wc|elastic]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged|d4bc|c2|wc|elastic|table1]
 """
 from __future__ import annotations
 
@@ -372,7 +372,74 @@ def bench_copy(args, torch, m):
             "ms_per_step": ms, "steps": args.steps, "config": {"workload": "copy_1GiB"}}
 
 
-WORKLOADS = {"copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
+def bench_table1(args, torch, m):
+    """Every row of the paper's Table I as a single op on 256 smooth-noise RGB 512x512 u8 images
+    (PadToSize512 pads 448x448 images), one GPU launch per op and batch."""
+    import synth
+    n, S = 256, 512
+    img = synth.smooth_u8_hwc(1809068397, n, S, S, device="cuda")
+    small = synth.smooth_u8_hwc(1809068398, n, 448, 448, device="cuda")
+    out = torch.empty_like(img)
+    s = torch.cuda.Stream()
+    rng = np.random.default_rng(1809068397)
+    zero_fl = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
+    fl_h = zero_fl.clone(); fl_h[:, 0] = 1
+    fl_v = zero_fl.clone(); fl_v[:, 1] = 1
+    ab = torch.from_numpy(np.stack([rng.uniform(0.8, 1.2, n), rng.uniform(-51, 51, n)], 1).astype(np.float32)).cuda()
+    ident_ab = torch.tensor([[1.0, 0.0]] * n, dtype=torch.float32, device="cuda")
+    sh = rng.uniform(-20, 20, (n, 3)).astype(np.float32)
+    luts_rgb = torch.from_numpy(m.compile_color_luts(None, sh, n)).cuda()
+    luts_id = torch.from_numpy(m.compile_color_luts(None, None, n)).cuda()
+    gray = torch.ones(n, dtype=torch.int32, device="cuda")
+    f_rot = np.stack([rng.uniform(-45, 45, n), np.ones(n), np.zeros(n), np.zeros(n)], 1).astype(np.float32)
+    f_ssr = np.stack([rng.uniform(-45, 45, n), rng.uniform(0.9, 1.1, n), rng.uniform(-0.0625, 0.0625, n),
+                      rng.uniform(-0.0625, 0.0625, n)], 1).astype(np.float32)
+    aq_rot = torch.from_numpy(m.compile_ssr_q32(f_rot, S, S)).cuda()
+    aq_ssr = torch.from_numpy(m.compile_ssr_q32(f_ssr, S, S)).cuda()
+
+    def c2_rec(f5, k5, crop):
+        return torch.from_numpy(m.compile_c2(np.asarray(f5, np.float32), np.asarray(k5, np.int32), S, S, crop)).cuda()
+    ident_f = [[0.0, 1.0, 0.0, 0.0, 1.0]] * n
+    rec_hsv = c2_rec(ident_f, [[0, 0, int(rng.integers(-20, 21)), int(rng.integers(-30, 31)), 0] for _ in range(n)], S)
+    rec_gam = c2_rec([[0.0, 1.0, 0.0, 0.0, float(rng.uniform(0.8, 1.2))] for _ in range(n)], [[0, 0, 0, 0, 0]] * n, S)
+    rec_crop = c2_rec(ident_f, [[int(rng.integers(0, S - 63)), int(rng.integers(0, S - 63)), 0, 0, 0]
+                                for _ in range(n)], 64)
+    out64 = torch.empty((n, 64, 64, 3), dtype=torch.uint8, device="cuda")
+    pad_out = torch.empty_like(img)
+    px = n * S * S * 3
+    ops = [
+        ("RandomCrop64", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_crop, 64, 64, out64, st),
+         2 * n * 64 * 64 * 3, "k_c2 (identity warp, 64x64 crop)"),
+        ("PadToSize512", lambda st: m.pad_u8(small, S, S, 0, 0, pad_out, st), n * (448 * 448 * 3) + px,
+         "k_pad<3>"),
+        ("HorizontalFlip", lambda st: m.d4_bc_u8(img, fl_h, ident_ab, out, st), 2 * px, "k_d4_bc<3>"),
+        ("VerticalFlip", lambda st: m.d4_bc_u8(img, fl_v, ident_ab, out, st), 2 * px, "k_d4_bc<3>"),
+        ("Rotate", lambda st: m.warp_affine_u8(img, aq_rot, 0, 0, out, st), 2 * px, "k_warp<3>"),
+        ("ShiftScaleRotate", lambda st: m.warp_affine_u8(img, aq_ssr, 0, 0, out, st), 2 * px, "k_warp<3>"),
+        ("Brightness", lambda st: m.d4_bc_u8(img, zero_fl, ab, out, st), 2 * px, "k_d4_bc<3>"),
+        ("ShiftHSV", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_hsv, S, S, out, st), 2 * px,
+         "k_c2 (identity warp and resize)"),
+        ("ShiftRGB", lambda st: m.d4_lut_u8(img, zero_fl, luts_rgb, None, out, st), 2 * px, "k_d4_bc<3, LUTs>"),
+        ("Gamma", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_gam, S, S, out, st), 2 * px,
+         "k_c2 (identity warp and resize)"),
+        ("Grayscale", lambda st: m.d4_lut_u8(img, zero_fl, luts_id, gray, out, st), 2 * px, "k_d4_bc<3, gray>"),
+    ]
+    rows = {}
+    for name, fn, alg, kernel in ops:
+        ms = time_on_stream(torch, fn, args.steps, args.warmup, s)
+        rows[name] = {"ms_per_batch": ms, "images_per_s": n / (ms * 1e-3), "gb_per_s": alg / (ms * 1e-3) / 1e9,
+                      "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "kernel": kernel}
+        print("# %-16s %8.3f ms  %10.0f img/s  %7.0f GB/s" % (name, ms, n / (ms * 1e-3), rows[name]["gb_per_s"]),
+              file=sys.stderr, flush=True)
+    total = sum(r["ms_per_batch"] for r in rows.values())
+    res = line("images/sec per Table I op (one launch per op), 256 x 512x512x3 u8", n * len(rows), total, args, "u8",
+               {"workload": "table1_single_ops_256x512x512x3"}, None, {"ops": rows})
+    res["value"] = n / (total * 1e-3) * len(rows)
+    res["unit"] = "op-images/s"
+    return res
+
+
+WORKLOADS = {"table1": bench_table1, "copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
 
 
 def main():

@@ -115,6 +115,46 @@ int miaug_ctx_destroy(miaug_ctx *ctx);
 int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
                    uint8_t *out, void *stream);
 
+/* ---------------------------------------------------------------- the other Table I single ops
+ * ShiftRGB and Grayscale (Table I): the Dih4 kernel with per-channel LUTs
+ * and an optional grayscale step.  out_i = G_i(L_i[d4_i(in_i)]) where
+ * L_i applies luts[i][c][.] to channel c, and G_i (when gray != NULL and
+ * gray[i] != 0; C = 3 only) replaces every pixel by its BT.601 luma
+ * Y = (4899 R + 9617 G + 1868 B + 8192) >> 14 in all three channels.
+ *   luts device u8 [n][C][256] (miaug_compile_color_luts); gray device int32
+ *   [n] or NULL; other arguments as miaug_d4_bc_u8 (flags all zero: no
+ *   geometric change).  Errors as miaug_d4_bc_u8; ESHAPE gray with C != 3. */
+int miaug_d4_lut_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const uint8_t *luts,
+                    const int32_t *gray, uint8_t *out, void *stream);
+/* Host: luts[i][c][v] = S_ic(B_i(v)) with B_i(v) = sat8(rint(alpha_i v + beta_i))
+ * (ab host float [n][2], NULL: identity) and S_ic(u) = sat8(rint(u + shift[i][c]))
+ * (ShiftRGB; shift host float [n][C], NULL: identity), in IEEE double. */
+int miaug_compile_color_luts(const float *ab, const float *shift, int n, int C, uint8_t *luts);
+
+/* PadToSize (Table I PadToSize512): out_i has size max(H, min_h) x
+ * max(W, min_w); the padding along an axis is split floor(d / 2) before and
+ * the rest after; out[y][x] = in[y - top][x - left] inside, else the
+ * reflect-101 image of that index (border MIAUG_BORDER_REFLECT101) or value
+ * (MIAUG_BORDER_CONSTANT).  in device u8 [n][H][W][C]; out device u8
+ * [n][Ho][Wo][C].  Errors: EINVAL bad sizes, border or value; ESHAPE C. */
+int miaug_pad_u8(const uint8_t *in, int n, int H, int W, int C, int min_h, int min_w, int border, int value,
+                 uint8_t *out, void *stream);
+
+/* Standalone affine warp (Table I Rotate; ShiftScaleRotate without crop):
+ * out[y][x] samples in at the Q10 position rshr_he(A_i (x, y, 1), 22) of the
+ * Q32 inverse matrix A_i = aq[6i .. 6i+5] (miaug_compile_ssr_q32): bilinear
+ * (weights (1024 - a, a), one round-half-even of the 2^20-scaled sum) or
+ * nearest (index (q + 512) >> 10); taps outside the image take reflect-101
+ * or 0 (constant border).  Output has the input's shape.
+ *   aq device int64 [n][6].  Errors: EINVAL, ESHAPE (H, W > 16384). */
+int miaug_warp_affine_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
+                         uint8_t *out, void *stream);
+/* Host: the Q32 inverse matrices of shift-scale-rotate maps
+ * p' = s R(angle) (p - c) + c + (dx W, dy H) (the map of the full u8 chain),
+ * f host float [n][4] = {angle_deg, scale, dx, dy}; Rotate is scale 1,
+ * dx = dy = 0.  aq host int64 [n][6].  Errors: EINVAL, ESHAPE (scale 0). */
+int miaug_compile_ssr_q32(const float *f, int n, int H, int W, int64_t *aq);
+
 /* ---------------------------------------------------------------- full u8 pipeline
  * Table I ShiftScaleRotate -> RandomCrop -> resize -> ShiftHSV -> Gamma, then
  * a 3x3 binomial blur with probability 0.3, per RGB image, each op rounding
@@ -161,6 +201,28 @@ int miaug_compile_c2(const float *f, const int32_t *k, int n, int H, int W, int 
  * ESHAPE unless 1 <= crop <= min(H, W), 1 <= outsz <= 4096, H, W <= 16384. */
 int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec,
                                             int crop, int outsz, uint8_t *out, void *stream);
+
+/* Masks of the same chain (Sec. II-A: masks take the image's geometry, with
+ * nearest interpolation and no colour op): out[i][y][x] = the mask warped by
+ * rec[i]'s matrix (nearest tap of the Q10 position, index (q + 512) >> 10,
+ * reflect-101), cropped at (crop_x, crop_y) and resized to outsz x outsz with
+ * the nearest rule of the ragged batch (replicate at the crop's edges).
+ *   in device u8 [n][H][W]; out device u8 [n][outsz][outsz].
+ * Errors as miaug_ssr_crop_resize_hsv_gamma_blur_u8. */
+int miaug_ssr_crop_resize_mask_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop,
+                                  int outsz, uint8_t *out, void *stream);
+
+/* Boxes of the same chain (xyxy, continuous coordinates: pixel i spans
+ * [i, i + 1)).  The warp's forward map F is the inverse of rec[i]'s Q32
+ * matrix (in double); a corner u maps to F(u - 1/2) + 1/2; a box becomes the
+ * bounding box of its four mapped corners, clipped to [0, W] x [0, H], then
+ * shifted by (-crop_x, -crop_y), clipped to [0, crop]^2 and scaled by
+ * outsz / crop; stored as float.  A box that leaves the image or the crop
+ * keeps its slot with zero width or height.
+ *   boxes device float [nbox][4]; box_off device int32 [n + 1] (CSR by image);
+ *   out device float [nbox][4].  Errors: EINVAL null pointers; ESHAPE sizes. */
+int miaug_boxes_ssr_crop_resize(const float *boxes, const int32_t *box_off, int n, int H, int W,
+                                const miaug_c2_record *rec, int crop, int outsz, float *out, void *stream);
 
 /* ---------------------------------------------------------------- ragged batch
  * Sec. II-A: images of a detection / segmentation set (uneven sizes) are
@@ -320,6 +382,20 @@ int miaug_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H,
                           const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
                           uint8_t *out_mask, int per_image, void *stream);
 
+/* Boxes under the same distortion (Sec. II-A: boxes follow the image).  A box
+ * (xyxy, continuous coordinates) covers the source pixels whose centres lie
+ * in [x1, x2) x [y1, y2); output pixel (x, y) reaches, on the mask path, the
+ * source pixel of the grid's nearest tap followed by the elastic map's
+ * nearest tap (reflect-101 both times).  The transformed box is the bounding
+ * box [min x, min y, max x + 1, max y + 1] of the output pixels whose source
+ * pixel it covers: the box transformed as its own mask.  A box no output
+ * pixel reaches becomes (0, 0, 0, 0) and keeps its slot.
+ *   boxes device float [nbox][4]; box_off device int32 [n + 1]; off, mapx,
+ *   mapy as miaug_elastic_grid_u8; out device float [nbox][4] (also used as
+ *   int32 accumulators while the call runs).  Errors: EINVAL, ESHAPE. */
+int miaug_boxes_elastic_grid(const float *boxes, const int32_t *box_off, int n, int H, int W, const int32_t *off,
+                             const int32_t *mapx, const int32_t *mapy, float *out, void *stream);
+
 /* Float copy of the chain without u8 rounding (same Q10 positions, dyadic
  * weights), CHW float32, and its adjoint w.r.t. the image (fields and grid
  * are random draws, not parameters).  The backward accumulates with float
@@ -349,15 +425,26 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  * pattern, onto one of the fused chains above (brackets: optional; the ops
  * must come in this order):
  *   MIAUG_PIPE_DIH4      [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
- *                        dense u8 images (and masks) -> u8, miaug_d4_bc_u8
+ *                        [SHIFT_RGB] [TO_GRAY]
+ *                        dense u8 images (and masks, Dih4 only) -> u8,
+ *                        miaug_d4_bc_u8 or, with colour ops, miaug_d4_lut_u8
  *   MIAUG_PIPE_RAGGED    [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [SIZED_CROP]
  *                        [BRIGHT_CONTRAST] RESIZE [NORMALIZE]
  *                        ragged RGB u8 + masks + boxes -> f32 NCHW, miaug_ragged_apply
  *   MIAUG_PIPE_U8CHAIN   [SSR] CROP RESIZE [HSV] [GAMMA] [BLUR3]
- *                        dense RGB u8 -> u8 (square crop and output),
- *                        miaug_ssr_crop_resize_hsv_gamma_blur_u8
+ *                        dense RGB u8 (+ masks, + boxes CSR by image) -> u8
+ *                        (square crop and output),
+ *                        miaug_ssr_crop_resize_hsv_gamma_blur_u8,
+ *                        miaug_ssr_crop_resize_mask_u8, miaug_boxes_ssr_crop_resize
  *   MIAUG_PIPE_DISTORT   ELASTIC [GRID] | GRID
- *                        dense u8 images (and masks) -> u8, miaug_elastic_grid_u8
+ *                        dense u8 images (and masks, boxes) -> u8,
+ *                        miaug_elastic_grid_u8, miaug_boxes_elastic_grid
+ *   MIAUG_PIPE_WARP      ROTATE | SSR (alone)
+ *                        dense u8 images (and masks, nearest) -> u8 of the same
+ *                        shape, miaug_warp_affine_u8
+ *   MIAUG_PIPE_PAD       PAD
+ *                        dense u8 images (and masks, label 0) -> u8
+ *                        [n][max(H, out_h)][max(W, out_w)][C], miaug_pad_u8
  * Any other list is rejected with MIAUG_EUNSUPPORTED and a message naming
  * the first op that does not fit.
  *
@@ -369,7 +456,15 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *                     (pixel units); skipped: (1, 0).
  *   SSR               p; angle_deg in [lo[0], hi[0]], scale in [lo[1], hi[1]],
  *                     dx, dy in [lo[2], hi[2]], [lo[3], hi[3]] (fractions of
- *                     W, H); bilinear, reflect-101 only; skipped: identity.
+ *                     W, H); skipped: identity.  In the u8 chain bilinear with
+ *                     reflect-101 only; alone (WARP) any interp and border.
+ *   ROTATE            p; angle_deg in [lo[0], hi[0]] (scale 1, no shift);
+ *                     interp, border; skipped: identity.
+ *   SHIFT_RGB         p; channel c moves by U[lo[c], hi[c]] (c < 3, pixel
+ *                     units, rounded in the LUT); skipped: 0.
+ *   TO_GRAY           p; BT.601 luma to all channels (RGB only).
+ *   PAD               to at least out_h x out_w (border; lo[0] = constant
+ *                     value); p must be 1; no draws.
  *   CROP              out_h x out_w window at offsets uniform in
  *                     {0 .. H - out_h} x {0 .. W - out_w}; p must be 1.
  *   SIZED_CROP        p; random-sized crop of the Dih4 image (H' x W'):
@@ -405,11 +500,14 @@ enum {
     MIAUG_OP_HFLIP = 1, MIAUG_OP_VFLIP = 2, MIAUG_OP_ROT90 = 3, MIAUG_OP_TRANSPOSE = 4, MIAUG_OP_SSR = 5,
     MIAUG_OP_CROP = 6, MIAUG_OP_RESIZE = 7, MIAUG_OP_BRIGHT_CONTRAST = 8, MIAUG_OP_HSV = 9, MIAUG_OP_GAMMA = 10,
     MIAUG_OP_BLUR3 = 11, MIAUG_OP_BLUR5 = 12, MIAUG_OP_ELASTIC = 13, MIAUG_OP_GRID = 14, MIAUG_OP_NORMALIZE = 15,
-    MIAUG_OP_SIZED_CROP = 16
+    MIAUG_OP_SIZED_CROP = 16, MIAUG_OP_SHIFT_RGB = 17, MIAUG_OP_TO_GRAY = 18, MIAUG_OP_PAD = 19, MIAUG_OP_ROTATE = 20
 };
 enum { MIAUG_INTERP_BILINEAR = 0, MIAUG_INTERP_NEAREST = 1 };
 enum { MIAUG_BORDER_REFLECT101 = 0, MIAUG_BORDER_CONSTANT = 1 };
-enum { MIAUG_PIPE_DIH4 = 1, MIAUG_PIPE_RAGGED = 2, MIAUG_PIPE_U8CHAIN = 3, MIAUG_PIPE_DISTORT = 4 };
+enum {
+    MIAUG_PIPE_DIH4 = 1, MIAUG_PIPE_RAGGED = 2, MIAUG_PIPE_U8CHAIN = 3, MIAUG_PIPE_DISTORT = 4, MIAUG_PIPE_WARP = 5,
+    MIAUG_PIPE_PAD = 6
+};
 
 typedef struct {
     uint32_t kind;         /* MIAUG_OP_*                                          */
@@ -434,6 +532,8 @@ typedef struct {
     int32_t blur;                   /* 3x3 blur flag                             */
     int32_t crop_h, crop_w;         /* random-sized crop window size (0: none);
                                        its offsets are crop_y, crop_x            */
+    float shift[3];                 /* ShiftRGB channel shifts                   */
+    int32_t gray;                   /* grayscale flag                            */
     double grid[10];                /* grid factors: x d_0..d_4, y d_0..d_4      */
 } miaug_params;
 
@@ -465,7 +565,7 @@ typedef struct {
     const int32_t *hw;
     const uint8_t *mask;      /* NULL: no masks                                   */
     const int64_t *mask_off;
-    const float *boxes;       /* NULL: no boxes (ragged pipeline only)            */
+    const float *boxes;       /* NULL: no boxes (ragged, u8 and distortion chains) */
     const int32_t *box_off;
 } miaug_batch_in;
 /* Outputs (device): img u8 like the input (DIH4: image i keeps its byte range,

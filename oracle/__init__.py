@@ -88,6 +88,10 @@ _SIGS = {
     "or_ssr_matrix_q32": (None, [_f, _f, _f, _f, _i, _i, _i64p]),
     "or_warp_affine_u8": (None, [_u8p, _i, _i, _i, _i64p, _i, _i, _u8p]),
     "or_crop_u8": (None, [_u8p, _i, _i, _i, _i, _i, _i, _i, _u8p]),
+    "or_pad_u8": (None, [_u8p, _i, _i, _i, _i, _i, _i, _i, _u8p, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "or_shift_rgb_lut": (None, [_f32p, _i, _u8p]),
+    "or_apply_lut_c": (None, [_u8p, ctypes.c_int64, _i, _u8p, _u8p]),
+    "or_gray_u8": (None, [_u8p, ctypes.c_int64, _u8p]),
     "or_rgb_to_hsv8": (None, [_i, _i, _i, _ip, _ip, _ip]),
     "or_hsv8_to_rgb": (None, [_i, _i, _i, _ip, _ip, _ip]),
     "or_hsv_shift_u8": (None, [_u8p, _i64, _i, _i, _i, _u8p]),
@@ -108,6 +112,8 @@ _SIGS = {
     "or_pipe_ragged_one": (None, [_u8p, ctypes.c_void_p, _i, _i, _i32p, _f32p, ctypes.c_void_p, ctypes.c_void_p,
                                   _i, _f32p, _f32p, _i, _i, _f32p, ctypes.c_void_p, ctypes.c_void_p]),
     "or_boxes_d4_crop_resize": (None, [_f32p, _i, _i, _i, _i, _i, _i, _i, ctypes.c_void_p, _i, _i, _f32p]),
+    "or_boxes_ssr_crop_resize": (None, [_f32p, _i, _i, _i, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, _i, _i, _i, _i, _f32p]),
     "or_pipe_elastic_grid_one": (None, [_u8p, ctypes.c_void_p, _i, _i, _i, _u64, _u64, _d, _i, _i,
                                         _f64p, _u8p, ctypes.c_void_p]),
     "or_wc_forward": (None, [_f32p, _i, _i, _i, _f64p, _f64p]),
@@ -293,6 +299,16 @@ def boxes_d4_crop_resize(boxes, H, W, flags, win, Hd, Wd):
     return out
 
 
+def boxes_ssr_crop_resize(boxes, H, W, f, crop_x, crop_y, crop_, outsz):
+    """f = (angle_deg, scale, dx, dy) as float32 values."""
+    boxes = _c(boxes, np.float32).reshape(-1, 4)
+    out = np.zeros_like(boxes)
+    if len(boxes):
+        lib().or_boxes_ssr_crop_resize(boxes, len(boxes), H, W, float(f[0]), float(f[1]), float(f[2]), float(f[3]),
+                                       int(crop_x), int(crop_y), int(crop_), int(outsz), out)
+    return out
+
+
 def resize_q(j, Ws, Wd):
     return lib().or_resize_q(j, Ws, Wd)
 
@@ -327,7 +343,40 @@ def crop(img, ox, oy, Hc, Wc):
     return out
 
 
+def pad(img, Hmin, Wmin, border=REFLECT101, value=0):
+    img, H, W, C = _hwc(img)
+    ho, wo = max(H, Hmin), max(W, Wmin)
+    out = _like(img, ho, wo, C)
+    a, b = ctypes.c_int(), ctypes.c_int()
+    lib().or_pad_u8(img, H, W, C, Hmin, Wmin, border, value, out, ctypes.byref(a), ctypes.byref(b))
+    assert (a.value, b.value) == (ho, wo)
+    return out
+
+
 # ---------------------------------------------------------------- point ops
+def shift_rgb_lut(shift):
+    shift = _c(shift, np.float32)
+    lut = np.zeros((len(shift), 256), np.uint8)
+    lib().or_shift_rgb_lut(shift, len(shift), lut)
+    return lut
+
+
+def apply_lut_c(img, lut):
+    """Per-channel LUT (lut [C, 256]) on an HWC image."""
+    img, H, W, C = _hwc(img)
+    out = _like(img, H, W, C)
+    lib().or_apply_lut_c(img, H * W, C, _c(lut, np.uint8), out)
+    return out
+
+
+def gray(img):
+    img, H, W, C = _hwc(img)
+    assert C == 3
+    out = _like(img, H, W, C)
+    lib().or_gray_u8(img, H * W, out)
+    return out
+
+
 def bc_lut(alpha, beta):
     lut = np.zeros(256, np.uint8); lib().or_bc_lut(alpha, beta, lut); return lut
 
@@ -441,6 +490,27 @@ def grid_table(d, n, ncell=5):
 def grid_remap(img, mapx, mapy, interp=BILINEAR):
     img, H, W, C = _hwc(img); out = _like(img, H, W, C)
     lib().or_grid_remap_u8(img, H, W, C, _c(mapx, np.int32), _c(mapy, np.int32), interp, out)
+    return out
+
+
+def boxes_distort(boxes, H, W, offx, offy, mapx, mapy):
+    """Boxes under elastic then grid distortion, as the masks see them: each box is
+    rasterised (pixels whose centres lie in [x1, x2) x [y1, y2)), the 0/1 mask goes through
+    the nearest elastic remap and the nearest grid remap of the oracle, and the result's
+    bounding box [min x, min y, max x + 1, max y + 1] is the transformed box (empty: zeros)."""
+    boxes = _c(boxes, np.float32).reshape(-1, 4)
+    out = np.zeros_like(boxes)
+    cx = np.arange(W, dtype=np.float32) + np.float32(0.5)
+    cy = np.arange(H, dtype=np.float32) + np.float32(0.5)
+    for i, (x1, y1, x2, y2) in enumerate(boxes):
+        inx = (cx >= x1) & (cx < x2)
+        iny = (cy >= y1) & (cy < y2)
+        mask = (iny[:, None] & inx[None, :]).astype(np.uint8)
+        e = remap_field(mask, offx, offy, NEAREST)
+        g = grid_remap(e, mapx, mapy, NEAREST)
+        ys, xs = np.nonzero(g)
+        if len(xs):
+            out[i] = (xs.min(), ys.min(), xs.max() + 1, ys.max() + 1)
     return out
 
 

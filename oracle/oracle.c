@@ -358,6 +358,35 @@ void or_apply_lut(const uint8_t *in, int64_t n, const uint8_t *lut, uint8_t *out
     for (int64_t i = 0; i < n; ++i) out[i] = lut[in[i]];
 }
 
+/* ShiftRGB (Table I): channel c of every pixel moves by shift[c] (pixel
+ * units), rounded half to even and saturated: lut[c*256 + v] =
+ * sat8(rint(v + shift_c)) in IEEE double. */
+void or_shift_rgb_lut(const float *shift, int C, uint8_t *lut)
+{
+    for (int c = 0; c < C; ++c)
+        for (int v = 0; v < 256; ++v)
+            lut[c * 256 + v] = (uint8_t)sat8((int64_t)rint((double)v + (double)shift[c]));
+}
+
+/* Per-channel LUT on an interleaved image: out[p*C + c] = lut[c*256 + in[p*C + c]]. */
+void or_apply_lut_c(const uint8_t *in, int64_t npix, int C, const uint8_t *lut, uint8_t *out)
+{
+    for (int64_t p = 0; p < npix; ++p)
+        for (int c = 0; c < C; ++c) out[p * C + c] = lut[c * 256 + in[p * C + c]];
+}
+
+/* Grayscale (Table I): BT.601 luma with the weights 0.299, 0.587, 0.114
+ * quantised to Q14 (4899, 9617, 1868; they sum to 2^14, so a grey pixel
+ * keeps its value), rounded half up; the luma goes to all three channels. */
+void or_gray_u8(const uint8_t *in, int64_t npix, uint8_t *out)
+{
+    for (int64_t p = 0; p < npix; ++p) {
+        int64_t y = (4899 * (int64_t)in[3 * p] + 9617 * (int64_t)in[3 * p + 1] + 1868 * (int64_t)in[3 * p + 2] +
+                     8192) >> 14;
+        out[3 * p] = out[3 * p + 1] = out[3 * p + 2] = (uint8_t)y;
+    }
+}
+
 /* lut[c*256 + v] = (float)((v/255 - mean_c) / std_c) in IEEE double. */
 void or_normalize_lut(const float *mean, const float *stdv, int C, float *lut)
 {
@@ -460,6 +489,45 @@ void or_ssr_matrix_q32(float angle_deg, float scale, float dx, float dy, int H, 
     for (int i = 0; i < 6; ++i) aq[i] = (int64_t)llrint(a[i] * 4294967296.0);
 }
 
+/* Boxes under shift-scale-rotate, then a crop (offset crop_x, crop_y, size
+ * crop x crop) and a resize to outsz x outsz.  The SSR forward map, from the
+ * definition above: a source pixel index p goes to s R(-t) (p - c) + c + T
+ * (c the image centre, T = (dx W, dy H)).  A box corner u in continuous
+ * coordinates (pixel i spans [i, i + 1)) is the index position u - 1/2, so
+ * it maps to F(u - 1/2) + 1/2.  The box becomes the bounding box of its four
+ * mapped corners, clipped to the image [0, W] x [0, H] (the warp keeps the
+ * image size); the crop shifts and clips it to [0, crop]^2; the resize scales
+ * it by outsz / crop.  All in double, stored as float. */
+void or_boxes_ssr_crop_resize(const float *boxes, int nb, int H, int W, float angle_deg, float scale, float dx,
+                              float dy, int crop_x, int crop_y, int crop, int outsz, float *out)
+{
+    double t = (double)angle_deg * (3.14159265358979323846 / 180.0);
+    double cs = cos(t), sn = sin(t), s = (double)scale;
+    double cx = (W - 1) * 0.5, cy = (H - 1) * 0.5;
+    double tx = (double)dx * W, ty = (double)dy * H;
+    for (int i = 0; i < nb; ++i) {
+        double ux[4] = {boxes[4 * i + 0], boxes[4 * i + 2], boxes[4 * i + 0], boxes[4 * i + 2]};
+        double uy[4] = {boxes[4 * i + 1], boxes[4 * i + 1], boxes[4 * i + 3], boxes[4 * i + 3]};
+        double x1 = 1e300, y1 = 1e300, x2 = -1e300, y2 = -1e300;
+        for (int k = 0; k < 4; ++k) {
+            double px = ux[k] - 0.5 - cx, py = uy[k] - 0.5 - cy;
+            double ox = s * (cs * px + sn * py) + cx + tx + 0.5;
+            double oy = s * (-sn * px + cs * py) + cy + ty + 0.5;
+            x1 = ox < x1 ? ox : x1; x2 = ox > x2 ? ox : x2;
+            y1 = oy < y1 ? oy : y1; y2 = oy > y2 ? oy : y2;
+        }
+        x1 = clampd(x1, 0.0, W); x2 = clampd(x2, 0.0, W);
+        y1 = clampd(y1, 0.0, H); y2 = clampd(y2, 0.0, H);
+        x1 = clampd(x1 - crop_x, 0.0, crop); x2 = clampd(x2 - crop_x, 0.0, crop);
+        y1 = clampd(y1 - crop_y, 0.0, crop); y2 = clampd(y2 - crop_y, 0.0, crop);
+        double k = (double)outsz / crop;
+        out[4 * i + 0] = (float)(x1 * k);
+        out[4 * i + 1] = (float)(y1 * k);
+        out[4 * i + 2] = (float)(x2 * k);
+        out[4 * i + 3] = (float)(y2 * k);
+    }
+}
+
 /* Affine warp with a Q32 inverse matrix: sx_q = a0 x + a1 y + a2 (exact),
  * then rshr_he(., 32 - F).  Output has the input's shape. */
 void or_warp_affine_u8(const uint8_t *in, int H, int W, int C, const int64_t *aq, int interp,
@@ -472,6 +540,30 @@ void or_warp_affine_u8(const uint8_t *in, int H, int W, int C, const int64_t *aq
             for (int c = 0; c < C; ++c)
                 out[((int64_t)y * W + x) * C + c] = (uint8_t)sample_q(in, H, W, C, qx, qy, c, interp, border);
         }
+}
+
+/* PadToSize (Table I PadToSize512): an image smaller than Hmin x Wmin along
+ * an axis is padded to that size, the padding split as floor(d / 2) before
+ * and the rest after; border OR_REFLECT101 (reflect-101 of the source index)
+ * or OR_CONSTANT (value).  Larger axes are left as they are.  *Ho x *Wo is
+ * the output size. */
+void or_pad_u8(const uint8_t *in, int H, int W, int C, int Hmin, int Wmin, int border, int value, uint8_t *out,
+               int *Ho, int *Wo)
+{
+    int ho = H > Hmin ? H : Hmin, wo = W > Wmin ? W : Wmin;
+    int top = (ho - H) / 2, left = (wo - W) / 2;
+    for (int y = 0; y < ho; ++y)
+        for (int x = 0; x < wo; ++x)
+            for (int c = 0; c < C; ++c) {
+                int64_t sy = y - top, sx = x - left;
+                int v;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W) v = in[(sy * W + sx) * C + c];
+                else if (border == OR_CONSTANT) v = value;
+                else v = in[(or_reflect101(sy, H) * W + or_reflect101(sx, W)) * C + c];
+                out[((int64_t)y * wo + x) * C + c] = (uint8_t)v;
+            }
+    *Ho = ho;
+    *Wo = wo;
 }
 
 /* Crop (Table I RandomCrop64; Sec. II-B cropping): out = in[oy:oy+Hc, ox:ox+Wc]. */

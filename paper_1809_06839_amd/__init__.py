@@ -65,7 +65,7 @@ class Params(ctypes.Structure):
                 ("crop_x", ctypes.c_int32), ("crop_y", ctypes.c_int32), ("dh", ctypes.c_int32),
                 ("ds", ctypes.c_int32), ("dv", ctypes.c_int32), ("gamma", ctypes.c_float),
                 ("blur", ctypes.c_int32), ("crop_h", ctypes.c_int32), ("crop_w", ctypes.c_int32),
-                ("grid", ctypes.c_double * 10)]
+                ("shift", ctypes.c_float * 3), ("gray", ctypes.c_int32), ("grid", ctypes.c_double * 10)]
 
 
 class BatchIn(ctypes.Structure):
@@ -93,6 +93,14 @@ _SIGS = {
     "miaug_ctx_destroy": (_i, [_vp]),
     "miaug_d4_bc_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "miaug_ssr_crop_resize_hsv_gamma_blur_u8": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
+    "miaug_ssr_crop_resize_mask_u8": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
+    "miaug_d4_lut_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "miaug_boxes_elastic_grid": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "miaug_compile_color_luts": (_i, [_vp, _vp, _i, _i, _vp]),
+    "miaug_pad_u8": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp, _vp]),
+    "miaug_warp_affine_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
+    "miaug_compile_ssr_q32": (_i, [_vp, _i, _i, _i, _vp]),
+    "miaug_boxes_ssr_crop_resize": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
     "miaug_ragged_apply": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
     "miaug_ragged_apply_per_image": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp]),
     "miaug_ragged_graph_create": (_i, [_vp, ctypes.POINTER(RaggedArgs), _vp, ctypes.POINTER(_vp)]),
@@ -269,6 +277,86 @@ def ssr_crop_resize_hsv_gamma_blur_u8(img, rec, crop=448, outsz=224, out=None, s
         out = torch.empty((n, outsz, outsz, 3), dtype=torch.uint8, device=img.device)
     _check(lib().miaug_ssr_crop_resize_hsv_gamma_blur_u8(_p(img), n, H, W, _p(rec), crop, outsz, _p(out),
                                                          _stream(stream)))
+    return out
+
+
+def ssr_crop_resize_mask_u8(mask, rec, crop=448, outsz=224, out=None, stream=None):
+    """Masks [n, H, W] u8 under the same records (nearest, no colour ops)."""
+    _dev(mask, torch.uint8, "mask"); _dev(rec, torch.uint8, "rec")
+    n, H, W = mask.shape
+    if rec.numel() != n * ctypes.sizeof(C2Record):
+        raise ValueError("rec must hold n records")
+    if out is None:
+        out = torch.empty((n, outsz, outsz), dtype=torch.uint8, device=mask.device)
+    _check(lib().miaug_ssr_crop_resize_mask_u8(_p(mask), n, H, W, _p(rec), crop, outsz, _p(out), _stream(stream)))
+    return out
+
+
+def boxes_ssr_crop_resize(boxes, box_off, H, W, rec, crop=448, outsz=224, out=None, stream=None):
+    """Boxes float [nbox, 4] (CSR by image: box_off int32 [n + 1]) under the same records."""
+    _dev(boxes, torch.float32, "boxes"); _dev(box_off, torch.int32, "box_off"); _dev(rec, torch.uint8, "rec")
+    n = box_off.numel() - 1
+    if rec.numel() != n * ctypes.sizeof(C2Record):
+        raise ValueError("rec must hold n records")
+    if out is None:
+        out = torch.empty_like(boxes)
+    _check(lib().miaug_boxes_ssr_crop_resize(_p(boxes), _p(box_off), n, H, W, _p(rec), crop, outsz, _p(out),
+                                             _stream(stream)))
+    return out
+
+
+def compile_color_luts(ab=None, shift=None, n=None, C=3):
+    """Host u8 [n, C, 256]: brightness/contrast (ab [n, 2]) then ShiftRGB (shift [n, C]) LUTs."""
+    abh = None if ab is None else np.ascontiguousarray(ab, np.float32)
+    sh = None if shift is None else np.ascontiguousarray(shift, np.float32)
+    n = n if n is not None else (len(abh) if abh is not None else len(sh))
+    luts = np.zeros((n, C, 256), np.uint8)
+    _check(lib().miaug_compile_color_luts(None if abh is None else abh.ctypes.data,
+                                          None if sh is None else sh.ctypes.data, n, C, luts.ctypes.data))
+    return luts
+
+
+def d4_lut_u8(img, flags, luts, gray=None, out=None, stream=None):
+    """img [n, H, W, C] u8; flags [n, 4] int32; luts [n, C, 256] u8; gray [n] int32 or None (device)."""
+    _dev(img, torch.uint8, "img"); _dev(flags, torch.int32, "flags"); _dev(luts, torch.uint8, "luts")
+    if gray is not None:
+        _dev(gray, torch.int32, "gray")
+    n, H, W = img.shape[:3]
+    C = img.shape[3] if img.dim() == 4 else 1
+    if out is None:
+        out = torch.empty_like(img)
+    _check(lib().miaug_d4_lut_u8(_p(img), n, H, W, C, _p(flags), _p(luts), None if gray is None else _p(gray),
+                                 _p(out), _stream(stream)))
+    return out
+
+
+def pad_u8(img, min_h, min_w, border=0, value=0, out=None, stream=None):
+    _dev(img, torch.uint8, "img")
+    n, H, W = img.shape[:3]
+    C = img.shape[3] if img.dim() == 4 else 1
+    Ho, Wo = max(H, min_h), max(W, min_w)
+    if out is None:
+        out = torch.empty((n, Ho, Wo) + ((C,) if img.dim() == 4 else ()), dtype=torch.uint8, device=img.device)
+    _check(lib().miaug_pad_u8(_p(img), n, H, W, C, min_h, min_w, border, value, _p(out), _stream(stream)))
+    return out
+
+
+def compile_ssr_q32(f, H, W):
+    """Host int64 [n, 6] Q32 inverse matrices of f [n, 4] = {angle_deg, scale, dx, dy}."""
+    fh = np.ascontiguousarray(f, np.float32).reshape(-1, 4)
+    aq = np.zeros((len(fh), 6), np.int64)
+    _check(lib().miaug_compile_ssr_q32(fh.ctypes.data, len(fh), H, W, aq.ctypes.data))
+    return aq
+
+
+def warp_affine_u8(img, aq, interp=0, border=0, out=None, stream=None):
+    """img [n, H, W(, C)] u8; aq device int64 [n, 6]."""
+    _dev(img, torch.uint8, "img"); _dev(aq, torch.int64, "aq")
+    n, H, W = img.shape[:3]
+    C = img.shape[3] if img.dim() == 4 else 1
+    if out is None:
+        out = torch.empty_like(img)
+    _check(lib().miaug_warp_affine_u8(_p(img), n, H, W, C, _p(aq), interp, border, _p(out), _stream(stream)))
     return out
 
 
@@ -508,8 +596,8 @@ def image_stats_u8(img, C=None, stream=None):
 # ---------------------------------------------------------------- op-list pipelines
 OP = {"HFLIP": 1, "VFLIP": 2, "ROT90": 3, "TRANSPOSE": 4, "SSR": 5, "CROP": 6, "RESIZE": 7, "BRIGHT_CONTRAST": 8,
       "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15,
-      "SIZED_CROP": 16}
-PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT"}
+      "SIZED_CROP": 16, "SHIFT_RGB": 17, "TO_GRAY": 18, "PAD": 19, "ROTATE": 20}
+PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT", 5: "WARP", 6: "PAD"}
 INTERP_BILINEAR, INTERP_NEAREST = 0, 1
 BORDER_REFLECT101, BORDER_CONSTANT = 0, 1
 
@@ -553,9 +641,10 @@ class Pipeline:
         return recs
 
     @staticmethod
-    def batch(img=None, mask=None, ragged=None):
-        """miaug_batch_in / miaug_batch_out for a dense batch (img [n, H, W, C] u8, mask [n, H, W] u8) or a
-        Ragged (its packed inputs and outputs).  Returns (batch_in, batch_out, outputs)."""
+    def batch(img=None, mask=None, ragged=None, boxes=None, box_off=None):
+        """miaug_batch_in / miaug_batch_out for a dense batch (img [n, H, W, C] u8, mask [n, H, W] u8, boxes
+        float [nbox, 4] with box_off int32 [n + 1]) or a Ragged (its packed inputs and outputs).  Returns
+        (batch_in, batch_out, outputs); the caller sets the output pointers of a dense batch."""
         bi, bo = BatchIn(), BatchOut()
         if ragged is not None:
             a = ragged.args
@@ -571,6 +660,9 @@ class Pipeline:
         if mask is not None:
             _dev(mask, torch.uint8, "mask")
             bi.mask = mask.data_ptr()
+        if boxes is not None:
+            _dev(boxes, torch.float32, "boxes"); _dev(box_off, torch.int32, "box_off")
+            bi.boxes, bi.box_off = boxes.data_ptr(), box_off.data_ptr()
         return bi, bo, None
 
     def apply(self, bi, bo, params, stream=None, per_image=False):

@@ -136,6 +136,50 @@ int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t 
     return hip_status(launch_d4_bc_u8(in, n, H, W, C, flags, ab, out, as_stream(stream)), "d4_bc_u8 launch");
 }
 
+int miaug_d4_lut_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const uint8_t *luts,
+                    const int32_t *gray, uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "d4_lut_u8: negative size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "d4_lut_u8: C=%d (1, 3 or 4)", C);
+    if (gray && C != 3) return set_error(MIAUG_ESHAPE, "d4_lut_u8: grayscale needs C = 3");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!in || !flags || !luts || !out) return set_error(MIAUG_EINVAL, "d4_lut_u8: NULL pointer");
+    if ((long long)H * W * C > (1ll << 31) - 1) return set_error(MIAUG_ESHAPE, "d4_lut_u8: image too large");
+    return hip_status(launch_d4_lut_u8(in, n, H, W, C, flags, luts, gray, out, as_stream(stream)), "d4_lut_u8 launch");
+}
+
+int miaug_pad_u8(const uint8_t *in, int n, int H, int W, int C, int min_h, int min_w, int border, int value,
+                 uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 1 || W < 1 || min_h < 0 || min_w < 0) return set_error(MIAUG_EINVAL, "pad_u8: bad size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "pad_u8: C=%d (1, 3 or 4)", C);
+    if (border != MIAUG_BORDER_REFLECT101 && border != MIAUG_BORDER_CONSTANT)
+        return set_error(MIAUG_EINVAL, "pad_u8: border %d", border);
+    if (value < 0 || value > 255) return set_error(MIAUG_EINVAL, "pad_u8: value %d", value);
+    const int Ho = H > min_h ? H : min_h, Wo = W > min_w ? W : min_w;
+    if ((long long)Ho * Wo * C > (1ll << 31) - 1) return set_error(MIAUG_ESHAPE, "pad_u8: output too large");
+    if (n == 0) return MIAUG_OK;
+    if (!in || !out) return set_error(MIAUG_EINVAL, "pad_u8: NULL pointer");
+    return hip_status(launch_pad_u8(in, n, H, W, C, Ho, Wo, border, value, out, as_stream(stream)), "pad_u8 launch");
+}
+
+int miaug_warp_affine_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
+                         uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "warp_affine_u8: negative size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "warp_affine_u8: C=%d (1, 3 or 4)", C);
+    if (interp != MIAUG_INTERP_BILINEAR && interp != MIAUG_INTERP_NEAREST)
+        return set_error(MIAUG_EINVAL, "warp_affine_u8: interp %d", interp);
+    if (border != MIAUG_BORDER_REFLECT101 && border != MIAUG_BORDER_CONSTANT)
+        return set_error(MIAUG_EINVAL, "warp_affine_u8: border %d", border);
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!in || !aq || !out) return set_error(MIAUG_EINVAL, "warp_affine_u8: NULL pointer");
+    if ((long long)H * W * C > (1ll << 31) - 1 || H > 16384 || W > 16384)
+        return set_error(MIAUG_ESHAPE, "warp_affine_u8: image too large");
+    return hip_status(launch_warp_u8(in, n, H, W, C, aq, interp, border, out, as_stream(stream)),
+                      "warp_affine_u8 launch");
+}
+
 int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec,
                                             int crop, int outsz, uint8_t *out, void *stream) {
     begin_call();
@@ -145,6 +189,29 @@ int miaug_ssr_crop_resize_hsv_gamma_blur_u8(const uint8_t *in, int n, int H, int
     if (H < 1 || W < 1 || crop < 1 || crop > H || crop > W || outsz < 1 || outsz > 4096 || H > 16384 || W > 16384)
         return set_error(MIAUG_ESHAPE, "c2: H=%d W=%d crop=%d outsz=%d", H, W, crop, outsz);
     return hip_status(launch_c2(in, n, H, W, rec, crop, outsz, out, as_stream(stream)), "c2 launch");
+}
+
+int miaug_ssr_crop_resize_mask_u8(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop,
+                                  int outsz, uint8_t *out, void *stream) {
+    clear_error();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "c2 mask: negative size");
+    if (n == 0) return MIAUG_OK;
+    if (!in || !rec || !out) return set_error(MIAUG_EINVAL, "c2 mask: NULL pointer");
+    if (crop < 1 || crop > H || crop > W || outsz < 1 || outsz > 4096 || H > 16384 || W > 16384)
+        return set_error(MIAUG_ESHAPE, "c2 mask: H=%d W=%d crop=%d outsz=%d", H, W, crop, outsz);
+    return hip_status(launch_c2_mask(in, n, H, W, rec, crop, outsz, out, as_stream(stream)), "c2 mask launch");
+}
+
+int miaug_boxes_ssr_crop_resize(const float *boxes, const int32_t *box_off, int n, int H, int W,
+                                const miaug_c2_record *rec, int crop, int outsz, float *out, void *stream) {
+    clear_error();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "c2 boxes: negative size");
+    if (n == 0) return MIAUG_OK;
+    if (!boxes || !box_off || !rec || !out) return set_error(MIAUG_EINVAL, "c2 boxes: NULL pointer");
+    if (crop < 1 || crop > H || crop > W || outsz < 1 || outsz > 4096)
+        return set_error(MIAUG_ESHAPE, "c2 boxes: H=%d W=%d crop=%d outsz=%d", H, W, crop, outsz);
+    return hip_status(launch_c2_boxes(boxes, box_off, n, H, W, rec, crop, outsz, out, as_stream(stream)),
+                      "c2 boxes launch");
 }
 
 int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream) {
@@ -380,6 +447,19 @@ int miaug_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H,
     return hip_status(launch_elastic_grid_u8(img, mask, n, H, W, C, off, mapx, mapy, out, out_mask, per_image,
                                              as_stream(stream)),
                       "elastic_grid_u8 launch");
+}
+
+int miaug_boxes_elastic_grid(const float *boxes, const int32_t *box_off, int n, int H, int W, const int32_t *off,
+                             const int32_t *mapx, const int32_t *mapy, float *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "boxes_elastic_grid: negative size");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!boxes || !box_off || !off || !mapx || !mapy || !out)
+        return set_error(MIAUG_EINVAL, "boxes_elastic_grid: NULL pointer");
+    if ((long long)H * W > (1ll << 30) || H > 16384 || W > 16384)
+        return set_error(MIAUG_ESHAPE, "boxes_elastic_grid: image too large");
+    return hip_status(launch_boxes_distort(boxes, box_off, n, H, W, off, mapx, mapy, out, as_stream(stream)),
+                      "boxes_elastic_grid launch");
 }
 
 size_t miaug_chain_f32_workspace_bytes(int n, int C, int H, int W) {

@@ -28,6 +28,12 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 // ---- launchers (each returns the hipError_t of its launches)
 hipError_t launch_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
                            uint8_t *out, hipStream_t s);
+hipError_t launch_d4_lut_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const uint8_t *luts,
+                            const int32_t *gray, uint8_t *out, hipStream_t s);
+hipError_t launch_pad_u8(const uint8_t *in, int n, int H, int W, int C, int Ho, int Wo, int border, int value,
+                         uint8_t *out, hipStream_t s);
+hipError_t launch_warp_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
+                          uint8_t *out, hipStream_t s);
 
 struct RaggedLaunch {
     int variant;      // index into the variant table
@@ -41,6 +47,10 @@ int ragged_default_variant();
 
 hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
                      uint8_t *out, hipStream_t s);
+hipError_t launch_c2_mask(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
+                          uint8_t *out, hipStream_t s);
+hipError_t launch_c2_boxes(const float *boxes, const int32_t *box_off, int n, int H, int W,
+                           const miaug_c2_record *rec, int crop, int outsz, float *out, hipStream_t s);
 
 hipError_t launch_wc_fwd(const float *x, int n, int C, int H, int W, const float *p, float *y, hipStream_t s);
 size_t wc_workspace_bytes(int n, int C, int H, int W);
@@ -59,6 +69,8 @@ hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *
 hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
                                   const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
                                   uint8_t *out_mask, int per_image, hipStream_t s);
+hipError_t launch_boxes_distort(const float *boxes, const int32_t *box_off, int n, int H, int W, const int32_t *off,
+                                const int32_t *mapx, const int32_t *mapy, float *out, hipStream_t s);
 size_t chain_f32_workspace_bytes(int n, int C, int H, int W);
 hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
                                 const int32_t *mapy, float *y, void *ws, hipStream_t s);

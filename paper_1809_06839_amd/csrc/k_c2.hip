@@ -269,7 +269,92 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
     }
 }
 
+// Reflect-101 of a 64-bit index (a strongly shrinking warp can reach far out).
+__device__ __forceinline__ int reflect101_64(int64_t i, int n) {
+    if (n == 1) return 0;
+    const int64_t p = 2 * (int64_t)n - 2;
+    i %= p;
+    if (i < 0) i += p;
+    return (int)(i >= n ? p - i : i);
+}
+
+// Masks of the u8 chain: the same geometry with nearest taps and no colour
+// ops.  Output (y, x) takes the nearest resize index of the crop (source
+// index (q + 512) >> 10 of the Q10 position, clamped into the crop), shifts
+// it by the crop offset and samples the warped mask there: nearest tap of the
+// Q32 inverse map rounded to Q10, reflect-101.  One thread per output pixel.
+__global__ __launch_bounds__(kThreads) void k_c2_mask(const uint8_t *__restrict__ in, int H, int W,
+                                                      const miaug_c2_record *__restrict__ rec, int crop, int outsz,
+                                                      uint8_t *__restrict__ out) {
+    const int img = blockIdx.y;
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= outsz * outsz) return;
+    const int y = e / outsz, x = e - y * outsz;
+    const miaug_c2_record &r = rec[img];
+    const int ny = min(max((resize_q(y, crop, outsz) + kFOne / 2) >> kFBits, 0), crop - 1) + r.crop_y;
+    const int nx = min(max((resize_q(x, crop, outsz) + kFOne / 2) >> kFBits, 0), crop - 1) + r.crop_x;
+    const int64_t qx = rshr_he64(r.aq[0] * nx + r.aq[1] * ny + r.aq[2], 32 - kFBits);
+    const int64_t qy = rshr_he64(r.aq[3] * nx + r.aq[4] * ny + r.aq[5], 32 - kFBits);
+    const int64_t ix = (qx + kFOne / 2) >> kFBits, iy = (qy + kFOne / 2) >> kFBits;
+    const int sx = reflect101_64(ix, W), sy = reflect101_64(iy, H);
+    out[(size_t)img * outsz * outsz + e] = in[(size_t)img * H * W + (size_t)sy * W + sx];
+}
+
+// Boxes of the u8 chain: the forward map of the warp (the inverse of the
+// record's Q32 matrix, in double) takes each corner u of a box (continuous
+// coordinates, pixel i spans [i, i + 1)) as the index position u - 1/2 to
+// F(u - 1/2) + 1/2; the box becomes the bounding box of its four corners,
+// clipped to the image, then shifted by the crop offset, clipped to the crop
+// and scaled by outsz / crop.  One workgroup per image, a thread per box.
+__global__ __launch_bounds__(64) void k_c2_boxes(const float *__restrict__ boxes, const int32_t *__restrict__ box_off,
+                                                 int H, int W, const miaug_c2_record *__restrict__ rec, int crop,
+                                                 int outsz, float *__restrict__ out) {
+    const int img = blockIdx.x;
+    const miaug_c2_record &r = rec[img];
+    const double q = 4294967296.0;
+    const double a0 = r.aq[0] / q, a1 = r.aq[1] / q, a2 = r.aq[2] / q;
+    const double a3 = r.aq[3] / q, a4 = r.aq[4] / q, a5 = r.aq[5] / q;
+    const double det = a0 * a4 - a1 * a3;
+    const double i00 = a4 / det, i01 = -a1 / det, i10 = -a3 / det, i11 = a0 / det;
+    const double k = (double)outsz / crop;
+    for (int b = box_off[img] + (int)threadIdx.x; b < box_off[img + 1]; b += 64) {
+        const float *bx = boxes + 4 * (size_t)b;
+        double x1 = 1e300, y1 = 1e300, x2 = -1e300, y2 = -1e300;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double px = (double)bx[(c & 1) ? 2 : 0] - 0.5 - a2, py = (double)bx[(c & 2) ? 3 : 1] - 0.5 - a5;
+            const double ox = i00 * px + i01 * py + 0.5, oy = i10 * px + i11 * py + 0.5;
+            x1 = fmin(x1, ox); x2 = fmax(x2, ox);
+            y1 = fmin(y1, oy); y2 = fmax(y2, oy);
+        }
+        x1 = fmin(fmax(x1, 0.0), (double)W); x2 = fmin(fmax(x2, 0.0), (double)W);
+        y1 = fmin(fmax(y1, 0.0), (double)H); y2 = fmin(fmax(y2, 0.0), (double)H);
+        x1 = fmin(fmax(x1 - r.crop_x, 0.0), (double)crop); x2 = fmin(fmax(x2 - r.crop_x, 0.0), (double)crop);
+        y1 = fmin(fmax(y1 - r.crop_y, 0.0), (double)crop); y2 = fmin(fmax(y2 - r.crop_y, 0.0), (double)crop);
+        float *o = out + 4 * (size_t)b;
+        o[0] = (float)(x1 * k);
+        o[1] = (float)(y1 * k);
+        o[2] = (float)(x2 * k);
+        o[3] = (float)(y2 * k);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_c2_mask(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
+                          uint8_t *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_c2_mask, dim3((outsz * outsz + kThreads - 1) / kThreads, n), dim3(kThreads), 0, s, in, H, W,
+                       rec, crop, outsz, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_c2_boxes(const float *boxes, const int32_t *box_off, int n, int H, int W,
+                           const miaug_c2_record *rec, int crop, int outsz, float *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_c2_boxes, dim3(n), dim3(64), 0, s, boxes, box_off, H, W, rec, crop, outsz, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
                      uint8_t *out, hipStream_t s) {

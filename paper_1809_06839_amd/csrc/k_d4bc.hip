@@ -1,6 +1,6 @@
-// k_d4bc.hip -- random Dih4 element + brightness/contrast LUT on a dense u8
-// batch (Sec. II-B Dih4 transforms; Table I HorizontalFlip, VerticalFlip,
-// Brightness).
+// k_d4bc.hip -- random Dih4 element + colour LUTs on a dense u8 batch
+// (Sec. II-B Dih4 transforms; Table I HorizontalFlip, VerticalFlip,
+// Brightness, ShiftRGB, Grayscale).
 //
 // One workgroup per (image, 64x64 output tile).  The tile's source block is
 // an axis-aligned rectangle (a Dih4 element maps rectangles to rectangles);
@@ -17,14 +17,19 @@ namespace {
 constexpr int kT = 64;
 constexpr int kThreads = 256;
 
-template <int C>
+// FROM_AB: one LUT per image built from (alpha, beta); otherwise C LUTs per
+// image read from `luts` ([n][C][256], composed on the host) and, for C = 3,
+// an optional per-image grayscale flag applied after them.
+template <int C, bool FROM_AB>
 __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ in, int H, int W,
                                                    const int32_t *__restrict__ flags, const float *__restrict__ ab,
+                                                   const uint8_t *__restrict__ luts, const int32_t *__restrict__ gray,
                                                    uint8_t *__restrict__ out) {
     constexpr int kChunks = (kT * C + 30) / 16;          // 16-byte chunks per staged row (phase included)
     constexpr int kStride = kChunks * 16 + 16;           // LDS bytes per row (+16 against bank conflicts)
+    constexpr int kLuts = FROM_AB ? 1 : C;
     __shared__ __align__(16) uint8_t src[kT * kStride];
-    __shared__ uint8_t lut[256];
+    __shared__ uint8_t lut[kLuts][256];
 
     const int img = blockIdx.y;
     const int tid = threadIdx.x;
@@ -49,10 +54,13 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
         const uint8_t *g = base + ((size_t)(sr0 + row) * W + sc0) * C;
         if (ch < span_chunks(g, nsc * C)) load_span16_chunk(g, ch, src + row * kStride);
     }
-    if (tid < 256) {
+    if (FROM_AB) {
         double t = (double)ab[2 * img] * (double)tid + (double)ab[2 * img + 1];
-        lut[tid] = (uint8_t)sat8((int)rint(t));
+        lut[0][tid] = (uint8_t)sat8((int)rint(t));
+    } else {
+        for (int e = tid; e < C * 256; e += kThreads) lut[e >> 8][e & 255] = luts[(size_t)img * C * 256 + e];
     }
+    const bool to_gray = !FROM_AB && C == 3 && gray && gray[img];
     __syncthreads();
 
     uint8_t *obase = out + (size_t)img * plane;
@@ -68,7 +76,12 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
             int c = c0 + px;
             int sy = m.sy(orow, c), sx = m.sx(orow, c);
             const uint8_t *grow = base + ((size_t)sy * W + sc0) * C;
-            return lut[src[(sy - sr0) * kStride + span_phase(grow) + (sx - sc0) * C + chn]];
+            const uint8_t *p = &src[(sy - sr0) * kStride + span_phase(grow) + (sx - sc0) * C];
+            if (FROM_AB) return lut[0][p[chn]];
+            if (!to_gray) return lut[chn][p[chn]];
+            // BT.601 luma in Q14 (4899, 9617, 1868), rounded half up, on the LUT'd channels
+            const int r = lut[0][p[0]], g = lut[C > 1 ? 1 : 0][p[C > 1 ? 1 : 0]], bl = lut[C > 2 ? 2 : 0][p[C > 2 ? 2 : 0]];
+            return (uint8_t)((4899 * r + 9617 * g + 1868 * bl + 8192) >> 14);
         };
         store_span_item(g, len, j, byte_at);
     }
@@ -81,9 +94,23 @@ hipError_t launch_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const 
     if (n == 0 || H == 0 || W == 0) return hipSuccess;
     int t = (max(H, W) + kT - 1) / kT;
     dim3 grid(t * t, n);
-    if (C == 1) hipLaunchKernelGGL(k_d4_bc<1>, grid, dim3(kThreads), 0, s, in, H, W, flags, ab, out);
-    else if (C == 3) hipLaunchKernelGGL(k_d4_bc<3>, grid, dim3(kThreads), 0, s, in, H, W, flags, ab, out);
-    else hipLaunchKernelGGL(k_d4_bc<4>, grid, dim3(kThreads), 0, s, in, H, W, flags, ab, out);
+    const uint8_t *nl = nullptr;
+    const int32_t *ng = nullptr;
+    if (C == 1) hipLaunchKernelGGL((k_d4_bc<1, true>), grid, dim3(kThreads), 0, s, in, H, W, flags, ab, nl, ng, out);
+    else if (C == 3) hipLaunchKernelGGL((k_d4_bc<3, true>), grid, dim3(kThreads), 0, s, in, H, W, flags, ab, nl, ng, out);
+    else hipLaunchKernelGGL((k_d4_bc<4, true>), grid, dim3(kThreads), 0, s, in, H, W, flags, ab, nl, ng, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_d4_lut_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const uint8_t *luts,
+                            const int32_t *gray, uint8_t *out, hipStream_t s) {
+    if (n == 0 || H == 0 || W == 0) return hipSuccess;
+    int t = (max(H, W) + kT - 1) / kT;
+    dim3 grid(t * t, n);
+    const float *na = nullptr;
+    if (C == 1) hipLaunchKernelGGL((k_d4_bc<1, false>), grid, dim3(kThreads), 0, s, in, H, W, flags, na, luts, gray, out);
+    else if (C == 3) hipLaunchKernelGGL((k_d4_bc<3, false>), grid, dim3(kThreads), 0, s, in, H, W, flags, na, luts, gray, out);
+    else hipLaunchKernelGGL((k_d4_bc<4, false>), grid, dim3(kThreads), 0, s, in, H, W, flags, na, luts, gray, out);
     return hipGetLastError();
 }
 

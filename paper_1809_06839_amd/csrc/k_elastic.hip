@@ -505,6 +505,105 @@ __global__ void k_chain_f_elastic_adj(const float *__restrict__ ge, int C, int H
     }
 }
 
+// ---------------------------------------------------------------- boxes under the distortion
+// A box covers the source pixels whose centres lie in [x1, x2) x [y1, y2).
+// Output pixel (x, y) takes, on the mask path, the source pixel reached by the
+// grid's nearest tap and then the elastic map's nearest tap; the transformed
+// box is the bounding box of the output pixels whose source pixel it covers
+// (empty: all zeros).  The outputs are first used as int32 accumulators.
+constexpr int kBoxChunk = 16;
+
+__global__ __launch_bounds__(64) void k_boxes_distort_init(const int32_t *__restrict__ box_off, int32_t *acc) {
+    for (int b = box_off[blockIdx.x] + (int)threadIdx.x; b < box_off[blockIdx.x + 1]; b += 64) {
+        acc[4 * (size_t)b] = INT32_MAX;
+        acc[4 * (size_t)b + 1] = INT32_MAX;
+        acc[4 * (size_t)b + 2] = -1;
+        acc[4 * (size_t)b + 3] = -1;
+    }
+}
+
+constexpr int kBoxPx = 16;  // output pixels per thread
+
+__global__ __launch_bounds__(kThreads) void k_boxes_distort(const float *__restrict__ boxes,
+                                                            const int32_t *__restrict__ box_off, int H, int W,
+                                                            const int32_t *__restrict__ off,
+                                                            const int32_t *__restrict__ mapx,
+                                                            const int32_t *__restrict__ mapy, int32_t *acc) {
+    __shared__ int red[kBoxChunk][4];
+    const int im = blockIdx.y;
+    const int b0 = box_off[im], nb = box_off[im + 1] - b0;
+    if (nb <= 0) return;
+    const size_t plane = (size_t)H * W;
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    // source pixel of each of this thread's output pixels (mask path)
+    int sxs[kBoxPx], sys[kBoxPx], xs[kBoxPx], ys[kBoxPx];
+    const int64_t e0 = ((int64_t)blockIdx.x * kThreads * kBoxPx) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kBoxPx; ++k) {
+        const int64_t e = e0 + (int64_t)k * kThreads;
+        sxs[k] = -1;
+        if (e >= (int64_t)plane) continue;
+        const int y = (int)(e / W), x = (int)(e - (int64_t)y * W);
+        const int X = reflect101((mapx[(size_t)im * W + x] + kFOne / 2) >> kFBits, W);
+        const int Y = reflect101((mapy[(size_t)im * H + y] + kFOne / 2) >> kFBits, H);
+        const size_t q = (size_t)Y * W + X;
+        sxs[k] = reflect101(((X << kFBits) + ox[q] + kFOne / 2) >> kFBits, W);
+        sys[k] = reflect101(((Y << kFBits) + oy[q] + kFOne / 2) >> kFBits, H);
+        xs[k] = x;
+        ys[k] = y;
+    }
+    for (int c0 = 0; c0 < nb; c0 += kBoxChunk) {
+        const int cn = min(kBoxChunk, nb - c0);
+        if (threadIdx.x < kBoxChunk * 4) red[threadIdx.x >> 2][threadIdx.x & 3] = (threadIdx.x & 2) ? -1 : INT32_MAX;
+        __syncthreads();
+        for (int j = 0; j < cn; ++j) {
+            const float *bx = boxes + 4 * (size_t)(b0 + c0 + j);
+            const float x1 = bx[0], y1 = bx[1], x2 = bx[2], y2 = bx[3];
+            int mnx = INT32_MAX, mny = INT32_MAX, mxx = -1, mxy = -1;
+#pragma unroll
+            for (int k = 0; k < kBoxPx; ++k) {
+                if (sxs[k] < 0) continue;
+                const float cx = (float)sxs[k] + 0.5f, cy = (float)sys[k] + 0.5f;
+                if (cx >= x1 && cx < x2 && cy >= y1 && cy < y2) {
+                    mnx = min(mnx, xs[k]);
+                    mny = min(mny, ys[k]);
+                    mxx = max(mxx, xs[k]);
+                    mxy = max(mxy, ys[k]);
+                }
+            }
+            if (mxx >= 0) {
+                atomicMin(&red[j][0], mnx);
+                atomicMin(&red[j][1], mny);
+                atomicMax(&red[j][2], mxx);
+                atomicMax(&red[j][3], mxy);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < cn && red[threadIdx.x][2] >= 0) {
+            int32_t *a = acc + 4 * (size_t)(b0 + c0 + threadIdx.x);
+            atomicMin(a, red[threadIdx.x][0]);
+            atomicMin(a + 1, red[threadIdx.x][1]);
+            atomicMax(a + 2, red[threadIdx.x][2]);
+            atomicMax(a + 3, red[threadIdx.x][3]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_boxes_distort_final(const int32_t *__restrict__ box_off, int32_t *acc) {
+    for (int b = box_off[blockIdx.x] + (int)threadIdx.x; b < box_off[blockIdx.x + 1]; b += 64) {
+        int32_t *a = acc + 4 * (size_t)b;
+        const bool empty = a[2] < 0;
+        float *o = (float *)a;
+        const float v0 = empty ? 0.f : (float)a[0], v1 = empty ? 0.f : (float)a[1];
+        const float v2 = empty ? 0.f : (float)(a[2] + 1), v3 = empty ? 0.f : (float)(a[3] + 1);
+        o[0] = v0;
+        o[1] = v1;
+        o[2] = v2;
+        o[3] = v3;
+    }
+}
+
 }  // namespace
 
 size_t elastic_workspace_bytes(int n, int H, int W) {
@@ -621,6 +720,18 @@ hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H
     hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr, off);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxes_distort(const float *boxes, const int32_t *box_off, int n, int H, int W, const int32_t *off,
+                                const int32_t *mapx, const int32_t *mapy, float *out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    int32_t *acc = (int32_t *)out;
+    hipLaunchKernelGGL(k_boxes_distort_init, dim3(n), dim3(64), 0, s, box_off, acc);
+    const int64_t per = (int64_t)kThreads * kBoxPx;
+    hipLaunchKernelGGL(k_boxes_distort, dim3((unsigned)(((int64_t)H * W + per - 1) / per), n), dim3(kThreads), 0, s,
+                       boxes, box_off, H, W, off, mapx, mapy, acc);
+    hipLaunchKernelGGL(k_boxes_distort_final, dim3(n), dim3(64), 0, s, box_off, acc);
     return hipGetLastError();
 }
 

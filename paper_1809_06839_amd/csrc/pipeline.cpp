@@ -93,18 +93,21 @@ struct Gen {
 const char *op_name(uint32_t k) {
     static const char *names[] = {"?", "HFLIP", "VFLIP", "ROT90", "TRANSPOSE", "SSR", "CROP", "RESIZE",
                                   "BRIGHT_CONTRAST", "HSV", "GAMMA", "BLUR3", "BLUR5", "ELASTIC", "GRID",
-                                  "NORMALIZE", "SIZED_CROP"};
+                                  "NORMALIZE", "SIZED_CROP", "SHIFT_RGB", "TO_GRAY", "PAD", "ROTATE"};
     return k < sizeof(names) / sizeof(names[0]) ? names[k] : "?";
 }
 
 // Allowed op sequences per chain (each op at most once, in this order).
-const uint32_t kSeqDih4[] = {MIAUG_OP_HFLIP, MIAUG_OP_VFLIP, MIAUG_OP_ROT90, MIAUG_OP_TRANSPOSE,
-                             MIAUG_OP_BRIGHT_CONTRAST};
+const uint32_t kSeqDih4[] = {MIAUG_OP_HFLIP,           MIAUG_OP_VFLIP,     MIAUG_OP_ROT90, MIAUG_OP_TRANSPOSE,
+                             MIAUG_OP_BRIGHT_CONTRAST, MIAUG_OP_SHIFT_RGB, MIAUG_OP_TO_GRAY};
 const uint32_t kSeqRagged[] = {MIAUG_OP_HFLIP,      MIAUG_OP_VFLIP,           MIAUG_OP_ROT90,
                                MIAUG_OP_TRANSPOSE,  MIAUG_OP_SIZED_CROP,      MIAUG_OP_BRIGHT_CONTRAST,
                                MIAUG_OP_RESIZE,     MIAUG_OP_NORMALIZE};
 const uint32_t kSeqU8[] = {MIAUG_OP_SSR, MIAUG_OP_CROP, MIAUG_OP_RESIZE, MIAUG_OP_HSV, MIAUG_OP_GAMMA, MIAUG_OP_BLUR3};
 const uint32_t kSeqDistort[] = {MIAUG_OP_ELASTIC, MIAUG_OP_GRID};
+const uint32_t kSeqRotate[] = {MIAUG_OP_ROTATE};
+const uint32_t kSeqSsr[] = {MIAUG_OP_SSR};
+const uint32_t kSeqPad[] = {MIAUG_OP_PAD};
 
 // Index of the first op of `ops` that breaks the order of `seq` (n if none).
 int match_order(const miaug_op *ops, int n, const uint32_t *seq, int nseq) {
@@ -137,6 +140,10 @@ struct miaug_pipeline {
     float mean[3], stdv[3];  // NORMALIZE (RAGGED)
     int el_alpha, el_radius; // ELASTIC (DISTORT); el_alpha < 0: no elastic op
     bool wcrop;              // SIZED_CROP (RAGGED): records carry a crop window
+    bool color;              // SHIFT_RGB or TO_GRAY (DIH4): per-channel LUTs and grayscale flags
+    int interp, border;      // WARP: of the ROTATE / SSR op; PAD: border
+    int pad_value;           // PAD, constant border
+    int chan;                // channels of the batch being staged (DIH4 colour LUT layout)
     double el_sigma;
     bool el_box;             // box-cascade approximation of the field
     // pinned staging of packed records, device copies, chain buffers
@@ -151,7 +158,7 @@ struct miaug_pipeline {
 
 struct miaug_pipeline_graph {
     miaug_pipeline *p;
-    int n, H, W;
+    int n, H, W, chan;
     void *pinned;  // this graph's own staging buffer (read by its copy node)
     size_t packed;
     hipGraph_t graph;
@@ -166,7 +173,7 @@ int op_check(const miaug_op &o, int i) {
     if (!(o.p >= 0.f && o.p <= 1.f)) return set_error(MIAUG_EINVAL, "pipeline: op %d (%s): p outside [0, 1]", i, nm);
     for (int k = 0; k < 4; ++k)
         if (!(o.lo[k] <= o.hi[k]) && o.kind != MIAUG_OP_NORMALIZE && o.kind != MIAUG_OP_ELASTIC &&
-            o.kind != MIAUG_OP_GRID)
+            o.kind != MIAUG_OP_GRID && o.kind != MIAUG_OP_PAD)
             return set_error(MIAUG_EINVAL, "pipeline: op %d (%s): lo[%d] > hi[%d]", i, nm, k, k);
     switch (o.kind) {
     case MIAUG_OP_ROT90:
@@ -174,8 +181,10 @@ int op_check(const miaug_op &o, int i) {
             return set_error(MIAUG_EINVAL, "pipeline: op %d (ROT90): k range must be integers in 0..3", i);
         break;
     case MIAUG_OP_SSR:
-        if (o.interp != MIAUG_INTERP_BILINEAR || o.border != MIAUG_BORDER_REFLECT101)
-            return set_error(MIAUG_EUNSUPPORTED, "pipeline: op %d (SSR): only bilinear with reflect-101", i);
+        if (o.interp != MIAUG_INTERP_BILINEAR && o.interp != MIAUG_INTERP_NEAREST)
+            return set_error(MIAUG_EINVAL, "pipeline: op %d (SSR): interp %u", i, o.interp);
+        if (o.border != MIAUG_BORDER_REFLECT101 && o.border != MIAUG_BORDER_CONSTANT)
+            return set_error(MIAUG_EINVAL, "pipeline: op %d (SSR): border %u", i, o.border);
         if (!(o.lo[1] > 0.f)) return set_error(MIAUG_EINVAL, "pipeline: op %d (SSR): scale must be > 0", i);
         break;
     case MIAUG_OP_CROP:
@@ -202,6 +211,20 @@ int op_check(const miaug_op &o, int i) {
         for (int c = 0; c < 3; ++c)
             if (!(o.hi[c] != 0.f)) return set_error(MIAUG_EINVAL, "pipeline: op %d (NORMALIZE): std[%d] is 0", i, c);
         break;
+    case MIAUG_OP_ROTATE:
+    case MIAUG_OP_PAD:
+        if (o.interp != MIAUG_INTERP_BILINEAR && o.interp != MIAUG_INTERP_NEAREST)
+            return set_error(MIAUG_EINVAL, "pipeline: op %d (%s): interp %u", i, nm, o.interp);
+        if (o.border != MIAUG_BORDER_REFLECT101 && o.border != MIAUG_BORDER_CONSTANT)
+            return set_error(MIAUG_EINVAL, "pipeline: op %d (%s): border %u", i, nm, o.border);
+        if (o.kind == MIAUG_OP_PAD) {
+            if (o.p != 1.f) return set_error(MIAUG_EUNSUPPORTED, "pipeline: op %d (PAD): p must be 1", i);
+            if (o.out_h < 0 || o.out_w < 0 || o.out_h > 16384 || o.out_w > 16384)
+                return set_error(MIAUG_EINVAL, "pipeline: op %d (PAD): size %dx%d outside 0..16384", i, o.out_h, o.out_w);
+            if (!(o.lo[0] >= 0.f && o.lo[0] <= 255.f))
+                return set_error(MIAUG_EINVAL, "pipeline: op %d (PAD): value outside 0..255", i);
+        }
+        break;
     case MIAUG_OP_SIZED_CROP:
         if (!(o.lo[0] > 0.f && o.hi[0] <= 1.f && o.lo[1] > 0.f))
             return set_error(MIAUG_EINVAL, "pipeline: op %d (SIZED_CROP): need 0 < scale <= 1, ratio > 0", i);
@@ -209,7 +232,7 @@ int op_check(const miaug_op &o, int i) {
     case MIAUG_OP_BLUR5:
         return set_error(MIAUG_EUNSUPPORTED, "pipeline: op %d (BLUR5): no fused chain takes a 5x5 blur", i);
     default:
-        if (o.kind < MIAUG_OP_HFLIP || o.kind > MIAUG_OP_SIZED_CROP)
+        if (o.kind < MIAUG_OP_HFLIP || o.kind > MIAUG_OP_ROTATE)
             return set_error(MIAUG_EINVAL, "pipeline: op %d: unknown kind %u", i, o.kind);
     }
     return MIAUG_OK;
@@ -243,19 +266,36 @@ int grow_device(void **ptr, size_t *cap, size_t bytes, const char *what) {
 
 // Packed device form of the records of one batch (host side), by chain:
 //   DIH4, RAGGED: int32 flags [n][4], then float ab [n][2] (RAGGED with
-//                 SIZED_CROP: then int32 windows [n][4])
+//                 SIZED_CROP: then int32 windows [n][4]; DIH4: then the
+//                 identity ab block of the masks, float [n][2], and with
+//                 colour ops u8 LUTs [n][C][256] and int32 gray flags [n])
 //   U8CHAIN:      miaug_c2_record [n]
 //   DISTORT:      double grid [n][10]
-size_t packed_bytes(const miaug_pipeline *p, int n) {
+//   WARP:         int64 Q32 matrices [n][6]
+//   PAD:          nothing (8 bytes of padding)
+size_t packed_bytes(const miaug_pipeline *p, int n, int C) {
     switch (p->kind) {
-    case MIAUG_PIPE_DIH4: return (size_t)n * 24;
+    case MIAUG_PIPE_DIH4: return (size_t)n * 32 + (p->color ? (size_t)n * (256 * C + 4) : 0);
     case MIAUG_PIPE_RAGGED: return (size_t)n * (p->wcrop ? 40 : 24);
     case MIAUG_PIPE_U8CHAIN: return (size_t)n * sizeof(miaug_c2_record);
+    case MIAUG_PIPE_WARP: return (size_t)n * 48;
+    case MIAUG_PIPE_PAD: return 8;
     default: return (size_t)n * 10 * sizeof(double);
     }
 }
 
-int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, void *dst) {
+int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, int C, void *dst) {
+    if (p->kind == MIAUG_PIPE_PAD) return MIAUG_OK;
+    if (p->kind == MIAUG_PIPE_WARP) {
+        std::vector<float> f(4 * (size_t)n);
+        for (int i = 0; i < n; ++i) {
+            f[4 * i] = r[i].angle;
+            f[4 * i + 1] = r[i].scale;
+            f[4 * i + 2] = r[i].dx;
+            f[4 * i + 3] = r[i].dy;
+        }
+        return miaug_compile_ssr_q32(f.data(), n, H, W, (int64_t *)dst);
+    }
     if (p->kind == MIAUG_PIPE_DIH4 || p->kind == MIAUG_PIPE_RAGGED) {
         int32_t *fl = (int32_t *)dst;
         float *ab = (float *)((char *)dst + (size_t)n * 16);
@@ -263,6 +303,24 @@ int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, vo
             for (int k = 0; k < 4; ++k) fl[4 * i + k] = r[i].flags[k];
             ab[2 * i] = r[i].alpha;
             ab[2 * i + 1] = r[i].beta;
+        }
+        if (p->kind == MIAUG_PIPE_DIH4) {
+            float *ab1 = (float *)((char *)dst + (size_t)n * 24);
+            for (int i = 0; i < n; ++i) {
+                ab1[2 * i] = 1.f;
+                ab1[2 * i + 1] = 0.f;
+            }
+        }
+        if (p->kind == MIAUG_PIPE_DIH4 && p->color) {
+            uint8_t *luts = (uint8_t *)dst + (size_t)n * 32;
+            int32_t *gray = (int32_t *)(luts + (size_t)n * 256 * C);
+            std::vector<float> sh((size_t)n * C, 0.f);
+            for (int i = 0; i < n; ++i) {
+                for (int c = 0; c < C && c < 3; ++c) sh[(size_t)C * i + c] = r[i].shift[c];
+                gray[i] = r[i].gray;
+            }
+            int st = miaug_compile_color_luts(ab, sh.data(), n, C, luts);
+            if (st) return st;
         }
         if (p->wcrop) {
             int32_t *win = (int32_t *)((char *)dst + (size_t)n * 24);
@@ -317,11 +375,18 @@ int batch_check(const miaug_pipeline *p, const miaug_batch_in *in, const miaug_b
         if (in->boxes && (!in->box_off || !out->boxes)) return set_error(MIAUG_EINVAL, "apply: boxes without offsets/output");
         return MIAUG_OK;
     }
-    if (in->boxes) return set_error(MIAUG_EUNSUPPORTED, "apply: boxes are supported by the ragged chain only");
+    if ((p->kind == MIAUG_PIPE_WARP || p->kind == MIAUG_PIPE_PAD || p->kind == MIAUG_PIPE_DIH4) &&
+        in->channels != 1 && in->channels != 3 && in->channels != 4)
+        return set_error(MIAUG_ESHAPE, "apply: channels must be 1, 3 or 4");
+    if (p->kind == MIAUG_PIPE_DIH4 && p->color && has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_TO_GRAY) &&
+        in->channels != 3)
+        return set_error(MIAUG_ESHAPE, "apply: TO_GRAY takes RGB images");
+    if (in->boxes && p->kind != MIAUG_PIPE_U8CHAIN && p->kind != MIAUG_PIPE_DISTORT)
+        return set_error(MIAUG_EUNSUPPORTED, "apply: boxes are supported by the ragged, u8 and distortion chains only");
+    if (in->boxes && (!in->box_off || !out->boxes)) return set_error(MIAUG_EINVAL, "apply: boxes without offsets/output");
     if (in->H < 1 || in->W < 1) return set_error(MIAUG_ESHAPE, "apply: dense batch needs H, W >= 1");
     if (p->kind == MIAUG_PIPE_U8CHAIN) {
         if (in->channels != 3) return set_error(MIAUG_ESHAPE, "apply: the u8 chain takes RGB images");
-        if (in->mask) return set_error(MIAUG_EUNSUPPORTED, "apply: the u8 chain takes no masks");
         if (p->crop_h != p->crop_w || p->out_h != p->out_w)
             return set_error(MIAUG_EUNSUPPORTED, "apply: the u8 chain needs a square crop and output");
         if (p->crop_h > in->H || p->crop_w > in->W) return set_error(MIAUG_ESHAPE, "apply: crop larger than the image");
@@ -365,8 +430,19 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
             return per_image ? miaug_ragged_apply_per_image(p->ctx, &a, s) : miaug_ragged_apply(p->ctx, &a, s);
         }
         const size_t isz = (size_t)in->H * in->W * in->channels, msz = (size_t)in->H * in->W;
+        const uint8_t *luts = (const uint8_t *)dp + (size_t)n * 32;
+        const int32_t *gray = (const int32_t *)(luts + (size_t)n * 256 * in->channels);
+        const bool to_gray = p->color && has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_TO_GRAY);
+        auto images = [&](int i0, int cnt) {
+            const uint8_t *src = in->img + i0 * isz;
+            uint8_t *dst = (uint8_t *)out->img + i0 * isz;
+            if (p->color)
+                return miaug_d4_lut_u8(src, cnt, in->H, in->W, in->channels, fl + 4 * i0,
+                                       luts + (size_t)i0 * 256 * in->channels, to_gray ? gray + i0 : nullptr, dst, s);
+            return miaug_d4_bc_u8(src, cnt, in->H, in->W, in->channels, fl + 4 * i0, ab + 2 * i0, dst, s);
+        };
         if (!per_image) {
-            int st = miaug_d4_bc_u8(in->img, n, in->H, in->W, in->channels, fl, ab, (uint8_t *)out->img, s);
+            int st = images(0, n);
             // masks: same Dih4 element, no colour change (alpha 1, beta 0 is the identity LUT)
             if (!st && in->mask) {
                 float *ab1 = (float *)((char *)dp + (size_t)n * 24);
@@ -375,8 +451,7 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
             return st;
         }
         for (int i = 0; i < n; ++i) {
-            int st = miaug_d4_bc_u8(in->img + i * isz, 1, in->H, in->W, in->channels, fl + 4 * i, ab + 2 * i,
-                                    (uint8_t *)out->img + i * isz, s);
+            int st = images(i, 1);
             if (!st && in->mask) {
                 float *ab1 = (float *)((char *)dp + (size_t)n * 24);
                 st = miaug_d4_bc_u8(in->mask + i * msz, 1, in->H, in->W, 1, fl + 4 * i, ab1 + 2 * i,
@@ -388,16 +463,55 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
     }
     if (p->kind == MIAUG_PIPE_U8CHAIN) {
         const miaug_c2_record *rec = (const miaug_c2_record *)dp;
-        if (!per_image)
-            return miaug_ssr_crop_resize_hsv_gamma_blur_u8(in->img, n, in->H, in->W, rec, p->crop_h, p->out_h,
-                                                           (uint8_t *)out->img, s);
-        const size_t isz = (size_t)in->H * in->W * 3, osz = (size_t)p->out_h * p->out_w * 3;
-        for (int i = 0; i < n; ++i) {
-            int st = miaug_ssr_crop_resize_hsv_gamma_blur_u8(in->img + i * isz, 1, in->H, in->W, rec + i, p->crop_h,
+        int st = MIAUG_OK;
+        if (!per_image) {
+            st = miaug_ssr_crop_resize_hsv_gamma_blur_u8(in->img, n, in->H, in->W, rec, p->crop_h, p->out_h,
+                                                         (uint8_t *)out->img, s);
+            if (!st && in->mask)
+                st = miaug_ssr_crop_resize_mask_u8(in->mask, n, in->H, in->W, rec, p->crop_h, p->out_h, out->mask, s);
+        } else {
+            const size_t isz = (size_t)in->H * in->W * 3, osz = (size_t)p->out_h * p->out_w * 3;
+            const size_t msz = (size_t)in->H * in->W, mosz = (size_t)p->out_h * p->out_w;
+            for (int i = 0; i < n && !st; ++i) {
+                st = miaug_ssr_crop_resize_hsv_gamma_blur_u8(in->img + i * isz, 1, in->H, in->W, rec + i, p->crop_h,
                                                              p->out_h, (uint8_t *)out->img + i * osz, s);
-            if (st) return st;
+                if (!st && in->mask)
+                    st = miaug_ssr_crop_resize_mask_u8(in->mask + i * msz, 1, in->H, in->W, rec + i, p->crop_h,
+                                                       p->out_h, out->mask + i * mosz, s);
+            }
         }
-        return MIAUG_OK;
+        // boxes: one small launch over the whole batch in both forms (their offsets live on the device)
+        if (!st && in->boxes)
+            st = miaug_boxes_ssr_crop_resize(in->boxes, in->box_off, n, in->H, in->W, rec, p->crop_h, p->out_h,
+                                             out->boxes, s);
+        return st;
+    }
+    if (p->kind == MIAUG_PIPE_WARP || p->kind == MIAUG_PIPE_PAD) {
+        const int C = in->channels, H = in->H, W = in->W;
+        const int Ho = p->kind == MIAUG_PIPE_PAD ? (H > p->out_h ? H : p->out_h) : H;
+        const int Wo = p->kind == MIAUG_PIPE_PAD ? (W > p->out_w ? W : p->out_w) : W;
+        const size_t isz = (size_t)H * W * C, osz = (size_t)Ho * Wo * C, msz = (size_t)H * W, mosz = (size_t)Ho * Wo;
+        const int64_t *aq = (const int64_t *)dp;
+        int st = MIAUG_OK;
+        for (int i0 = 0; i0 < n && !st; i0 += per_image ? 1 : n) {
+            const int cnt = per_image ? 1 : n;
+            if (p->kind == MIAUG_PIPE_WARP) {
+                st = miaug_warp_affine_u8(in->img + i0 * isz, cnt, H, W, C, aq + 6 * i0, p->interp, p->border,
+                                          (uint8_t *)out->img + i0 * osz, s);
+                // masks: the same map with nearest taps
+                if (!st && in->mask)
+                    st = miaug_warp_affine_u8(in->mask + i0 * msz, cnt, H, W, 1, aq + 6 * i0, MIAUG_INTERP_NEAREST,
+                                              p->border, out->mask + i0 * mosz, s);
+            } else {
+                st = miaug_pad_u8(in->img + i0 * isz, cnt, H, W, C, p->out_h, p->out_w, p->border, p->pad_value,
+                                  (uint8_t *)out->img + i0 * osz, s);
+                // masks: the same border, constant padding with label 0
+                if (!st && in->mask)
+                    st = miaug_pad_u8(in->mask + i0 * msz, cnt, H, W, 1, p->out_h, p->out_w, p->border, 0,
+                                      out->mask + i0 * mosz, s);
+            }
+        }
+        return st;
     }
     // DISTORT: fields (or zero offsets), grid tables (from the records, or identity factors), remap chain
     const int H = in->H, W = in->W;
@@ -423,6 +537,8 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
     if (!st)
         st = miaug_elastic_grid_u8(in->img, in->mask, n, H, W, in->channels, off, mapx, mapy, (uint8_t *)out->img,
                                    out->mask, per_image, s);
+    if (!st && in->boxes)
+        st = miaug_boxes_elastic_grid(in->boxes, in->box_off, n, H, W, off, mapx, mapy, out->boxes, s);
     return st;
 }
 
@@ -436,8 +552,8 @@ size_t distort_work_bytes(const miaug_pipeline *p, int n, int H, int W) {
 // Device buffers for a batch of this shape.
 int prepare(miaug_pipeline *p, const miaug_batch_in *in) {
     const int n = in->n;
-    // DIH4 masks read an identity (1, 0) ab block after the packed records
-    size_t need = packed_bytes(p, n) + (p->kind == MIAUG_PIPE_DIH4 ? (size_t)n * 8 : 0);
+    p->chan = in->channels;
+    size_t need = packed_bytes(p, n, in->channels);
     int st = grow_device(&p->dparams, &p->dparams_cap, need + 256, "pipeline: device records");
     if (st) return st;
     if (p->kind == MIAUG_PIPE_DISTORT) {
@@ -447,10 +563,8 @@ int prepare(miaug_pipeline *p, const miaug_batch_in *in) {
     return st;
 }
 
-// Host bytes staged per batch (records, and the identity ab block of DIH4).
-size_t staged_bytes(const miaug_pipeline *p, int n) {
-    return packed_bytes(p, n) + (p->kind == MIAUG_PIPE_DIH4 ? (size_t)n * 8 : 0);
-}
+// Host bytes staged per batch.
+size_t staged_bytes(const miaug_pipeline *p, int n, int C) { return packed_bytes(p, n, C); }
 
 int fill_staging(const miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *params, void *buf) {
     const int n = in->n;
@@ -460,16 +574,7 @@ int fill_staging(const miaug_pipeline *p, const miaug_batch_in *in, const miaug_
                 return set_error(MIAUG_EUNSUPPORTED,
                                  "apply: distortion records must be consecutive samples of one seed (sample %d)", i);
     }
-    int st = pack(p, params, n, in->H, in->W, buf);
-    if (st) return st;
-    if (p->kind == MIAUG_PIPE_DIH4) {
-        float *ab1 = (float *)((char *)buf + (size_t)n * 24);
-        for (int i = 0; i < n; ++i) {
-            ab1[2 * i] = 1.f;
-            ab1[2 * i + 1] = 0.f;
-        }
-    }
-    return MIAUG_OK;
+    return pack(p, params, n, in->H, in->W, in->channels, buf);
 }
 
 int apply_impl(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *params, miaug_batch_out *out,
@@ -482,7 +587,7 @@ int apply_impl(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *
     if (!params) return set_error(MIAUG_EINVAL, "apply: NULL params");
     hipStream_t s = as_stream(stream);
     int st = prepare(p, in);
-    const size_t bytes = staged_bytes(p, in->n);
+    const size_t bytes = staged_bytes(p, in->n, in->channels);
     if (!st) st = grow_pinned(p, bytes);
     if (st) return st;
     if (p->staged) hipEventSynchronize(p->staged);  // the previous call's copy has left the staging buffer
@@ -513,8 +618,10 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
         int kind;
         const uint32_t *seq;
         int nseq;
-    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 5}, {MIAUG_PIPE_RAGGED, kSeqRagged, 8}, {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},
-                 {MIAUG_PIPE_DISTORT, kSeqDistort, 2}};
+    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 7},     {MIAUG_PIPE_RAGGED, kSeqRagged, 8},
+                 {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},    {MIAUG_PIPE_DISTORT, kSeqDistort, 2},
+                 {MIAUG_PIPE_WARP, kSeqRotate, 1},   {MIAUG_PIPE_WARP, kSeqSsr, 1},
+                 {MIAUG_PIPE_PAD, kSeqPad, 1}};
     int kind = 0, worst = -1;
     for (const Cand &c : cands) {
         const int at = match_order(ops, n_ops, c.seq, c.nseq);
@@ -528,6 +635,12 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
             worst = n_ops - 1;
             continue;
         }
+        if (c.kind == MIAUG_PIPE_U8CHAIN)
+            for (int i = 0; i < n_ops; ++i)
+                if (ops[i].kind == MIAUG_OP_SSR &&
+                    (ops[i].interp != MIAUG_INTERP_BILINEAR || ops[i].border != MIAUG_BORDER_REFLECT101))
+                    return set_error(MIAUG_EUNSUPPORTED,
+                                     "pipeline_create: op %d (SSR): the u8 chain warps bilinearly with reflect-101", i);
         kind = c.kind;
         break;
     }
@@ -549,8 +662,23 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     p->el_sigma = 0.0;
     p->el_box = false;
     p->wcrop = false;
+    p->color = false;
+    p->interp = MIAUG_INTERP_BILINEAR;
+    p->border = MIAUG_BORDER_REFLECT101;
+    p->pad_value = 0;
+    p->chan = 3;
     for (const miaug_op &o : p->ops) {
         if (o.kind == MIAUG_OP_SIZED_CROP) p->wcrop = true;
+        if (o.kind == MIAUG_OP_SHIFT_RGB || o.kind == MIAUG_OP_TO_GRAY) p->color = true;
+        if (o.kind == MIAUG_OP_ROTATE || o.kind == MIAUG_OP_PAD || (o.kind == MIAUG_OP_SSR && kind == MIAUG_PIPE_WARP)) {
+            p->interp = (int)o.interp;
+            p->border = (int)o.border;
+        }
+        if (o.kind == MIAUG_OP_PAD) {
+            p->out_h = o.out_h;
+            p->out_w = o.out_w;
+            p->pad_value = (int)o.lo[0];
+        }
         if (o.kind == MIAUG_OP_RESIZE) {
             p->out_h = o.out_h;
             p->out_w = o.out_w;
@@ -651,6 +779,14 @@ int miaug_sample(const miaug_pipeline *p, uint64_t seed, uint64_t first_index, i
                 r.crop_x = G.below(d + 2, (uint32_t)(W - o.out_w + 1));
                 break;
             }
+            case MIAUG_OP_ROTATE:
+                if (on) r.angle = G.range(d + 1, o.lo[0], o.hi[0]);
+                break;
+            case MIAUG_OP_SHIFT_RGB:
+                if (on)
+                    for (int c = 0; c < 3; ++c) r.shift[c] = G.range(d + 1 + (uint64_t)c, o.lo[c], o.hi[c]);
+                break;
+            case MIAUG_OP_TO_GRAY: r.gray = on; break;
             case MIAUG_OP_SIZED_CROP:
                 if (on) {
                     // the window lives in the Dih4 image (drawn by the ops before this one)
@@ -713,10 +849,10 @@ int miaug_pipeline_graph_capture(miaug_pipeline *p, const miaug_batch_in *in, co
                          "graph_capture: the elastic field's noise stream is a launch argument, not a record");
     int st = prepare(p, in);
     if (st) return st;
-    miaug_pipeline_graph *G = new (std::nothrow) miaug_pipeline_graph{p, in->n, in->H, in->W, nullptr, 0, nullptr,
-                                                                       nullptr, nullptr};
+    miaug_pipeline_graph *G = new (std::nothrow) miaug_pipeline_graph{p, in->n, in->H, in->W, in->channels, nullptr,
+                                                                       0, nullptr, nullptr, nullptr};
     if (!G) return set_error(MIAUG_ENOMEM, "graph_capture: host allocation");
-    G->packed = staged_bytes(p, in->n);
+    G->packed = staged_bytes(p, in->n, in->channels);
     st = hip_status(hipHostMalloc(&G->pinned, G->packed, hipHostMallocDefault), "graph_capture: pinned staging");
     if (!st) st = hip_status(hipEventCreateWithFlags(&G->done, hipEventDisableTiming), "event");
     // every record the chains read comes from the staging buffer at replay time; run_chain only
@@ -751,6 +887,7 @@ int miaug_pipeline_graph_launch(miaug_pipeline_graph *G, const miaug_params *par
     in.n = G->n;
     in.H = G->H;
     in.W = G->W;
+    in.channels = G->chan;
     int st = fill_staging(G->p, &in, params, G->pinned);
     if (st) return st;
     hipStream_t s = as_stream(stream);

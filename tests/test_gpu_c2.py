@@ -73,3 +73,38 @@ def test_full_size_batch_sampled_against_oracle(m):
     got = out.cpu().numpy()
     rng = np.random.default_rng(8)
     check(imgs, f, k, 448, 224, got, sorted(rng.choice(256, 10, replace=False)))
+
+
+# ---------------------------------------------------------------- masks and boxes of the u8 chain
+def rand_boxes(rng, n, H, W, per=(0, 9)):
+    counts = rng.integers(per[0], per[1], n)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    x1 = rng.uniform(-5, W, off[-1]); y1 = rng.uniform(-5, H, off[-1])
+    bx = np.stack([x1, y1, x1 + rng.uniform(0.5, W / 2, off[-1]), y1 + rng.uniform(0.5, H / 2, off[-1])], 1)
+    return bx.astype(np.float32), off
+
+
+@pytest.mark.parametrize("H,W,crop,outsz", [(96, 80, 64, 40), (70, 70, 70, 70), (61, 130, 50, 96), (512, 512, 448, 224)])
+def test_masks_and_boxes_follow_the_image_geometry(m, H, W, crop, outsz):
+    import torch
+    rng = np.random.default_rng(H * 1000 + W)
+    n = 6
+    masks = np.ascontiguousarray(synth.blob_masks(H * 7 + W, n, H, W, 8, 16).numpy())
+    f, k = m.sample_c2(H + W, 0, n, crop_range=max(1, min(H, W) - crop + 1))
+    f[0] = (90.0, 1.0, 0.0, 0.0, 1.0)
+    f[1] = (0.0, 1.0, 0.0, 0.0, 1.0)
+    rec = torch.from_numpy(m.compile_c2(f, k, H, W, crop)).cuda()
+    om = m.ssr_crop_resize_mask_u8(torch.from_numpy(masks).cuda(), rec, crop, outsz)
+    bx, off = rand_boxes(rng, n, H, W)
+    ob = m.boxes_ssr_crop_resize(torch.from_numpy(bx).cuda(), torch.from_numpy(off).cuda(), H, W, rec, crop, outsz)
+    torch.cuda.synchronize()
+    om, ob = om.cpu().numpy(), ob.cpu().numpy()
+    for i in range(n):
+        kx, ky = min(max(int(k[i][0]), 0), W - crop), min(max(int(k[i][1]), 0), H - crop)
+        aq = oracle.ssr_matrix_q32(*f[i][:4], H, W)
+        ref = oracle.resize(oracle.crop(oracle.warp_affine(masks[i], aq, oracle.NEAREST), kx, ky, crop, crop),
+                            outsz, outsz, oracle.NEAREST)
+        assert np.array_equal(om[i], ref), ("mask", i)
+        rb = oracle.boxes_ssr_crop_resize(bx[off[i]:off[i + 1]], H, W, f[i][:4], kx, ky, crop, outsz)
+        got = ob[off[i]:off[i + 1]]
+        assert np.all(np.abs(got - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), ("boxes", i, np.abs(got - rb).max())

@@ -214,3 +214,40 @@ def test_image_stats_match_numpy():
     assert mn.tolist() == flat.min(0).tolist() and mx.tolist() == flat.max(0).tolist()
     for c in range(3):
         assert np.array_equal(h[c], np.bincount(flat[:, c], minlength=256))
+
+
+# ---------------------------------------------------------------- ShiftRGB and Grayscale (Table I)
+def test_shift_rgb_lut_special_cases():
+    lut = oracle.shift_rgb_lut([0.0, 300.0, -300.0])
+    assert np.array_equal(lut[0], np.arange(256))              # no shift: identity
+    assert np.all(lut[1] == 255) and np.all(lut[2] == 0)       # saturation on both ends
+    lut = oracle.shift_rgb_lut([20.0, -20.0, 0.5])
+    assert np.array_equal(lut[0], np.minimum(np.arange(256) + 20, 255))
+    assert np.array_equal(lut[1], np.maximum(np.arange(256) - 20, 0))
+    # a half shift rounds to even: v + 0.5 -> v when v is even, v + 1 when odd
+    v = np.arange(255)
+    assert np.array_equal(lut[2][:255], v + (v & 1))
+
+
+def test_shift_rgb_is_a_per_channel_lut():
+    rng = np.random.default_rng(40)
+    img = rng.integers(0, 256, (9, 7, 3), dtype=np.uint8)
+    lut = oracle.shift_rgb_lut([5.0, -12.0, 33.0])
+    out = oracle.apply_lut_c(img, lut)
+    for c in range(3):
+        assert np.array_equal(out[..., c], lut[c][img[..., c]])
+
+
+def test_gray_keeps_grey_pixels_and_tracks_bt601():
+    v = np.arange(256, dtype=np.uint8)
+    g = oracle.gray(np.stack([v, v, v], -1).reshape(16, 16, 3))
+    assert np.array_equal(g[..., 0].ravel(), v) and np.array_equal(g[..., 1], g[..., 0])
+    rng = np.random.default_rng(41)
+    img = rng.integers(0, 256, (40, 40, 3), dtype=np.uint8)
+    y = 0.299 * img[..., 0] + 0.587 * img[..., 1] + 0.114 * img[..., 2]
+    g = oracle.gray(img)[..., 0].astype(np.float64)
+    assert np.abs(g - y).max() <= 0.5 + 0.5 * 255 * 3 / 2 ** 14  # rounding + Q14 weight quantisation
+    # pure primaries: the Q14 weights themselves
+    prim = np.array([[[255, 0, 0], [0, 255, 0], [0, 0, 255]]], np.uint8)
+    assert oracle.gray(prim)[0, :, 0].tolist() == [(4899 * 255 + 8192) >> 14, (9617 * 255 + 8192) >> 14,
+                                                   (1868 * 255 + 8192) >> 14]

@@ -170,3 +170,54 @@ def test_box_field_tracks_the_gaussian_field_and_zero_alpha_is_zero():
         assert 0.9 < b.std() / e.std() < 1.1
     zx, zy = oracle.elastic_field_box(1, 0, H, W, sigma, 0)
     assert not zx.any() and not zy.any()
+
+
+# ---------------------------------------------------------------- boxes under the distortion
+def _ident_tables(H, W):
+    return (np.arange(W, dtype=np.int32) * 1024, np.arange(H, dtype=np.int32) * 1024)
+
+
+def test_distort_boxes_identity_and_integer_shift():
+    H, W = 40, 56
+    z = np.zeros((H, W), np.int32)
+    mx, my = _ident_tables(H, W)
+    boxes = np.array([[10, 5, 30, 20], [10.2, 5.7, 29.5, 20.5], [0, 0, 56, 40]], np.float32)
+    out = oracle.boxes_distort(boxes, H, W, z, z, mx, my)
+    # pixels whose centres lie in [x1, x2): 10.2 -> first centre 10.5, 29.5 -> last centre 28.5
+    assert out.tolist() == [[10, 5, 30, 20], [10, 6, 29, 20], [0, 0, 56, 40]]
+    # every output pixel samples the source 5 px to the right and 3 px down: the box moves left and up
+    out = oracle.boxes_distort(boxes[:1], H, W, z + 5 * 1024, z + 3 * 1024, mx, my)
+    assert out.tolist() == [[5, 2, 25, 17]]
+
+
+def test_distort_boxes_follow_separable_grid_tables():
+    H, W = 48, 64
+    rng = np.random.default_rng(21)
+    d = 1 + rng.uniform(-0.3, 0.3, 10)
+    mx, my = oracle.grid_table(d[:5], W), oracle.grid_table(d[5:], H)
+    z = np.zeros((H, W), np.int32)
+    box = np.array([[13.0, 9.0, 41.0, 30.0]], np.float32)
+    out = oracle.boxes_distort(box, H, W, z, z, mx, my)[0]
+    # brute force on the tables: output column x reaches source column reflect((mapx[x] + 512) >> 10)
+    def src(q, n):
+        i = (q.astype(np.int64) + 512) >> 10
+        p = 2 * n - 2
+        i = np.mod(i, p)
+        return np.where(i >= n, p - i, i)
+    sx, sy = src(mx, W), src(my, H)
+    xs = np.nonzero((sx + 0.5 >= 13) & (sx + 0.5 < 41))[0]
+    ys = np.nonzero((sy + 0.5 >= 9) & (sy + 0.5 < 30))[0]
+    assert out.tolist() == [xs.min(), ys.min(), xs.max() + 1, ys.max() + 1]
+
+
+def test_distort_boxes_match_the_transformed_mask_of_a_blob():
+    # a box drawn around a blob of labels stays around the blob after the distortion
+    H, W = 64, 80
+    ox, oy = oracle.elastic_field(3, 0, H, W, sigma=6.0, alpha=300, radius=18)
+    d = 1 + np.random.default_rng(22).uniform(-0.3, 0.3, 10)
+    mx, my = oracle.grid_table(d[:5], W), oracle.grid_table(d[5:], H)
+    m = np.zeros((H, W), np.uint8); m[20:35, 30:50] = 1
+    out = oracle.boxes_distort(np.array([[30, 20, 50, 35]], np.float32), H, W, ox, oy, mx, my)[0]
+    g = oracle.grid_remap(oracle.remap_field(m, ox, oy, oracle.NEAREST), mx, my, oracle.NEAREST)
+    ys, xs = np.nonzero(g)
+    assert out.tolist() == [xs.min(), ys.min(), xs.max() + 1, ys.max() + 1]

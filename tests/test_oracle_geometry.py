@@ -275,3 +275,78 @@ def test_boxes_follow_resize_within_one_pixel_of_the_mask():
         mr = oracle.resize(m, 224, 224, oracle.NEAREST)
         out = oracle.boxes_d4_resize(np.array([box], np.float32), H, W, flags, 224, 224)
         assert np.abs(np.array(bbox_of(mr)) - out[0]).max() <= 1.0
+
+
+# ---------------------------------------------------------------- boxes under shift-scale-rotate
+def test_ssr_boxes_quarter_turns_match_the_dih4_element_of_the_image():
+    # the warp by 90 / 180 degrees of a square image is rot90 / a half turn (pinned above);
+    # its boxes must be the Dih4 element's boxes exactly
+    rng = np.random.default_rng(17)
+    n = 11
+    for _ in range(20):
+        x1, y1 = int(rng.integers(0, n - 1)), int(rng.integers(0, n - 1))
+        box = np.array([[x1, y1, int(rng.integers(x1 + 1, n + 1)), int(rng.integers(y1 + 1, n + 1))]], np.float32)
+        b90 = oracle.boxes_ssr_crop_resize(box, n, n, (90.0, 1.0, 0.0, 0.0), 0, 0, n, n)
+        m90 = oracle.warp_affine(rasterize(box[0].astype(int).tolist(), n, n), oracle.ssr_matrix_q32(90.0, 1, 0, 0, n, n),
+                                 oracle.NEAREST)
+        assert np.allclose(b90[0], bbox_of(m90), atol=1e-9)
+        b180 = oracle.boxes_ssr_crop_resize(box, n, n, (180.0, 1.0, 0.0, 0.0), 0, 0, n, n)
+        ref = oracle.boxes_d4_resize(box, n, n, (1, 1, 0, 0), n, n)
+        assert np.allclose(b180, ref, atol=1e-9)
+
+
+def test_ssr_boxes_identity_shift_and_crop_closed_form():
+    box = np.array([[10.0, 20.0, 40.0, 30.0]], np.float32)
+    # identity warp, crop at (5, 8) of size 50, resize to 100: shift then scale by 2
+    out = oracle.boxes_ssr_crop_resize(box, 60, 70, (0.0, 1.0, 0.0, 0.0), 5, 8, 50, 100)
+    assert np.allclose(out[0], [10.0, 24.0, 70.0, 44.0])
+    # a shift by dx W = +7 pixels (W = 70, dx = 0.1) moves the box right by 7, clipped at the image edge
+    out = oracle.boxes_ssr_crop_resize(np.array([[60.0, 1.0, 68.0, 2.0]], np.float32), 60, 70,
+                                       (0.0, 1.0, np.float32(0.1), 0.0), 10, 0, 60, 60)
+    assert np.allclose(out[0], [57.0, 1.0, 60.0, 2.0], atol=1e-5)  # 67..70 (clipped at W), minus the crop offset
+    # scale 2 about the centre c = ((W-1)/2, (H-1)/2) maps continuous u to 2 (u - 1/2 - c) + c + 1/2
+    out = oracle.boxes_ssr_crop_resize(np.array([[30.0, 25.0, 35.0, 30.0]], np.float32), 60, 70,
+                                       (0.0, 2.0, 0.0, 0.0), 0, 0, 60, 60)
+    c = np.array([34.5, 29.5])
+    ref = [2 * (30 - 0.5 - c[0]) + c[0] + 0.5, 2 * (25 - 0.5 - c[1]) + c[1] + 0.5,
+           2 * (35 - 0.5 - c[0]) + c[0] + 0.5, 2 * (30 - 0.5 - c[1]) + c[1] + 0.5]
+    assert np.allclose(out[0], ref, atol=1e-5)
+
+
+def test_ssr_boxes_contain_the_warped_mask_of_the_box():
+    # the bounding box of the four mapped corners contains every pixel the warped box mask covers
+    # (up to one pixel for nearest sampling), at arbitrary angles
+    rng = np.random.default_rng(18)
+    H, W = 64, 80
+    for _ in range(12):
+        angle, scale = float(rng.uniform(-45, 45)), float(rng.uniform(0.9, 1.1))
+        dx, dy = float(rng.uniform(-0.06, 0.06)), float(rng.uniform(-0.06, 0.06))
+        f = np.float32([angle, scale, dx, dy])
+        x1, y1 = int(rng.integers(16, 40)), int(rng.integers(16, 30))
+        box = [x1, y1, x1 + int(rng.integers(4, 20)), y1 + int(rng.integers(4, 18))]
+        m = oracle.warp_affine(rasterize(box, H, W), oracle.ssr_matrix_q32(*f, H, W), oracle.NEAREST, oracle.CONSTANT)
+        got = oracle.boxes_ssr_crop_resize(np.array([box], np.float32), H, W, f, 0, 0, min(H, W), min(H, W))[0]
+        mb = bbox_of(m)
+        assert got[0] <= mb[0] + 1 and got[1] <= mb[1] + 1 and got[2] >= mb[2] - 1 and got[3] >= mb[3] - 1
+        # and is not much larger: at most the rotation's corner overhang plus a pixel
+        assert (got[2] - got[0]) <= (mb[2] - mb[0]) + 2 and (got[3] - got[1]) <= (mb[3] - mb[1]) + 2
+
+
+# ---------------------------------------------------------------- PadToSize (Table I PadToSize512)
+@pytest.mark.parametrize("H,W,Hm,Wm", [(5, 7, 9, 12), (1, 1, 4, 3), (6, 6, 6, 6), (10, 3, 4, 8), (3, 10, 8, 4)])
+def test_pad_matches_numpy_reflect_and_constant(H, W, Hm, Wm):
+    rng = np.random.default_rng(H * 100 + W)
+    img = rng.integers(0, 256, (H, W, 3), dtype=np.uint8)
+    ho, wo = max(H, Hm), max(W, Wm)
+    top, left = (ho - H) // 2, (wo - W) // 2
+    pw = ((top, ho - H - top), (left, wo - W - left), (0, 0))
+    if H > 1 and W > 1 and max(pw[0]) < H and max(pw[1]) < W:  # numpy's single reflection
+        assert np.array_equal(oracle.pad(img, Hm, Wm, oracle.REFLECT101), np.pad(img, pw, mode="reflect"))
+    assert np.array_equal(oracle.pad(img, Hm, Wm, oracle.CONSTANT, 17), np.pad(img, pw, constant_values=17))
+
+
+def test_pad_reflects_repeatedly_for_large_pads():
+    img = np.arange(3, dtype=np.uint8).reshape(1, 3)
+    out = oracle.pad(img, 1, 11, oracle.REFLECT101)
+    # reflect-101 of 0 1 2 has period 4: ... 2 1 0 1 2 1 0 ...
+    assert out[0].tolist() == [0, 1, 2, 1, 0, 1, 2, 1, 0, 1, 2]

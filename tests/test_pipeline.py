@@ -126,7 +126,7 @@ def test_crop_needs_source_sizes_and_fitting_images():
 
 def test_param_record_size():
     p = m.Pipeline(None, [op("HFLIP")])
-    assert m.lib().miaug_param_bytes(p.handle, 3) == 3 * 176
+    assert m.lib().miaug_param_bytes(p.handle, 3) == 3 * 192
 
 
 # ---------------------------------------------------------------- GPU
@@ -357,3 +357,166 @@ def test_ragged_pipeline_with_sized_crop_matches_the_oracle(ctx):
         if len(rb):
             got = ob[b.box_off[i]:b.box_off[i + 1]]
             assert np.all(np.abs(got - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), i
+
+
+@pytest.mark.gpu
+def test_u8_chain_pipeline_takes_masks_and_boxes(ctx):
+    import torch
+    n, H, W, crop, outsz = 4, 96, 80, 64, 40
+    p = m.Pipeline(ctx, [op("SSR", 1, (-45, 0.9, -0.0625, -0.0625), (45, 1.1, 0.0625, 0.0625)),
+                         op("CROP", out=(crop, crop)), op("RESIZE", out=(outsz, outsz)), op("GAMMA", 1, (0.8,), (1.2,))])
+    imgs = synth.smooth_u8_hwc(32, n, H, W).numpy()
+    masks = np.ascontiguousarray(synth.blob_masks(33, n, H, W, 8, 16).numpy())
+    boxes = np.array([[5, 6, 40, 50], [0, 0, 80, 96], [30, 30, 31, 31], [70, 2, 79, 90], [10, 80, 60, 95]], np.float32)
+    off = np.array([0, 2, 2, 4, 5], np.int32)
+    recs = p.sample(10, 0, n, np.tile(np.array([[H, W]], np.int32), (n, 1)))
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    bxd, offd = torch.from_numpy(boxes).cuda(), torch.from_numpy(off).cuda()
+    out = torch.empty((n, outsz, outsz, 3), dtype=torch.uint8, device="cuda")
+    om = torch.empty((n, outsz, outsz), dtype=torch.uint8, device="cuda")
+    ob = torch.empty_like(bxd)
+    bi, bo, _ = p.batch(img=x, mask=xm, boxes=bxd, box_off=offd)
+    bo.img, bo.mask, bo.boxes = out.data_ptr(), om.data_ptr(), ob.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    gm, gb = om.cpu().numpy(), ob.cpu().numpy()
+    for i in range(n):
+        r = recs[i]
+        aq = oracle.ssr_matrix_q32(r.angle, r.scale, r.dx, r.dy, H, W)
+        ref = oracle.resize(oracle.crop(oracle.warp_affine(masks[i], aq, oracle.NEAREST), r.crop_x, r.crop_y, crop, crop),
+                            outsz, outsz, oracle.NEAREST)
+        assert np.array_equal(gm[i], ref), i
+        rb = oracle.boxes_ssr_crop_resize(boxes[off[i]:off[i + 1]], H, W, (r.angle, r.scale, r.dx, r.dy), r.crop_x,
+                                          r.crop_y, crop, outsz)
+        assert np.all(np.abs(gb[off[i]:off[i + 1]] - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), i
+    om2 = torch.empty_like(om)
+    bo.mask = om2.data_ptr()
+    p.apply(bi, bo, recs, per_image=True)
+    assert torch.equal(om, om2)
+
+
+# ---------------------------------------------------------------- the other Table I ops
+def test_table1_op_lists_map_onto_their_chains():
+    assert kind_of([op("HFLIP", 0.5), op("BRIGHT_CONTRAST", 1, (0.8, -51), (1.2, 51)),
+                    op("SHIFT_RGB", 0.5, (-20, -20, -20), (20, 20, 20)), op("TO_GRAY", 0.3)]) == "DIH4"
+    assert kind_of([op("SHIFT_RGB", 1, (-20, -20, -20), (20, 20, 20))]) == "DIH4"
+    assert kind_of([op("ROTATE", 1, (-45,), (45,))]) == "WARP"
+    assert kind_of([op("SSR", 1, (-45, 0.9, -0.06, -0.06), (45, 1.1, 0.06, 0.06), border=1)]) == "WARP"
+    assert kind_of([op("PAD", out=(512, 512))]) == "PAD"
+    with pytest.raises(m.MiaugError):
+        m.Pipeline(None, [op("TO_GRAY"), op("SHIFT_RGB")])  # order
+    with pytest.raises(m.MiaugError):
+        m.Pipeline(None, [op("PAD", 0.5, out=(8, 8))])      # PAD has p = 1
+
+
+def test_table1_sampler_draws():
+    seed = 1809068396
+    p = m.Pipeline(None, [op("SHIFT_RGB", 0.5, (-20, -10, 0), (20, 10, 5)), op("TO_GRAY", 0.3)])
+    recs = p.sample(seed, 7, 300)
+    for i in range(300):
+        r, g = recs[i], 7 + i
+        if uniform(seed, g, 0) < 0.5:
+            for c, (lo, hi) in enumerate(((-20, 20), (-10, 10), (0, 5))):
+                assert r.shift[c] == f32_range(seed, g, 1 + c, lo, hi)
+        else:
+            assert list(r.shift) == [0.0, 0.0, 0.0]
+        assert r.gray == int(uniform(seed, g, 16) < 0.3)
+    p = m.Pipeline(None, [op("ROTATE", 0.7, (-45,), (45,))])
+    recs = p.sample(seed, 0, 100)
+    for i in range(100):
+        on = uniform(seed, i, 0) < 0.7
+        assert recs[i].angle == (f32_range(seed, i, 1, -45, 45) if on else 0.0)
+        assert recs[i].scale == 1.0 and recs[i].dx == 0.0 and recs[i].dy == 0.0
+
+
+@pytest.mark.gpu
+def test_color_chain_pipeline_matches_the_oracle(ctx):
+    import torch
+    n, H, W = 6, 37, 52
+    rng = np.random.default_rng(11)
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    masks = rng.integers(0, 21, (n, H, W), dtype=np.uint8)
+    p = m.Pipeline(ctx, [op("HFLIP", 0.5), op("ROT90", 1, (0,), (3,)), op("BRIGHT_CONTRAST", 0.8, (0.8, -51), (1.2, 51)),
+                         op("SHIFT_RGB", 0.7, (-20, -20, -20), (20, 20, 20)), op("TO_GRAY", 0.5)])
+    recs = p.sample(12, 0, n)
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    out, om = torch.empty_like(x), torch.empty_like(xm)
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    got, gm = out.cpu().numpy().reshape(n, -1), om.cpu().numpy().reshape(n, -1)
+    for i in range(n):
+        r = recs[i]
+        fl = [r.flags[k] for k in range(4)]
+        y = oracle.apply_lut(oracle.d4(imgs[i], *fl), oracle.bc_lut(r.alpha, r.beta))
+        y = oracle.apply_lut_c(y, oracle.shift_rgb_lut(list(r.shift)))
+        if r.gray:
+            y = oracle.gray(y)
+        assert np.array_equal(got[i], y.reshape(-1)), i
+        assert np.array_equal(gm[i], oracle.d4(masks[i], *fl).reshape(-1)), i
+    out2 = torch.empty_like(out)
+    bo.img = out2.data_ptr()
+    p.apply(bi, bo, recs, per_image=True)
+    assert torch.equal(out, out2)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("interp,border", [(0, 0), (1, 1)])
+def test_rotate_and_pad_pipelines_match_the_oracle(ctx, interp, border):
+    import torch
+    n, H, W = 5, 45, 60
+    imgs = synth.smooth_u8_hwc(13, n, H, W).numpy()
+    masks = np.ascontiguousarray(synth.blob_masks(14, n, H, W, 8, 16).numpy())
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    p = m.Pipeline(ctx, [op("ROTATE", 0.8, (-45,), (45,), interp=interp, border=border)])
+    recs = p.sample(15, 0, n)
+    out, om = torch.empty_like(x), torch.empty_like(xm)
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    bor = oracle.CONSTANT if border else oracle.REFLECT101
+    for i in range(n):
+        aq = oracle.ssr_matrix_q32(recs[i].angle, 1.0, 0.0, 0.0, H, W)
+        ref = oracle.warp_affine(imgs[i], aq, oracle.NEAREST if interp else oracle.BILINEAR, bor)
+        assert np.array_equal(out.cpu().numpy()[i], ref), i
+        assert np.array_equal(om.cpu().numpy()[i], oracle.warp_affine(masks[i], aq, oracle.NEAREST, bor)), i
+    p = m.Pipeline(ctx, [op("PAD", 1, (33,), out=(64, 80), border=border)])
+    recs = p.sample(16, 0, n)
+    out = torch.empty((n, 64, 80, 3), dtype=torch.uint8, device="cuda")
+    om = torch.empty((n, 64, 80), dtype=torch.uint8, device="cuda")
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    for i in range(n):
+        assert np.array_equal(out.cpu().numpy()[i], oracle.pad(imgs[i], 64, 80, bor, 33)), i
+        assert np.array_equal(om.cpu().numpy()[i], oracle.pad(masks[i], 64, 80, bor, 0)), i
+
+
+@pytest.mark.gpu
+def test_distortion_pipeline_transforms_boxes_like_their_masks(ctx):
+    import torch
+    n, H, W = 3, 72, 96
+    p = m.Pipeline(ctx, [op("ELASTIC", 1, (300, 6, 18)), op("GRID", 1, (0.3,))])
+    imgs = synth.smooth_u8_hwc(44, n, H, W).numpy()
+    boxes = np.array([[10, 5, 40, 30], [0, 0, 96, 72], [50.5, 40.2, 70.7, 71.9], [90, 60, 96, 72], [20, 20, 20.2, 20.2],
+                      [33, 11, 34, 12]], np.float32)
+    off = np.array([0, 2, 5, 6], np.int32)
+    recs = p.sample(79, 3, n)
+    x = torch.from_numpy(imgs).cuda()
+    bxd, offd = torch.from_numpy(boxes).cuda(), torch.from_numpy(off).cuda()
+    out = torch.empty_like(x)
+    ob = torch.full_like(bxd, -7.0)
+    bi, bo, _ = p.batch(img=x, boxes=bxd, box_off=offd)
+    bo.img, bo.boxes = out.data_ptr(), ob.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    gb = ob.cpu().numpy()
+    for i in range(n):
+        ox, oy = oracle.elastic_field(79, 3 + i, H, W, sigma=6.0, alpha=300, radius=18)
+        d = np.array(list(recs[i].grid), np.float64)
+        ref = oracle.boxes_distort(boxes[off[i]:off[i + 1]], H, W, ox, oy, oracle.grid_table(d[:5], W),
+                                   oracle.grid_table(d[5:], H))
+        assert np.array_equal(gb[off[i]:off[i + 1]], ref), (i, gb[off[i]:off[i + 1]], ref)
