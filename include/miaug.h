@@ -272,6 +272,16 @@ typedef struct {
  * Errors: EINVAL null ctx/args/pointers; ESHAPE bad sizes; EDEVICE launch. */
 int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *args, void *stream);
 
+/* Multi-channel (instance) masks of a ragged batch: args->mask holds, per
+ * image, H x W pixels of `channels` u8 values (one per instance; byte offsets
+ * in args->mask_off), and each output pixel of out [n][out_h][out_w][channels]
+ * copies the source pixel that the one-channel masks of miaug_ragged_apply
+ * take (Dih4 element, crop window, nearest resize).  Reads hw, flags, crop,
+ * mask, mask_off, n, out_h, out_w of args; skipped images (see hw and crop)
+ * leave their output untouched.  Errors: EINVAL null pointers; ESHAPE sizes
+ * or channels outside 1..256. */
+int miaug_ragged_masks_u8(const miaug_ragged_args *args, int channels, uint8_t *out, void *stream);
+
 /* Comparison form: the same kernels launched once per image (n launches, no
  * persistence, no queue).  Output is bit-identical to miaug_ragged_apply. */
 int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *args, void *stream);

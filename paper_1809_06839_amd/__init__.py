@@ -96,6 +96,7 @@ _SIGS = {
     "miaug_ssr_crop_resize_mask_u8": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
     "miaug_d4_lut_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "miaug_boxes_elastic_grid": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+    "miaug_ragged_masks_u8": (_i, [ctypes.POINTER(RaggedArgs), _i, _vp, _vp]),
     "miaug_compile_color_luts": (_i, [_vp, _vp, _i, _i, _vp]),
     "miaug_pad_u8": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp, _vp]),
     "miaug_warp_affine_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
@@ -418,6 +419,15 @@ class Ragged:
 def ragged_apply(ctx: Context, r: Ragged, stream=None):
     _check(lib().miaug_ragged_apply(ctx.handle, ctypes.byref(r.args), _stream(stream)))
     return r
+
+
+def ragged_masks_u8(r: Ragged, channels: int, out=None, stream=None):
+    """Multi-channel masks of a Ragged whose mask buffer holds `channels` bytes per pixel."""
+    a = r.args
+    if out is None:
+        out = torch.empty((a.n, a.out_h, a.out_w, channels), dtype=torch.uint8, device=r.out.device)
+    _check(lib().miaug_ragged_masks_u8(ctypes.byref(a), channels, _p(out), _stream(stream)))
+    return out
 
 
 def ragged_apply_per_image(ctx: Context, r: Ragged, stream=None):

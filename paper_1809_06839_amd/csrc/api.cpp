@@ -222,6 +222,19 @@ int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream)
     return hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply launch");
 }
 
+int miaug_ragged_masks_u8(const miaug_ragged_args *a, int channels, uint8_t *out, void *stream) {
+    begin_call();
+    if (!a) return set_error(MIAUG_EINVAL, "ragged_masks: args is NULL");
+    if (a->n < 0) return set_error(MIAUG_EINVAL, "ragged_masks: n < 0");
+    if (channels < 1 || channels > 256) return set_error(MIAUG_ESHAPE, "ragged_masks: channels %d outside 1..256", channels);
+    if (a->out_h < 1 || a->out_w < 1 || a->out_h > 4096 || a->out_w > 4096)
+        return set_error(MIAUG_ESHAPE, "ragged_masks: output size %dx%d outside 1..4096", a->out_h, a->out_w);
+    if (a->n == 0) return MIAUG_OK;
+    if (!a->mask || !a->mask_off || !a->hw || !a->flags || !out)
+        return set_error(MIAUG_EINVAL, "ragged_masks: a required pointer is NULL");
+    return hip_status(launch_ragged_masks(a, channels, out, as_stream(stream)), "ragged_masks launch");
+}
+
 int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream) {
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply_per_image: ctx is NULL");

@@ -71,6 +71,7 @@ hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n
                                   uint8_t *out_mask, int per_image, hipStream_t s);
 hipError_t launch_boxes_distort(const float *boxes, const int32_t *box_off, int n, int H, int W, const int32_t *off,
                                 const int32_t *mapx, const int32_t *mapy, float *out, hipStream_t s);
+hipError_t launch_ragged_masks(const miaug_ragged_args *a, int K, uint8_t *out, hipStream_t s);
 size_t chain_f32_workspace_bytes(int n, int C, int H, int W);
 hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
                                 const int32_t *mapy, float *y, void *ws, hipStream_t s);

@@ -195,3 +195,36 @@ def test_full_size_batch_with_crop_windows_sampled_against_oracle(m, ctx):
     torch.cuda.synchronize()
     rng = np.random.default_rng(6)
     check_crop_outputs(b, r, flags, ab, win, sorted(rng.choice(2048, 32, replace=False)))
+
+
+# ---------------------------------------------------------------- multi-channel instance masks
+@pytest.mark.parametrize("K", [1, 3, 7])
+def test_multichannel_instance_masks_follow_the_one_channel_masks(m, ctx, small, K):
+    import torch
+    b, flags, ab = small
+    win = crop_windows(b, flags, 80 + K)
+    win[::3, 2] = 0  # no window for every third image
+    parts, offs, o = [], [], 0
+    for i in range(b.n):
+        lab = b.mask_of(i)
+        mc = np.stack([(lab % K == k).astype(np.uint8) * (k + 1) for k in range(K)], -1)  # instance k -> value k + 1
+        parts.append(mc.reshape(-1)); offs.append(o); o += mc.size
+    packed = np.concatenate(parts) if parts else np.zeros(1, np.uint8)
+    r = m.Ragged.from_host(b, flags, ab, crop=win, out_h=48, out_w=40)
+    r1 = m.Ragged(r.keep[0], r.keep[1], r.keep[2], r.keep[3], r.keep[4], out_h=48, out_w=40,
+                  mask=torch.from_numpy(packed).cuda(), mask_off=torch.tensor(offs, dtype=torch.int64).cuda(),
+                  crop=r.keep[9])
+    got = m.ragged_masks_u8(r1, K).cpu().numpy()
+    for i in range(b.n):
+        H, W = int(b.hw[i][0]), int(b.hw[i][1])
+        mc = parts[i].reshape(H, W, K)
+        d = oracle.d4(mc, *flags[i])
+        if win[i][2]:
+            y0, x0, h, w = (int(v) for v in win[i])
+            d = oracle.crop(d, x0, y0, h, w)
+        ref = oracle.resize(d, 48, 40, oracle.NEAREST)
+        assert np.array_equal(got[i], ref), (i, K)
+    if K == 1:  # on the real one-channel labels: the same pixels as the fused kernel's masks
+        m.ragged_apply(ctx, r)
+        torch.cuda.synchronize()
+        assert torch.equal(m.ragged_masks_u8(r, 1)[..., 0], r.out_mask)
