@@ -17,11 +17,12 @@
 // passes over the halves of its span positions; a half that still does not
 // fit reads its taps straight from global memory.
 //
-// The default form is a persistent launch in which every workgroup plans its
-// next pass (one wave, tables double-buffered) while the LDS-DMA of the
-// current pass is in flight.  Other launch forms are kept as autotuner
-// candidates: one pass at a time with chunked claims, a flat grid, and a
-// streaming form.
+// The default form is a persistent launch in which four worker waves of a
+// workgroup stream and blend pass k while a fifth wave claims items and plans
+// pass k+1 into a second table set.  Other launch forms are kept as autotuner
+// candidates: the same pipeline with the planning done by a rotating worker
+// wave, one pass at a time with chunked claims, a flat grid, and a streaming
+// form.
 //
 // The streaming form is a persistent launch in which every workgroup runs a
 // three-stage software pipeline over its passes: in one iteration it builds
@@ -496,41 +497,80 @@ __device__ __forceinline__ void pass_tables(const miaug_ragged_args &a, const Pa
     }
 }
 
+// 16 bytes per lane from a buffer (32-bit offset) into LDS at lds + 16 * lane.
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, uint8_t *lds, uint32_t voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)lds, 16, voff, 0, 0, 0);
+}
+
+// floor(x / d) for 0 <= x < 2^12, 1 <= d < 2^11, given M = ceil(2^32 / d)
+// (M = 0 for d = 1): with M d = 2^32 + e, 0 <= e < d, the error term x e is
+// below 2^23, far under 2^32, so the high word of x M is the exact quotient.
+__device__ __forceinline__ int div_by_m(int x, int d, uint32_t M) { return d == 1 ? x : (int)__umulhi((uint32_t)x, M); }
+__device__ __forceinline__ uint32_t div_magic(int d) {
+    return d <= 1 ? 0u : (uint32_t)((0x100000000ull + (uint64_t)d - 1) / (uint64_t)d);
+}
+
 // Issues the LDS-DMA of a staged pass: chunk `it` of the pass (image rows
 // first, 2 nl slots of nchi chunks, then nl mask slots of nchm chunks) lands
-// at stage byte 16 it.  The 64 lanes of a wave take 64 consecutive chunks,
-// which is the DMA's lane layout (LDS base in M0 + 16 * lane); threads
-// 0..NT-1 take part.  All row-table reads come first, then the DMAs, so their
-// LDS latencies overlap.  Completion is counted by vmcnt.
+// at stage byte 16 it.  Image and mask chunks are issued in two loops, each
+// through a buffer resource of its own base (32-bit offsets); the 64 lanes of
+// a wave take 64 consecutive chunks, which is the DMA's lane layout (LDS base
+// in M0 + 16 * lane); threads 0..NT-1 take part.  All row-table reads of a
+// loop come first, then its DMAs, so their LDS latencies overlap.
+// Completion is counted by vmcnt.
 template <int NT, int CAP, int N>
 __device__ __forceinline__ void pass_dma(const miaug_ragged_args &a, const Meta &mt, const int2 *rw,
                                          uint8_t (&st)[N]) {
     constexpr int kIt = (CAP + NT - 1) / NT;
     if (!mt.valid || mt.empty || !mt.staged) return;
     const int tid = threadIdx.x, lane = tid & 63;
-    const uint8_t *ib = align16(a.img + mt.img_off);
-    const uint8_t *mb = a.mask ? align16(a.mask + mt.mask_off) : ib;
-    const int nchi = mt.nchi, nchm = mt.nchm, items = mt.items, total = mt.total;
-    const float ri = __builtin_amdgcn_rcpf((float)nchi), rm = __builtin_amdgcn_rcpf((float)max(nchm, 1));
-    const int mslot0 = 2 * mt.nl;
-    const uint8_t *src[kIt];
+    const int wbase = __builtin_amdgcn_readfirstlane(tid - lane);
+    const int items = mt.items, nmask = mt.total - mt.items, nl = mt.nl;
+    {
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((void *)align16(a.img + mt.img_off), 0x7fffffffu);
+        const int d = mt.nchi;
+        const uint32_t M = div_magic(d);
+        uint32_t vo[kIt];
+        bool ok[kIt];
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        src[u] = nullptr;
-        if (tid - lane + u * NT >= total) break;  // uniform per wave
-        const int it = tid + u * NT;
-        const bool im = it < items;
-        int ch;
-        const int slot = fdiv_small(im ? it : it - items, im ? nchi : max(nchm, 1), im ? ri : rm, ch) +
-                         (im ? 0 : mslot0);
-        const int2 r = rw[min(max(slot, 0), 3 * mslot0 / 2 - 1)];
-        src[u] = (it < total && ch < r.y) ? (im ? ib : mb) + r.x + 16 * ch : nullptr;
+        for (int u = 0; u < kIt; ++u) {
+            ok[u] = false;
+            vo[u] = 0;
+            if (wbase + u * NT >= items) break;  // uniform per wave
+            const int it = tid + u * NT;
+            const int slot = div_by_m(it, d, M), ch = it - slot * d;
+            const int2 r = rw[min(slot, 2 * nl - 1)];
+            ok[u] = it < items && ch < r.y;
+            vo[u] = (uint32_t)(r.x + 16 * ch);
+        }
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            if (wbase + u * NT >= items) break;
+            if (ok[u]) dma16(rs, st + 16 * (wbase + u * NT), vo[u]);
+        }
     }
+    if (nmask > 0) {
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((void *)align16(a.mask + mt.mask_off), 0x7fffffffu);
+        const int d = mt.nchm;
+        const uint32_t M = div_magic(d);
+        uint32_t vo[kIt];
+        bool ok[kIt];
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-        const int base = tid - lane + u * NT;
-        if (base >= total) break;
-        if (src[u]) __builtin_amdgcn_global_load_lds((const void *)src[u], (lds_ptr_t)(st + 16 * base), 16, 0, 0);
+        for (int u = 0; u < kIt; ++u) {
+            ok[u] = false;
+            vo[u] = 0;
+            if (wbase + u * NT >= nmask) break;
+            const int jt = tid + u * NT;
+            const int slot = div_by_m(jt, d, M), ch = jt - slot * d;
+            const int2 r = rw[2 * nl + min(slot, nl - 1)];
+            ok[u] = jt < nmask && ch < r.y;
+            vo[u] = (uint32_t)(r.x + 16 * ch);
+        }
+#pragma unroll
+        for (int u = 0; u < kIt; ++u) {
+            if (wbase + u * NT >= nmask) break;
+            if (ok[u]) dma16(rs, st + 16 * (items + wbase + u * NT), vo[u]);
+        }
     }
 }
 
@@ -824,6 +864,78 @@ __global__ __launch_bounds__(kThreads) void k_ragged_pipe(miaug_ragged_args a, i
     }
 }
 
+// The same pipeline with a fifth, dedicated planning wave: it claims items
+// (one atomic ahead) and plans pass k+1 into the other table set while the
+// four worker waves stream and blend pass k, so neither planning nor claiming
+// sits in a worker's path.  Two barriers per pass, as above.
+template <int TL, int TS, int CAP>
+__global__ __launch_bounds__(kThreads + 64) void k_ragged_pipe5(miaug_ragged_args a, int *__restrict__ counters) {
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[2][TL];
+    __shared__ int4 cl[2][TS];
+    __shared__ int2 rw[2][3 * TL];
+    __shared__ __align__(16) int meta[2][M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
+    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    const bool planner = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == kThreads / 64;
+    build_norm_lut(a, nlut);
+    int b = 0;
+    if (planner) {
+        __builtin_amdgcn_s_setprio(2);
+        const int lane = threadIdx.x & 63;
+        Claimer<1> C{tiles, (int)(blockIdx.x % kQueues), 0, 0};  // meaningful in lane 0
+        int v = -1;
+        if (lane == 0) {
+            C.issue(counters);
+            v = claim_item(C, a, counters);
+        }
+        plan_item<TL, TS, CAP>(a, __builtin_amdgcn_readfirstlane(v), 0, tiles, ln[0], cl[0], rw[0], meta[0]);
+        __syncthreads();
+        for (;;) {
+            const int valid = __builtin_amdgcn_readfirstlane(meta[b][M_VALID]);
+            if (!valid) break;
+            const int part = __builtin_amdgcn_readfirstlane(meta[b][M_PART]);
+            int item;
+            if (part == 1) {
+                item = __builtin_amdgcn_readfirstlane(meta[b][M_IMG]) * tiles +
+                       __builtin_amdgcn_readfirstlane(meta[b][M_TILE]);
+            } else {
+                v = -1;
+                if (lane == 0) v = claim_item(C, a, counters);
+                item = __builtin_amdgcn_readfirstlane(v);
+            }
+            plan_item<TL, TS, CAP>(a, item, part == 1 ? 2 : 0, tiles, ln[b ^ 1], cl[b ^ 1], rw[b ^ 1], meta[b ^ 1]);
+            __syncthreads();
+            __syncthreads();
+            b ^= 1;
+        }
+        return;
+    }
+    int bc_img = -1;
+    __syncthreads();
+    for (;;) {
+        const Meta mt = read_meta(meta[b]);
+        if (!mt.valid) break;
+        if (!mt.empty) {
+            if (bc_img != mt.img) {
+                build_bc_lut(mt.alpha, mt.beta, bc);
+                bc_img = mt.img;
+            }
+            if (mt.tile == 0 && mt.part <= 1 && a.boxes) ragged_boxes<kThreads>(a, mt.img);
+        }
+        pass_dma<kThreads, CAP>(a, mt, rw[b], st);
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
+        __syncthreads();
+        if (!mt.empty) {
+            if (mt.staged) pass_blend<TL, TS, kThreads>(a, mt, st, ln[b], cl[b], bc, nlut);
+            else pass_direct<kThreads>(a, mt, bc, nlut);
+        }
+        __syncthreads();  // the stage and this table set are rewritten next
+        b ^= 1;
+    }
+}
+
 // Flat grid: one workgroup per item, XCD-aware: workgroup b runs on XCD b mod 8
 // and takes item b / 8 of queue b mod 8.
 template <int TL, int TS, int CAP>
@@ -1035,12 +1147,13 @@ __global__ void k_zero_counters(int *counters, int n) {
 struct Variant {
     int tl, ts;
     int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid, 3 persistent with
-                    // the next pass planned during the current pass's DMA
+                    // the next pass planned during the current pass's DMA, 4 the same with a planning wave
     int wg_per_cu;  // workgroups per CU of the persistent modes
     int chunk;      // tiles claimed per atomic (persistent mode)
     const char *name;
 };
 const Variant kVariants[] = {
+    {32, 32, 4, 4, 1, "tile 32x32, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
     {32, 32, 1, 4, 1, "tile 32x32, persistent 4 wg/CU, chunks of 1"},
     {32, 32, 1, 4, 4, "tile 32x32, persistent 4 wg/CU, chunks of 4"},
@@ -1089,6 +1202,11 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     }
     if (v.mode == 3) {
         hipLaunchKernelGGL((k_ragged_pipe<TL, TS, full_cap<TL, TS, 43>()>), dim3(grid), dim3(kThreads), 0, s,
+                           *a, L.counters);
+        return hipGetLastError();
+    }
+    if (v.mode == 4) {
+        hipLaunchKernelGGL((k_ragged_pipe5<TL, TS, full_cap<TL, TS, 43>()>), dim3(grid), dim3(kThreads + 64), 0, s,
                            *a, L.counters);
         return hipGetLastError();
     }
