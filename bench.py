@@ -103,6 +103,8 @@ def ragged_algorithmic_bytes(hw, nboxes, out=224):
 
 def ragged_kernel_name(variant_name: str) -> str:
     """Kernel that a ragged launch variant runs."""
+    if "double-buffered" in variant_name:
+        return "k_ragged_pipe6"
     if "planning wave" in variant_name:
         return "k_ragged_pipe5"
     if "next pass planned" in variant_name:

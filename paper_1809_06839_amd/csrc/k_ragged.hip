@@ -129,7 +129,8 @@ __host__ __device__ __forceinline__ int tiles_per_image(int OH, int OW) {
 
 // Largest staged footprint (16-byte chunks) of a whole TL x TS tile whose
 // source extent along the span axis is up to R / 10 times the output's
-// (4.6 by default; 4.3 leaves room for a second table set in 40 KB).
+// (4.6 by default; 4.3 leaves room for a second table set in 40 KB, which is
+// what a workgroup may take for two of them to share one half of the LDS).
 template <int TL, int TS, int R = 46>
 constexpr int full_cap() {
     return 2 * TL * ((((TS - 1) * R / 10 + 4) * 3 + 30) / 16) + TL * ((((TS - 1) * R / 10 + 4) + 30) / 16);
@@ -515,70 +516,58 @@ __device__ __forceinline__ uint32_t div_magic(int d) {
 // at stage byte 16 it.  Image and mask chunks are issued in two loops, each
 // through a buffer resource of its own base (32-bit offsets); the 64 lanes of
 // a wave take 64 consecutive chunks, which is the DMA's lane layout (LDS base
-// in M0 + 16 * lane); threads 0..NT-1 take part.  All row-table reads of a
-// loop come first, then its DMAs, so their LDS latencies overlap.
+// in M0 + 16 * lane); threads 0..NT-1 take part.  Row-table reads go in
+// groups of four ahead of their DMAs, so their LDS latencies overlap (a wave
+// that has run out of chunks reads clamped entries and issues nothing).
 // Completion is counted by vmcnt.
 template <int NT, int CAP, int N>
 __device__ __forceinline__ void pass_dma(const miaug_ragged_args &a, const Meta &mt, const int2 *rw,
                                          uint8_t (&st)[N]) {
     constexpr int kIt = (CAP + NT - 1) / NT;
+    constexpr int kB = 4;  // row-table reads issued together
     if (!mt.valid || mt.empty || !mt.staged) return;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wbase = __builtin_amdgcn_readfirstlane(tid - lane);
     const int items = mt.items, nmask = mt.total - mt.items, nl = mt.nl;
-    {
-        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((void *)align16(a.img + mt.img_off), 0x7fffffffu);
-        const int d = mt.nchi;
+    // chunks [0, n) of slots of d chunks each, rows rw[r0 + slot] (slot clamped
+    // to smax), landing at stage byte 16 (sbase + chunk)
+    auto issue = [&](const __amdgpu_buffer_rsrc_t rs, int n, int d, int r0, int smax, int sbase) {
         const uint32_t M = div_magic(d);
-        uint32_t vo[kIt];
-        bool ok[kIt];
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            ok[u] = false;
-            vo[u] = 0;
-            if (wbase + u * NT >= items) break;  // uniform per wave
-            const int it = tid + u * NT;
-            const int slot = div_by_m(it, d, M), ch = it - slot * d;
-            const int2 r = rw[min(slot, 2 * nl - 1)];
-            ok[u] = it < items && ch < r.y;
-            vo[u] = (uint32_t)(r.x + 16 * ch);
-        }
+        for (int u0 = 0; u0 < kIt; u0 += kB) {
+            if (wbase + u0 * NT >= n) break;  // uniform per wave
+            int2 r[kB];
+            int ch[kB];
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            if (wbase + u * NT >= items) break;
-            if (ok[u]) dma16(rs, st + 16 * (wbase + u * NT), vo[u]);
-        }
-    }
-    if (nmask > 0) {
-        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc((void *)align16(a.mask + mt.mask_off), 0x7fffffffu);
-        const int d = mt.nchm;
-        const uint32_t M = div_magic(d);
-        uint32_t vo[kIt];
-        bool ok[kIt];
+            for (int u = 0; u < kB; ++u) {
+                const int it = tid + (u0 + u) * NT;
+                const int slot = div_by_m(it, d, M);
+                ch[u] = it - slot * d;
+                r[u] = rw[r0 + min(slot, smax)];
+            }
 #pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            ok[u] = false;
-            vo[u] = 0;
-            if (wbase + u * NT >= nmask) break;
-            const int jt = tid + u * NT;
-            const int slot = div_by_m(jt, d, M), ch = jt - slot * d;
-            const int2 r = rw[2 * nl + min(slot, nl - 1)];
-            ok[u] = jt < nmask && ch < r.y;
-            vo[u] = (uint32_t)(r.x + 16 * ch);
+            for (int u = 0; u < kB; ++u) {
+                if (u0 + u >= kIt || wbase + (u0 + u) * NT >= n) break;
+                const int it = tid + (u0 + u) * NT;
+                if (it < n && ch[u] < r[u].y)
+                    dma16(rs, st + 16 * (sbase + wbase + (u0 + u) * NT), (uint32_t)(r[u].x + 16 * ch[u]));
+            }
         }
-#pragma unroll
-        for (int u = 0; u < kIt; ++u) {
-            if (wbase + u * NT >= nmask) break;
-            if (ok[u]) dma16(rs, st + 16 * (items + wbase + u * NT), vo[u]);
-        }
-    }
+    };
+    issue(buffer_rsrc((void *)align16(a.img + mt.img_off), 0x7fffffffu), items, mt.nchi, 0, 2 * nl - 1, 0);
+    if (nmask > 0)
+        issue(buffer_rsrc((void *)align16(a.mask + mt.mask_off), 0x7fffffffu), nmask, mt.nchm, 2 * nl, nl - 1,
+              items);
 }
 
 // Blend, normalise and store a staged pass.  Each tap byte is one ds_read_u8
 // (the channel is the instruction's immediate offset) whose result indexes
 // the brightness/contrast LUT directly.  The separable blend uses full-rate
 // 24-bit multiplies (weights <= 1024, partial sums < 2^18, total < 2^28).
-// Stores take per-channel scalar offsets.  Lanes take output row segments
+// Stores take per-channel scalar offsets.  A lane's pixels go in groups of up
+// to four whose tap, LUT and normalisation reads are issued together, so a
+// wave waits for three LDS round trips per group rather than per pixel (the
+// blend is bound by LDS latency).  Lanes take output row segments
 // when the element keeps the axes (consecutive lanes read consecutive columns
 // of the same two staged rows), and 8 x 8 blocks when it swaps them
 // (consecutive lanes would otherwise read the same column of many staged rows,
@@ -588,47 +577,85 @@ __device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta 
                                          const int4 *ln, const int4 *cl, const uint8_t *bc,
                                          const float (&nlut)[3][256]) {
     constexpr int kPix = (TL * TS + NT - 1) / NT;
-    static_assert(NT % 64 == 0 && (TL * TS) % NT == 0, "whole waves, whole tiles");
+    constexpr int G = kPix < 4 ? kPix : 4;  // pixels per lane whose LDS reads are issued together
+    static_assert(NT % 64 == 0 && (TL * TS) % NT == 0 && kPix % G == 0, "whole waves, whole tiles, whole groups");
     const int tid = threadIdx.x;
     const int plane = a.out_h * a.out_w;  // outputs are at most 4096 x 4096
     const int OW = a.out_w;
     const bool has_mask = a.mask != nullptr;
     const int wlog = mt.part ? log2_of<TS>() - 1 : log2_of<TS>();
-    const int npx = TL << wlog;
+    const int npx = TL << wlog;  // a multiple of NT
     const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(a.out + (size_t)mt.img * 3 * plane, (uint32_t)(12 * plane));
     const __amdgpu_buffer_rsrc_t rm =
         buffer_rsrc(has_mask ? a.out_mask + (size_t)mt.img * plane : a.out_mask, (uint32_t)plane);
     const int base = mt.j0 * OW + mt.i0;
 #pragma unroll
-    for (int k = 0; k < kPix; ++k) {
-        const int p = tid + k * NT;
-        if (p >= npx) break;
-        int l, si;  // line and span position within the pass
-        if (!SWAP) {
-            l = p >> wlog;
-            si = p & ((1 << wlog) - 1);
-        } else {
-            const int lane = p & 63, blk = p >> 6;  // 8 x 8 blocks
-            l = 8 * (blk % (TL / 8)) + (lane & 7);
-            si = 8 * (blk / (TL / 8)) + (lane >> 3);
-        }
-        if (l >= mt.nl || si >= mt.ns) continue;
-        const int4 L = ln[l];
-        const int4 C = cl[si];
-        const uint32_t ws1 = C.z, ws0 = kFOne - ws1, wl1 = L.z, wl0 = kFOne - wl1;
-        const int o00 = L.x + C.x, o01 = L.x + C.y, o10 = L.y + C.x, o11 = L.y + C.y;
-        const int off = base + (SWAP ? umad24(si, OW, l) : umad24(l, OW, si));
+    for (int k0 = 0; k0 < kPix; k0 += G) {
+        if (k0 * NT >= npx) break;
+        bool ok[G];
+        int off[G];
+        uint32_t wl[G], ws[G];
+        uint32_t v[G][12];
+        uint32_t mk[G];
+        int4 Lg[G], Cg[G];
+        // table entries of the whole group
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const uint32_t p00 = bc[st[o00 + c]], p01 = bc[st[o01 + c]];
-            const uint32_t p10 = bc[st[o10 + c]], p11 = bc[st[o11 + c]];
-            const uint32_t t0 = umad24(p01, ws1, __umul24(p00, ws0));
-            const uint32_t t1 = umad24(p11, ws1, __umul24(p10, ws0));
-            const int v = rhe20((int)umad24(t1, wl1, __umul24(t0, wl0)));
-            // the b32 store takes the bit pattern: pass the float's bits, not its value
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(nlut[c][v]), ro, 4 * off, 4 * c * plane, 0);
+        for (int g = 0; g < G; ++g) {
+            const int p = tid + (k0 + g) * NT;
+            int l, si;  // line and span position within the pass
+            if (!SWAP) {
+                l = p >> wlog;
+                si = p & ((1 << wlog) - 1);
+            } else {
+                const int lane = p & 63, blk = p >> 6;  // 8 x 8 blocks
+                l = 8 * (blk % (TL / 8)) + (lane & 7);
+                si = 8 * (blk / (TL / 8)) + (lane >> 3);
+            }
+            ok[g] = l < mt.nl && si < mt.ns;
+            if (!ok[g]) l = si = 0;  // read table entries that exist; nothing is stored
+            Lg[g] = ln[l];
+            Cg[g] = cl[si];
+            off[g] = base + (SWAP ? umad24(si, OW, l) : umad24(l, OW, si));
         }
-        if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(st[L.w + C.w], rm, off, 0, 0);
+        // taps (and the mask byte) of the whole group
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int4 L = Lg[g], C = Cg[g];
+            ws[g] = C.z;
+            wl[g] = L.z;
+            const int o00 = L.x + C.x, o01 = L.x + C.y, o10 = L.y + C.x, o11 = L.y + C.y;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[g][4 * c] = st[o00 + c];
+                v[g][4 * c + 1] = st[o01 + c];
+                v[g][4 * c + 2] = st[o10 + c];
+                v[g][4 * c + 3] = st[o11 + c];
+            }
+            mk[g] = st[L.w + C.w];  // inside the stage even without a mask (offsets 0 and < nmx then)
+        }
+        // brightness / contrast of every tap
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int e = 0; e < 12; ++e) v[g][e] = bc[v[g][e]];
+        // separable blend, normalisation, stores
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t ws1 = ws[g], ws0 = kFOne - ws1, wl1 = wl[g], wl0 = kFOne - wl1;
+            float f[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const uint32_t t0 = umad24(v[g][4 * c + 1], ws1, __umul24(v[g][4 * c], ws0));
+                const uint32_t t1 = umad24(v[g][4 * c + 3], ws1, __umul24(v[g][4 * c + 2], ws0));
+                f[c] = nlut[c][rhe20((int)umad24(t1, wl1, __umul24(t0, wl0)))];
+            }
+            if (ok[g]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)  // the b32 store takes the bit pattern: pass the float's bits
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[c]), ro, 4 * off[g], 4 * c * plane, 0);
+                if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(mk[g], rm, off[g], 0, 0);
+            }
+        }
     }
 }
 
@@ -869,7 +896,8 @@ __global__ __launch_bounds__(kThreads) void k_ragged_pipe(miaug_ragged_args a, i
 // four worker waves stream and blend pass k, so neither planning nor claiming
 // sits in a worker's path.  Two barriers per pass, as above.
 template <int TL, int TS, int CAP>
-__global__ __launch_bounds__(kThreads + 64) void k_ragged_pipe5(miaug_ragged_args a, int *__restrict__ counters) {
+__global__ __launch_bounds__(kThreads + 64) __attribute__((amdgpu_waves_per_eu(5))) void k_ragged_pipe5(
+    miaug_ragged_args a, int *__restrict__ counters) {
     __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
     __shared__ int4 ln[2][TL];
     __shared__ int4 cl[2][TS];
@@ -933,6 +961,109 @@ __global__ __launch_bounds__(kThreads + 64) void k_ragged_pipe5(miaug_ragged_arg
         }
         __syncthreads();  // the stage and this table set are rewritten next
         b ^= 1;
+    }
+}
+
+// Pipelined form with a double-buffered stage: the four worker waves issue the
+// LDS-DMA of pass k+1 into one stage and then blend pass k out of the other,
+// so every workgroup keeps loads in flight while it computes.  The planning
+// wave runs two passes ahead into a third table set (pass k+2 while pass k is
+// blended and pass k+1 streamed).  The two stages are separate LDS variables
+// and the loop is unrolled by two, so each blend's LDS reads carry no wait on
+// the other stage's DMA.  One barrier per pass; the brightness/contrast LUT is
+// double-buffered by pass parity and built one pass ahead.  Both sides leave
+// the loop at the first invalid pass, after the same number of barriers.
+// Two stages do not fit in 40 KB with a useful footprint, so this form runs
+// two workgroups per CU; it measured slower than the single-stage form at
+// three (1.10 against 0.81 ms on the 2048-image batch).
+template <int TL, int TS, int CAP, int N>
+__device__ __forceinline__ bool pipe6_step(const miaug_ragged_args &a, int k, int4 (*ln)[TL], int4 (*cl)[TS],
+                                           int2 (*rw)[3 * TL], int (*meta)[M_N], uint8_t (*bc)[256],
+                                           const float (&nlut)[3][256], uint8_t (&cur)[N], uint8_t (&nxt)[N]) {
+    const int t = k % 3, t1 = (k + 1) % 3;
+    if (!__builtin_amdgcn_readfirstlane(meta[t][M_VALID])) return false;
+    if (a.boxes && !__builtin_amdgcn_readfirstlane(meta[t][M_EMPTY]) &&
+        __builtin_amdgcn_readfirstlane(meta[t][M_TILE]) == 0 && __builtin_amdgcn_readfirstlane(meta[t][M_PART]) <= 1)
+        ragged_boxes<kThreads>(a, __builtin_amdgcn_readfirstlane(meta[t][M_IMG]));  // before the DMA: its loads
+                                                                                   // would wait for it
+    {
+        const Meta mn = read_meta(meta[t1]);
+        if (mn.valid && !mn.empty) build_bc_lut(mn.alpha, mn.beta, bc[(k + 1) & 1]);
+        pass_dma<kThreads, CAP>(a, mn, rw[t1], nxt);
+    }
+    const Meta mc = read_meta(meta[t]);
+    if (!mc.empty) {
+        if (mc.staged) pass_blend<TL, TS, kThreads>(a, mc, cur, ln[t], cl[t], bc[k & 1], nlut);
+        else pass_direct<kThreads>(a, mc, bc[k & 1], nlut);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // the next pass's LDS-DMA writes are counted by vmcnt
+    __syncthreads();
+    return true;
+}
+
+template <int TL, int TS, int CAP>
+__global__ __launch_bounds__(kThreads + 64) void k_ragged_pipe6(miaug_ragged_args a, int *__restrict__ counters) {
+    __shared__ __align__(16) uint8_t st0[stage_bytes(CAP)];
+    __shared__ __align__(16) uint8_t st1[stage_bytes(CAP)];
+    __shared__ int4 ln[3][TL];
+    __shared__ int4 cl[3][TS];
+    __shared__ int2 rw[3][3 * TL];
+    __shared__ __align__(16) int meta[3][M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[2][256];
+    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    const bool planner = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == kThreads / 64;
+    build_norm_lut(a, nlut);
+    if (planner) {
+        __builtin_amdgcn_s_setprio(2);
+        const int lane = threadIdx.x & 63;
+        Claimer<1> C{tiles, (int)(blockIdx.x % kQueues), 0, 0};  // meaningful in lane 0
+        // item and part of pass k + 1 (from pass k's plan)
+        auto next_of = [&](const int *m, int &item, int &part) {
+            if (!__builtin_amdgcn_readfirstlane(m[M_VALID])) {
+                item = -1;
+                part = 0;
+            } else if (__builtin_amdgcn_readfirstlane(m[M_PART]) == 1) {
+                item = __builtin_amdgcn_readfirstlane(m[M_IMG]) * tiles + __builtin_amdgcn_readfirstlane(m[M_TILE]);
+                part = 2;
+            } else {
+                int v = -1;
+                if (lane == 0) v = claim_item(C, a, counters);
+                item = __builtin_amdgcn_readfirstlane(v);
+                part = 0;
+            }
+        };
+        int v = -1;
+        if (lane == 0) {
+            C.issue(counters);
+            v = claim_item(C, a, counters);
+        }
+        plan_item<TL, TS, CAP>(a, __builtin_amdgcn_readfirstlane(v), 0, tiles, ln[0], cl[0], rw[0], meta[0]);
+        int item, part;
+        next_of(meta[0], item, part);
+        plan_item<TL, TS, CAP>(a, item, part, tiles, ln[1], cl[1], rw[1], meta[1]);
+        __syncthreads();  // tables of passes 0 and 1
+        __syncthreads();  // pass 0 staged
+        for (int k = 0;; ++k) {
+            if (!__builtin_amdgcn_readfirstlane(meta[k % 3][M_VALID])) break;
+            next_of(meta[(k + 1) % 3], item, part);
+            const int t2 = (k + 2) % 3;
+            plan_item<TL, TS, CAP>(a, item, part, tiles, ln[t2], cl[t2], rw[t2], meta[t2]);
+            __syncthreads();
+        }
+        return;
+    }
+    __syncthreads();  // tables of passes 0 and 1
+    {
+        const Meta m0 = read_meta(meta[0]);
+        if (m0.valid && !m0.empty) build_bc_lut(m0.alpha, m0.beta, bc[0]);
+        pass_dma<kThreads, CAP>(a, m0, rw[0], st0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // pass 0 staged
+    for (int k = 0;; k += 2) {
+        if (!pipe6_step<TL, TS, CAP>(a, k, ln, cl, rw, meta, bc, nlut, st0, st1)) break;
+        if (!pipe6_step<TL, TS, CAP>(a, k + 1, ln, cl, rw, meta, bc, nlut, st1, st0)) break;
     }
 }
 
@@ -1147,18 +1278,27 @@ __global__ void k_zero_counters(int *counters, int n) {
 struct Variant {
     int tl, ts;
     int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid, 3 persistent with
-                    // the next pass planned during the current pass's DMA, 4 the same with a planning wave
+                    // the next pass planned during the current pass's DMA, 4 the same with a planning wave,
+                    // 5 double-buffered stage with the planning wave two passes ahead
     int wg_per_cu;  // workgroups per CU of the persistent modes
     int chunk;      // tiles claimed per atomic (persistent mode)
     const char *name;
 };
+// Variant 0 is the default.  Workgroups per CU are chosen against the LDS as
+// measured on gfx950: a workgroup above about 40 KB runs as if only one fits
+// in each 80 KB half of the 160 KB (three 42.5 KB workgroups per CU run like
+// two), so the staged forms keep a workgroup at or under 40 KB.  Of those,
+// three per CU beat four (about 7%): fewer streams contend for the CU.
 const Variant kVariants[] = {
+    {32, 32, 4, 3, 1, "tile 32x32, persistent 3 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 4, 4, 1, "tile 32x32, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
+    {32, 32, 5, 2, 1, "tile 32x32, persistent 2 wg/CU, double-buffered stage, planning wave two passes ahead"},
     {32, 32, 1, 4, 1, "tile 32x32, persistent 4 wg/CU, chunks of 1"},
     {32, 32, 1, 4, 4, "tile 32x32, persistent 4 wg/CU, chunks of 4"},
     {32, 32, 1, 4, 8, "tile 32x32, persistent 4 wg/CU, chunks of 8"},
     {16, 32, 1, 8, 8, "tile 16x32, persistent 8 wg/CU, chunks of 8"},
+    {16, 32, 4, 6, 1, "tile 16x32, persistent 6 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 2, 0, 1, "tile 32x32, flat grid"},
     {32, 32, 0, 2, 1, "tile 32x32, streaming pipeline 8+1 waves, 2 wg/CU"},
 };
@@ -1207,6 +1347,11 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     }
     if (v.mode == 4) {
         hipLaunchKernelGGL((k_ragged_pipe5<TL, TS, full_cap<TL, TS, 43>()>), dim3(grid), dim3(kThreads + 64), 0, s,
+                           *a, L.counters);
+        return hipGetLastError();
+    }
+    if (v.mode == 5) {
+        hipLaunchKernelGGL((k_ragged_pipe6<TL, TS, full_cap<TL, TS, 26>()>), dim3(grid), dim3(kThreads + 64), 0, s,
                            *a, L.counters);
         return hipGetLastError();
     }
