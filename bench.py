@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--min-warmup-s", type=float, default=1.0,
+                   help="after the W warm-up steps, keep running untimed steps until this much time has passed "
+                        "(GPU clocks reach their working level only after some back-to-back work)")
     p.add_argument("--workload", default="ragged")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -155,9 +158,7 @@ def bench_ragged(args, torch, m):
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         g = m.Graph(ctx, r, s)
-        for _ in range(args.warmup):
-            g.launch(s)
-        s.synchronize()
+        warm_up(lambda st: g.launch(st), args, s)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -184,7 +185,7 @@ def bench_ragged(args, torch, m):
     achieved = alg / (ms * 1e-3) / 1e9
     res = {
         "metric": "images/sec and HBM GB/s (% peak) for batched augment pipeline; batched vs per-image",
-        "value": n / (ms * 1e-3), "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": n / (ms * 1e-3), "unit": "images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "min_warmup_s": args.min_warmup_s,
         "ms_per_step": ms, "wall_s_timed": wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "ragged_d4_bc_resize224_normalize_f32", "global_batch": n,
@@ -204,12 +205,35 @@ def bench_ragged(args, torch, m):
     return res
 
 
-def time_on_stream(torch, fn, steps, warmup, s):
-    """Average ms of fn(s) over `steps` calls on stream s, HIP events around the loop."""
+def warm_up(fn, args, s):
+    """W untimed calls of fn(s), then more until --min-warmup-s seconds have passed."""
+    for _ in range(args.warmup):
+        fn(s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < args.min_warmup_s:
+        for _ in range(4):
+            fn(s)
+        s.synchronize()
+
+
+MIN_WARMUP_S = 1.0  # set from --min-warmup-s
+
+
+def time_on_stream(torch, fn, steps, warmup, s, min_warmup_s=None):
+    """Average ms of fn(s) over `steps` calls on stream s, HIP events around the loop, after
+    `warmup` untimed calls and more until min_warmup_s (default --min-warmup-s) seconds have passed."""
+    if min_warmup_s is None:
+        min_warmup_s = MIN_WARMUP_S
     with torch.cuda.stream(s):
         for _ in range(warmup):
             fn(s)
         s.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < min_warmup_s:
+            for _ in range(4):
+                fn(s)
+            s.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(s)
@@ -222,7 +246,7 @@ def time_on_stream(torch, fn, steps, warmup, s):
 
 def line(metric, n, ms, args, dtype, config, roofline, extra=None):
     res = {"metric": metric, "value": n / (ms * 1e-3), "unit": "images/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "warmup": args.warmup, "min_warmup_s": args.min_warmup_s, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
     if extra:
         res.update(extra)
@@ -448,6 +472,8 @@ WORKLOADS = {"table1": bench_table1, "copy": bench_copy, "ragged": bench_ragged,
 
 def main():
     args = parse()
+    global MIN_WARMUP_S
+    MIN_WARMUP_S = args.min_warmup_s
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (shards would be independent "
               "per-GPU batches); run with --gpus 1", file=sys.stderr)

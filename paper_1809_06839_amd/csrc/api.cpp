@@ -341,6 +341,9 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
         if (st) break;
         if (memcmp(ref.data(), got.data(), out_bytes) != 0 || memcmp(mref.data(), mgot.data(), mask_bytes) != 0)
             continue;  // parity gate: only variants identical to the per-image form compete
+        // untimed launches first: the parity copy above leaves the GPU idle, and
+        // its clocks need some back-to-back work to come up again
+        for (int r = 0; r < 2 * reps && !st; ++r) st = hip_status(launch_ragged(a, L, 0, s), "autotune warm-up");
         hipEventRecord(e0, s);
         for (int r = 0; r < reps && !st; ++r) st = hip_status(launch_ragged(a, L, 0, s), "autotune timing");
         hipEventRecord(e1, s);

@@ -116,7 +116,7 @@ __device__ __forceinline__ int rhe20(int acc) { return (acc + 0x7FFFF + ((acc >>
 constexpr int stage_bytes(int cap) { return cap * 16 + 16; }
 
 template <int TS>
-constexpr int log2_of() { return TS == 64 ? 6 : TS == 32 ? 5 : TS == 16 ? 4 : 3; }
+constexpr int log2_of() { return TS == 128 ? 7 : TS == 64 ? 6 : TS == 32 ? 5 : TS == 16 ? 4 : 3; }
 
 // Work items per image: the tile grid in line x span coordinates depends on
 // whether the element swaps axes, so the queue reserves the larger count.
@@ -413,6 +413,10 @@ __device__ __forceinline__ const uint8_t *align16(const uint8_t *g) {
     return (const uint8_t *)((uintptr_t)g & ~(uintptr_t)15);
 }
 
+template <int TL, int TS>
+__device__ __forceinline__ void table_entry(const miaug_ragged_args &a, const Pass &p, const D4Map &m, bool isl,
+                                            int idx, int64_t io, int64_t mo, int4 *ln, int4 *cl, int2 *rw);
+
 // Tables of a pass, built by wave 0 alone (the other waves only read them
 // after a barrier):
 //   ln[l]  = LDS byte offsets of the two tap rows of line l, its Q10 weight and
@@ -423,12 +427,12 @@ __device__ __forceinline__ const uint8_t *align16(const uint8_t *g) {
 //            its first 16-byte chunk from the image's (mask's) aligned base,
 //            and its chunk count;
 //   meta   = what the DMA and blend stages need.
-// Lane l < TL builds line l, lane TL + s span position s, with one shared
-// evaluation of the resize position.
+// Entry l < TL is line l, entry TL + s span position s (lane e takes entries
+// e, e + 64, ...), with one shared evaluation of the resize position.
 template <int TL, int TS>
 __device__ __forceinline__ void pass_tables(const miaug_ragged_args &a, const Pass &p, int4 *ln, int4 *cl, int2 *rw,
                                             int *meta) {
-    static_assert(TL + TS <= 64, "one wave builds the tables");
+
     const int lane = threadIdx.x & 63;
     const bool live = p.valid && !p.empty;
     const int64_t io = live ? p.io : 0;
@@ -469,9 +473,17 @@ __device__ __forceinline__ void pass_tables(const miaug_ragged_args &a, const Pa
     }
     if (!live || !p.staged) return;
     const D4Map &m = p.m;
-    const bool isl = lane < TL;  // lanes 0..TL-1: lines; TL..TL+TS-1: span positions
-    const int idx = isl ? lane : lane - TL;
-    if (idx >= (isl ? p.nl : p.ns) || lane >= TL + TS) return;
+    for (int e = lane; e < TL + TS; e += 64) {
+        const bool isl = e < TL;  // entries 0..TL-1: lines; TL..TL+TS-1: span positions
+        const int idx = isl ? e : e - TL;
+        if (idx >= (isl ? p.nl : p.ns)) continue;
+        table_entry<TL, TS>(a, p, m, isl, idx, io, mo, ln, cl, rw);
+    }
+}
+
+template <int TL, int TS>
+__device__ __forceinline__ void table_entry(const miaug_ragged_args &a, const Pass &p, const D4Map &m, bool isl,
+                                            int idx, int64_t io, int64_t mo, int4 *ln, int4 *cl, int2 *rw) {
     const int Lsrc = isl ? p.Ll : p.Ls;
     const int q = resize_q(isl ? p.l0 + idx : p.s0 + idx, Lsrc, isl ? p.OL : p.OS);
     const int d0 = clampi(q >> kFBits, Lsrc), d1 = clampi((q >> kFBits) + 1, Lsrc);
@@ -497,6 +509,8 @@ __device__ __forceinline__ void pass_tables(const miaug_ragged_args &a, const Pa
                             p.ks * dn + m.cx - p.mxlo);
     }
 }
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // 16 bytes per lane from a buffer (32-bit offset) into LDS at lds + 16 * lane.
 __device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t rs, uint8_t *lds, uint32_t voff) {
@@ -560,43 +574,118 @@ __device__ __forceinline__ void pass_dma(const miaug_ragged_args &a, const Meta 
               items);
 }
 
-// Blend, normalise and store a staged pass.  Each tap byte is one ds_read_u8
+// Register staging of a pass: the same chunks as pass_dma, loaded into VGPRs
+// (16 bytes each; chunk j = tid + u NT of the pass, image chunks first, then
+// mask chunks), so that the loads can be in flight while the previous pass is
+// blended out of the single LDS stage; pass_stage then writes them to stage
+// byte 16 j.  Bit u of the returned mask marks the chunks loaded.
+template <int NT, int CAP>
+constexpr int chunks_per_lane() {
+    return (CAP + NT - 1) / NT;
+}
+
+template <int NT, int CAP>
+__device__ __forceinline__ uint32_t pass_load(const miaug_ragged_args &a, const Meta &mt, const int2 *rw,
+                                              u32x4 (&R)[chunks_per_lane<NT, CAP>()]) {
+    constexpr int kIt = chunks_per_lane<NT, CAP>();
+    constexpr int kB = 4;  // row-table reads issued together
+    static_assert(kIt <= 32, "one bit per chunk");
+    uint32_t okm = 0;
+    if (!mt.valid || mt.empty || !mt.staged) return okm;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wbase = __builtin_amdgcn_readfirstlane(tid - lane);
+    const int items = mt.items, total = mt.total, nl = mt.nl;
+    const int di = mt.nchi, dm = mt.nchm;
+    const uint32_t Mi = div_magic(di), Mm = div_magic(dm);
+    const __amdgpu_buffer_rsrc_t ri = buffer_rsrc((void *)align16(a.img + mt.img_off), 0x7fffffffu);
+    const __amdgpu_buffer_rsrc_t rm =
+        buffer_rsrc((void *)(a.mask ? align16(a.mask + mt.mask_off) : a.img), 0x7fffffffu);
+#pragma unroll
+    for (int u0 = 0; u0 < kIt; u0 += kB) {
+        if (wbase + u0 * NT >= total) break;  // uniform per wave
+        int2 r[kB];
+        int ch[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int j = tid + (u0 + u) * NT;
+            const bool im = j < items;
+            const int jj = im ? j : j - items;
+            const int d = im ? di : dm;
+            const int slot = div_by_m(jj, d, im ? Mi : Mm);
+            ch[u] = jj - slot * d;
+            r[u] = rw[im ? min(slot, 2 * nl - 1) : 2 * nl + min(slot, nl - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            if (u0 + u >= kIt || wbase + (u0 + u) * NT >= total) break;
+            const int j = tid + (u0 + u) * NT;
+            if (j < total && ch[u] < r[u].y) {
+                const uint32_t off = (uint32_t)(r[u].x + 16 * ch[u]);
+                if (j < items) R[u0 + u] = __builtin_amdgcn_raw_buffer_load_b128(ri, off, 0, 0);
+                else R[u0 + u] = __builtin_amdgcn_raw_buffer_load_b128(rm, off, 0, 0);
+                okm |= 1u << (u0 + u);
+            }
+        }
+    }
+    return okm;
+}
+
+template <int NT, int CAP, int N>
+__device__ __forceinline__ void pass_stage(const u32x4 (&R)[chunks_per_lane<NT, CAP>()], uint32_t okm,
+                                           uint8_t (&st)[N]) {
+    constexpr int kIt = chunks_per_lane<NT, CAP>();
+#pragma unroll
+    for (int u = 0; u < kIt; ++u)
+        if (okm & (1u << u)) *(u32x4 *)(st + 16 * (threadIdx.x + u * NT)) = R[u];
+}
+
+// One lane's blended pixels of a pass, held in registers until stored.
+template <int K>
+struct BlendOut {
+    float f[K][3];
+    uint32_t m[K];
+    int off[K];  // element offset within the image's output plane
+    bool ok[K];
+};
+
+template <int TL, int TS, int NT>
+constexpr int pix_per_lane() {
+    return (TL * TS + NT - 1) / NT;
+}
+
+// Blend and normalise a staged pass into registers (store_out writes them;
+// blend_px does both).  Each tap byte is one ds_read_u8
 // (the channel is the instruction's immediate offset) whose result indexes
 // the brightness/contrast LUT directly.  The separable blend uses full-rate
 // 24-bit multiplies (weights <= 1024, partial sums < 2^18, total < 2^28).
 // Stores take per-channel scalar offsets.  A lane's pixels go in groups of up
 // to four whose tap, LUT and normalisation reads are issued together, so a
-// wave waits for three LDS round trips per group rather than per pixel (the
-// blend is bound by LDS latency).  Lanes take output row segments
-// when the element keeps the axes (consecutive lanes read consecutive columns
-// of the same two staged rows), and 8 x 8 blocks when it swaps them
-// (consecutive lanes would otherwise read the same column of many staged rows,
-// which share few LDS banks).
+// wave waits for three LDS round trips per group rather than per pixel.
+// Lanes take output row segments when the element keeps the axes (consecutive
+// lanes read consecutive columns of the same two staged rows), and 8 x 8
+// blocks when it swaps them (consecutive lanes would otherwise read the same
+// column of many staged rows, which share few LDS banks).
 template <int TL, int TS, int NT, bool SWAP, int N>
-__device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta &mt, const uint8_t (&st)[N],
-                                         const int4 *ln, const int4 *cl, const uint8_t *bc,
-                                         const float (&nlut)[3][256]) {
-    constexpr int kPix = (TL * TS + NT - 1) / NT;
+__device__ __forceinline__ void blend_keep(const miaug_ragged_args &a, const Meta &mt, const uint8_t (&st)[N],
+                                           const int4 *ln, const int4 *cl, const uint8_t *bc,
+                                           const float (&nlut)[3][256], BlendOut<pix_per_lane<TL, TS, NT>()> &o) {
+    constexpr int kPix = pix_per_lane<TL, TS, NT>();
     constexpr int G = kPix < 4 ? kPix : 4;  // pixels per lane whose LDS reads are issued together
     static_assert(NT % 64 == 0 && (TL * TS) % NT == 0 && kPix % G == 0, "whole waves, whole tiles, whole groups");
     const int tid = threadIdx.x;
-    const int plane = a.out_h * a.out_w;  // outputs are at most 4096 x 4096
     const int OW = a.out_w;
-    const bool has_mask = a.mask != nullptr;
     const int wlog = mt.part ? log2_of<TS>() - 1 : log2_of<TS>();
     const int npx = TL << wlog;  // a multiple of NT
-    const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(a.out + (size_t)mt.img * 3 * plane, (uint32_t)(12 * plane));
-    const __amdgpu_buffer_rsrc_t rm =
-        buffer_rsrc(has_mask ? a.out_mask + (size_t)mt.img * plane : a.out_mask, (uint32_t)plane);
     const int base = mt.j0 * OW + mt.i0;
 #pragma unroll
     for (int k0 = 0; k0 < kPix; k0 += G) {
-        if (k0 * NT >= npx) break;
-        bool ok[G];
-        int off[G];
+        if (k0 * NT >= npx) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) o.ok[k0 + g] = false;
+            continue;
+        }
         uint32_t wl[G], ws[G];
         uint32_t v[G][12];
-        uint32_t mk[G];
         int4 Lg[G], Cg[G];
         // table entries of the whole group
 #pragma unroll
@@ -611,11 +700,11 @@ __device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta 
                 l = 8 * (blk % (TL / 8)) + (lane & 7);
                 si = 8 * (blk / (TL / 8)) + (lane >> 3);
             }
-            ok[g] = l < mt.nl && si < mt.ns;
-            if (!ok[g]) l = si = 0;  // read table entries that exist; nothing is stored
+            o.ok[k0 + g] = l < mt.nl && si < mt.ns;
+            if (!o.ok[k0 + g]) l = si = 0;  // read table entries that exist; nothing is stored
             Lg[g] = ln[l];
             Cg[g] = cl[si];
-            off[g] = base + (SWAP ? umad24(si, OW, l) : umad24(l, OW, si));
+            o.off[k0 + g] = base + (SWAP ? umad24(si, OW, l) : umad24(l, OW, si));
         }
         // taps (and the mask byte) of the whole group
 #pragma unroll
@@ -631,32 +720,51 @@ __device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta 
                 v[g][4 * c + 2] = st[o10 + c];
                 v[g][4 * c + 3] = st[o11 + c];
             }
-            mk[g] = st[L.w + C.w];  // inside the stage even without a mask (offsets 0 and < nmx then)
+            o.m[k0 + g] = st[L.w + C.w];  // inside the stage even without a mask (offsets 0 and < nmx then)
         }
         // brightness / contrast of every tap
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int e = 0; e < 12; ++e) v[g][e] = bc[v[g][e]];
-        // separable blend, normalisation, stores
+        // separable blend and normalisation
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const uint32_t ws1 = ws[g], ws0 = kFOne - ws1, wl1 = wl[g], wl0 = kFOne - wl1;
-            float f[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const uint32_t t0 = umad24(v[g][4 * c + 1], ws1, __umul24(v[g][4 * c], ws0));
                 const uint32_t t1 = umad24(v[g][4 * c + 3], ws1, __umul24(v[g][4 * c + 2], ws0));
-                f[c] = nlut[c][rhe20((int)umad24(t1, wl1, __umul24(t0, wl0)))];
-            }
-            if (ok[g]) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c)  // the b32 store takes the bit pattern: pass the float's bits
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[c]), ro, 4 * off[g], 4 * c * plane, 0);
-                if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(mk[g], rm, off[g], 0, 0);
+                o.f[k0 + g][c] = nlut[c][rhe20((int)umad24(t1, wl1, __umul24(t0, wl0)))];
             }
         }
     }
+}
+
+template <int K>
+__device__ __forceinline__ void store_out(const miaug_ragged_args &a, int img, const BlendOut<K> &o) {
+    const int plane = a.out_h * a.out_w;  // outputs are at most 4096 x 4096
+    const bool has_mask = a.mask != nullptr;
+    const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(a.out + (size_t)img * 3 * plane, (uint32_t)(12 * plane));
+    const __amdgpu_buffer_rsrc_t rm =
+        buffer_rsrc(has_mask ? a.out_mask + (size_t)img * plane : a.out_mask, (uint32_t)plane);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!o.ok[k]) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)  // the b32 store takes the bit pattern: pass the float's bits
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o.f[k][c]), ro, 4 * o.off[k], 4 * c * plane, 0);
+        if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(o.m[k], rm, o.off[k], 0, 0);
+    }
+}
+
+template <int TL, int TS, int NT, bool SWAP, int N>
+__device__ __forceinline__ void blend_px(const miaug_ragged_args &a, const Meta &mt, const uint8_t (&st)[N],
+                                         const int4 *ln, const int4 *cl, const uint8_t *bc,
+                                         const float (&nlut)[3][256]) {
+    BlendOut<pix_per_lane<TL, TS, NT>()> o;
+    blend_keep<TL, TS, NT, SWAP>(a, mt, st, ln, cl, bc, nlut, o);
+    store_out(a, mt.img, o);
 }
 
 template <int TL, int TS, int NT, int N>
@@ -1067,6 +1175,102 @@ __global__ __launch_bounds__(kThreads + 64) void k_ragged_pipe6(miaug_ragged_arg
     }
 }
 
+// Pipelined form with register staging: the four worker waves load pass k+1
+// into VGPRs, blend pass k out of the single LDS stage into registers, and
+// only after a barrier write the loaded chunks into the stage and store pass
+// k's pixels, so the loads are in flight during the blend and the stores
+// during the next pass, with one stage of LDS (two do not fit in the 40 KB a
+// workgroup may take).  The planning wave runs two passes ahead into a third
+// table set; two barriers per pass; both sides leave the loop at the first
+// invalid pass, after the same number of barriers.
+template <int TL, int TS, int CAP>
+__global__ __launch_bounds__(kThreads + 64) __attribute__((amdgpu_waves_per_eu(4))) void k_ragged_pipe7(miaug_ragged_args a, int *__restrict__ counters) {
+    __shared__ __align__(16) uint8_t st[stage_bytes(CAP)];
+    __shared__ int4 ln[3][TL];
+    __shared__ int4 cl[3][TS];
+    __shared__ int2 rw[3][3 * TL];
+    __shared__ __align__(16) int meta[3][M_N];
+    __shared__ float nlut[3][256];
+    __shared__ uint8_t bc[256];
+    constexpr int kIt = chunks_per_lane<kThreads, CAP>();
+    const int tiles = tiles_per_image<TL, TS>(a.out_h, a.out_w);
+    const bool planner = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == kThreads / 64;
+    build_norm_lut(a, nlut);
+    if (planner) {
+        __builtin_amdgcn_s_setprio(2);
+        const int lane = threadIdx.x & 63;
+        Claimer<1> C{tiles, (int)(blockIdx.x % kQueues), 0, 0};  // meaningful in lane 0
+        auto next_of = [&](const int *m, int &item, int &part) {  // item and part of the pass after m's
+            if (!__builtin_amdgcn_readfirstlane(m[M_VALID])) {
+                item = -1;
+                part = 0;
+            } else if (__builtin_amdgcn_readfirstlane(m[M_PART]) == 1) {
+                item = __builtin_amdgcn_readfirstlane(m[M_IMG]) * tiles + __builtin_amdgcn_readfirstlane(m[M_TILE]);
+                part = 2;
+            } else {
+                int v = -1;
+                if (lane == 0) v = claim_item(C, a, counters);
+                item = __builtin_amdgcn_readfirstlane(v);
+                part = 0;
+            }
+        };
+        int v = -1;
+        if (lane == 0) {
+            C.issue(counters);
+            v = claim_item(C, a, counters);
+        }
+        plan_item<TL, TS, CAP>(a, __builtin_amdgcn_readfirstlane(v), 0, tiles, ln[0], cl[0], rw[0], meta[0]);
+        int item, part;
+        next_of(meta[0], item, part);
+        plan_item<TL, TS, CAP>(a, item, part, tiles, ln[1], cl[1], rw[1], meta[1]);
+        __syncthreads();  // tables of passes 0 and 1
+        __syncthreads();  // pass 0 staged
+        for (int k = 0;; ++k) {
+            if (!__builtin_amdgcn_readfirstlane(meta[k % 3][M_VALID])) break;
+            next_of(meta[(k + 1) % 3], item, part);
+            const int t2 = (k + 2) % 3;
+            plan_item<TL, TS, CAP>(a, item, part, tiles, ln[t2], cl[t2], rw[t2], meta[t2]);
+            __syncthreads();
+            __syncthreads();
+        }
+        return;
+    }
+    __syncthreads();  // tables of passes 0 and 1
+    {
+        const Meta m0 = read_meta(meta[0]);
+        u32x4 R[kIt];
+        const uint32_t okm = pass_load<kThreads, CAP>(a, m0, rw[0], R);
+        pass_stage<kThreads, CAP>(R, okm, st);
+        if (m0.valid && !m0.empty) build_bc_lut(m0.alpha, m0.beta, bc);
+    }
+    __syncthreads();  // pass 0 staged
+    for (int k = 0;; ++k) {
+        const int t = k % 3, t1 = (k + 1) % 3;
+        if (!__builtin_amdgcn_readfirstlane(meta[t][M_VALID])) break;
+        if (a.boxes && !__builtin_amdgcn_readfirstlane(meta[t][M_EMPTY]) &&
+            __builtin_amdgcn_readfirstlane(meta[t][M_TILE]) == 0 && __builtin_amdgcn_readfirstlane(meta[t][M_PART]) <= 1)
+            ragged_boxes<kThreads>(a, __builtin_amdgcn_readfirstlane(meta[t][M_IMG]));  // before the loads: its
+                                                                                       // loads would wait for them
+        const Meta mn = read_meta(meta[t1]);
+        u32x4 R[kIt];
+        const uint32_t okm = pass_load<kThreads, CAP>(a, mn, rw[t1], R);
+        const Meta mc = read_meta(meta[t]);
+        BlendOut<pix_per_lane<TL, TS, kThreads>()> o;
+        const bool keep = !mc.empty && mc.staged;
+        if (keep) {
+            if (mc.swap) blend_keep<TL, TS, kThreads, true>(a, mc, st, ln[t], cl[t], bc, nlut, o);
+            else blend_keep<TL, TS, kThreads, false>(a, mc, st, ln[t], cl[t], bc, nlut, o);
+        } else if (!mc.empty) {
+            pass_direct<kThreads>(a, mc, bc, nlut);
+        }
+        __syncthreads();  // the stage and the LUT are free
+        pass_stage<kThreads, CAP>(R, okm, st);
+        if (mn.valid && !mn.empty) build_bc_lut(mn.alpha, mn.beta, bc);
+        if (keep) store_out(a, mc.img, o);
+        __syncthreads();  // pass k+1 staged
+    }
+}
+
 // Flat grid: one workgroup per item, XCD-aware: workgroup b runs on XCD b mod 8
 // and takes item b / 8 of queue b mod 8.
 template <int TL, int TS, int CAP>
@@ -1279,7 +1483,7 @@ struct Variant {
     int tl, ts;
     int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid, 3 persistent with
                     // the next pass planned during the current pass's DMA, 4 the same with a planning wave,
-                    // 5 double-buffered stage with the planning wave two passes ahead
+                    // 5 double-buffered stage with the planning wave two passes ahead, 6 register-staged loads
     int wg_per_cu;  // workgroups per CU of the persistent modes
     int chunk;      // tiles claimed per atomic (persistent mode)
     const char *name;
@@ -1294,6 +1498,7 @@ const Variant kVariants[] = {
     {32, 32, 4, 4, 1, "tile 32x32, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
     {32, 32, 5, 2, 1, "tile 32x32, persistent 2 wg/CU, double-buffered stage, planning wave two passes ahead"},
+    {32, 32, 6, 3, 1, "tile 32x32, persistent 3 wg/CU, register-staged loads, planning wave two passes ahead"},
     {32, 32, 1, 4, 1, "tile 32x32, persistent 4 wg/CU, chunks of 1"},
     {32, 32, 1, 4, 4, "tile 32x32, persistent 4 wg/CU, chunks of 4"},
     {32, 32, 1, 4, 8, "tile 32x32, persistent 4 wg/CU, chunks of 8"},
@@ -1301,6 +1506,8 @@ const Variant kVariants[] = {
     {16, 32, 4, 6, 1, "tile 16x32, persistent 6 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 2, 0, 1, "tile 32x32, flat grid"},
     {32, 32, 0, 2, 1, "tile 32x32, streaming pipeline 8+1 waves, 2 wg/CU"},
+    {16, 64, 4, 4, 1, "tile 16x64, persistent 4 wg/CU, 4 worker waves + a planning wave"},
+    {8, 128, 4, 4, 1, "tile 8x128, persistent 4 wg/CU, 4 worker waves + a planning wave"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1350,6 +1557,11 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
                            *a, L.counters);
         return hipGetLastError();
     }
+    if (v.mode == 6) {
+        hipLaunchKernelGGL((k_ragged_pipe7<TL, TS, full_cap<TL, TS, 41>()>), dim3(grid), dim3(kThreads + 64), 0, s,
+                           *a, L.counters);
+        return hipGetLastError();
+    }
     if (v.mode == 5) {
         hipLaunchKernelGGL((k_ragged_pipe6<TL, TS, full_cap<TL, TS, 26>()>), dim3(grid), dim3(kThreads + 64), 0, s,
                            *a, L.counters);
@@ -1358,6 +1570,23 @@ hipError_t launch_t(const miaug_ragged_args *a, const Variant &v, const RaggedLa
     if (v.chunk >= 8) return launch_chunked<TL, TS, 8>(a, grid, L.counters, s);
     if (v.chunk >= 4) return launch_chunked<TL, TS, 4>(a, grid, L.counters, s);
     return launch_chunked<TL, TS, 1>(a, grid, L.counters, s);
+}
+
+// Tile shapes that only the planning-wave form runs.
+template <int TL, int TS>
+hipError_t launch_pipe5_only(const miaug_ragged_args *a, const Variant &v, const RaggedLaunch &L, hipStream_t s) {
+    if (v.mode != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(256), 0, s, L.counters, kQueues * kCounterStride);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int tiles = tiles_per_image<TL, TS>(a->out_h, a->out_w);
+    int grid = L.num_cu * v.wg_per_cu;
+    const long items = (long)a->n * tiles;
+    if (grid > items) grid = (int)items;
+    grid = ((grid + kQueues - 1) / kQueues) * kQueues;
+    hipLaunchKernelGGL((k_ragged_pipe5<TL, TS, full_cap<TL, TS, 43>()>), dim3(grid), dim3(kThreads + 64), 0, s, *a,
+                       L.counters);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -1369,7 +1598,9 @@ int ragged_default_variant() { return 0; }
 hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s) {
     if (a->n == 0) return hipSuccess;
     const Variant &v = kVariants[(L.variant >= 0 && L.variant < kNumVariants) ? L.variant : 0];
-    if (v.tl == 32) return launch_t<32, 32>(a, v, L, per_image, s);
+    if (per_image || v.tl == 32) return launch_t<32, 32>(a, v, L, per_image, s);
+    if (v.ts == 64) return launch_pipe5_only<16, 64>(a, v, L, s);
+    if (v.ts == 128) return launch_pipe5_only<8, 128>(a, v, L, s);
     return launch_t<16, 32>(a, v, L, per_image, s);
 }
 
