@@ -428,8 +428,10 @@ def bench_table1(args, torch, m):
     def c2_rec(f5, k5, crop):
         return torch.from_numpy(m.compile_c2(np.asarray(f5, np.float32), np.asarray(k5, np.int32), S, S, crop)).cuda()
     ident_f = [[0.0, 1.0, 0.0, 0.0, 1.0]] * n
-    rec_hsv = c2_rec(ident_f, [[0, 0, int(rng.integers(-20, 21)), int(rng.integers(-30, 31)), 0] for _ in range(n)], S)
-    rec_gam = c2_rec([[0.0, 1.0, 0.0, 0.0, float(rng.uniform(0.8, 1.2))] for _ in range(n)], [[0, 0, 0, 0, 0]] * n, S)
+    dhsv = torch.tensor([[int(rng.integers(-20, 21)), int(rng.integers(-30, 31)), 0] for _ in range(n)],
+                        dtype=torch.int32, device="cuda")
+    luts_gam = torch.from_numpy(m.compile_gamma_luts(np.array([rng.uniform(0.8, 1.2) for _ in range(n)],
+                                                              np.float32))).cuda()
     rec_crop = c2_rec(ident_f, [[int(rng.integers(0, S - 63)), int(rng.integers(0, S - 63)), 0, 0, 0]
                                 for _ in range(n)], 64)
     out64 = torch.empty((n, 64, 64, 3), dtype=torch.uint8, device="cuda")
@@ -445,11 +447,9 @@ def bench_table1(args, torch, m):
         ("Rotate", lambda st: m.warp_affine_u8(img, aq_rot, 0, 0, out, st), 2 * px, "k_warp<3>"),
         ("ShiftScaleRotate", lambda st: m.warp_affine_u8(img, aq_ssr, 0, 0, out, st), 2 * px, "k_warp<3>"),
         ("Brightness", lambda st: m.d4_bc_u8(img, zero_fl, ab, out, st), 2 * px, "k_d4_bc<3>"),
-        ("ShiftHSV", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_hsv, S, S, out, st), 2 * px,
-         "k_c2 (identity warp and resize)"),
+        ("ShiftHSV", lambda st: m.hsv_shift_u8(img, dhsv, out, st), 2 * px, "k_hsv_u8"),
         ("ShiftRGB", lambda st: m.d4_lut_u8(img, zero_fl, luts_rgb, None, out, st), 2 * px, "k_d4_bc<3, LUTs>"),
-        ("Gamma", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_gam, S, S, out, st), 2 * px,
-         "k_c2 (identity warp and resize)"),
+        ("Gamma", lambda st: m.d4_lut_u8(img, zero_fl, luts_gam, None, out, st), 2 * px, "k_d4_bc<3, LUTs>"),
         ("Grayscale", lambda st: m.d4_lut_u8(img, zero_fl, luts_id, gray, out, st), 2 * px, "k_d4_bc<3, gray>"),
     ]
     rows = {}

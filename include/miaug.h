@@ -131,6 +131,22 @@ int miaug_d4_lut_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t
  * (ShiftRGB; shift host float [n][C], NULL: identity), in IEEE double. */
 int miaug_compile_color_luts(const float *ab, const float *shift, int n, int C, uint8_t *luts);
 
+/* Host: Gamma as a per-channel LUT for miaug_d4_lut_u8 (Table I Gamma):
+ * luts[i][c][v] = sat8(rint(255 (v / 255)^gamma_i)) in IEEE double, the same
+ * table as the gamma step of miaug_ssr_crop_resize_hsv_gamma_blur_u8, for
+ * every c < C.  gamma host float [n]; luts host u8 [n][C][256].  Errors:
+ * EINVAL bad arguments or a gamma that is not finite. */
+int miaug_compile_gamma_luts(const float *gamma, int n, int C, uint8_t *luts);
+
+/* ShiftHSV alone (Table I ShiftHSV): each RGB pixel goes through the integer
+ * hexcone HSV round trip of the u8 chain (step 4 of
+ * miaug_ssr_crop_resize_hsv_gamma_blur_u8) with hue, saturation and value
+ * shifts dhsv[i] = {dh, ds, dv} (dh in 2-degree units; dv is 0 in the chain).
+ * in device u8 [n][H][W][3]; dhsv device int32 [n][3]; out device u8
+ * [n][H][W][3] (may equal in).  Errors: EINVAL negative sizes or NULL
+ * pointers; ESHAPE images above 2^40 bytes. */
+int miaug_hsv_shift_u8(const uint8_t *in, int n, int H, int W, const int32_t *dhsv, uint8_t *out, void *stream);
+
 /* PadToSize (Table I PadToSize512): out_i has size max(H, min_h) x
  * max(W, min_w); the padding along an axis is split floor(d / 2) before and
  * the rest after; out[y][x] = in[y - top][x - left] inside, else the
@@ -435,7 +451,7 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  * pattern, onto one of the fused chains above (brackets: optional; the ops
  * must come in this order):
  *   MIAUG_PIPE_DIH4      [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [BRIGHT_CONTRAST]
- *                        [SHIFT_RGB] [TO_GRAY]
+ *                        [SHIFT_RGB] [GAMMA] [TO_GRAY]
  *                        dense u8 images (and masks, Dih4 only) -> u8,
  *                        miaug_d4_bc_u8 or, with colour ops, miaug_d4_lut_u8
  *   MIAUG_PIPE_RAGGED    [HFLIP] [VFLIP] [ROT90] [TRANSPOSE] [SIZED_CROP]
@@ -455,6 +471,9 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *   MIAUG_PIPE_PAD       PAD
  *                        dense u8 images (and masks, label 0) -> u8
  *                        [n][max(H, out_h)][max(W, out_w)][C], miaug_pad_u8
+ *   MIAUG_PIPE_HSV       HSV (alone)
+ *                        dense RGB u8 (masks copied unchanged) -> u8,
+ *                        miaug_hsv_shift_u8
  * Any other list is rejected with MIAUG_EUNSUPPORTED and a message naming
  * the first op that does not fit.
  *
@@ -516,7 +535,7 @@ enum { MIAUG_INTERP_BILINEAR = 0, MIAUG_INTERP_NEAREST = 1 };
 enum { MIAUG_BORDER_REFLECT101 = 0, MIAUG_BORDER_CONSTANT = 1 };
 enum {
     MIAUG_PIPE_DIH4 = 1, MIAUG_PIPE_RAGGED = 2, MIAUG_PIPE_U8CHAIN = 3, MIAUG_PIPE_DISTORT = 4, MIAUG_PIPE_WARP = 5,
-    MIAUG_PIPE_PAD = 6
+    MIAUG_PIPE_PAD = 6, MIAUG_PIPE_HSV = 7
 };
 
 typedef struct {

@@ -99,6 +99,8 @@ _SIGS = {
     "miaug_ragged_masks_u8": (_i, [ctypes.POINTER(RaggedArgs), _i, _vp, _vp]),
     "miaug_compile_color_luts": (_i, [_vp, _vp, _i, _i, _vp]),
     "miaug_pad_u8": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp, _vp]),
+    "miaug_compile_gamma_luts": (_i, [_vp, _i, _i, _vp]),
+    "miaug_hsv_shift_u8": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
     "miaug_warp_affine_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
     "miaug_compile_ssr_q32": (_i, [_vp, _i, _i, _i, _vp]),
     "miaug_boxes_ssr_crop_resize": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
@@ -328,6 +330,26 @@ def d4_lut_u8(img, flags, luts, gray=None, out=None, stream=None):
         out = torch.empty_like(img)
     _check(lib().miaug_d4_lut_u8(_p(img), n, H, W, C, _p(flags), _p(luts), None if gray is None else _p(gray),
                                  _p(out), _stream(stream)))
+    return out
+
+
+def compile_gamma_luts(gamma, C=3):
+    """Host u8 [n, C, 256]: the Gamma LUT of each image (gamma [n]) for every channel."""
+    g = np.ascontiguousarray(gamma, np.float32)
+    luts = np.zeros((len(g), C, 256), np.uint8)
+    _check(lib().miaug_compile_gamma_luts(g.ctypes.data, len(g), C, luts.ctypes.data))
+    return luts
+
+
+def hsv_shift_u8(img, dhsv, out=None, stream=None):
+    """img [n, H, W, 3] u8; dhsv [n, 3] int32 (dh, ds, dv), both on the device."""
+    _dev(img, torch.uint8, "img"); _dev(dhsv, torch.int32, "dhsv")
+    if img.dim() != 4 or img.shape[3] != 3:
+        raise MiaugError(ESHAPE, "hsv_shift_u8: img must be [n, H, W, 3]")
+    n, H, W = img.shape[:3]
+    if out is None:
+        out = torch.empty_like(img)
+    _check(lib().miaug_hsv_shift_u8(_p(img), n, H, W, _p(dhsv), _p(out), _stream(stream)))
     return out
 
 
@@ -607,7 +629,7 @@ def image_stats_u8(img, C=None, stream=None):
 OP = {"HFLIP": 1, "VFLIP": 2, "ROT90": 3, "TRANSPOSE": 4, "SSR": 5, "CROP": 6, "RESIZE": 7, "BRIGHT_CONTRAST": 8,
       "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15,
       "SIZED_CROP": 16, "SHIFT_RGB": 17, "TO_GRAY": 18, "PAD": 19, "ROTATE": 20}
-PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT", 5: "WARP", 6: "PAD"}
+PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT", 5: "WARP", 6: "PAD", 7: "HSV"}
 INTERP_BILINEAR, INTERP_NEAREST = 0, 1
 BORDER_REFLECT101, BORDER_CONSTANT = 0, 1
 

@@ -163,6 +163,15 @@ int miaug_pad_u8(const uint8_t *in, int n, int H, int W, int C, int min_h, int m
     return hip_status(launch_pad_u8(in, n, H, W, C, Ho, Wo, border, value, out, as_stream(stream)), "pad_u8 launch");
 }
 
+int miaug_hsv_shift_u8(const uint8_t *in, int n, int H, int W, const int32_t *dhsv, uint8_t *out, void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "hsv_shift_u8: negative size");
+    if ((long long)H * W * 3 > (1ll << 40)) return set_error(MIAUG_ESHAPE, "hsv_shift_u8: image too large");
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!in || !out || !dhsv) return set_error(MIAUG_EINVAL, "hsv_shift_u8: NULL pointer");
+    return hip_status(launch_hsv_u8(in, n, H, W, dhsv, out, as_stream(stream)), "hsv_shift_u8 launch");
+}
+
 int miaug_warp_affine_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
                          uint8_t *out, void *stream) {
     begin_call();

@@ -339,6 +339,48 @@ __global__ __launch_bounds__(64) void k_c2_boxes(const float *__restrict__ boxes
     }
 }
 
+// Standalone ShiftHSV (Table I): the chain's HSV step on a dense RGB batch.
+// A lane takes four pixels (12 bytes, three dwords) when every image's bytes
+// and the pointers are dword-aligned, else one pixel in bytes.
+__global__ __launch_bounds__(256) void k_hsv_u8(const uint8_t *__restrict__ in, int64_t npx,
+                                                const int32_t *__restrict__ dhsv, bool quads,
+                                                uint8_t *__restrict__ out) {
+    const int img = blockIdx.y;
+    const int dh = dhsv[3 * img], ds = dhsv[3 * img + 1], dv = dhsv[3 * img + 2];
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint8_t *src = in + (size_t)img * npx * 3;
+    uint8_t *dst = out + (size_t)img * npx * 3;
+    if (quads) {
+        if (4 * q + 3 < npx) {
+            const uint32_t *w = (const uint32_t *)(src + 12 * q);
+            const uint32_t w0 = w[0], w1 = w[1], w2 = w[2];
+            const uint32_t o0 = hsv_shift(w0 & 0xFFFFFFu, dh, ds, dv);
+            const uint32_t o1 = hsv_shift((w0 >> 24) | ((w1 & 0xFFFFu) << 8), dh, ds, dv);
+            const uint32_t o2 = hsv_shift((w1 >> 16) | ((w2 & 0xFFu) << 16), dh, ds, dv);
+            const uint32_t o3 = hsv_shift(w2 >> 8, dh, ds, dv);
+            uint32_t *o = (uint32_t *)(dst + 12 * q);
+            o[0] = o0 | (o1 << 24);
+            o[1] = (o1 >> 8) | (o2 << 16);
+            o[2] = (o2 >> 16) | (o3 << 8);
+            return;
+        }
+        for (int64_t p = 4 * q; p < npx && p < 4 * q + 4; ++p) {  // the tail of an image
+            const uint8_t *a = src + 3 * p;
+            const uint32_t o = hsv_shift(a[0] | (a[1] << 8) | (a[2] << 16), dh, ds, dv);
+            dst[3 * p] = o & 255;
+            dst[3 * p + 1] = (o >> 8) & 255;
+            dst[3 * p + 2] = o >> 16;
+        }
+        return;
+    }
+    if (q >= npx) return;
+    const uint8_t *a = src + 3 * q;
+    const uint32_t o = hsv_shift(a[0] | (a[1] << 8) | (a[2] << 16), dh, ds, dv);
+    dst[3 * q] = o & 255;
+    dst[3 * q + 1] = (o >> 8) & 255;
+    dst[3 * q + 2] = o >> 16;
+}
+
 }  // namespace
 
 hipError_t launch_c2_mask(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
@@ -361,6 +403,16 @@ hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_reco
     if (n == 0) return hipSuccess;
     const int t = (outsz + kT - 1) / kT;
     hipLaunchKernelGGL(k_c2, dim3(t * t, n), dim3(kThreads), 0, s, in, H, W, rec, crop, outsz, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hsv_u8(const uint8_t *in, int n, int H, int W, const int32_t *dhsv, uint8_t *out, hipStream_t s) {
+    if (n == 0 || H == 0 || W == 0) return hipSuccess;
+    const int64_t npx = (int64_t)H * W;
+    const bool quads = ((uintptr_t)in & 3) == 0 && ((uintptr_t)out & 3) == 0 && (npx & 3) == 0;
+    const int64_t lanes = quads ? (npx + 3) / 4 : npx;
+    dim3 grid((unsigned)((lanes + 255) / 256), n);
+    hipLaunchKernelGGL(k_hsv_u8, grid, dim3(256), 0, s, in, npx, dhsv, quads, out);
     return hipGetLastError();
 }
 

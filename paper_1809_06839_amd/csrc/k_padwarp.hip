@@ -1,8 +1,8 @@
 // k_padwarp.hip -- the remaining geometric rows of Table I as single ops on a
 // dense u8 batch: PadToSize (identity map plus a border) and a standalone
 // affine warp (Rotate; ShiftScaleRotate without crop or resize), both with a
-// reflect-101 or constant border.  One thread per output pixel: these ops
-// move C bytes per pixel and have no reuse to stage.
+// reflect-101 or constant border.  The pad is one thread per output pixel (no
+// reuse to stage); the warp stages each output tile's source box in LDS.
 #include "dev_common.h"
 #include "internal.h"
 
@@ -20,9 +20,14 @@ __device__ __forceinline__ int64_t reflect101_64(int64_t i, int64_t n) {
 }
 
 // Source index of a tap, or -1 for the constant border outside the image.
+// Indices within one reflection of the image take the reflection directly;
+// only farther ones need the period.
 __device__ __forceinline__ int64_t border_index(int64_t i, int n, int border) {
     if (i >= 0 && i < n) return i;
-    return border == MIAUG_BORDER_CONSTANT ? -1 : reflect101_64(i, n);
+    if (border == MIAUG_BORDER_CONSTANT) return -1;
+    if (n > 1 && i < 0 && i > -n) return -i;
+    if (n > 1 && i >= n && i < 2 * (int64_t)n - 1) return 2 * (int64_t)n - 2 - i;
+    return reflect101_64(i, n);
 }
 
 template <int C>
@@ -43,19 +48,26 @@ __global__ __launch_bounds__(kThreads) void k_pad(const uint8_t *__restrict__ in
 // Output (x, y) samples the source at the Q10 position rshr_he(A (x, y, 1), 22)
 // of the record's Q32 inverse matrix A: bilinear (weights (1024 - a, a), one
 // round-half-even of the 2^20-scaled sum) or nearest ((q + 512) >> 10).
+__device__ __forceinline__ void warp_pos(const int64_t *a, int x, int y, int64_t &qx, int64_t &qy) {
+    qx = rshr_he64(a[0] * x + a[1] * y + a[2], 32 - kFBits);
+    qy = rshr_he64(a[3] * x + a[4] * y + a[5], 32 - kFBits);
+}
+
+// Bilinear value of one channel from four taps (the blend of the u8 chain).
+__device__ __forceinline__ uint8_t blend4(int v00, int v01, int v10, int v11, int ax, int ay) {
+    const int t0 = (v00 << kFBits) + ax * (v01 - v00);
+    const int t1 = (v10 << kFBits) + ax * (v11 - v10);
+    const int acc = (t0 << kFBits) + ay * (t1 - t0);
+    return (uint8_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20);
+}
+
+// One output pixel straight from global memory (tiles whose source box does
+// not fit the stage).
 template <int C>
-__global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ in, int H, int W,
-                                                   const int64_t *__restrict__ aq, int interp, int border,
-                                                   uint8_t *__restrict__ out) {
-    const int img = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= (int64_t)H * W) return;
-    const int y = (int)(e / W), x = (int)(e - (int64_t)y * W);
-    const int64_t *a = aq + 6 * img;
-    const int64_t qx = rshr_he64(a[0] * x + a[1] * y + a[2], 32 - kFBits);
-    const int64_t qy = rshr_he64(a[3] * x + a[4] * y + a[5], 32 - kFBits);
-    const uint8_t *src = in + (size_t)img * H * W * C;
-    uint8_t *o = out + (size_t)img * H * W * C + (size_t)e * C;
+__device__ __forceinline__ void warp_px_direct(const uint8_t *src, int H, int W, const int64_t *a, int interp,
+                                               int border, int x, int y, uint8_t *o) {
+    int64_t qx, qy;
+    warp_pos(a, x, y, qx, qy);
     if (interp == MIAUG_INTERP_NEAREST) {
         const int64_t sy = border_index((qy + kFOne / 2) >> kFBits, H, border);
         const int64_t sx = border_index((qx + kFOne / 2) >> kFBits, W, border);
@@ -75,10 +87,115 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
 #pragma unroll
             for (int i = 0; i < 2; ++i)
                 v[j][i] = (ys[j] < 0 || xs[i] < 0) ? 0 : src[((size_t)ys[j] * W + xs[i]) * C + c];
-        const int t0 = (v[0][0] << kFBits) + ax * (v[0][1] - v[0][0]);
-        const int t1 = (v[1][0] << kFBits) + ax * (v[1][1] - v[1][0]);
-        const int acc = (t0 << kFBits) + ay * (t1 - t0);
-        o[c] = (uint8_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20);
+        o[c] = blend4(v[0][0], v[0][1], v[1][0], v[1][1], ax, ay);
+    }
+}
+
+constexpr int kWarpTile = 32;            // output tile side
+constexpr int kWarpStage = 16 * 1024;    // bytes of staged source box per workgroup
+
+// floor(e / d) for 0 <= e < 2^20, 1 <= d < 2^12, from a float estimate and
+// one correction each way.
+__device__ __forceinline__ int small_div(int e, int d, float rd) {
+    int q = (int)((float)e * rd);
+    if (q * d > e) --q;
+    else if ((q + 1) * d <= e) ++q;
+    return q;
+}
+
+// One workgroup per 32 x 32 output tile.  The affine map is monotone along
+// every line, so every tap of the tile lies in the box spanned by the Q10
+// positions of its four corners (floor, plus one for the second bilinear tap);
+// that box is staged in LDS with the border rule applied per staged pixel
+// (reflect-101 index or the constant 0), and the taps read LDS in the box's
+// own coordinates.  A box larger than the stage (a strong zoom-out) takes the
+// direct path.
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ in, int H, int W,
+                                                   const int64_t *__restrict__ aq, int interp, int border,
+                                                   uint8_t *__restrict__ out) {
+    __shared__ uint8_t box[kWarpStage];
+    __shared__ __align__(4) uint8_t obuf[kWarpTile * kWarpTile * C];
+    const int img = blockIdx.y;
+    const int ntx = (W + kWarpTile - 1) / kWarpTile;
+    const int tx0 = (int)(blockIdx.x % ntx) * kWarpTile, ty0 = (int)(blockIdx.x / ntx) * kWarpTile;
+    const int tw = min(kWarpTile, W - tx0), th = min(kWarpTile, H - ty0);
+    int64_t a[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = aq[6 * img + k];
+    const uint8_t *src = in + (size_t)img * H * W * C;
+    uint8_t *dst = out + (size_t)img * H * W * C;
+    // source box of the tile's taps
+    int64_t qx[4], qy[4];
+    warp_pos(a, tx0, ty0, qx[0], qy[0]);
+    warp_pos(a, tx0 + tw - 1, ty0, qx[1], qy[1]);
+    warp_pos(a, tx0, ty0 + th - 1, qx[2], qy[2]);
+    warp_pos(a, tx0 + tw - 1, ty0 + th - 1, qx[3], qy[3]);
+    int64_t xlo = qx[0], xhi = qx[0], ylo = qy[0], yhi = qy[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        xlo = min(xlo, qx[k]); xhi = max(xhi, qx[k]);
+        ylo = min(ylo, qy[k]); yhi = max(yhi, qy[k]);
+    }
+    const int64_t bx0 = xlo >> kFBits, by0 = ylo >> kFBits;
+    const int64_t bw64 = (xhi >> kFBits) + 2 - bx0, bh64 = (yhi >> kFBits) + 2 - by0;
+    if (bw64 > kWarpStage || bh64 > kWarpStage || bw64 * bh64 * C > kWarpStage) {  // sides first: no overflow
+        for (int p = threadIdx.x; p < tw * th; p += kThreads) {
+            const int y = ty0 + p / tw, x = tx0 + p % tw;
+            warp_px_direct<C>(src, H, W, a, interp, border, x, y, dst + ((size_t)y * W + x) * C);
+        }
+        return;
+    }
+    const int bw = (int)bw64, bh = (int)bh64;
+    const float rbw = 1.0f / (float)bw;
+    for (int e = threadIdx.x; e < bw * bh; e += kThreads) {
+        const int r = small_div(e, bw, rbw), c = e - r * bw;
+        const int64_t sy = border_index(by0 + r, H, border), sx = border_index(bx0 + c, W, border);
+        const uint8_t *p = src + ((size_t)sy * W + sx) * C;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) box[e * C + ch] = (sy < 0 || sx < 0) ? 0 : p[ch];
+    }
+    __syncthreads();
+    // lane (lx, ly0) takes pixels (lx, ly0 + 8 k): the Q32 sums step by 8 a1 / 8 a4
+    constexpr int kRows = kThreads / kWarpTile;
+    const int lx = threadIdx.x % kWarpTile, ly0 = threadIdx.x / kWarpTile;
+    int64_t sxq = a[0] * (tx0 + lx) + a[1] * (ty0 + ly0) + a[2];
+    int64_t syq = a[3] * (tx0 + lx) + a[4] * (ty0 + ly0) + a[5];
+    const int64_t dx = a[1] * kRows, dy = a[4] * kRows;
+#pragma unroll
+    for (int k = 0; k < kWarpTile / kRows; ++k, sxq += dx, syq += dy) {
+        const int ly = ly0 + kRows * k;
+        if (ly >= th || lx >= tw) continue;  // outside the image: taps outside the box; never copied out
+        uint8_t *o = obuf + (ly * kWarpTile + lx) * C;
+        const int64_t px = rshr_he64(sxq, 32 - kFBits), py = rshr_he64(syq, 32 - kFBits);
+        if (interp == MIAUG_INTERP_NEAREST) {
+            const int sx = (int)(((px + kFOne / 2) >> kFBits) - bx0), sy = (int)(((py + kFOne / 2) >> kFBits) - by0);
+            const uint8_t *b = box + (sy * bw + sx) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) o[c] = b[c];
+            continue;
+        }
+        const int sx = (int)((px >> kFBits) - bx0), sy = (int)((py >> kFBits) - by0);
+        const int ax = (int)(px & (kFOne - 1)), ay = (int)(py & (kFOne - 1));
+        const uint8_t *b0 = box + (sy * bw + sx) * C, *b1 = b0 + bw * C;
+#pragma unroll
+        for (int c = 0; c < C; ++c) o[c] = blend4(b0[c], b0[C + c], b1[c], b1[C + c], ax, ay);
+    }
+    __syncthreads();
+    // the tile's rows out of LDS: dwords when rows are 4-byte aligned, else bytes
+    const int rb = tw * C;
+    if ((((uintptr_t)dst + ((size_t)ty0 * W + tx0) * C) & 3) == 0 && ((W * C) & 3) == 0 && (rb & 3) == 0) {
+        const int nd = rb / 4;
+        for (int e = threadIdx.x; e < nd * th; e += kThreads) {
+            const int r = e / nd, d = e - r * nd;
+            *(uint32_t *)(dst + ((size_t)(ty0 + r) * W + tx0) * C + 4 * d) =
+                *(const uint32_t *)(obuf + r * kWarpTile * C + 4 * d);
+        }
+    } else {
+        for (int e = threadIdx.x; e < rb * th; e += kThreads) {
+            const int r = e / rb, d = e - r * rb;
+            dst[((size_t)(ty0 + r) * W + tx0) * C + d] = obuf[r * kWarpTile * C + d];
+        }
     }
 }
 
@@ -98,7 +215,7 @@ hipError_t launch_pad_u8(const uint8_t *in, int n, int H, int W, int C, int Ho, 
 hipError_t launch_warp_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
                           uint8_t *out, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    dim3 grid((unsigned)(((int64_t)H * W + kThreads - 1) / kThreads), n);
+    dim3 grid((unsigned)(((W + kWarpTile - 1) / kWarpTile) * ((H + kWarpTile - 1) / kWarpTile)), n);
     if (C == 1) hipLaunchKernelGGL(k_warp<1>, grid, dim3(kThreads), 0, s, in, H, W, aq, interp, border, out);
     else if (C == 3) hipLaunchKernelGGL(k_warp<3>, grid, dim3(kThreads), 0, s, in, H, W, aq, interp, border, out);
     else hipLaunchKernelGGL(k_warp<4>, grid, dim3(kThreads), 0, s, in, H, W, aq, interp, border, out);

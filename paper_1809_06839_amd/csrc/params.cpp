@@ -1,6 +1,7 @@
 // params.cpp -- host-side parameter compile (per-sample records -> integer
 // records the kernels consume).  Transcendental functions run here, once per
 // image in IEEE double, so every kernel is integer-only and reproducible.
+#include <cmath>
 #include <math.h>
 
 #include "internal.h"
@@ -56,6 +57,22 @@ extern "C" int miaug_compile_color_luts(const float *ab, const float *shift, int
                 }
                 luts[((size_t)i * C + c) * 256 + v] = (uint8_t)u;
             }
+    return MIAUG_OK;
+}
+
+extern "C" int miaug_compile_gamma_luts(const float *gamma, int n, int C, uint8_t *luts) {
+    if (n < 0 || (n > 0 && (!gamma || !luts)) || C < 1 || C > 4)
+        return set_error(MIAUG_EINVAL, "compile_gamma_luts: bad arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(gamma[i])) return set_error(MIAUG_EINVAL, "compile_gamma_luts: gamma %d not finite", i);
+        const double g = (double)gamma[i];
+        for (int v = 0; v < 256; ++v) {
+            // the same LUT as the u8 chain's gamma step
+            const double e = rint(255.0 * pow(v / 255.0, g));
+            const uint8_t u = (uint8_t)(e < 0 ? 0 : (e > 255 ? 255 : e));
+            for (int c = 0; c < C; ++c) luts[((size_t)i * C + c) * 256 + v] = u;
+        }
+    }
     return MIAUG_OK;
 }
 

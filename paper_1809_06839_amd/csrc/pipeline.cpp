@@ -99,7 +99,7 @@ const char *op_name(uint32_t k) {
 
 // Allowed op sequences per chain (each op at most once, in this order).
 const uint32_t kSeqDih4[] = {MIAUG_OP_HFLIP,           MIAUG_OP_VFLIP,     MIAUG_OP_ROT90, MIAUG_OP_TRANSPOSE,
-                             MIAUG_OP_BRIGHT_CONTRAST, MIAUG_OP_SHIFT_RGB, MIAUG_OP_TO_GRAY};
+                             MIAUG_OP_BRIGHT_CONTRAST, MIAUG_OP_SHIFT_RGB, MIAUG_OP_GAMMA, MIAUG_OP_TO_GRAY};
 const uint32_t kSeqRagged[] = {MIAUG_OP_HFLIP,      MIAUG_OP_VFLIP,           MIAUG_OP_ROT90,
                                MIAUG_OP_TRANSPOSE,  MIAUG_OP_SIZED_CROP,      MIAUG_OP_BRIGHT_CONTRAST,
                                MIAUG_OP_RESIZE,     MIAUG_OP_NORMALIZE};
@@ -108,6 +108,7 @@ const uint32_t kSeqDistort[] = {MIAUG_OP_ELASTIC, MIAUG_OP_GRID};
 const uint32_t kSeqRotate[] = {MIAUG_OP_ROTATE};
 const uint32_t kSeqSsr[] = {MIAUG_OP_SSR};
 const uint32_t kSeqPad[] = {MIAUG_OP_PAD};
+const uint32_t kSeqHsv[] = {MIAUG_OP_HSV};
 
 // Index of the first op of `ops` that breaks the order of `seq` (n if none).
 int match_order(const miaug_op *ops, int n, const uint32_t *seq, int nseq) {
@@ -273,6 +274,7 @@ int grow_device(void **ptr, size_t *cap, size_t bytes, const char *what) {
 //   DISTORT:      double grid [n][10]
 //   WARP:         int64 Q32 matrices [n][6]
 //   PAD:          nothing (8 bytes of padding)
+//   HSV:          int32 shifts [n][3] (dh, ds, dv)
 size_t packed_bytes(const miaug_pipeline *p, int n, int C) {
     switch (p->kind) {
     case MIAUG_PIPE_DIH4: return (size_t)n * 32 + (p->color ? (size_t)n * (256 * C + 4) : 0);
@@ -280,12 +282,22 @@ size_t packed_bytes(const miaug_pipeline *p, int n, int C) {
     case MIAUG_PIPE_U8CHAIN: return (size_t)n * sizeof(miaug_c2_record);
     case MIAUG_PIPE_WARP: return (size_t)n * 48;
     case MIAUG_PIPE_PAD: return 8;
+    case MIAUG_PIPE_HSV: return (size_t)n * 12;
     default: return (size_t)n * 10 * sizeof(double);
     }
 }
 
 int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, int C, void *dst) {
     if (p->kind == MIAUG_PIPE_PAD) return MIAUG_OK;
+    if (p->kind == MIAUG_PIPE_HSV) {
+        int32_t *d = (int32_t *)dst;
+        for (int i = 0; i < n; ++i) {
+            d[3 * i] = r[i].dh;
+            d[3 * i + 1] = r[i].ds;
+            d[3 * i + 2] = r[i].dv;
+        }
+        return MIAUG_OK;
+    }
     if (p->kind == MIAUG_PIPE_WARP) {
         std::vector<float> f(4 * (size_t)n);
         for (int i = 0; i < n; ++i) {
@@ -321,6 +333,16 @@ int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, in
             }
             int st = miaug_compile_color_luts(ab, sh.data(), n, C, luts);
             if (st) return st;
+            if (has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_GAMMA)) {
+                // gamma after brightness/contrast and ShiftRGB, each step rounded to u8
+                uint8_t g[256];
+                for (int i = 0; i < n; ++i) {
+                    const float gi = r[i].gamma;
+                    if ((st = miaug_compile_gamma_luts(&gi, 1, 1, g))) return st;
+                    uint8_t *l = luts + (size_t)i * C * 256;
+                    for (int e = 0; e < C * 256; ++e) l[e] = g[l[e]];
+                }
+            }
         }
         if (p->wcrop) {
             int32_t *win = (int32_t *)((char *)dst + (size_t)n * 24);
@@ -381,6 +403,7 @@ int batch_check(const miaug_pipeline *p, const miaug_batch_in *in, const miaug_b
     if (p->kind == MIAUG_PIPE_DIH4 && p->color && has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_TO_GRAY) &&
         in->channels != 3)
         return set_error(MIAUG_ESHAPE, "apply: TO_GRAY takes RGB images");
+    if (p->kind == MIAUG_PIPE_HSV && in->channels != 3) return set_error(MIAUG_ESHAPE, "apply: HSV takes RGB images");
     if (in->boxes && p->kind != MIAUG_PIPE_U8CHAIN && p->kind != MIAUG_PIPE_DISTORT)
         return set_error(MIAUG_EUNSUPPORTED, "apply: boxes are supported by the ragged, u8 and distortion chains only");
     if (in->boxes && (!in->box_off || !out->boxes)) return set_error(MIAUG_EINVAL, "apply: boxes without offsets/output");
@@ -484,6 +507,19 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
         if (!st && in->boxes)
             st = miaug_boxes_ssr_crop_resize(in->boxes, in->box_off, n, in->H, in->W, rec, p->crop_h, p->out_h,
                                              out->boxes, s);
+        return st;
+    }
+    if (p->kind == MIAUG_PIPE_HSV) {
+        const size_t isz = (size_t)in->H * in->W * 3, msz = (size_t)in->H * in->W;
+        const int32_t *d = (const int32_t *)dp;
+        int st = MIAUG_OK;
+        for (int i0 = 0; i0 < n && !st; i0 += per_image ? 1 : n)
+            st = miaug_hsv_shift_u8(in->img + i0 * isz, per_image ? 1 : n, in->H, in->W, d + 3 * i0,
+                                    (uint8_t *)out->img + i0 * isz, s);
+        // masks: a point op leaves them as they are
+        if (!st && in->mask && out->mask != in->mask)
+            st = hip_status(hipMemcpyAsync(out->mask, in->mask, (size_t)n * msz, hipMemcpyDeviceToDevice,
+                                           (hipStream_t)s), "apply: mask copy");
         return st;
     }
     if (p->kind == MIAUG_PIPE_WARP || p->kind == MIAUG_PIPE_PAD) {
@@ -618,10 +654,10 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
         int kind;
         const uint32_t *seq;
         int nseq;
-    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 7},     {MIAUG_PIPE_RAGGED, kSeqRagged, 8},
+    } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 8},     {MIAUG_PIPE_RAGGED, kSeqRagged, 8},
                  {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},    {MIAUG_PIPE_DISTORT, kSeqDistort, 2},
                  {MIAUG_PIPE_WARP, kSeqRotate, 1},   {MIAUG_PIPE_WARP, kSeqSsr, 1},
-                 {MIAUG_PIPE_PAD, kSeqPad, 1}};
+                 {MIAUG_PIPE_PAD, kSeqPad, 1},       {MIAUG_PIPE_HSV, kSeqHsv, 1}};
     int kind = 0, worst = -1;
     for (const Cand &c : cands) {
         const int at = match_order(ops, n_ops, c.seq, c.nseq);
@@ -669,7 +705,8 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     p->chan = 3;
     for (const miaug_op &o : p->ops) {
         if (o.kind == MIAUG_OP_SIZED_CROP) p->wcrop = true;
-        if (o.kind == MIAUG_OP_SHIFT_RGB || o.kind == MIAUG_OP_TO_GRAY) p->color = true;
+        if (o.kind == MIAUG_OP_SHIFT_RGB || o.kind == MIAUG_OP_TO_GRAY || (o.kind == MIAUG_OP_GAMMA && kind == MIAUG_PIPE_DIH4))
+            p->color = true;
         if (o.kind == MIAUG_OP_ROTATE || o.kind == MIAUG_OP_PAD || (o.kind == MIAUG_OP_SSR && kind == MIAUG_PIPE_WARP)) {
             p->interp = (int)o.interp;
             p->border = (int)o.border;

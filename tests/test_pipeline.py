@@ -50,7 +50,7 @@ def test_op_lists_map_onto_their_chains():
     ([op("RESIZE", out=(8, 8)), op("HFLIP")], m.MiaugError),            # order
     ([op("HFLIP"), op("HFLIP")], m.MiaugError),                          # repeated op
     ([op("BLUR5")], m.MiaugError),                                       # no chain takes it
-    ([op("HSV", 1, (-20, -30), (20, 30))], m.MiaugError),                # u8 chain without crop/resize
+    ([op("HSV", 1, (-20, -30), (20, 30)), op("BLUR3", 0.3)], m.MiaugError),  # u8 chain without crop/resize
     ([op("HFLIP", 1.5)], m.MiaugError),                                  # p outside [0, 1]
     ([op("ROT90", 1, (0,), (4,))], m.MiaugError),                        # k outside 0..3
     ([op("SSR", 1, (0, 1, 0, 0), (0, 1, 0, 0), border=1), op("CROP", out=(4, 4)), op("RESIZE", out=(4, 4))],
@@ -407,6 +407,17 @@ def test_table1_op_lists_map_onto_their_chains():
         m.Pipeline(None, [op("TO_GRAY"), op("SHIFT_RGB")])  # order
     with pytest.raises(m.MiaugError):
         m.Pipeline(None, [op("PAD", 0.5, out=(8, 8))])      # PAD has p = 1
+    # Gamma as a LUT step of the Dih4 chain; ShiftHSV alone
+    assert kind_of([op("GAMMA", 1, (0.8,), (1.2,))]) == "DIH4"
+    assert kind_of([op("HFLIP", 0.5), op("BRIGHT_CONTRAST", 1, (0.8, -51), (1.2, 51)), op("SHIFT_RGB", 0.5, (-9,) * 3,
+                    (9,) * 3), op("GAMMA", 0.5, (0.8,), (1.2,)), op("TO_GRAY", 0.3)]) == "DIH4"
+    assert kind_of([op("HSV", 1, (-20, -30, 0), (20, 30, 0))]) == "HSV"
+    assert kind_of([op("CROP", out=(64, 64)), op("RESIZE", out=(64, 64)), op("HSV", 1, (-20, -30, 0), (20, 30, 0)),
+                    op("GAMMA", 1, (0.8,), (1.2,))]) == "U8CHAIN"
+    with pytest.raises(m.MiaugError):
+        m.Pipeline(None, [op("TO_GRAY"), op("GAMMA", 1, (0.8,), (1.2,))])  # order
+    with pytest.raises(m.MiaugError):
+        m.Pipeline(None, [op("HSV", 1, (-20, -30, 0), (20, 30, 0)), op("GAMMA", 1, (0.8,), (1.2,))])
 
 
 def test_table1_sampler_draws():
@@ -455,6 +466,59 @@ def test_color_chain_pipeline_matches_the_oracle(ctx):
             y = oracle.gray(y)
         assert np.array_equal(got[i], y.reshape(-1)), i
         assert np.array_equal(gm[i], oracle.d4(masks[i], *fl).reshape(-1)), i
+    out2 = torch.empty_like(out)
+    bo.img = out2.data_ptr()
+    p.apply(bi, bo, recs, per_image=True)
+    assert torch.equal(out, out2)
+
+
+@pytest.mark.gpu
+def test_gamma_in_the_color_chain_matches_the_oracle(ctx):
+    import torch
+    n, H, W = 6, 41, 29
+    rng = np.random.default_rng(21)
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    p = m.Pipeline(ctx, [op("VFLIP", 0.5), op("BRIGHT_CONTRAST", 0.8, (0.8, -51), (1.2, 51)),
+                         op("SHIFT_RGB", 0.7, (-20, -20, -20), (20, 20, 20)), op("GAMMA", 0.8, (0.7,), (1.4,)),
+                         op("TO_GRAY", 0.4)])
+    recs = p.sample(22, 0, n)
+    x = torch.from_numpy(imgs).cuda()
+    out = torch.empty_like(x)
+    bi, bo, _ = p.batch(img=x)
+    bo.img = out.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(n, -1)
+    for i in range(n):
+        r = recs[i]
+        y = oracle.apply_lut(oracle.d4(imgs[i], *[r.flags[k] for k in range(4)]), oracle.bc_lut(r.alpha, r.beta))
+        y = oracle.apply_lut_c(y, oracle.shift_rgb_lut(list(r.shift)))
+        y = oracle.apply_lut(y, oracle.gamma_lut(r.gamma))
+        if r.gray:
+            y = oracle.gray(y)
+        assert np.array_equal(got[i], y.reshape(-1)), i
+
+
+@pytest.mark.gpu
+def test_hsv_pipeline_matches_the_oracle(ctx):
+    import torch
+    n, H, W = 5, 33, 48
+    rng = np.random.default_rng(23)
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    masks = rng.integers(0, 9, (n, H, W), dtype=np.uint8)
+    p = m.Pipeline(ctx, [op("HSV", 0.7, (-20, -30, -10), (20, 30, 10))])
+    recs = p.sample(24, 0, n)
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    out, om = torch.empty_like(x), torch.empty_like(xm)
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i in range(n):
+        r = recs[i]
+        assert np.array_equal(got[i], oracle.hsv_shift(imgs[i], r.dh, r.ds, r.dv)), i
+    assert np.array_equal(om.cpu().numpy(), masks)
     out2 = torch.empty_like(out)
     bo.img = out2.data_ptr()
     p.apply(bi, bo, recs, per_image=True)
