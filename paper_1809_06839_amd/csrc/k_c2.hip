@@ -61,16 +61,35 @@ __device__ __forceinline__ uint32_t warp_sample(const uint8_t *img, int H, int W
     return out;
 }
 
+// n / d rounded to nearest, ties to even, for n < 2^16 and 1 <= d <= 255: a
+// float estimate (relative error below 2^-22, so at most one off) and one
+// correction each way give the exact floor and remainder.
+__device__ __forceinline__ uint32_t udiv_he_small(uint32_t n, uint32_t d) {
+    uint32_t q = (uint32_t)((float)n * __builtin_amdgcn_rcpf((float)d));
+    int r = (int)n - (int)(q * d);
+    if (r < 0) {
+        --q;
+        r += (int)d;
+    } else if (r >= (int)d) {
+        ++q;
+        r -= (int)d;
+    }
+    return q + ((2 * r > (int)d) | ((2 * r == (int)d) & (q & 1)));
+}
+
 // Integer hexcone HSV shift of one RGB pixel (packed R | G<<8 | B<<16).
+// The hue's signed quotient t / C with |t| <= 30 C is taken as
+// (t + 30 C) / C - 30: shifting by the even integer 30 keeps the
+// ties-to-even rounding.
 __device__ __forceinline__ uint32_t hsv_shift(uint32_t rgb, int dh, int ds, int dv) {
     const int R = rgb & 255, G = (rgb >> 8) & 255, B = (rgb >> 16) & 255;
     const int V = max(R, max(G, B)), m = min(R, min(G, B)), C = V - m;
-    const int S8 = V ? (int)udiv_he(255u * (uint32_t)C, (uint32_t)V) : 0;
+    const int S8 = V ? (int)udiv_he_small(255u * (uint32_t)C, (uint32_t)V) : 0;
     int h = 0;
     if (C != 0) {
-        if (V == R) h = sdiv_he(30 * (G - B), C);
-        else if (V == G) h = 60 + sdiv_he(30 * (B - R), C);
-        else h = 120 + sdiv_he(30 * (R - G), C);
+        const int t = V == R ? G - B : (V == G ? B - R : R - G);
+        const int base = V == R ? 0 : (V == G ? 60 : 120);
+        h = base + (int)udiv_he_small((uint32_t)(30 * t + 30 * C), (uint32_t)C) - 30;
     }
     int H8 = h % 180;
     if (H8 < 0) H8 += 180;
