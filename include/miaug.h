@@ -138,6 +138,16 @@ int miaug_compile_color_luts(const float *ab, const float *shift, int n, int C, 
  * EINVAL bad arguments or a gamma that is not finite. */
 int miaug_compile_gamma_luts(const float *gamma, int n, int C, uint8_t *luts);
 
+/* Binomial blur: out = rdiv_he(sum_ij k_i k_j in[y + j - r][x + i - r], N)
+ * per channel with k = [1, 2, 1], N = 16 (ksize 3, r = 1) or
+ * k = [1, 4, 6, 4, 1], N = 256 (ksize 5, r = 2), reflect-101 border (the
+ * blur step of the u8 chain is the 3x3 case).  apply device int32 [n]
+ * (0: image copied unchanged) or NULL (every image blurred).  in, out device
+ * u8 [n][H][W][C], not overlapping.  Errors: EINVAL bad size, ksize, NULL
+ * pointer or overlap; ESHAPE C or sides above 65535. */
+int miaug_blur_u8(const uint8_t *in, int n, int H, int W, int C, int ksize, const int32_t *apply, uint8_t *out,
+                  void *stream);
+
 /* ShiftHSV alone (Table I ShiftHSV): each RGB pixel goes through the integer
  * hexcone HSV round trip of the u8 chain (step 4 of
  * miaug_ssr_crop_resize_hsv_gamma_blur_u8) with hue, saturation and value
@@ -474,6 +484,9 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *   MIAUG_PIPE_HSV       HSV (alone)
  *                        dense RGB u8 (masks copied unchanged) -> u8,
  *                        miaug_hsv_shift_u8
+ *   MIAUG_PIPE_BLUR      BLUR3 | BLUR5 (alone)
+ *                        dense u8 images (masks copied unchanged) -> u8,
+ *                        miaug_blur_u8
  * Any other list is rejected with MIAUG_EUNSUPPORTED and a message naming
  * the first op that does not fit.
  *
@@ -514,7 +527,7 @@ int miaug_image_stats_u8(const uint8_t *img, int n, int64_t npix, int C, uint64_
  *   HSV               p; dh = rint(U[lo[0], hi[0]]) (2-degree units),
  *                     ds = rint(U[lo[1], hi[1]]), dv = rint(U[lo[2], hi[2]]).
  *   GAMMA             p; gamma in [lo[0], hi[0]]; skipped: 1.
- *   BLUR3             p (3x3 binomial).
+ *   BLUR3, BLUR5      p (3x3 / 5x5 binomial).
  *   ELASTIC           alpha = lo[0] (pixels, integer 0..65535), sigma = lo[1],
  *                     radius = lo[2] (0: ceil(3 sigma), at most 200); p must be 1;
  *                     hi[0] != 0 selects the box-cascade approximation
@@ -535,7 +548,7 @@ enum { MIAUG_INTERP_BILINEAR = 0, MIAUG_INTERP_NEAREST = 1 };
 enum { MIAUG_BORDER_REFLECT101 = 0, MIAUG_BORDER_CONSTANT = 1 };
 enum {
     MIAUG_PIPE_DIH4 = 1, MIAUG_PIPE_RAGGED = 2, MIAUG_PIPE_U8CHAIN = 3, MIAUG_PIPE_DISTORT = 4, MIAUG_PIPE_WARP = 5,
-    MIAUG_PIPE_PAD = 6, MIAUG_PIPE_HSV = 7
+    MIAUG_PIPE_PAD = 6, MIAUG_PIPE_HSV = 7, MIAUG_PIPE_BLUR = 8
 };
 
 typedef struct {

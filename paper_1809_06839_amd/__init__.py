@@ -101,6 +101,7 @@ _SIGS = {
     "miaug_pad_u8": (_i, [_vp, _i, _i, _i, _i, _i, _i, _i, _i, _vp, _vp]),
     "miaug_compile_gamma_luts": (_i, [_vp, _i, _i, _vp]),
     "miaug_hsv_shift_u8": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp]),
+    "miaug_blur_u8": (_i, [_vp, _i, _i, _i, _i, _i, _vp, _vp, _vp]),
     "miaug_warp_affine_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
     "miaug_compile_ssr_q32": (_i, [_vp, _i, _i, _i, _vp]),
     "miaug_boxes_ssr_crop_resize": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
@@ -339,6 +340,20 @@ def compile_gamma_luts(gamma, C=3):
     luts = np.zeros((len(g), C, 256), np.uint8)
     _check(lib().miaug_compile_gamma_luts(g.ctypes.data, len(g), C, luts.ctypes.data))
     return luts
+
+
+def blur_u8(img, ksize=3, apply=None, out=None, stream=None):
+    """img [n, H, W(, C)] u8; ksize 3 or 5; apply [n] int32 (device) or None (every image)."""
+    _dev(img, torch.uint8, "img")
+    if apply is not None:
+        _dev(apply, torch.int32, "apply")
+    n, H, W = img.shape[:3]
+    C = img.shape[3] if img.dim() == 4 else 1
+    if out is None:
+        out = torch.empty_like(img)
+    _check(lib().miaug_blur_u8(_p(img), n, H, W, C, ksize, None if apply is None else _p(apply), _p(out),
+                               _stream(stream)))
+    return out
 
 
 def hsv_shift_u8(img, dhsv, out=None, stream=None):
@@ -629,7 +644,7 @@ def image_stats_u8(img, C=None, stream=None):
 OP = {"HFLIP": 1, "VFLIP": 2, "ROT90": 3, "TRANSPOSE": 4, "SSR": 5, "CROP": 6, "RESIZE": 7, "BRIGHT_CONTRAST": 8,
       "HSV": 9, "GAMMA": 10, "BLUR3": 11, "BLUR5": 12, "ELASTIC": 13, "GRID": 14, "NORMALIZE": 15,
       "SIZED_CROP": 16, "SHIFT_RGB": 17, "TO_GRAY": 18, "PAD": 19, "ROTATE": 20}
-PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT", 5: "WARP", 6: "PAD", 7: "HSV"}
+PIPE = {1: "DIH4", 2: "RAGGED", 3: "U8CHAIN", 4: "DISTORT", 5: "WARP", 6: "PAD", 7: "HSV", 8: "BLUR"}
 INTERP_BILINEAR, INTERP_NEAREST = 0, 1
 BORDER_REFLECT101, BORDER_CONSTANT = 0, 1
 

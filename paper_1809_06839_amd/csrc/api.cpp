@@ -163,6 +163,21 @@ int miaug_pad_u8(const uint8_t *in, int n, int H, int W, int C, int min_h, int m
     return hip_status(launch_pad_u8(in, n, H, W, C, Ho, Wo, border, value, out, as_stream(stream)), "pad_u8 launch");
 }
 
+int miaug_blur_u8(const uint8_t *in, int n, int H, int W, int C, int ksize, const int32_t *apply, uint8_t *out,
+                  void *stream) {
+    begin_call();
+    if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "blur_u8: negative size");
+    if (C != 1 && C != 3 && C != 4) return set_error(MIAUG_ESHAPE, "blur_u8: C=%d (1, 3 or 4)", C);
+    if (ksize != 3 && ksize != 5) return set_error(MIAUG_EINVAL, "blur_u8: ksize %d (3 or 5)", ksize);
+    if (H > 65535 || W > 65535) return set_error(MIAUG_ESHAPE, "blur_u8: %dx%d image too large", H, W);
+    if (n == 0 || H == 0 || W == 0) return MIAUG_OK;
+    if (!in || !out) return set_error(MIAUG_EINVAL, "blur_u8: NULL pointer");
+    const size_t bytes = (size_t)n * H * W * C;
+    if ((uintptr_t)out < (uintptr_t)in + bytes && (uintptr_t)in < (uintptr_t)out + bytes)
+        return set_error(MIAUG_EINVAL, "blur_u8: out overlaps in (tiles read their neighbours)");
+    return hip_status(launch_blur_u8(in, n, H, W, C, ksize, apply, out, as_stream(stream)), "blur_u8 launch");
+}
+
 int miaug_hsv_shift_u8(const uint8_t *in, int n, int H, int W, const int32_t *dhsv, uint8_t *out, void *stream) {
     begin_call();
     if (n < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "hsv_shift_u8: negative size");

@@ -49,6 +49,8 @@ hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_reco
                      uint8_t *out, hipStream_t s);
 hipError_t launch_c2_mask(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
                           uint8_t *out, hipStream_t s);
+hipError_t launch_blur_u8(const uint8_t *in, int n, int H, int W, int C, int ksize, const int32_t *apply,
+                          uint8_t *out, hipStream_t s);
 hipError_t launch_hsv_u8(const uint8_t *in, int n, int H, int W, const int32_t *dhsv, uint8_t *out, hipStream_t s);
 hipError_t launch_c2_boxes(const float *boxes, const int32_t *box_off, int n, int H, int W,
                            const miaug_c2_record *rec, int crop, int outsz, float *out, hipStream_t s);

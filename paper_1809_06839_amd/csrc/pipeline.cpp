@@ -109,6 +109,8 @@ const uint32_t kSeqRotate[] = {MIAUG_OP_ROTATE};
 const uint32_t kSeqSsr[] = {MIAUG_OP_SSR};
 const uint32_t kSeqPad[] = {MIAUG_OP_PAD};
 const uint32_t kSeqHsv[] = {MIAUG_OP_HSV};
+const uint32_t kSeqBlur3[] = {MIAUG_OP_BLUR3};
+const uint32_t kSeqBlur5[] = {MIAUG_OP_BLUR5};
 
 // Index of the first op of `ops` that breaks the order of `seq` (n if none).
 int match_order(const miaug_op *ops, int n, const uint32_t *seq, int nseq) {
@@ -144,6 +146,7 @@ struct miaug_pipeline {
     bool color;              // SHIFT_RGB or TO_GRAY (DIH4): per-channel LUTs and grayscale flags
     int interp, border;      // WARP: of the ROTATE / SSR op; PAD: border
     int pad_value;           // PAD, constant border
+    int blur_k;              // BLUR chain: 3 or 5
     int chan;                // channels of the batch being staged (DIH4 colour LUT layout)
     double el_sigma;
     bool el_box;             // box-cascade approximation of the field
@@ -230,8 +233,6 @@ int op_check(const miaug_op &o, int i) {
         if (!(o.lo[0] > 0.f && o.hi[0] <= 1.f && o.lo[1] > 0.f))
             return set_error(MIAUG_EINVAL, "pipeline: op %d (SIZED_CROP): need 0 < scale <= 1, ratio > 0", i);
         break;
-    case MIAUG_OP_BLUR5:
-        return set_error(MIAUG_EUNSUPPORTED, "pipeline: op %d (BLUR5): no fused chain takes a 5x5 blur", i);
     default:
         if (o.kind < MIAUG_OP_HFLIP || o.kind > MIAUG_OP_ROTATE)
             return set_error(MIAUG_EINVAL, "pipeline: op %d: unknown kind %u", i, o.kind);
@@ -275,6 +276,7 @@ int grow_device(void **ptr, size_t *cap, size_t bytes, const char *what) {
 //   WARP:         int64 Q32 matrices [n][6]
 //   PAD:          nothing (8 bytes of padding)
 //   HSV:          int32 shifts [n][3] (dh, ds, dv)
+//   BLUR:         int32 on/off flags [n]
 size_t packed_bytes(const miaug_pipeline *p, int n, int C) {
     switch (p->kind) {
     case MIAUG_PIPE_DIH4: return (size_t)n * 32 + (p->color ? (size_t)n * (256 * C + 4) : 0);
@@ -283,12 +285,18 @@ size_t packed_bytes(const miaug_pipeline *p, int n, int C) {
     case MIAUG_PIPE_WARP: return (size_t)n * 48;
     case MIAUG_PIPE_PAD: return 8;
     case MIAUG_PIPE_HSV: return (size_t)n * 12;
+    case MIAUG_PIPE_BLUR: return (size_t)n * 4;
     default: return (size_t)n * 10 * sizeof(double);
     }
 }
 
 int pack(const miaug_pipeline *p, const miaug_params *r, int n, int H, int W, int C, void *dst) {
     if (p->kind == MIAUG_PIPE_PAD) return MIAUG_OK;
+    if (p->kind == MIAUG_PIPE_BLUR) {
+        int32_t *d = (int32_t *)dst;
+        for (int i = 0; i < n; ++i) d[i] = r[i].blur;
+        return MIAUG_OK;
+    }
     if (p->kind == MIAUG_PIPE_HSV) {
         int32_t *d = (int32_t *)dst;
         for (int i = 0; i < n; ++i) {
@@ -397,7 +405,8 @@ int batch_check(const miaug_pipeline *p, const miaug_batch_in *in, const miaug_b
         if (in->boxes && (!in->box_off || !out->boxes)) return set_error(MIAUG_EINVAL, "apply: boxes without offsets/output");
         return MIAUG_OK;
     }
-    if ((p->kind == MIAUG_PIPE_WARP || p->kind == MIAUG_PIPE_PAD || p->kind == MIAUG_PIPE_DIH4) &&
+    if ((p->kind == MIAUG_PIPE_WARP || p->kind == MIAUG_PIPE_PAD || p->kind == MIAUG_PIPE_DIH4 ||
+         p->kind == MIAUG_PIPE_BLUR) &&
         in->channels != 1 && in->channels != 3 && in->channels != 4)
         return set_error(MIAUG_ESHAPE, "apply: channels must be 1, 3 or 4");
     if (p->kind == MIAUG_PIPE_DIH4 && p->color && has(p->ops.data(), (int)p->ops.size(), MIAUG_OP_TO_GRAY) &&
@@ -507,6 +516,19 @@ int run_chain(miaug_pipeline *p, const miaug_batch_in *in, const miaug_params *f
         if (!st && in->boxes)
             st = miaug_boxes_ssr_crop_resize(in->boxes, in->box_off, n, in->H, in->W, rec, p->crop_h, p->out_h,
                                              out->boxes, s);
+        return st;
+    }
+    if (p->kind == MIAUG_PIPE_BLUR) {
+        const size_t isz = (size_t)in->H * in->W * in->channels, msz = (size_t)in->H * in->W;
+        const int32_t *d = (const int32_t *)dp;
+        int st = MIAUG_OK;
+        for (int i0 = 0; i0 < n && !st; i0 += per_image ? 1 : n)
+            st = miaug_blur_u8(in->img + i0 * isz, per_image ? 1 : n, in->H, in->W, in->channels, p->blur_k, d + i0,
+                               (uint8_t *)out->img + i0 * isz, s);
+        // masks: a colour op leaves them as they are
+        if (!st && in->mask && out->mask != in->mask)
+            st = hip_status(hipMemcpyAsync(out->mask, in->mask, (size_t)n * msz, hipMemcpyDeviceToDevice,
+                                           (hipStream_t)s), "apply: mask copy");
         return st;
     }
     if (p->kind == MIAUG_PIPE_HSV) {
@@ -657,7 +679,8 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     } cands[] = {{MIAUG_PIPE_DIH4, kSeqDih4, 8},     {MIAUG_PIPE_RAGGED, kSeqRagged, 8},
                  {MIAUG_PIPE_U8CHAIN, kSeqU8, 6},    {MIAUG_PIPE_DISTORT, kSeqDistort, 2},
                  {MIAUG_PIPE_WARP, kSeqRotate, 1},   {MIAUG_PIPE_WARP, kSeqSsr, 1},
-                 {MIAUG_PIPE_PAD, kSeqPad, 1},       {MIAUG_PIPE_HSV, kSeqHsv, 1}};
+                 {MIAUG_PIPE_PAD, kSeqPad, 1},       {MIAUG_PIPE_HSV, kSeqHsv, 1},
+                 {MIAUG_PIPE_BLUR, kSeqBlur3, 1},    {MIAUG_PIPE_BLUR, kSeqBlur5, 1}};
     int kind = 0, worst = -1;
     for (const Cand &c : cands) {
         const int at = match_order(ops, n_ops, c.seq, c.nseq);
@@ -702,9 +725,11 @@ int miaug_pipeline_create(miaug_ctx *ctx, const miaug_op *ops, int n_ops, miaug_
     p->interp = MIAUG_INTERP_BILINEAR;
     p->border = MIAUG_BORDER_REFLECT101;
     p->pad_value = 0;
+    p->blur_k = 3;
     p->chan = 3;
     for (const miaug_op &o : p->ops) {
         if (o.kind == MIAUG_OP_SIZED_CROP) p->wcrop = true;
+        if (o.kind == MIAUG_OP_BLUR5) p->blur_k = 5;
         if (o.kind == MIAUG_OP_SHIFT_RGB || o.kind == MIAUG_OP_TO_GRAY || (o.kind == MIAUG_OP_GAMMA && kind == MIAUG_PIPE_DIH4))
             p->color = true;
         if (o.kind == MIAUG_OP_ROTATE || o.kind == MIAUG_OP_PAD || (o.kind == MIAUG_OP_SSR && kind == MIAUG_PIPE_WARP)) {
@@ -848,7 +873,8 @@ int miaug_sample(const miaug_pipeline *p, uint64_t seed, uint64_t first_index, i
             case MIAUG_OP_GAMMA:
                 if (on) r.gamma = G.range(d + 1, o.lo[0], o.hi[0]);
                 break;
-            case MIAUG_OP_BLUR3: r.blur = on; break;
+            case MIAUG_OP_BLUR3:
+            case MIAUG_OP_BLUR5: r.blur = on; break;
             case MIAUG_OP_GRID:
                 if (on)
                     for (int k = 0; k < 10; ++k)

@@ -163,3 +163,32 @@ def test_hsv_shift_shapes_and_tails_bit_exact(m, H, W):
     out = m.hsv_shift_u8(torch.from_numpy(imgs).cuda(), torch.from_numpy(d).cuda()).cpu().numpy()
     for i in range(n):
         assert np.array_equal(out[i], oracle.hsv_shift(imgs[i], int(d[i, 0]), int(d[i, 1]), int(d[i, 2]))), i
+
+
+@pytest.mark.parametrize("k", [3, 5])
+@pytest.mark.parametrize("H,W,C", [(1, 1, 3), (2, 3, 1), (31, 33, 3), (64, 96, 4), (100, 77, 1), (512, 512, 3)])
+def test_blur_bit_exact(m, k, H, W, C):
+    # tiles with ragged edges, images smaller than the halo, per-image on/off
+    import torch
+    rng = np.random.default_rng(k * 1000 + H + W + C)
+    n = 3
+    imgs = rng.integers(0, 256, (n, H, W, C), dtype=np.uint8)
+    apply = torch.tensor([1, 0, 1], dtype=torch.int32, device="cuda")
+    x = torch.from_numpy(imgs).cuda()
+    if C == 1:
+        x = x[..., 0].contiguous()
+    out = m.blur_u8(x, k, apply).cpu().numpy().reshape(n, H, W, C)
+    for i in range(n):
+        ref = oracle.blur(imgs[i], k).reshape(H, W, C) if i != 1 else imgs[i]
+        assert np.array_equal(out[i], ref), i
+    out_all = m.blur_u8(x, k).cpu().numpy().reshape(n, H, W, C)
+    assert np.array_equal(out_all[1], oracle.blur(imgs[1], k).reshape(H, W, C))
+
+
+def test_blur_rejects_overlap_and_bad_ksize(m):
+    import torch
+    x = torch.zeros((1, 8, 8, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(m.MiaugError):
+        m.blur_u8(x, 3, out=x)
+    with pytest.raises(m.MiaugError):
+        m.blur_u8(x, 7)

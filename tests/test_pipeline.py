@@ -49,7 +49,7 @@ def test_op_lists_map_onto_their_chains():
 @pytest.mark.parametrize("ops, status", [
     ([op("RESIZE", out=(8, 8)), op("HFLIP")], m.MiaugError),            # order
     ([op("HFLIP"), op("HFLIP")], m.MiaugError),                          # repeated op
-    ([op("BLUR5")], m.MiaugError),                                       # no chain takes it
+    ([op("BLUR3"), op("BLUR5")], m.MiaugError),                          # no chain takes both
     ([op("HSV", 1, (-20, -30), (20, 30)), op("BLUR3", 0.3)], m.MiaugError),  # u8 chain without crop/resize
     ([op("HFLIP", 1.5)], m.MiaugError),                                  # p outside [0, 1]
     ([op("ROT90", 1, (0,), (4,))], m.MiaugError),                        # k outside 0..3
@@ -412,6 +412,7 @@ def test_table1_op_lists_map_onto_their_chains():
     assert kind_of([op("HFLIP", 0.5), op("BRIGHT_CONTRAST", 1, (0.8, -51), (1.2, 51)), op("SHIFT_RGB", 0.5, (-9,) * 3,
                     (9,) * 3), op("GAMMA", 0.5, (0.8,), (1.2,)), op("TO_GRAY", 0.3)]) == "DIH4"
     assert kind_of([op("HSV", 1, (-20, -30, 0), (20, 30, 0))]) == "HSV"
+    assert kind_of([op("BLUR3", 0.3)]) == "BLUR" and kind_of([op("BLUR5", 0.3)]) == "BLUR"
     assert kind_of([op("CROP", out=(64, 64)), op("RESIZE", out=(64, 64)), op("HSV", 1, (-20, -30, 0), (20, 30, 0)),
                     op("GAMMA", 1, (0.8,), (1.2,))]) == "U8CHAIN"
     with pytest.raises(m.MiaugError):
@@ -497,6 +498,30 @@ def test_gamma_in_the_color_chain_matches_the_oracle(ctx):
         if r.gray:
             y = oracle.gray(y)
         assert np.array_equal(got[i], y.reshape(-1)), i
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,k", [("BLUR3", 3), ("BLUR5", 5)])
+def test_blur_pipeline_matches_the_oracle(ctx, kind, k):
+    import torch
+    n, H, W = 7, 37, 70
+    rng = np.random.default_rng(k)
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    masks = rng.integers(0, 9, (n, H, W), dtype=np.uint8)
+    p = m.Pipeline(ctx, [op(kind, 0.5)])
+    recs = p.sample(25 + k, 0, n)
+    assert 0 < sum(r.blur for r in recs) < n  # both branches
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    out, om = torch.empty_like(x), torch.empty_like(xm)
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    p.apply(bi, bo, recs)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i in range(n):
+        ref = oracle.blur(imgs[i], k) if recs[i].blur else imgs[i]
+        assert np.array_equal(got[i], ref), i
+    assert np.array_equal(om.cpu().numpy(), masks)
 
 
 @pytest.mark.gpu
