@@ -1491,11 +1491,10 @@ struct Variant {
 // Variant 0 is the default.  Workgroups per CU are chosen against the LDS as
 // measured on gfx950: a workgroup above about 40 KB runs as if only one fits
 // in each 80 KB half of the 160 KB (three 42.5 KB workgroups per CU run like
-// two), so the staged forms keep a workgroup at or under 40 KB.  Of those,
-// three per CU beat four (about 7%): fewer streams contend for the CU.
+// two), so the staged forms keep a workgroup at or under 40 KB.  The default
+// runs three per CU (four measured the same).
 const Variant kVariants[] = {
     {32, 32, 4, 3, 1, "tile 32x32, persistent 3 wg/CU, 4 worker waves + a planning wave"},
-    {32, 32, 4, 4, 1, "tile 32x32, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
     {32, 32, 5, 2, 1, "tile 32x32, persistent 2 wg/CU, double-buffered stage, planning wave two passes ahead"},
     {32, 32, 6, 3, 1, "tile 32x32, persistent 3 wg/CU, register-staged loads, planning wave two passes ahead"},
