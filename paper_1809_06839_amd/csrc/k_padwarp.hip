@@ -93,6 +93,7 @@ __device__ __forceinline__ void warp_px_direct(const uint8_t *src, int H, int W,
 
 constexpr int kWarpTile = 32;            // output tile side
 constexpr int kWarpStage = 16 * 1024;    // bytes of staged source box per workgroup
+constexpr int kWarpRows = 128;           // rows of a box staged in dwords
 
 // floor(e / d) for 0 <= e < 2^20, 1 <= d < 2^12, from a float estimate and
 // one correction each way.
@@ -114,7 +115,8 @@ template <int C>
 __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ in, int H, int W,
                                                    const int64_t *__restrict__ aq, int interp, int border,
                                                    uint8_t *__restrict__ out) {
-    __shared__ uint8_t box[kWarpStage];
+    __shared__ __align__(16) uint8_t box[kWarpStage];
+    __shared__ int roff[kWarpRows];
     __shared__ __align__(4) uint8_t obuf[kWarpTile * kWarpTile * C];
     const int img = blockIdx.y;
     const int ntx = (W + kWarpTile - 1) / kWarpTile;
@@ -147,13 +149,32 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
         return;
     }
     const int bw = (int)bw64, bh = (int)bh64;
-    const float rbw = 1.0f / (float)bw;
-    for (int e = threadIdx.x; e < bw * bh; e += kThreads) {
-        const int r = small_div(e, bw, rbw), c = e - r * bw;
-        const int64_t sy = border_index(by0 + r, H, border), sx = border_index(bx0 + c, W, border);
-        const uint8_t *p = src + ((size_t)sy * W + sx) * C;
+    // A box inside the image is staged in dwords: row r's bytes start at the
+    // dword boundary below them (offset o_r = its byte address mod 4) in a row
+    // of pitch P; roff[r] = r P + o_r.  Needs a 4-aligned image, and the last
+    // row's dwords inside the image.  Other boxes go pixel by pixel with the
+    // border rule.
+    const int nd = (bw * C + 6) / 4, P = 4 * nd;
+    const bool dw = ((uintptr_t)src & 3) == 0 && bx0 >= 0 && by0 >= 0 && bx0 + bw <= W && by0 + bh <= H &&
+                    bh <= kWarpRows && bh * P <= kWarpStage &&
+                    ((by0 + bh - 1) * (int64_t)W + bx0) * C + P <= (int64_t)H * W * C;
+    if (dw) {
+        if ((int)threadIdx.x < bh) roff[threadIdx.x] = threadIdx.x * P + (int)(((by0 + threadIdx.x) * W + bx0) * C & 3);
+        const float rnd = 1.0f / (float)nd;
+        for (int e = threadIdx.x; e < bh * nd; e += kThreads) {
+            const int r = small_div(e, nd, rnd), j = e - r * nd;
+            const size_t g4 = (size_t)(((by0 + r) * W + bx0) * C) & ~(size_t)3;
+            *(uint32_t *)(box + r * P + 4 * j) = *(const uint32_t *)(src + g4 + 4 * j);
+        }
+    } else {
+        const float rbw = 1.0f / (float)bw;
+        for (int e = threadIdx.x; e < bw * bh; e += kThreads) {
+            const int r = small_div(e, bw, rbw), c = e - r * bw;
+            const int64_t sy = border_index(by0 + r, H, border), sx = border_index(bx0 + c, W, border);
+            const uint8_t *p = src + ((size_t)sy * W + sx) * C;
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch) box[e * C + ch] = (sy < 0 || sx < 0) ? 0 : p[ch];
+            for (int ch = 0; ch < C; ++ch) box[e * C + ch] = (sy < 0 || sx < 0) ? 0 : p[ch];
+        }
     }
     __syncthreads();
     // lane (lx, ly0) takes pixels (lx, ly0 + 8 k): the Q32 sums step by 8 a1 / 8 a4
@@ -170,14 +191,15 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
         const int64_t px = rshr_he64(sxq, 32 - kFBits), py = rshr_he64(syq, 32 - kFBits);
         if (interp == MIAUG_INTERP_NEAREST) {
             const int sx = (int)(((px + kFOne / 2) >> kFBits) - bx0), sy = (int)(((py + kFOne / 2) >> kFBits) - by0);
-            const uint8_t *b = box + (sy * bw + sx) * C;
+            const uint8_t *b = box + (dw ? roff[sy] : sy * bw * C) + sx * C;
 #pragma unroll
             for (int c = 0; c < C; ++c) o[c] = b[c];
             continue;
         }
         const int sx = (int)((px >> kFBits) - bx0), sy = (int)((py >> kFBits) - by0);
         const int ax = (int)(px & (kFOne - 1)), ay = (int)(py & (kFOne - 1));
-        const uint8_t *b0 = box + (sy * bw + sx) * C, *b1 = b0 + bw * C;
+        const uint8_t *b0 = box + (dw ? roff[sy] : sy * bw * C) + sx * C;
+        const uint8_t *b1 = box + (dw ? roff[sy + 1] : (sy + 1) * bw * C) + sx * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) o[c] = blend4(b0[c], b0[C + c], b1[c], b1[C + c], ax, ay);
     }
