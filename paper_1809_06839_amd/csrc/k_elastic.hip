@@ -3,10 +3,12 @@
 //
 // Fields: per image and field, 16-bit Philox noise is smoothed by a separable
 // integer Gaussian (Q15 taps, reflect-101):
-//   k_field_h  one workgroup per (row segment of 1024, field, image): noise of
-//              the segment and its +-radius halo is generated into LDS, each
-//              thread produces 4 consecutive outputs with a sliding window (one
-//              noise read and one tap read per 4 multiply-adds);
+//   k_field_h2 one workgroup per (row segment of 2560, field, image): noise of
+//              the segment and its +-radius halo is generated into LDS as
+//              int16, each thread produces 10 consecutive outputs from pairs
+//              of noise values and taps (packed 16-bit multiply-adds into
+//              int32, exact); k_field_h is the int32 form for taps of 2^15
+//              (segments of 1280, 5 outputs per thread);
 //   k_field_v  one workgroup per (32-column strip x 64 rows, field, image): the
 //              strip of the H-pass result with its +-radius halo is staged in
 //              LDS, each thread produces 8 consecutive rows of one column the
@@ -45,23 +47,16 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 constexpr int kHPer = 5;                   // consecutive outputs per thread (odd: no LDS bank sharing)
 constexpr int kHSeg = kHPer * kThreads;    // outputs per workgroup
 
-__global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t first, int H, int W, int radius,
-                                                      const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
-    __shared__ int32_t noise[kHSeg + 2 * kMaxRadius + 16];
-    __shared__ int32_t tp[2 * kMaxRadius + 16];  // taps, zero-padded to a multiple of kHPer
-    const int segs = (W + kHSeg - 1) / kHSeg;
-    const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kHSeg;
-    const int field = blockIdx.y, img = blockIdx.z;
-    const uint64_t g = first + (uint64_t)img;
-    const int nt = 2 * radius + 1, ntp = (nt + kHPer - 1) / kHPer * kHPer;
-    for (int k = threadIdx.x; k < ntp; k += kThreads) tp[k] = k < nt ? taps[k] : 0;
-    // noise at reflected columns x0 - radius .. x0 + kHSeg + radius - 1 (as far as needed)
-    const int n_need = min(kHSeg, W - x0) + 2 * radius;
-    // The segment's own columns x0 .. x0 + m - 1 (m <= kHSeg) first: one Philox block gives
-    // the 16 values of 16 consecutive stream positions.  Then the reflected halo columns,
-    // which are copies of columns already generated when the row is covered by this segment
-    // and are generated one by one otherwise.
-    const int m = min(kHSeg, W - x0);
+// Noise of row y of one field at reflected columns x0 - radius .. x0 + SEG + radius - 1 (as far as needed)
+// into noise[0 ..): the segment's own columns x0 .. x0 + m - 1 (m <= SEG) first, where one Philox block
+// gives the 16 values of 16 consecutive stream positions; then the reflected halo columns, which are copies
+// of columns already generated when the row is covered by this segment and are generated one by one
+// otherwise.  Ends with a barrier.
+template <int SEG, typename T>
+__device__ __forceinline__ void row_noise(uint64_t seed, uint64_t g, int field, int y, int W, int radius, int x0,
+                                          T *noise) {
+    const int n_need = min(SEG, W - x0) + 2 * radius;
+    const int m = min(SEG, W - x0);
     const int64_t e0 = (int64_t)y * W + x0, e1 = e0 + m;
     for (int64_t grp = (e0 >> 4) + threadIdx.x; grp <= ((e1 - 1) >> 4); grp += kThreads) {
         uint64_t c[4] = {(uint64_t)grp, g, (uint64_t)field, 4};
@@ -69,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t fi
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             const int64_t e = grp * 16 + k;
-            if (e >= e0 && e < e1) noise[radius + (int)(e - e0)] = (int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768;
+            if (e >= e0 && e < e1) noise[radius + (int)(e - e0)] = (T)((int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768);
         }
     }
     __syncthreads();
@@ -83,10 +78,23 @@ __global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t fi
             uint64_t c[4] = {(uint64_t)(e >> 4), g, (uint64_t)field, 4};
             philox4x64_10(c, seed, 0);
             const uint64_t word = c[(e & 15) >> 2];
-            noise[i] = (int32_t)((word >> (16 * (e & 3))) & 0xFFFFu) - 32768;
+            noise[i] = (T)((int32_t)((word >> (16 * (e & 3))) & 0xFFFFu) - 32768);
         }
     }
     __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t first, int H, int W, int radius,
+                                                      const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
+    __shared__ int32_t noise[kHSeg + 2 * kMaxRadius + 16];
+    __shared__ int32_t tp[2 * kMaxRadius + 16];  // taps, zero-padded to a multiple of kHPer
+    const int segs = (W + kHSeg - 1) / kHSeg;
+    const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kHSeg;
+    const int field = blockIdx.y, img = blockIdx.z;
+    const uint64_t g = first + (uint64_t)img;
+    const int nt = 2 * radius + 1, ntp = (nt + kHPer - 1) / kHPer * kHPer;
+    for (int k = threadIdx.x; k < ntp; k += kThreads) tp[k] = k < nt ? taps[k] : 0;
+    row_noise<kHSeg>(seed, g, field, y, W, radius, x0, noise);
     const int xl = kHPer * threadIdx.x;  // first of this thread's outputs, relative to x0
     if (x0 + xl >= W) return;
     // Register-blocked correlation: per block of kHPer taps, 2 kHPer - 1 noise values and
@@ -110,6 +118,70 @@ __global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t fi
     int32_t *row = hout + (((size_t)img * 2 + field) * H + y) * W + x0 + xl;
 #pragma unroll
     for (int o = 0; o < kHPer; ++o)
+        if (x0 + xl + o < W) row[o] = rshr_he(acc[o], 15);
+}
+
+// The same pass with packed 16-bit multiply-adds (v_dot2c_i32_i16: two products and the int32
+// accumulator, exact), for taps below 2^15 (every sigma above about 0.4).  Noise is kept as int16 in
+// LDS; an even-aligned pair (n[2k], n[2k+1]) is dword k of that array, an odd-aligned pair
+// (n[2k+1], n[2k+2]) dword k of a second array, and the taps are packed in pairs, so output x + o takes
+// sum_j pair(x + o + 2j) . (t[2j], t[2j+1]).  Ten outputs per thread (an odd stride of five dwords
+// between lanes: no bank sharing), four tap pairs per register block.
+constexpr int kH2Per = 10;
+constexpr int kH2Seg = kH2Per * kThreads;
+constexpr int kH2N = kH2Seg + 2 * kMaxRadius + 64;  // int16 noise entries: the segment, its halo, the reads past it
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int dot2(uint32_t a, uint32_t b, int c) {
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), c, false);
+}
+
+__global__ __launch_bounds__(kThreads) void k_field_h2(uint64_t seed, uint64_t first, int H, int W, int radius,
+                                                       const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
+    __shared__ __align__(16) int16_t noise[kH2N + 2];
+    __shared__ uint32_t odd[kH2N / 2];
+    __shared__ uint32_t tp2[kMaxRadius + 8];
+    const int segs = (W + kH2Seg - 1) / kH2Seg;
+    const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kH2Seg;
+    const int field = blockIdx.y, img = blockIdx.z;
+    const uint64_t g = first + (uint64_t)img;
+    const int nt = 2 * radius + 1, npair = ((nt + 1) / 2 + 3) / 4 * 4;
+    for (int j = threadIdx.x; j < npair; j += kThreads) {
+        const int t0 = 2 * j < nt ? taps[2 * j] : 0, t1 = 2 * j + 1 < nt ? taps[2 * j + 1] : 0;
+        tp2[j] = (uint32_t)(t0 & 0xFFFF) | ((uint32_t)t1 << 16);
+    }
+    row_noise<kH2Seg>(seed, g, field, y, W, radius, x0, noise);
+    for (int k = threadIdx.x; k < kH2N / 2; k += kThreads)
+        odd[k] = (uint32_t)(uint16_t)noise[2 * k + 1] | ((uint32_t)(uint16_t)noise[2 * k + 2] << 16);
+    __syncthreads();
+    const uint32_t *even = (const uint32_t *)noise;
+    const int xl = kH2Per * threadIdx.x;  // first of this thread's outputs, relative to x0
+    if (x0 + xl >= W) return;
+    // Reads past the noise of the segment meet zero taps.
+    int32_t acc[kH2Per];
+#pragma unroll
+    for (int o = 0; o < kH2Per; ++o) acc[o] = 0;
+    const int b = xl / 2;
+    for (int j0 = 0; j0 < npair; j0 += 4) {
+        uint32_t xe[kH2Per / 2 + 3], xo[kH2Per / 2 + 3], tv[4];
+#pragma unroll
+        for (int i = 0; i < kH2Per / 2 + 3; ++i) {
+            xe[i] = even[b + j0 + i];
+            xo[i] = odd[b + j0 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tv[i] = tp2[j0 + i];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int i = 0; i < kH2Per / 2; ++i) {
+                acc[2 * i] = dot2(xe[i + jj], tv[jj], acc[2 * i]);
+                acc[2 * i + 1] = dot2(xo[i + jj], tv[jj], acc[2 * i + 1]);
+            }
+    }
+    int32_t *row = hout + (((size_t)img * 2 + field) * H + y) * W + x0 + xl;
+#pragma unroll
+    for (int o = 0; o < kH2Per; ++o)
         if (x0 + xl + o < W) row[o] = rshr_he(acc[o], 15);
 }
 
@@ -622,9 +694,17 @@ hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, in
     int32_t *dtaps = hbuf + (size_t)n * 2 * H * W;
     hipError_t e = hipMemcpyAsync(dtaps, taps, sizeof(int32_t) * (2 * radius + 1), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    const int segs = (W + kHSeg - 1) / kHSeg;
-    hipLaunchKernelGGL(k_field_h, dim3((unsigned)H * segs, 2, n), dim3(kThreads), 0, s, seed, first, H, W, radius,
-                       dtaps, hbuf);
+    int tmax = 0;
+    for (int k = 0; k < 2 * radius + 1; ++k) tmax = taps[k] > tmax ? taps[k] : tmax;
+    if (tmax < 32768) {  // taps fit int16: packed multiply-adds
+        const int segs = (W + kH2Seg - 1) / kH2Seg;
+        hipLaunchKernelGGL(k_field_h2, dim3((unsigned)H * segs, 2, n), dim3(kThreads), 0, s, seed, first, H, W,
+                           radius, dtaps, hbuf);
+    } else {
+        const int segs = (W + kHSeg - 1) / kHSeg;
+        hipLaunchKernelGGL(k_field_h, dim3((unsigned)H * segs, 2, n), dim3(kThreads), 0, s, seed, first, H, W,
+                           radius, dtaps, hbuf);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int strips = ((W + kVCols - 1) / kVCols) * ((H + kVRows - 1) / kVRows);
     const int ntp = (2 * radius + 1 + kVPer - 1) / kVPer * kVPer;

@@ -19,7 +19,11 @@ def m(dev):
 
 
 @pytest.mark.parametrize("H,W,sigma,alpha,radius", [(40, 36, 4.0, 60, 12), (1, 50, 3.0, 100, 7), (67, 1, 2.0, 30, 5),
-                                                    (130, 1100, 50.0, 1000, 150), (3, 3, 1.0, 500, 1)])
+                                                    (130, 1100, 50.0, 1000, 150), (3, 3, 1.0, 500, 1),
+                                                    # rows wider than one horizontal-pass segment (2560 outputs)
+                                                    (3, 5200, 50.0, 1000, 150), (2, 2561, 10.0, 500, 30),
+                                                    # a centre tap of 2^15: the int32 multiply-add pass
+                                                    (4, 40, 0.2, 100, 1)])
 def test_fields_bit_exact(m, H, W, sigma, alpha, radius):
     off = m.elastic_fields(7, 3, 2, H, W, sigma, alpha, radius).cpu().numpy()
     for i in range(2):
