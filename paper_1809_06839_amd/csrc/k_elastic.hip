@@ -124,9 +124,9 @@ __global__ __launch_bounds__(kThreads) void k_field_h(uint64_t seed, uint64_t fi
 // The same pass with packed 16-bit multiply-adds (v_dot2c_i32_i16: two products and the int32
 // accumulator, exact), for taps below 2^15 (every sigma above about 0.4).  Noise is kept as int16 in
 // LDS; an even-aligned pair (n[2k], n[2k+1]) is dword k of that array, an odd-aligned pair
-// (n[2k+1], n[2k+2]) dword k of a second array, and the taps are packed in pairs, so output x + o takes
-// sum_j pair(x + o + 2j) . (t[2j], t[2j+1]).  Ten outputs per thread (an odd stride of five dwords
-// between lanes: no bank sharing), four tap pairs per register block.
+// (n[2k+1], n[2k+2]) is formed in registers from dwords k and k + 1 (alignbit), and the taps are packed
+// in pairs, so output x + o takes sum_j pair(x + o + 2j) . (t[2j], t[2j+1]).  Ten outputs per thread
+// (an odd stride of five dwords between lanes: no bank sharing), four tap pairs per register block.
 constexpr int kH2Per = 10;
 constexpr int kH2Seg = kH2Per * kThreads;
 constexpr int kH2N = kH2Seg + 2 * kMaxRadius + 64;  // int16 noise entries: the segment, its halo, the reads past it
@@ -139,7 +139,6 @@ __device__ __forceinline__ int dot2(uint32_t a, uint32_t b, int c) {
 __global__ __launch_bounds__(kThreads) void k_field_h2(uint64_t seed, uint64_t first, int H, int W, int radius,
                                                        const int32_t *__restrict__ taps, int32_t *__restrict__ hout) {
     __shared__ __align__(16) int16_t noise[kH2N + 2];
-    __shared__ uint32_t odd[kH2N / 2];
     __shared__ uint32_t tp2[kMaxRadius + 8];
     const int segs = (W + kH2Seg - 1) / kH2Seg;
     const int y = blockIdx.x / segs, x0 = (blockIdx.x % segs) * kH2Seg;
@@ -151,9 +150,6 @@ __global__ __launch_bounds__(kThreads) void k_field_h2(uint64_t seed, uint64_t f
         tp2[j] = (uint32_t)(t0 & 0xFFFF) | ((uint32_t)t1 << 16);
     }
     row_noise<kH2Seg>(seed, g, field, y, W, radius, x0, noise);
-    for (int k = threadIdx.x; k < kH2N / 2; k += kThreads)
-        odd[k] = (uint32_t)(uint16_t)noise[2 * k + 1] | ((uint32_t)(uint16_t)noise[2 * k + 2] << 16);
-    __syncthreads();
     const uint32_t *even = (const uint32_t *)noise;
     const int xl = kH2Per * threadIdx.x;  // first of this thread's outputs, relative to x0
     if (x0 + xl >= W) return;
@@ -163,12 +159,11 @@ __global__ __launch_bounds__(kThreads) void k_field_h2(uint64_t seed, uint64_t f
     for (int o = 0; o < kH2Per; ++o) acc[o] = 0;
     const int b = xl / 2;
     for (int j0 = 0; j0 < npair; j0 += 4) {
-        uint32_t xe[kH2Per / 2 + 3], xo[kH2Per / 2 + 3], tv[4];
+        uint32_t xe[kH2Per / 2 + 4], xo[kH2Per / 2 + 3], tv[4];
 #pragma unroll
-        for (int i = 0; i < kH2Per / 2 + 3; ++i) {
-            xe[i] = even[b + j0 + i];
-            xo[i] = odd[b + j0 + i];
-        }
+        for (int i = 0; i < kH2Per / 2 + 4; ++i) xe[i] = even[b + j0 + i];
+#pragma unroll
+        for (int i = 0; i < kH2Per / 2 + 3; ++i) xo[i] = __builtin_amdgcn_alignbit(xe[i + 1], xe[i], 16);
 #pragma unroll
         for (int i = 0; i < 4; ++i) tv[i] = tp2[j0 + i];
 #pragma unroll
@@ -188,10 +183,11 @@ __global__ __launch_bounds__(kThreads) void k_field_h2(uint64_t seed, uint64_t f
 // ---------------------------------------------------------------- V pass
 constexpr int kVCols = 32, kVRows = 64, kVPer = 8;  // 32 columns x (8 threads x 8 rows)
 
-__global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, int alpha,
-                                                      const int32_t *__restrict__ taps,
-                                                      const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
-    extern __shared__ int32_t smem[];
+// The int32 form: the strip of the H-pass result with its halo in LDS (smem), each thread 8 rows of one
+// column, register-blocked as in the H pass; rows past the strip meet zero taps.
+__device__ __forceinline__ void field_v_int32(int H, int W, int radius, int alpha, const int32_t *__restrict__ taps,
+                                              const int32_t *__restrict__ hin, int32_t *__restrict__ off,
+                                              int32_t *smem) {
     const int nt = 2 * radius + 1, ntp = (nt + kVPer - 1) / kVPer * kVPer;
     int32_t *tp = smem;          // taps, zero-padded to ntp
     int32_t *strip = smem + ntp;  // (kVRows + 2 radius + kVPer) x kVCols
@@ -210,7 +206,6 @@ __global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, 
     const int col = threadIdx.x % kVCols, grp = threadIdx.x / kVCols;
     const int x = xs0 + col, yl = grp * kVPer;
     if (x >= W || y0 + yl >= H) return;
-    // register-blocked as in the H pass; rows past the strip meet zero taps
     int32_t acc[kVPer];
 #pragma unroll
     for (int o = 0; o < kVPer; ++o) acc[o] = 0;
@@ -225,6 +220,91 @@ __global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, 
         for (int jj = 0; jj < kVPer; ++jj)
 #pragma unroll
             for (int o = 0; o < kVPer; ++o) acc[o] += __mul24(tv[jj], xv[jj + o]);
+    }
+    int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
+#pragma unroll
+    for (int o = 0; o < kVPer; ++o)
+        if (y0 + yl + o < H) ob[(size_t)(y0 + yl + o) * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc[o], 30 - kFBits);
+}
+
+__global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, int alpha,
+                                                      const int32_t *__restrict__ taps,
+                                                      const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
+    extern __shared__ int32_t smem[];
+    field_v_int32(H, W, radius, alpha, taps, hin, off, smem);
+}
+
+// Packed form of the V pass, for strips whose H-pass values all fit int16 (|h| <= the sum of the taps,
+// which rounding can lift a little above 2^15): pairs of consecutive rows (2k, 2k + 1) of a column are
+// one dword, the odd-aligned pairs are formed in registers as in the H pass, and taps go in pairs, so
+// each thread's 8 rows take 4 dot2 per tap pair.  A strip with a value outside int16
+// is restaged and done by the int32 form (a uniform branch: the result is the same either way).
+constexpr int kV2Pad = 8;  // pairs read past the strip (zero taps)
+__host__ __device__ constexpr int v2_pairs(int radius) { return (kVRows + 2 * radius) / 2 + 1 + kV2Pad; }
+
+__global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius, int alpha,
+                                                       const int32_t *__restrict__ taps,
+                                                       const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
+    extern __shared__ int32_t smem[];
+    __shared__ int wide;  // a staged value outside int16
+    const int nt = 2 * radius + 1, npair = ((nt + 1) / 2 + 3) / 4 * 4;
+    const int np = v2_pairs(radius);
+    uint32_t *tp2 = (uint32_t *)smem;
+    uint32_t *ev = tp2 + npair;
+    const int strips_x = (W + kVCols - 1) / kVCols;
+    const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kVRows;
+    const int field = blockIdx.y, img = blockIdx.z;
+    const int32_t *hb = hin + ((size_t)img * 2 + field) * H * W;
+    if (threadIdx.x == 0) wide = 0;
+    for (int j = threadIdx.x; j < npair; j += kThreads) {
+        const int t0 = 2 * j < nt ? taps[2 * j] : 0, t1 = 2 * j + 1 < nt ? taps[2 * j + 1] : 0;
+        tp2[j] = (uint32_t)(t0 & 0xFFFF) | ((uint32_t)t1 << 16);
+    }
+    __syncthreads();
+    // staged row r is image row reflect(y0 - radius + r); pairs past the needed rows repeat a valid row
+    const int rows = min(kVRows, H - y0) + 2 * radius;
+    bool out16 = false;
+    for (int e = threadIdx.x; e < np * kVCols; e += kThreads) {
+        const int k = e / kVCols, c = e - k * kVCols;
+        const int xx = min(xs0 + c, W - 1);
+        int32_t h[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int r = min(2 * k + d, rows - 1);
+            h[d] = hb[(size_t)reflect101(y0 - radius + r, H) * W + xx];
+            out16 |= h[d] < -32768 || h[d] > 32767;
+        }
+        ev[e] = (uint32_t)(h[0] & 0xFFFF) | ((uint32_t)h[1] << 16);
+    }
+    if (out16) wide = 1;
+    __syncthreads();
+    if (wide) {  // uniform
+        __syncthreads();  // every thread has read the flag before the int32 form reuses the buffer
+        field_v_int32(H, W, radius, alpha, taps, hin, off, smem);
+        return;
+    }
+    const int col = threadIdx.x % kVCols, grp = threadIdx.x / kVCols;
+    const int x = xs0 + col, yl = grp * kVPer;  // yl even: output row yl + o takes pair (yl + o + 2j)
+    if (x >= W || y0 + yl >= H) return;
+    int32_t acc[kVPer];
+#pragma unroll
+    for (int o = 0; o < kVPer; ++o) acc[o] = 0;
+    const int b = yl / 2;
+    for (int j0 = 0; j0 < npair; j0 += 4) {
+        uint32_t xe[kVPer / 2 + 4], xo[kVPer / 2 + 3], tv[4];
+#pragma unroll
+        for (int i = 0; i < kVPer / 2 + 4; ++i) xe[i] = ev[(b + j0 + i) * kVCols + col];
+#pragma unroll
+        for (int i = 0; i < kVPer / 2 + 3; ++i) xo[i] = __builtin_amdgcn_alignbit(xe[i + 1], xe[i], 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tv[i] = tp2[j0 + i];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+            for (int i = 0; i < kVPer / 2; ++i) {
+                acc[2 * i] = dot2(xe[i + jj], tv[jj], acc[2 * i]);
+                acc[2 * i + 1] = dot2(xo[i + jj], tv[jj], acc[2 * i + 1]);
+            }
     }
     int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
 #pragma unroll
@@ -709,7 +789,15 @@ hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, in
     const int strips = ((W + kVCols - 1) / kVCols) * ((H + kVRows - 1) / kVRows);
     const int ntp = (2 * radius + 1 + kVPer - 1) / kVPer * kVPer;
     const size_t lds = sizeof(int32_t) * (ntp + (size_t)(kVRows + 2 * radius + kVPer) * kVCols);
-    hipLaunchKernelGGL(k_field_v, dim3(strips, 2, n), dim3(kThreads), lds, s, H, W, radius, alpha, dtaps, hbuf, off);
+    if (tmax < 32768) {  // the packed form, which falls back to the int32 form per strip; LDS for either
+        const int npair = ((2 * radius + 1 + 1) / 2 + 3) / 4 * 4;
+        const size_t lds2 = sizeof(uint32_t) * (npair + (size_t)v2_pairs(radius) * kVCols);
+        hipLaunchKernelGGL(k_field_v2, dim3(strips, 2, n), dim3(kThreads), lds2 > lds ? lds2 : lds, s, H, W, radius,
+                           alpha, dtaps, hbuf, off);
+    } else {
+        hipLaunchKernelGGL(k_field_v, dim3(strips, 2, n), dim3(kThreads), lds, s, H, W, radius, alpha, dtaps, hbuf,
+                           off);
+    }
     return hipGetLastError();
 }
 
