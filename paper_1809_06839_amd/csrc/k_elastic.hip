@@ -9,10 +9,13 @@
 //              of noise values and taps (packed 16-bit multiply-adds into
 //              int32, exact); k_field_h is the int32 form for taps of 2^15
 //              (segments of 1280, 5 outputs per thread);
-//   k_field_v  one workgroup per (32-column strip x 64 rows, field, image): the
+//   k_field_v2 one workgroup per (32-column strip x 64 rows, field, image): the
 //              strip of the H-pass result with its +-radius halo is staged in
-//              LDS, each thread produces 8 consecutive rows of one column the
-//              same way, then offsets off = rdiv_he(alpha v, 2^20) (Q10 px).
+//              LDS as pairs of rows, each thread produces 8 consecutive rows of
+//              one column the same way, then offsets off = rdiv_he(alpha v,
+//              2^20) (Q10 px); a strip with a value outside int16 (possible
+//              only when rounding lifts the taps' sum above 2^15) and taps of
+//              2^15 take the int32 form (k_field_v).
 // Remap chain (u8): one workgroup per 32 x 32 output tile.  The grid tables
 // are monotone, so the tile's grid taps read a contiguous (before reflection)
 // block of rows and columns of the elastic result e; the tile computes that
