@@ -9,13 +9,14 @@
 //              of noise values and taps (packed 16-bit multiply-adds into
 //              int32, exact); k_field_h is the int32 form for taps of 2^15
 //              (segments of 1280, 5 outputs per thread);
-//   k_field_v2 one workgroup per (32-column strip x 64 rows, field, image): the
+//   k_field_v2 one workgroup per (32-column strip x 256 rows, field, image): the
 //              strip of the H-pass result with its +-radius halo is staged in
 //              LDS as pairs of rows, each thread produces 8 consecutive rows of
 //              one column the same way, then offsets off = rdiv_he(alpha v,
 //              2^20) (Q10 px); a strip with a value outside int16 (possible
-//              only when rounding lifts the taps' sum above 2^15) and taps of
-//              2^15 take the int32 form (k_field_v).
+//              only when rounding lifts the taps' sum above 2^15) is done
+//              with direct int32 sums; taps of 2^15 take the int32 form
+//              (k_field_v, strips of 64 rows).
 // Remap chain (u8): one workgroup per 32 x 32 output tile.  The grid tables
 // are monotone, so the tile's grid taps read a contiguous (before reflection)
 // block of rows and columns of the elastic result e; the tile computes that
@@ -188,14 +189,13 @@ constexpr int kVCols = 32, kVRows = 64, kVPer = 8;  // 32 columns x (8 threads x
 
 // The int32 form: the strip of the H-pass result with its halo in LDS (smem), each thread 8 rows of one
 // column, register-blocked as in the H pass; rows past the strip meet zero taps.
+// Rows y0 .. y0 + kVRows - 1 of columns xs0 .. xs0 + kVCols - 1.
 __device__ __forceinline__ void field_v_int32(int H, int W, int radius, int alpha, const int32_t *__restrict__ taps,
                                               const int32_t *__restrict__ hin, int32_t *__restrict__ off,
-                                              int32_t *smem) {
+                                              int32_t *smem, int xs0, int y0) {
     const int nt = 2 * radius + 1, ntp = (nt + kVPer - 1) / kVPer * kVPer;
     int32_t *tp = smem;          // taps, zero-padded to ntp
     int32_t *strip = smem + ntp;  // (kVRows + 2 radius + kVPer) x kVCols
-    const int strips_x = (W + kVCols - 1) / kVCols;
-    const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kVRows;
     const int field = blockIdx.y, img = blockIdx.z;
     const int32_t *hb = hin + ((size_t)img * 2 + field) * H * W;
     for (int k = threadIdx.x; k < ntp; k += kThreads) tp[k] = k < nt ? taps[k] : 0;
@@ -234,16 +234,21 @@ __global__ __launch_bounds__(kThreads) void k_field_v(int H, int W, int radius, 
                                                       const int32_t *__restrict__ taps,
                                                       const int32_t *__restrict__ hin, int32_t *__restrict__ off) {
     extern __shared__ int32_t smem[];
-    field_v_int32(H, W, radius, alpha, taps, hin, off, smem);
+    const int strips_x = (W + kVCols - 1) / kVCols;
+    field_v_int32(H, W, radius, alpha, taps, hin, off, smem, (blockIdx.x % strips_x) * kVCols,
+                  (blockIdx.x / strips_x) * kVRows);
 }
 
 // Packed form of the V pass, for strips whose H-pass values all fit int16 (|h| <= the sum of the taps,
 // which rounding can lift a little above 2^15): pairs of consecutive rows (2k, 2k + 1) of a column are
 // one dword, the odd-aligned pairs are formed in registers as in the H pass, and taps go in pairs, so
-// each thread's 8 rows take 4 dot2 per tap pair.  A strip with a value outside int16
-// is restaged and done by the int32 form (a uniform branch: the result is the same either way).
-constexpr int kV2Pad = 8;  // pairs read past the strip (zero taps)
-__host__ __device__ constexpr int v2_pairs(int radius) { return (kVRows + 2 * radius) / 2 + 1 + kV2Pad; }
+// each thread's 8-row blocks take 4 dot2 per tap pair.  Strips of 256 rows, so the 2 radius halo rows
+// are staged once per 256 output rows.  A strip with a value outside int16 is done with int32 sums read
+// straight from global memory (a uniform branch: the result is the same either way).
+constexpr int kV2Blocks = 4;                  // 64-row blocks per strip
+constexpr int kV2Rows = kV2Blocks * kVRows;  // rows per strip (each thread kV2Blocks blocks of kVPer rows)
+constexpr int kV2Pad = 8;            // pairs read past the strip (zero taps)
+__host__ __device__ constexpr int v2_pairs(int radius) { return (kV2Rows + 2 * radius) / 2 + 1 + kV2Pad; }
 
 __global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius, int alpha,
                                                        const int32_t *__restrict__ taps,
@@ -255,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius,
     uint32_t *tp2 = (uint32_t *)smem;
     uint32_t *ev = tp2 + npair;
     const int strips_x = (W + kVCols - 1) / kVCols;
-    const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kVRows;
+    const int xs0 = (blockIdx.x % strips_x) * kVCols, y0 = (blockIdx.x / strips_x) * kV2Rows;
     const int field = blockIdx.y, img = blockIdx.z;
     const int32_t *hb = hin + ((size_t)img * 2 + field) * H * W;
     if (threadIdx.x == 0) wide = 0;
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius,
     }
     __syncthreads();
     // staged row r is image row reflect(y0 - radius + r); pairs past the needed rows repeat a valid row
-    const int rows = min(kVRows, H - y0) + 2 * radius;
+    const int rows = min(kV2Rows, H - y0) + 2 * radius;
     bool out16 = false;
     for (int e = threadIdx.x; e < np * kVCols; e += kThreads) {
         const int k = e / kVCols, c = e - k * kVCols;
@@ -281,38 +286,49 @@ __global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius,
     }
     if (out16) wide = 1;
     __syncthreads();
-    if (wide) {  // uniform
-        __syncthreads();  // every thread has read the flag before the int32 form reuses the buffer
-        field_v_int32(H, W, radius, alpha, taps, hin, off, smem);
+    if (wide) {  // uniform: int32 sums straight from global memory (no staging, never on a hot path)
+        int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
+        for (int e = threadIdx.x; e < kV2Rows * kVCols; e += kThreads) {
+            const int r = e / kVCols, x = xs0 + e % kVCols, y = y0 + r;
+            if (y >= H || x >= W) continue;
+            int32_t acc = 0;
+            for (int k = 0; k < nt; ++k) acc += taps[k] * hb[(size_t)reflect101(y - radius + k, H) * W + x];
+            ob[(size_t)y * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc, 30 - kFBits);
+        }
         return;
     }
     const int col = threadIdx.x % kVCols, grp = threadIdx.x / kVCols;
-    const int x = xs0 + col, yl = grp * kVPer;  // yl even: output row yl + o takes pair (yl + o + 2j)
-    if (x >= W || y0 + yl >= H) return;
-    int32_t acc[kVPer];
-#pragma unroll
-    for (int o = 0; o < kVPer; ++o) acc[o] = 0;
-    const int b = yl / 2;
-    for (int j0 = 0; j0 < npair; j0 += 4) {
-        uint32_t xe[kVPer / 2 + 4], xo[kVPer / 2 + 3], tv[4];
-#pragma unroll
-        for (int i = 0; i < kVPer / 2 + 4; ++i) xe[i] = ev[(b + j0 + i) * kVCols + col];
-#pragma unroll
-        for (int i = 0; i < kVPer / 2 + 3; ++i) xo[i] = __builtin_amdgcn_alignbit(xe[i + 1], xe[i], 16);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) tv[i] = tp2[j0 + i];
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-            for (int i = 0; i < kVPer / 2; ++i) {
-                acc[2 * i] = dot2(xe[i + jj], tv[jj], acc[2 * i]);
-                acc[2 * i + 1] = dot2(xo[i + jj], tv[jj], acc[2 * i + 1]);
-            }
-    }
+    const int x = xs0 + col;
+    if (x >= W) return;
     int32_t *ob = off + ((size_t)img * 2 + field) * H * W;
+    for (int blk = 0; blk < kV2Blocks; ++blk) {
+        const int yl = blk * kVRows + grp * kVPer;  // yl even: output row yl + o takes pair (yl + o + 2j)
+        if (y0 + yl >= H) break;
+        int32_t acc[kVPer];
 #pragma unroll
-    for (int o = 0; o < kVPer; ++o)
-        if (y0 + yl + o < H) ob[(size_t)(y0 + yl + o) * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc[o], 30 - kFBits);
+        for (int o = 0; o < kVPer; ++o) acc[o] = 0;
+        const int b = yl / 2;
+        for (int j0 = 0; j0 < npair; j0 += 4) {
+            uint32_t xe[kVPer / 2 + 4], xo[kVPer / 2 + 3], tv[4];
+#pragma unroll
+            for (int i = 0; i < kVPer / 2 + 4; ++i) xe[i] = ev[(b + j0 + i) * kVCols + col];
+#pragma unroll
+            for (int i = 0; i < kVPer / 2 + 3; ++i) xo[i] = __builtin_amdgcn_alignbit(xe[i + 1], xe[i], 16);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tv[i] = tp2[j0 + i];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int i = 0; i < kVPer / 2; ++i) {
+                    acc[2 * i] = dot2(xe[i + jj], tv[jj], acc[2 * i]);
+                    acc[2 * i + 1] = dot2(xo[i + jj], tv[jj], acc[2 * i + 1]);
+                }
+        }
+#pragma unroll
+        for (int o = 0; o < kVPer; ++o)
+            if (y0 + yl + o < H)
+                ob[(size_t)(y0 + yl + o) * W + x] = (int32_t)rshr_he64((int64_t)alpha * acc[o], 30 - kFBits);
+    }
 }
 
 // ---------------------------------------------------------------- box-cascade field (approximate, opt-in)
@@ -792,11 +808,12 @@ hipError_t launch_elastic_fields(uint64_t seed, uint64_t first, int n, int H, in
     const int strips = ((W + kVCols - 1) / kVCols) * ((H + kVRows - 1) / kVRows);
     const int ntp = (2 * radius + 1 + kVPer - 1) / kVPer * kVPer;
     const size_t lds = sizeof(int32_t) * (ntp + (size_t)(kVRows + 2 * radius + kVPer) * kVCols);
-    if (tmax < 32768) {  // the packed form, which falls back to the int32 form per strip; LDS for either
+    if (tmax < 32768) {  // the packed form
         const int npair = ((2 * radius + 1 + 1) / 2 + 3) / 4 * 4;
         const size_t lds2 = sizeof(uint32_t) * (npair + (size_t)v2_pairs(radius) * kVCols);
-        hipLaunchKernelGGL(k_field_v2, dim3(strips, 2, n), dim3(kThreads), lds2 > lds ? lds2 : lds, s, H, W, radius,
-                           alpha, dtaps, hbuf, off);
+        const int strips2 = ((W + kVCols - 1) / kVCols) * ((H + kV2Rows - 1) / kV2Rows);
+        hipLaunchKernelGGL(k_field_v2, dim3(strips2, 2, n), dim3(kThreads), lds2, s, H, W, radius, alpha, dtaps, hbuf,
+                           off);
     } else {
         hipLaunchKernelGGL(k_field_v, dim3(strips, 2, n), dim3(kThreads), lds, s, H, W, radius, alpha, dtaps, hbuf,
                            off);
