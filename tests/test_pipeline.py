@@ -219,6 +219,44 @@ def test_ragged_pipeline_graph_takes_new_records_each_replay(ctx):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("ops", [
+    [("BLUR5", 0.5)],
+    [("HSV", 0.7, (-20, -30, -10), (20, 30, 10))],
+    [("HFLIP", 0.5), ("BRIGHT_CONTRAST", 0.8, (0.8, -51), (1.2, 51)), ("GAMMA", 0.8, (0.7,), (1.4,))],
+])
+def test_new_chains_graph_replays_take_new_records(ctx, ops):
+    # captured once, replayed with fresh records (eager work and a synchronisation between
+    # replays); every replay equals the eager apply of the same records, masks included
+    import torch
+    n, H, W = 4, 35, 52
+    rng = np.random.default_rng(len(ops))
+    imgs = rng.integers(0, 256, (n, H, W, 3), dtype=np.uint8)
+    masks = rng.integers(0, 9, (n, H, W), dtype=np.uint8)
+    p = m.Pipeline(ctx, [op(*o) for o in ops])
+    x, xm = torch.from_numpy(imgs).cuda(), torch.from_numpy(masks).cuda()
+    out, om = torch.empty_like(x), torch.empty_like(xm)
+    bi, bo, _ = p.batch(img=x, mask=xm)
+    bo.img, bo.mask = out.data_ptr(), om.data_ptr()
+    s = torch.cuda.Stream()
+    g = p.graph(bi, bo, s)
+    ref, rm = torch.empty_like(out), torch.empty_like(om)
+    bo2 = type(bo).from_buffer_copy(bo)
+    bo2.img, bo2.mask = ref.data_ptr(), rm.data_ptr()
+    for rep in range(3):
+        recs = p.sample(40 + rep, 0, n)
+        g.launch(recs, s)
+        s.synchronize()
+        p.apply(bi, bo2, recs)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        assert torch.equal(om, rm), rep
+        out.zero_()
+        om.zero_()
+        torch.cuda.synchronize()
+    g.close()
+
+
+@pytest.mark.gpu
 def test_u8_chain_pipeline_matches_the_oracle_ops_including_value_shift(ctx):
     import torch
     n, H, W, crop, outsz = 5, 96, 80, 64, 40
