@@ -466,118 +466,305 @@ __global__ void k_grid_tables(const double *__restrict__ grid, int H, int W, int
 }
 
 // ---------------------------------------------------------------- u8 remap chain
-constexpr int kRT = 32;       // output tile
-constexpr int kRE = 64;       // max e-block side held in LDS (grid factors up to ~1.9)
+constexpr int kRT = 32;  // output tile side
+constexpr int kRE = 48;  // max side of the e-block held in LDS (grid factors up to ~1.4)
+constexpr int kRS = 64;  // max side of the source block the e-block's displaced taps read
+constexpr int kREPer = (kRE * kRE + kThreads - 1) / kThreads;  // e-block entries per thread
+constexpr int kRSPer = (kRS * kRS + kThreads - 1) / kThreads;  // source-block entries per thread
+
+// reflect-101 with the in-range case inline and the rest out of line
+__device__ __noinline__ int reflect101_far(int i, int n) { return reflect101(i, n); }
+__device__ __forceinline__ int refl(int i, int n) { return (unsigned)i < (unsigned)n ? i : reflect101_far(i, n); }
+// reflect-101 of i in [-(n - 1), 2n - 2] (at most one reflection), branch-free
+__device__ __forceinline__ int refl1(int i, int n) {
+    const int a = i < 0 ? -i : i;
+    return a >= n ? 2 * n - 2 - a : a;
+}
+__device__ __forceinline__ bool near_range(int lo, int hi, int n) { return lo >= -(n - 1) && hi <= 2 * n - 2; }
 
 __device__ __forceinline__ uint32_t load_px(const uint8_t *p, int C) {
     if (C == 1) return p[0];
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t *w = (const uint32_t *)(a & ~(uintptr_t)3);
-    const int sh = (int)(a & 3);
+    const int sh = (int)((uintptr_t)p & 3);
+    const uint32_t *w = (const uint32_t *)(p - sh);  // pointer arithmetic keeps the global address space
     const uint32_t lo = w[0];
     if (sh + C <= 4) return lo >> (8 * sh);
     return __builtin_amdgcn_alignbyte(w[1], lo, sh);
 }
 
-__device__ __forceinline__ uint32_t blend_u8(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, int ax, int ay,
-                                             int C) {
+// The pixel at byte offset b from the word-aligned base wb, without branches:
+// the second word is clamped to last_dw, the word holding the image's last
+// byte.  Bytes above C of the result are unspecified.
+template <int C>
+__device__ __forceinline__ uint32_t load_px_nb(const uint32_t *wb, uint32_t b, uint32_t last_dw) {
+    const uint32_t d = b >> 2;
+    const uint32_t lo = wb[d];
+    if (C == 1) return lo >> (8 * (b & 3));
+    return __builtin_amdgcn_alignbyte(wb[min(d + 1, last_dw)], lo, b & 3);
+}
+
+// Bilinear blend of four packed pixels with Q10 weights, rounded half to even
+// (2^20 is the product of the weights' scales).  Per channel the row sums
+// t = a0 (1024 - ax) + a1 ax take one permute (the two bytes into 16-bit
+// lanes) and one packed 16-bit dot product, exact in int32; then
+// t0 (1024 - ay) + t1 ay with 24-bit multiplies.  wx = (1024 - ax) | ax << 16.
+template <int C>
+__device__ __forceinline__ uint32_t blend_px(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, uint32_t wx,
+                                             int ay) {
     uint32_t out = 0;
+#pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int a00 = (p00 >> (8 * c)) & 255, a01 = (p01 >> (8 * c)) & 255;
-        const int a10 = (p10 >> (8 * c)) & 255, a11 = (p11 >> (8 * c)) & 255;
-        const int t0 = (a00 << kFBits) + ax * (a01 - a00);
-        const int t1 = (a10 << kFBits) + ax * (a11 - a10);
-        const int acc = (t0 << kFBits) + ay * (t1 - t0);
-        out |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
+        const uint32_t sel = (uint32_t)c | 0x0c00u | (uint32_t)(4 + c) << 16 | 0x0c000000u;
+        const uint32_t t0 = (uint32_t)dot2(__builtin_amdgcn_perm(p01, p00, sel), wx, 0);
+        const uint32_t t1 = (uint32_t)dot2(__builtin_amdgcn_perm(p11, p10, sel), wx, 0);
+        const uint32_t acc = umad24(t0, (uint32_t)(kFOne - ay), umad24(t1, (uint32_t)ay, 0u));
+        out |= ((acc + 0x7FFFFu + ((acc >> 20) & 1u)) >> 20) << (8 * c);
     }
     return out;
 }
 
-// Elastic result at pixel (Y, X) (already inside the image).
-__device__ __forceinline__ uint32_t elastic_px(const uint8_t *img, int H, int W, int C, const int32_t *ox,
-                                               const int32_t *oy, int Y, int X) {
-    const size_t e = (size_t)Y * W + X;
-    const int qx = (X << kFBits) + ox[e], qy = (Y << kFBits) + oy[e];
-    int x0 = qx >> kFBits, y0 = qy >> kFBits;
-    const int ax = qx & (kFOne - 1), ay = qy & (kFOne - 1);
-    int x1 = x0 + 1, y1 = y0 + 1;
-    if (x0 < 0 || x1 >= W) { x0 = reflect101(x0, W); x1 = reflect101(x1, W); }
-    if (y0 < 0 || y1 >= H) { y0 = reflect101(y0, H); y1 = reflect101(y1, H); }
-    return blend_u8(load_px(img + ((size_t)y0 * W + x0) * C, C), load_px(img + ((size_t)y0 * W + x1) * C, C),
-                    load_px(img + ((size_t)y1 * W + x0) * C, C), load_px(img + ((size_t)y1 * W + x1) * C, C), ax, ay,
-                    C);
+__device__ __forceinline__ uint32_t wx_pair(int ax) { return (uint32_t)(kFOne - ax) | (uint32_t)ax << 16; }
+
+// Displaced Q10 position of the e pixel (Y, X) (inside the image).
+__device__ __forceinline__ void displaced(const int32_t *ox, const int32_t *oy, int W, int Y, int X, int &qx,
+                                          int &qy) {
+    const uint32_t e = (uint32_t)Y * W + X;
+    qx = (X << kFBits) + ox[e];
+    qy = (Y << kFBits) + oy[e];
 }
 
-__device__ __forceinline__ uint8_t elastic_mask(const uint8_t *m, int H, int W, const int32_t *ox, const int32_t *oy,
-                                                int Y, int X) {
-    const size_t e = (size_t)Y * W + X;
-    const int qx = (X << kFBits) + ox[e], qy = (Y << kFBits) + oy[e];
-    return m[(size_t)reflect101((qy + kFOne / 2) >> kFBits, H) * W + reflect101((qx + kFOne / 2) >> kFBits, W)];
+// Elastic result at the displaced position (qx, qy): four taps read from global memory.
+template <int C>
+__device__ __noinline__ uint32_t elastic_at(const uint8_t *img, int H, int W, int qx, int qy) {
+    const int x0 = qx >> kFBits, y0 = qy >> kFBits;
+    const int X0 = refl(x0, W), X1 = refl(x0 + 1, W), Y0 = refl(y0, H), Y1 = refl(y0 + 1, H);
+    return blend_px<C>(load_px(img + ((uint32_t)Y0 * W + X0) * C, C), load_px(img + ((uint32_t)Y0 * W + X1) * C, C),
+                       load_px(img + ((uint32_t)Y1 * W + X0) * C, C), load_px(img + ((uint32_t)Y1 * W + X1) * C, C),
+                       wx_pair(qx & (kFOne - 1)), qy & (kFOne - 1));
 }
 
-__global__ __launch_bounds__(kThreads) void k_remap_chain_u8(const uint8_t *__restrict__ img,
-                                                             const uint8_t *__restrict__ mask, int H, int W, int C,
-                                                             const int32_t *__restrict__ off,
-                                                             const int32_t *__restrict__ mapx,
-                                                             const int32_t *__restrict__ mapy,
-                                                             uint8_t *__restrict__ out, uint8_t *__restrict__ out_mask,
-                                                             int img_index) {
-    __shared__ uint32_t eb[kRE][kRE];
-    __shared__ uint8_t em[kRE][kRE];
+__device__ __forceinline__ uint8_t nearest_at(const uint8_t *m, int H, int W, int qx, int qy) {
+    return m[(uint32_t)refl((qy + kFOne / 2) >> kFBits, H) * W + refl((qx + kFOne / 2) >> kFBits, W)];
+}
+
+// Output pixel at grid position (gx, gy) with every tap from global memory (tiles whose
+// e-block does not fit in LDS).
+template <int C>
+__device__ __noinline__ void remap_direct(const uint8_t *src, const uint8_t *msrc, int H, int W, const int32_t *ox,
+                                          const int32_t *oy, int gx, int gy, uint32_t &v, uint32_t &mv) {
+    const int cx = gx >> kFBits, cy = gy >> kFBits;
+    const int X0 = refl(cx, W), X1 = refl(cx + 1, W), Y0 = refl(cy, H), Y1 = refl(cy + 1, H);
+    int q[8];
+    displaced(ox, oy, W, Y0, X0, q[0], q[1]);
+    displaced(ox, oy, W, Y0, X1, q[2], q[3]);
+    displaced(ox, oy, W, Y1, X0, q[4], q[5]);
+    displaced(ox, oy, W, Y1, X1, q[6], q[7]);
+    v = blend_px<C>(elastic_at<C>(src, H, W, q[0], q[1]), elastic_at<C>(src, H, W, q[2], q[3]),
+                    elastic_at<C>(src, H, W, q[4], q[5]), elastic_at<C>(src, H, W, q[6], q[7]),
+                    wx_pair(gx & (kFOne - 1)), gy & (kFOne - 1));
+    mv = 0;
+    if (msrc) {
+        int mqx, mqy;
+        displaced(ox, oy, W, refl((gy + kFOne / 2) >> kFBits, H), refl((gx + kFOne / 2) >> kFBits, W), mqx, mqy);
+        mv = nearest_at(msrc, H, W, mqx, mqy);
+    }
+}
+
+// Four packed pixels of C bytes as C little-endian words.
+template <int C>
+__device__ __forceinline__ void store4(uint8_t *o, const uint32_t v[4]) {
+    if (C == 1) {
+        *(uint32_t *)o = (v[0] & 255) | (v[1] & 255) << 8 | (v[2] & 255) << 16 | v[3] << 24;
+    } else if (C == 3) {
+        uint32_t *w = (uint32_t *)o;
+        w[0] = (v[0] & 0xFFFFFF) | v[1] << 24;
+        w[1] = (v[1] >> 8 & 0xFFFF) | v[2] << 16;
+        w[2] = (v[2] >> 16 & 0xFF) | v[3] << 8;
+    } else {
+        uint4 q;
+        q.x = v[0]; q.y = v[1]; q.z = v[2]; q.w = v[3];
+        *(uint4 *)o = q;
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_remap_chain_u8(
+    const uint8_t *__restrict__ img, const uint8_t *__restrict__ mask, int H, int W, const int32_t *__restrict__ off,
+    const int32_t *__restrict__ mapx, const int32_t *__restrict__ mapy, uint8_t *__restrict__ out,
+    uint8_t *__restrict__ out_mask, int img_index, int vec) {
+    __shared__ uint32_t ss[kRS * kRS];  // source block, one pixel per word
+    __shared__ uint8_t sm[kRS * kRS];   // its mask
+    __shared__ uint32_t eb[kRE * kRE];  // e-block
+    __shared__ uint8_t em[kRE * kRE];
     __shared__ int32_t qx[kRT], qy[kRT];
+    __shared__ int red[kThreads / 64][4];
+    __shared__ int rng[2][2];
+    const int tid = (int)threadIdx.x;
     const int im = img_index >= 0 ? img_index : (int)blockIdx.y;
     const int tiles_x = (W + kRT - 1) / kRT;
-    const int x0 = (blockIdx.x % tiles_x) * kRT, y0 = (blockIdx.x / tiles_x) * kRT;
+    // Workgroups go round-robin to the 8 XCDs, each with its own L2; neighbouring
+    // tiles share cache lines of every plane, so XCD b % 8 takes the b % 8-th
+    // contiguous eighth of the tiles (when the count divides by 8).
+    const int nt = (int)gridDim.x;
+    const int t = (nt & 7) == 0 ? ((int)blockIdx.x & 7) * (nt >> 3) + ((int)blockIdx.x >> 3) : (int)blockIdx.x;
+    const int x0 = (t % tiles_x) * kRT, y0 = (t / tiles_x) * kRT;
     const int tw = min(kRT, W - x0), th = min(kRT, H - y0);
     const size_t plane = (size_t)H * W;
     const uint8_t *src = img + (size_t)im * plane * C;
     const uint8_t *msrc = mask ? mask + (size_t)im * plane : nullptr;
     const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
     const int32_t *mx = mapx + (size_t)im * W, *my = mapy + (size_t)im * H;
-    if (threadIdx.x < tw) qx[threadIdx.x] = mx[x0 + threadIdx.x];
-    if (threadIdx.x >= 64 && threadIdx.x - 64 < th) qy[threadIdx.x - 64] = my[y0 + threadIdx.x - 64];
-    __syncthreads();
     // e rows/columns the tile's grid taps read (pre-reflection ranges; the
-    // extremes are taken over every entry, so any table is handled)
-    int c_lo = qx[0] >> kFBits, c_hi = c_lo, r_lo = qy[0] >> kFBits, r_hi = r_lo;
-    for (int i = 1; i < tw; ++i) { c_lo = min(c_lo, qx[i] >> kFBits); c_hi = max(c_hi, qx[i] >> kFBits); }
-    for (int i = 1; i < th; ++i) { r_lo = min(r_lo, qy[i] >> kFBits); r_hi = max(r_hi, qy[i] >> kFBits); }
-    c_hi += 1;
-    r_hi += 1;
-    const int ew = c_hi - c_lo + 1, eh = r_hi - r_lo + 1;
-    const bool staged = ew <= kRE && eh <= kRE;
-    if (staged) {
-        for (int e = threadIdx.x; e < ew * eh; e += kThreads) {
-            const int r = e / ew, c = e - r * ew;
-            const int Y = reflect101(r_lo + r, H), X = reflect101(c_lo + c, W);
-            eb[r][c] = elastic_px(src, H, W, C, ox, oy, Y, X);
-            if (msrc) em[r][c] = elastic_mask(msrc, H, W, ox, oy, Y, X);
+    // extremes are taken over every entry, so any table is handled): wave 0
+    // reduces the tile's columns, wave 1 its rows
+    if (tid < 128) {
+        const int lane = tid & 63, cnt = tid < 64 ? tw : th;
+        int lo = INT_MAX, hi = INT_MIN;
+        if (lane < cnt) {
+            const int q = tid < 64 ? mx[x0 + lane] : my[y0 + lane];
+            (tid < 64 ? qx : qy)[lane] = q;
+            lo = hi = q >> kFBits;
+        }
+        for (int o = 16; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o));
+            hi = max(hi, __shfl_xor(hi, o));
+        }
+        if (lane == 0) {
+            rng[tid >> 6][0] = lo;
+            rng[tid >> 6][1] = hi;
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < tw * th; e += kThreads) {
-        const int r = e / tw, c = e - r * tw;
-        const int gx = qx[c], gy = qy[r];
-        const int cx = gx >> kFBits, cy = gy >> kFBits;
-        const int ax = gx & (kFOne - 1), ay = gy & (kFOne - 1);
-        uint32_t v;
-        uint8_t mv = 0;
-        if (staged) {
-            v = blend_u8(eb[cy - r_lo][cx - c_lo], eb[cy - r_lo][cx + 1 - c_lo], eb[cy + 1 - r_lo][cx - c_lo],
-                         eb[cy + 1 - r_lo][cx + 1 - c_lo], ax, ay, C);
-            if (msrc) mv = em[((gy + kFOne / 2) >> kFBits) - r_lo][((gx + kFOne / 2) >> kFBits) - c_lo];
-        } else {
-            const int X0 = reflect101(cx, W), X1 = reflect101(cx + 1, W);
-            const int Y0 = reflect101(cy, H), Y1 = reflect101(cy + 1, H);
-            v = blend_u8(elastic_px(src, H, W, C, ox, oy, Y0, X0), elastic_px(src, H, W, C, ox, oy, Y0, X1),
-                         elastic_px(src, H, W, C, ox, oy, Y1, X0), elastic_px(src, H, W, C, ox, oy, Y1, X1), ax, ay, C);
-            if (msrc)
-                mv = elastic_mask(msrc, H, W, ox, oy, reflect101((gy + kFOne / 2) >> kFBits, H),
-                                  reflect101((gx + kFOne / 2) >> kFBits, W));
+    const int c_lo = rng[0][0], c_hi = rng[0][1] + 1, r_lo = rng[1][0], r_hi = rng[1][1] + 1;
+    const int ew = c_hi - c_lo + 1, eh = r_hi - r_lo + 1;
+    // the e-block is held in LDS when it fits and lies within one reflection of the image
+    const bool staged = ew <= kRE && eh <= kRE && near_range(c_lo, c_hi, W) && near_range(r_lo, r_hi, H);
+    if (staged) {
+        // displaced positions of this thread's e-block entries e = tid + k kThreads
+        // (row-major over ew x eh; entries past the end repeat the last one, so the
+        // code is branch-free and every load of the phase is in flight at once)
+        const int ne = ew * eh, kn = (ne + kThreads - 1) / kThreads;
+        const float rcp_ew = 1.0f / (float)ew;
+        int sx[kREPer], sy[kREPer];
+#pragma unroll
+        for (int k = 0; k < kREPer; ++k) {
+            if (k < kn) {
+                const int e = min(tid + k * kThreads, ne - 1);
+                const int r = (int)(((float)e + 0.5f) * rcp_ew), c = e - r * ew;
+                const uint32_t i = (uint32_t)refl1(r_lo + r, H) * W + refl1(c_lo + c, W);
+                sx[k] = ox[i];
+                sy[k] = oy[i];
+            }
         }
-        uint8_t *o = out + ((size_t)im * plane + (size_t)(y0 + r) * W + x0 + c) * C;
-        for (int ch = 0; ch < C; ++ch) o[ch] = (uint8_t)(v >> (8 * ch));
-        if (msrc) out_mask[(size_t)im * plane + (size_t)(y0 + r) * W + x0 + c] = mv;
+        int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+#pragma unroll
+        for (int k = 0; k < kREPer; ++k) {
+            if (k < kn) {
+                const int e = min(tid + k * kThreads, ne - 1);
+                const int r = (int)(((float)e + 0.5f) * rcp_ew), c = e - r * ew;
+                sx[k] += refl1(c_lo + c, W) << kFBits;
+                sy[k] += refl1(r_lo + r, H) << kFBits;
+                lx = min(lx, sx[k] >> kFBits);
+                hx = max(hx, sx[k] >> kFBits);
+                ly = min(ly, sy[k] >> kFBits);
+                hy = max(hy, sy[k] >> kFBits);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            lx = min(lx, __shfl_xor(lx, o));
+            hx = max(hx, __shfl_xor(hx, o));
+            ly = min(ly, __shfl_xor(ly, o));
+            hy = max(hy, __shfl_xor(hy, o));
+        }
+        if ((tid & 63) == 0) {
+            int *rw = red[tid >> 6];
+            rw[0] = lx; rw[1] = hx; rw[2] = ly; rw[3] = hy;
+        }
+        __syncthreads();
+        lx = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+        hx = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1])) + 1;
+        ly = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+        hy = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3])) + 1;
+        const int sw = hx - lx + 1, sh = hy - ly + 1;
+        if (sw <= kRS && sh <= kRS && near_range(lx, hx, W) && near_range(ly, hy, H)) {
+            // the source block (pre-reflection rows ly..hy, columns lx..hx), read
+            // once: all loads into registers, then into LDS (entry e at e = r sw + c)
+            const int ns = sw * sh, kns = (ns + kThreads - 1) / kThreads;
+            const float rcp_sw = 1.0f / (float)sw;
+            const int mis = (int)((uintptr_t)src & 3);
+            const uint32_t *wsrc = (const uint32_t *)(src - mis);
+            const uint32_t last_dw = (uint32_t)((plane * C - 1 + mis) >> 2);
+            uint32_t pv[kRSPer], mk[kRSPer];
+#pragma unroll
+            for (int k = 0; k < kRSPer; ++k) {
+                if (k < kns) {
+                    const int e = min(tid + k * kThreads, ns - 1);
+                    const int r = (int)(((float)e + 0.5f) * rcp_sw), c = e - r * sw;
+                    const uint32_t p = (uint32_t)refl1(ly + r, H) * W + refl1(lx + c, W);
+                    pv[k] = load_px_nb<C>(wsrc, p * C + mis, last_dw);
+                    if (msrc) mk[k] = msrc[p];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kRSPer; ++k) {
+                if (k < kns) {
+                    const int e = min(tid + k * kThreads, ns - 1);
+                    ss[e] = pv[k];
+                    if (msrc) sm[e] = (uint8_t)mk[k];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kREPer; ++k) {
+                if (k < kn) {
+                    const int e = min(tid + k * kThreads, ne - 1);
+                    const uint32_t *p = ss + ((sy[k] >> kFBits) - ly) * sw + (sx[k] >> kFBits) - lx;
+                    eb[e] = blend_px<C>(p[0], p[1], p[sw], p[sw + 1], wx_pair(sx[k] & (kFOne - 1)), sy[k] & (kFOne - 1));
+                    if (msrc)
+                        em[e] = sm[(((sy[k] + kFOne / 2) >> kFBits) - ly) * sw + ((sx[k] + kFOne / 2) >> kFBits) - lx];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kREPer; ++k) {
+                if (k < kn) {
+                    const int e = min(tid + k * kThreads, ne - 1);
+                    eb[e] = elastic_at<C>(src, H, W, sx[k], sy[k]);
+                    if (msrc) em[e] = nearest_at(msrc, H, W, sx[k], sy[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // four consecutive outputs of one row per thread
+    const int rr = tid >> 3, c0 = (tid & 7) * 4;
+    if (rr >= th || c0 >= tw) return;
+    const int gy = qy[rr], cy = gy >> kFBits, ay = gy & (kFOne - 1);
+    const int nc = min(4, tw - c0);
+    uint32_t v[4] = {0, 0, 0, 0}, mv[4] = {0, 0, 0, 0};
+    if (staged) {
+        const uint32_t *erow = eb + (cy - r_lo) * ew - c_lo;
+        const uint8_t *mrow = em + (((gy + kFOne / 2) >> kFBits) - r_lo) * ew - c_lo;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gx = qx[min(c0 + j, tw - 1)], cx = gx >> kFBits;
+            const uint32_t *p = erow + cx;
+            v[j] = blend_px<C>(p[0], p[1], p[ew], p[ew + 1], wx_pair(gx & (kFOne - 1)), ay);
+            if (msrc) mv[j] = mrow[(gx + kFOne / 2) >> kFBits];
+        }
+    } else {
+        for (int j = 0; j < nc; ++j) remap_direct<C>(src, msrc, H, W, ox, oy, qx[c0 + j], gy, v[j], mv[j]);
+    }
+    uint8_t *dst = out + (size_t)im * plane * C;
+    uint8_t *mdst = msrc ? out_mask + (size_t)im * plane : nullptr;
+    const uint32_t o = (uint32_t)(y0 + rr) * W + x0 + c0;
+    if (vec && nc == 4) {  // o is a multiple of 4 (W is)
+        store4<C>(dst + o * C, v);
+        if (msrc) *(uint32_t *)(mdst + o) = mv[0] | mv[1] << 8 | mv[2] << 16 | mv[3] << 24;
+    } else {
+        for (int j = 0; j < nc; ++j) {
+            for (int ch = 0; ch < C; ++ch) dst[(o + j) * C + ch] = (uint8_t)(v[j] >> (8 * ch));
+            if (msrc) mdst[o + j] = (uint8_t)mv[j];
+        }
     }
 }
 
@@ -830,19 +1017,30 @@ hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *
 hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
                                   const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
                                   uint8_t *out_mask, int per_image, hipStream_t s) {
+    if (n == 0 || H == 0 || W == 0) return hipSuccess;
     const int tiles = ((W + kRT - 1) / kRT) * ((H + kRT - 1) / kRT);
+    // packed stores of four pixels when every group of four starts on a word
+    const int vec = W % 4 == 0 && (uintptr_t)out % 4 == 0 && (uintptr_t)out_mask % 4 == 0;
+    auto go = [&](dim3 grid, int index) {
+        if (C == 1)
+            hipLaunchKernelGGL((k_remap_chain_u8<1>), grid, dim3(kThreads), 0, s, img, mask, H, W, off, mapx, mapy,
+                               out, out_mask, index, vec);
+        else if (C == 3)
+            hipLaunchKernelGGL((k_remap_chain_u8<3>), grid, dim3(kThreads), 0, s, img, mask, H, W, off, mapx, mapy,
+                               out, out_mask, index, vec);
+        else
+            hipLaunchKernelGGL((k_remap_chain_u8<4>), grid, dim3(kThreads), 0, s, img, mask, H, W, off, mapx, mapy,
+                               out, out_mask, index, vec);
+        return hipGetLastError();
+    };
     if (per_image) {
         for (int i = 0; i < n; ++i) {
-            hipLaunchKernelGGL(k_remap_chain_u8, dim3(tiles, 1), dim3(kThreads), 0, s, img, mask, H, W, C, off, mapx,
-                               mapy, out, out_mask, i);
-            hipError_t e = hipGetLastError();
+            hipError_t e = go(dim3(tiles, 1), i);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     }
-    hipLaunchKernelGGL(k_remap_chain_u8, dim3(tiles, n), dim3(kThreads), 0, s, img, mask, H, W, C, off, mapx, mapy, out,
-                       out_mask, -1);
-    return hipGetLastError();
+    return go(dim3(tiles, n), -1);
 }
 
 size_t chain_f32_workspace_bytes(int n, int C, int H, int W) { return (size_t)n * C * H * W * sizeof(float); }

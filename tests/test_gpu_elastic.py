@@ -70,6 +70,32 @@ def test_u8_chain_bit_exact_and_batched_equals_per_image(m, H, W, C):
         assert np.array_equal(om[i], rm), i
 
 
+@pytest.mark.parametrize("H,W,C,sigma,alpha,radius,limit", [
+    (130, 260, 3, 50.0, 1000, 150, 0.3),   # the large-image field: every source block staged
+    (70, 96, 4, 1.5, 300, 5, 0.3),         # rough, large displacements: source blocks too wide for LDS
+    (70, 96, 4, 3.0, 150, 9, 0.3),         # source blocks of both kinds, some exactly 64 rows
+    (150, 170, 3, 4.0, 80, 12, 0.95),      # grid steps up to 1.95x: e-blocks too wide for LDS, all three paths
+    (37, 44, 1, 3.0, 60, 9, 0.6),          # W % 4 == 0 with a ragged last tile
+])
+def test_u8_chain_staging_paths_bit_exact(m, H, W, C, sigma, alpha, radius, limit):
+    import torch
+    n = 2
+    img = synth.smooth_u8_hwc(H + 7 * W + C, n, H, W, C)
+    mask = synth.blob_masks(H * W, n, H, W, 8, 16)
+    off = m.elastic_fields(5, 0, n, H, W, sigma, alpha, radius)
+    g = m.sample_grid(5, 0, n, limit)
+    mx, my = m.grid_tables(torch.from_numpy(g).cuda(), H, W)
+    out, om = m.elastic_grid_u8(img.cuda(), off, mx, my, mask.cuda())
+    out2, _ = m.elastic_grid_u8(img.cuda(), off, mx, my, None)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    out, om = out.cpu().numpy(), om.cpu().numpy()
+    for i in range(n):
+        ref, rm = oracle.pipe_elastic_grid_one(img[i].numpy(), mask[i].numpy(), 5, i, g[i], sigma, alpha, radius)
+        assert np.array_equal(out[i], ref), i
+        assert np.array_equal(om[i], rm), i
+
+
 def test_f32_chain_forward_and_adjoint(m):
     import torch
     n, C, H, W = 2, 3, 48, 40
