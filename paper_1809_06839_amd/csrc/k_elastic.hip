@@ -467,8 +467,9 @@ __global__ void k_grid_tables(const double *__restrict__ grid, int H, int W, int
 
 // ---------------------------------------------------------------- u8 remap chain
 constexpr int kRT = 32;  // output tile side
-constexpr int kRE = 48;  // max side of the e-block held in LDS (grid factors up to ~1.4)
-constexpr int kRS = 64;  // max side of the source block the e-block's displaced taps read
+constexpr int kRE = 44;  // max side of the e-block held in LDS (grid factors up to ~1.3)
+constexpr int kRS = 56;  // max side of the source block the e-block's displaced taps read
+// (about 25 KB of LDS: three workgroups in each half of a CU's LDS)
 constexpr int kREPer = (kRE * kRE + kThreads - 1) / kThreads;  // e-block entries per thread
 constexpr int kRSPer = (kRS * kRS + kThreads - 1) / kThreads;  // source-block entries per thread
 
@@ -489,17 +490,6 @@ __device__ __forceinline__ uint32_t load_px(const uint8_t *p, int C) {
     const uint32_t lo = w[0];
     if (sh + C <= 4) return lo >> (8 * sh);
     return __builtin_amdgcn_alignbyte(w[1], lo, sh);
-}
-
-// The pixel at byte offset b from the word-aligned base wb, without branches:
-// the second word is clamped to last_dw, the word holding the image's last
-// byte.  Bytes above C of the result are unspecified.
-template <int C>
-__device__ __forceinline__ uint32_t load_px_nb(const uint32_t *wb, uint32_t b, uint32_t last_dw) {
-    const uint32_t d = b >> 2;
-    const uint32_t lo = wb[d];
-    if (C == 1) return lo >> (8 * (b & 3));
-    return __builtin_amdgcn_alignbyte(wb[min(d + 1, last_dw)], lo, b & 3);
 }
 
 // Bilinear blend of four packed pixels with Q10 weights, rounded half to even
@@ -587,7 +577,7 @@ __device__ __forceinline__ void store4(uint8_t *o, const uint32_t v[4]) {
 }
 
 template <int C>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_remap_chain_u8(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_remap_chain_u8(
     const uint8_t *__restrict__ img, const uint8_t *__restrict__ mask, int H, int W, const int32_t *__restrict__ off,
     const int32_t *__restrict__ mapx, const int32_t *__restrict__ mapy, uint8_t *__restrict__ out,
     uint8_t *__restrict__ out_mask, int img_index, int vec) {
@@ -639,30 +629,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
     // the e-block is held in LDS when it fits and lies within one reflection of the image
     const bool staged = ew <= kRE && eh <= kRE && near_range(c_lo, c_hi, W) && near_range(r_lo, r_hi, H);
     if (staged) {
-        // displaced positions of this thread's e-block entries e = tid + k kThreads
-        // (row-major over ew x eh; entries past the end repeat the last one, so the
-        // code is branch-free and every load of the phase is in flight at once)
-        const int ne = ew * eh, kn = (ne + kThreads - 1) / kThreads;
-        const float rcp_ew = 1.0f / (float)ew;
-        int sx[kREPer], sy[kREPer];
+        // Pass 1, rows of the e-block over the waves (row wave + 4k) and columns
+        // over the lanes (lanes past ew repeat the last column; rows past eh the
+        // last row): displaced Q10 position of every entry, every load of the
+        // phase in flight at once, and the source rows/columns their taps read.
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        const int ex = refl1(c_lo + min(lane, ew - 1), W);
+        int sx[kRE / 4], sy[kRE / 4];
 #pragma unroll
-        for (int k = 0; k < kREPer; ++k) {
-            if (k < kn) {
-                const int e = min(tid + k * kThreads, ne - 1);
-                const int r = (int)(((float)e + 0.5f) * rcp_ew), c = e - r * ew;
-                const uint32_t i = (uint32_t)refl1(r_lo + r, H) * W + refl1(c_lo + c, W);
-                sx[k] = ox[i];
-                sy[k] = oy[i];
+        for (int k = 0; k < kRE / 4; ++k) {
+            if (4 * k < eh) {
+                const int ey = refl1(r_lo + min(wave + 4 * k, eh - 1), H);
+                sx[k] = ox[(uint32_t)ey * W + ex];
+                sy[k] = oy[(uint32_t)ey * W + ex];
             }
         }
         int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
 #pragma unroll
-        for (int k = 0; k < kREPer; ++k) {
-            if (k < kn) {
-                const int e = min(tid + k * kThreads, ne - 1);
-                const int r = (int)(((float)e + 0.5f) * rcp_ew), c = e - r * ew;
-                sx[k] += refl1(c_lo + c, W) << kFBits;
-                sy[k] += refl1(r_lo + r, H) << kFBits;
+        for (int k = 0; k < kRE / 4; ++k) {
+            if (4 * k < eh) {
+                const int ey = refl1(r_lo + min(wave + 4 * k, eh - 1), H);
+                sx[k] += ex << kFBits;
+                sy[k] += ey << kFBits;
                 lx = min(lx, sx[k] >> kFBits);
                 hx = max(hx, sx[k] >> kFBits);
                 ly = min(ly, sy[k] >> kFBits);
@@ -675,8 +663,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
             ly = min(ly, __shfl_xor(ly, o));
             hy = max(hy, __shfl_xor(hy, o));
         }
-        if ((tid & 63) == 0) {
-            int *rw = red[tid >> 6];
+        if (lane == 0) {
+            int *rw = red[wave];
             rw[0] = lx; rw[1] = hx; rw[2] = ly; rw[3] = hy;
         }
         __syncthreads();
@@ -685,49 +673,65 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
         ly = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
         hy = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3])) + 1;
         const int sw = hx - lx + 1, sh = hy - ly + 1;
+        const int ne = ew * eh;
         if (sw <= kRS && sh <= kRS && near_range(lx, hx, W) && near_range(ly, hy, H)) {
+            // each entry's taps as one word in eb: source-block index of the top-left
+            // tap (12 bits), ax (10 bits), ay (10 bits); the blend pass replaces it
+#pragma unroll
+            for (int k = 0; k < kRE / 4; ++k) {
+                if (4 * k < eh && lane < ew && wave + 4 * k < eh)
+                    eb[(wave + 4 * k) * ew + lane] = (uint32_t)(((sy[k] >> kFBits) - ly) * sw + (sx[k] >> kFBits) - lx) |
+                                                     (uint32_t)(sx[k] & (kFOne - 1)) << 12 |
+                                                     (uint32_t)(sy[k] & (kFOne - 1)) << 22;
+            }
             // the source block (pre-reflection rows ly..hy, columns lx..hx), read
-            // once: all loads into registers, then into LDS (entry e at e = r sw + c)
-            const int ns = sw * sh, kns = (ns + kThreads - 1) / kThreads;
-            const float rcp_sw = 1.0f / (float)sw;
+            // once with the same row/lane split: all loads, then the LDS writes
             const int mis = (int)((uintptr_t)src & 3);
             const uint32_t *wsrc = (const uint32_t *)(src - mis);
             const uint32_t last_dw = (uint32_t)((plane * C - 1 + mis) >> 2);
-            uint32_t pv[kRSPer], mk[kRSPer];
+            const int sxc = refl1(lx + min(lane, sw - 1), W);
+            // the mask byte is loaded unconditionally (from the image when there is
+            // no mask), so no branch splits the batch of loads
+            const uint8_t *mload = msrc ? msrc : src;
+            uint32_t plo[kRS / 4], phi[kRS / 4], mk[kRS / 4];
 #pragma unroll
-            for (int k = 0; k < kRSPer; ++k) {
-                if (k < kns) {
-                    const int e = min(tid + k * kThreads, ns - 1);
-                    const int r = (int)(((float)e + 0.5f) * rcp_sw), c = e - r * sw;
-                    const uint32_t p = (uint32_t)refl1(ly + r, H) * W + refl1(lx + c, W);
-                    pv[k] = load_px_nb<C>(wsrc, p * C + mis, last_dw);
-                    if (msrc) mk[k] = msrc[p];
-                }
+            for (int k = 0; k < kRS / 4; ++k) {  // no branch: rows past sh repeat the last row
+                const int syr = refl1(ly + min(wave + 4 * k, sh - 1), H);
+                const uint32_t p = (uint32_t)syr * W + sxc, d = (p * C + mis) >> 2;
+                plo[k] = wsrc[d];
+                if (C == 3) phi[k] = wsrc[min(d + 1, last_dw)];
+                mk[k] = mload[p];
             }
+            // the pixels are cut out of their words only here, after every load was issued
 #pragma unroll
-            for (int k = 0; k < kRSPer; ++k) {
-                if (k < kns) {
-                    const int e = min(tid + k * kThreads, ns - 1);
-                    ss[e] = pv[k];
+            for (int k = 0; k < kRS / 4; ++k) {
+                if (4 * k < sh && lane < sw && wave + 4 * k < sh) {
+                    const int syr = refl1(ly + wave + 4 * k, H);
+                    const uint32_t sb = ((uint32_t)syr * W + sxc) * C + mis;
+                    const int e = (wave + 4 * k) * sw + lane;
+                    ss[e] = C == 4 ? plo[k]
+                                   : (C == 3 ? __builtin_amdgcn_alignbyte(phi[k], plo[k], sb & 3) : plo[k] >> (8 * (sb & 3)));
                     if (msrc) sm[e] = (uint8_t)mk[k];
                 }
             }
             __syncthreads();
+            // Pass 2: the e-block from LDS, entries e = tid + k kThreads
 #pragma unroll
             for (int k = 0; k < kREPer; ++k) {
-                if (k < kn) {
-                    const int e = min(tid + k * kThreads, ne - 1);
-                    const uint32_t *p = ss + ((sy[k] >> kFBits) - ly) * sw + (sx[k] >> kFBits) - lx;
-                    eb[e] = blend_px<C>(p[0], p[1], p[sw], p[sw + 1], wx_pair(sx[k] & (kFOne - 1)), sy[k] & (kFOne - 1));
-                    if (msrc)
-                        em[e] = sm[(((sy[k] + kFOne / 2) >> kFBits) - ly) * sw + ((sx[k] + kFOne / 2) >> kFBits) - lx];
+                const int e = tid + k * kThreads;
+                if (e < ne) {
+                    const uint32_t w = eb[e];
+                    const int ax = (int)(w >> 12) & (kFOne - 1), ay = (int)(w >> 22);
+                    const uint32_t *p = ss + (w & 4095);
+                    eb[e] = blend_px<C>(p[0], p[1], p[sw], p[sw + 1], wx_pair(ax), ay);
+                    if (msrc) em[e] = sm[(w & 4095) + (ax >> (kFBits - 1)) + (ay >> (kFBits - 1)) * sw];
                 }
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kREPer; ++k) {
-                if (k < kn) {
-                    const int e = min(tid + k * kThreads, ne - 1);
+            for (int k = 0; k < kRE / 4; ++k) {
+                if (4 * k < eh && lane < ew && wave + 4 * k < eh) {
+                    const int e = (wave + 4 * k) * ew + lane;
                     eb[e] = elastic_at<C>(src, H, W, sx[k], sy[k]);
                     if (msrc) em[e] = nearest_at(msrc, H, W, sx[k], sy[k]);
                 }
