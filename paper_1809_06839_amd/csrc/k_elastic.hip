@@ -17,13 +17,16 @@
 //              only when rounding lifts the taps' sum above 2^15) is done
 //              with direct int32 sums; taps of 2^15 take the int32 form
 //              (k_field_v, strips of 64 rows).
-// Remap chain (u8): one workgroup per 32 x 32 output tile.  The grid tables
-// are monotone, so the tile's grid taps read a contiguous (before reflection)
-// block of rows and columns of the elastic result e; the tile computes that
-// block of e in LDS (each e pixel: displaced Q10 position -> 4 source taps ->
-// u8, reflect-101) and then blends the grid taps from LDS.  The mask takes the
-// same two maps with nearest sampling.  Float copy: the same maps without
-// rounding; its adjoint scatters with float atomics.
+// Remap chain (u8): one workgroup per 32 x 32 output tile.  The tile's grid
+// taps read a block of rows and columns (before reflection) of the elastic
+// result e, the e-block; the displaced Q10 positions of the e-block read a
+// block of the source, which is staged in LDS once (one pixel per word, with
+// its mask); the e-block is blended from it into LDS (4 source taps -> u8,
+// reflect-101), and the output from the e-block.  Tiles whose blocks do not
+// fit, or reach past one reflection of the image, gather their taps from
+// global memory instead.  The mask takes the same two maps with nearest
+// sampling.  Float copy: the same maps without rounding; its adjoint scatters
+// with float atomics.
 #include "dev_common.h"
 #include "internal.h"
 
