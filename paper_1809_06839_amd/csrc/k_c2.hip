@@ -6,6 +6,7 @@
 // Every intermediate is rounded exactly as the sequential definition rounds
 // it; only the order of evaluation differs.
 #include "dev_common.h"
+#include "q10_blend.h"
 #include "internal.h"
 
 namespace miaug {
@@ -48,17 +49,7 @@ __device__ __forceinline__ uint32_t warp_sample(const uint8_t *img, int H, int W
     if (y0 < 0 || y1 >= H) { y0 = reflect101(y0, H); y1 = reflect101(y1, H); }
     const uint32_t p00 = load_rgb(img + ((size_t)y0 * W + x0) * 3), p01 = load_rgb(img + ((size_t)y0 * W + x1) * 3);
     const uint32_t p10 = load_rgb(img + ((size_t)y1 * W + x0) * 3), p11 = load_rgb(img + ((size_t)y1 * W + x1) * 3);
-    uint32_t out = 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int a00 = (p00 >> (8 * c)) & 255, a01 = (p01 >> (8 * c)) & 255;
-        const int a10 = (p10 >> (8 * c)) & 255, a11 = (p11 >> (8 * c)) & 255;
-        const int t0 = (a00 << kFBits) + ax * (a01 - a00);
-        const int t1 = (a10 << kFBits) + ax * (a11 - a10);
-        const int acc = (t0 << kFBits) + ay * (t1 - t0);
-        out |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
-    }
-    return out;
+    return blend_q10<3>(p00, p01, p10, p11, q10_pair(ax), ay);
 }
 
 // n / d rounded to nearest, ties to even, for n < 2^16 and 1 <= d <= 255: a
@@ -125,17 +116,7 @@ __device__ __forceinline__ uint32_t lds_rgb(const uint8_t *st, int o) {
 
 // Bilinear blend of four packed RGB taps with Q10 weights, one rounding.
 __device__ __forceinline__ uint32_t blend4(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, int ax, int ay) {
-    uint32_t out = 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int a00 = (p00 >> (8 * c)) & 255, a01 = (p01 >> (8 * c)) & 255;
-        const int a10 = (p10 >> (8 * c)) & 255, a11 = (p11 >> (8 * c)) & 255;
-        const int t0 = (a00 << kFBits) + ax * (a01 - a00);
-        const int t1 = (a10 << kFBits) + ax * (a11 - a10);
-        const int acc = (t0 << kFBits) + ay * (t1 - t0);
-        out |= (uint32_t)((acc + 0x7FFFF + ((acc >> 20) & 1)) >> 20) << (8 * c);
-    }
-    return out;
+    return blend_q10<3>(p00, p01, p10, p11, q10_pair(ax), ay);
 }
 
 // One workgroup per (image, T x T output tile):

@@ -28,6 +28,7 @@
 // sampling.  Float copy: the same maps without rounding; its adjoint scatters
 // with float atomics.
 #include "dev_common.h"
+#include "q10_blend.h"
 #include "internal.h"
 
 namespace miaug {
@@ -495,28 +496,6 @@ __device__ __forceinline__ uint32_t load_px(const uint8_t *p, int C) {
     return __builtin_amdgcn_alignbyte(w[1], lo, sh);
 }
 
-// Bilinear blend of four packed pixels with Q10 weights, rounded half to even
-// (2^20 is the product of the weights' scales).  Per channel the row sums
-// t = a0 (1024 - ax) + a1 ax take one permute (the two bytes into 16-bit
-// lanes) and one packed 16-bit dot product, exact in int32; then
-// t0 (1024 - ay) + t1 ay with 24-bit multiplies.  wx = (1024 - ax) | ax << 16.
-template <int C>
-__device__ __forceinline__ uint32_t blend_px(uint32_t p00, uint32_t p01, uint32_t p10, uint32_t p11, uint32_t wx,
-                                             int ay) {
-    uint32_t out = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const uint32_t sel = (uint32_t)c | 0x0c00u | (uint32_t)(4 + c) << 16 | 0x0c000000u;
-        const uint32_t t0 = (uint32_t)dot2(__builtin_amdgcn_perm(p01, p00, sel), wx, 0);
-        const uint32_t t1 = (uint32_t)dot2(__builtin_amdgcn_perm(p11, p10, sel), wx, 0);
-        const uint32_t acc = umad24(t0, (uint32_t)(kFOne - ay), umad24(t1, (uint32_t)ay, 0u));
-        out |= ((acc + 0x7FFFFu + ((acc >> 20) & 1u)) >> 20) << (8 * c);
-    }
-    return out;
-}
-
-__device__ __forceinline__ uint32_t wx_pair(int ax) { return (uint32_t)(kFOne - ax) | (uint32_t)ax << 16; }
-
 // Displaced Q10 position of the e pixel (Y, X) (inside the image).
 __device__ __forceinline__ void displaced(const int32_t *ox, const int32_t *oy, int W, int Y, int X, int &qx,
                                           int &qy) {
@@ -530,9 +509,9 @@ template <int C>
 __device__ __noinline__ uint32_t elastic_at(const uint8_t *img, int H, int W, int qx, int qy) {
     const int x0 = qx >> kFBits, y0 = qy >> kFBits;
     const int X0 = refl(x0, W), X1 = refl(x0 + 1, W), Y0 = refl(y0, H), Y1 = refl(y0 + 1, H);
-    return blend_px<C>(load_px(img + ((uint32_t)Y0 * W + X0) * C, C), load_px(img + ((uint32_t)Y0 * W + X1) * C, C),
+    return blend_q10<C>(load_px(img + ((uint32_t)Y0 * W + X0) * C, C), load_px(img + ((uint32_t)Y0 * W + X1) * C, C),
                        load_px(img + ((uint32_t)Y1 * W + X0) * C, C), load_px(img + ((uint32_t)Y1 * W + X1) * C, C),
-                       wx_pair(qx & (kFOne - 1)), qy & (kFOne - 1));
+                       q10_pair(qx & (kFOne - 1)), qy & (kFOne - 1));
 }
 
 __device__ __forceinline__ uint8_t nearest_at(const uint8_t *m, int H, int W, int qx, int qy) {
@@ -551,9 +530,9 @@ __device__ __noinline__ void remap_direct(const uint8_t *src, const uint8_t *msr
     displaced(ox, oy, W, Y0, X1, q[2], q[3]);
     displaced(ox, oy, W, Y1, X0, q[4], q[5]);
     displaced(ox, oy, W, Y1, X1, q[6], q[7]);
-    v = blend_px<C>(elastic_at<C>(src, H, W, q[0], q[1]), elastic_at<C>(src, H, W, q[2], q[3]),
+    v = blend_q10<C>(elastic_at<C>(src, H, W, q[0], q[1]), elastic_at<C>(src, H, W, q[2], q[3]),
                     elastic_at<C>(src, H, W, q[4], q[5]), elastic_at<C>(src, H, W, q[6], q[7]),
-                    wx_pair(gx & (kFOne - 1)), gy & (kFOne - 1));
+                    q10_pair(gx & (kFOne - 1)), gy & (kFOne - 1));
     mv = 0;
     if (msrc) {
         int mqx, mqy;
@@ -726,7 +705,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
                     const uint32_t w = eb[e];
                     const int ax = (int)(w >> 12) & (kFOne - 1), ay = (int)(w >> 22);
                     const uint32_t *p = ss + (w & 4095);
-                    eb[e] = blend_px<C>(p[0], p[1], p[sw], p[sw + 1], wx_pair(ax), ay);
+                    eb[e] = blend_q10<C>(p[0], p[1], p[sw], p[sw + 1], q10_pair(ax), ay);
                     if (msrc) em[e] = sm[(w & 4095) + (ax >> (kFBits - 1)) + (ay >> (kFBits - 1)) * sw];
                 }
             }
@@ -755,7 +734,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
         for (int j = 0; j < 4; ++j) {
             const int gx = qx[min(c0 + j, tw - 1)], cx = gx >> kFBits;
             const uint32_t *p = erow + cx;
-            v[j] = blend_px<C>(p[0], p[1], p[ew], p[ew + 1], wx_pair(gx & (kFOne - 1)), ay);
+            v[j] = blend_q10<C>(p[0], p[1], p[ew], p[ew + 1], q10_pair(gx & (kFOne - 1)), ay);
             if (msrc) mv[j] = mrow[(gx + kFOne / 2) >> kFBits];
         }
     } else {
