@@ -388,7 +388,7 @@ def bench_elastic(args, torch, m):
                                    "unit": "Tmac/s (packed 16-bit multiply-adds into int32)",
                                    "frac": macs / (ms_f * 1e-3) / 1e12 / FIELD_PEAK_TMACS},
                 "box_field_ms": ms_fb, "box_field_speedup": ms_f / ms_fb,
-                "box_field_roofline": hbm_roof(n * 2 * H * W * 4, ms_fb, "k_box_rows + 3 x k_box_cols")})
+                "box_field_roofline": hbm_roof(n * 2 * H * W * 4, ms_fb, "k_box_rows + 3 x k_box_cols2")})
     return res
 
 

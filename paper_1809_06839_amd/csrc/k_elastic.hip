@@ -340,9 +340,10 @@ __global__ __launch_bounds__(kThreads) void k_field_v2(int H, int W, int radius,
 // of Kovesi 2010), every pass rounding its mean: pass(x) = rdiv_he(sum over
 // |k| <= r of in[refl(x + k)], 2r + 1).  Rows: noise and the three passes in
 // LDS, one workgroup per row.  Columns: one pass per launch, each thread
-// sliding a window down kBoxSeg rows of one column; the last pass writes the
-// offsets rshr_he(alpha v, 5) (Q10 px).
-constexpr int kBoxSeg = 64;       // rows per thread in the column passes
+// sliding a window down a segment of rows of one column (of two adjacent
+// columns when W is even); the last pass writes the offsets rshr_he(alpha v, 5)
+// (Q10 px).
+constexpr int kBoxSeg = 64;       // rows per thread in the single-column passes
 
 // rdiv_he(s, w) for odd w and |s| <= 32768 w (w values of the noise range):
 // A = s + 32768 w >= 0, A / w <= 65536, so the float quotient (rw = v_rcp_f32(w))
@@ -447,6 +448,70 @@ __global__ __launch_bounds__(kThreads) void k_box_cols(const int16_t *__restrict
     for (int y = y0; y < ye; ++y) {
         emit(y, box_round(s, w, rw));
         s += col[(size_t)reflect101(y + r + 1, H) * W] - col[(size_t)reflect101(y - r, H) * W];
+    }
+}
+
+// The same column pass for even W, two adjacent columns per lane (32-bit loads
+// and stores of int16 pairs) and kBoxSeg2 rows per thread; reflected rows are
+// wave-uniform, and the loads of 8 rows are issued together.
+constexpr int kBoxSeg2 = 256;
+
+__device__ __forceinline__ int box_row(int y, int H, bool near) {
+    if (near) {  // y in [-(H - 1), 2H - 2]: at most one reflection
+        const int a = y < 0 ? -y : y;
+        return a >= H ? 2 * H - 2 - a : a;
+    }
+    return reflect101(y, H);
+}
+
+__global__ __launch_bounds__(kThreads) void k_box_cols2(const int16_t *__restrict__ in, int H, int W, int r,
+                                                        int alpha, int16_t *__restrict__ out16,
+                                                        int32_t *__restrict__ off) {
+    const int x = 2 * ((int)blockIdx.x * 64 + ((int)threadIdx.x & 63));
+    const int y0 = ((int)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) * kBoxSeg2;
+    const size_t plane = ((size_t)blockIdx.z) * H * W;  // (image, field) plane
+    if (x >= W || y0 >= H) return;
+    const int32_t *col = (const int32_t *)(in + plane + x);  // W even: every pair is word aligned
+    const int Wp = W / 2;                                    // words per row
+    const int w = 2 * r + 1;
+    const bool near = r <= H - 2;
+    const float rw = __builtin_amdgcn_rcpf((float)w);
+    const int ye = min(H, y0 + kBoxSeg2);
+    int s0 = 0, s1 = 0;
+    for (int k0 = -r; k0 <= r; k0 += 8) {
+        int v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = k0 + k <= r ? col[(size_t)box_row(y0 + k0 + k, H, near) * Wp] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            s0 += (v[k] << 16) >> 16;
+            s1 += v[k] >> 16;
+        }
+    }
+    for (int y = y0; y < ye; y += 8) {
+        int av[8], sv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool in_seg = y + k < ye;
+            av[k] = in_seg ? col[(size_t)box_row(y + k + r + 1, H, near) * Wp] : 0;
+            sv[k] = in_seg ? col[(size_t)box_row(y + k - r, H, near) * Wp] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (y + k >= ye) break;
+            const int b0 = box_round(s0, w, rw), b1 = box_round(s1, w, rw);
+            const size_t o = plane + (size_t)(y + k) * W + x;
+            if (alpha < 0) {
+                *(int32_t *)(out16 + o) = (b0 & 0xFFFF) | (b1 << 16);
+            } else {
+                int2 q;
+                q.x = (int32_t)rshr_he64((int64_t)alpha * b0, 5);
+                q.y = (int32_t)rshr_he64((int64_t)alpha * b1, 5);
+                *(int2 *)(off + o) = q;
+            }
+            s0 += ((av[k] << 16) >> 16) - ((sv[k] << 16) >> 16);
+            s1 += (av[k] >> 16) - (sv[k] >> 16);
+        }
     }
 }
 
@@ -1086,6 +1151,15 @@ hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H
     hipLaunchKernelGGL(k_box_rows, dim3(H, 2, n), dim3(kThreads), lds, s, seed, first, H, W, r[0], r[1], r[2], a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (W % 2 == 0) {  // column pairs
+        const dim3 grid2((W / 2 + 63) / 64, (H + 4 * kBoxSeg2 - 1) / (4 * kBoxSeg2), 2 * n);
+        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr, off);
+        return hipGetLastError();
+    }
     const dim3 grid((W + 63) / 64, (H + 4 * kBoxSeg - 1) / (4 * kBoxSeg), 2 * n);
     hipLaunchKernelGGL(k_box_cols, grid, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
