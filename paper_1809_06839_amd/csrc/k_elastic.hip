@@ -358,12 +358,13 @@ __device__ __forceinline__ int box_round(int s, int w, float rw) {
     return q - 32768 + (2 * r > w);
 }
 
-// LDS (dynamic): two lines of W + 2 (r2 + 1) int32; the halo offset is hb = r2 + 1.
+// LDS (dynamic): two lines of W + 2 (r2 + 1) int16 (the noise and every rounded
+// box mean lie in the int16 range); the halo offset is hb = r2 + 1.
 __global__ __launch_bounds__(kThreads) void k_box_rows(uint64_t seed, uint64_t first, int H, int W, int r0, int r1,
                                                        int r2, int16_t *__restrict__ out) {
-    extern __shared__ int32_t lines[];
+    extern __shared__ int16_t lines[];
     const int hb = r2 + 1;  // halo of the widest pass
-    int32_t *bufa = lines, *bufb = lines + W + 2 * hb;
+    int16_t *bufa = lines, *bufb = lines + ((W + 2 * hb + 1) & ~1);  // both lines start on a word
     const int y = blockIdx.x, field = blockIdx.y, img = blockIdx.z;
     const uint64_t g = first + (uint64_t)img;
     const int64_t e0 = (int64_t)y * W, e1 = e0 + W;
@@ -375,10 +376,10 @@ __global__ __launch_bounds__(kThreads) void k_box_rows(uint64_t seed, uint64_t f
         for (int k = 0; k < 16; ++k) {
             const int64_t e = grp * 16 + k;
             if (e >= e0 && e < e1)
-                bufa[hb + (int)(e - e0)] = (int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768;
+                bufa[hb + (int)(e - e0)] = (int16_t)((int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768);
         }
     }
-    int32_t *src = bufa, *dst = bufb;
+    int16_t *src = bufa, *dst = bufb;
     // each thread slides over `chunk` consecutive outputs; an odd chunk puts the 64
     // lanes of a wave in 64 different LDS banks (an even one would share few banks)
     const int chunk = ((W + kThreads - 1) / kThreads) | 1, x0 = threadIdx.x * chunk;
@@ -392,19 +393,25 @@ __global__ __launch_bounds__(kThreads) void k_box_rows(uint64_t seed, uint64_t f
         __syncthreads();
         if (x0 < W) {
             const float rw = __builtin_amdgcn_rcpf((float)w);
-            int s = 0;
-            for (int k = -r; k <= r; ++k) s += src[hb + x0 + k];
+            // the first window: int16 pairs summed by one packed dot product with (1, 1)
+            int s = 0, i = hb + x0 - r;
+            const int iend = hb + x0 + r;
+            if (i & 1) s += src[i++];
+            const uint32_t *pw = (const uint32_t *)(src + i);
+            const int np = (iend - i + 1) >> 1;
+            for (int k = 0; k < np; ++k) s = dot2(pw[k], 0x00010001u, s);
+            if ((iend - i + 1) & 1) s += src[iend];
             const int xe = min(W, x0 + chunk);
             for (int x = x0; x < xe; ++x) {
-                dst[hb + x] = box_round(s, w, rw);
+                dst[hb + x] = (int16_t)box_round(s, w, rw);
                 s += src[hb + x + r + 1] - src[hb + x - r];
             }
         }
-        int32_t *t = src; src = dst; dst = t;
+        int16_t *t = src; src = dst; dst = t;
     }
     __syncthreads();
     int16_t *o = out + (((size_t)img * 2 + field) * H + y) * W;
-    for (int x = threadIdx.x; x < W; x += kThreads) o[x] = (int16_t)src[hb + x];
+    for (int x = threadIdx.x; x < W; x += kThreads) o[x] = src[hb + x];
 }
 
 // One column pass: in -> out16 (alpha < 0) or in -> offsets rshr_he(alpha v, 5).
@@ -1147,7 +1154,7 @@ hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H
     int r[3];
     box_radii(sigma, r);
     int16_t *a = (int16_t *)ws, *b = a + (size_t)n * 2 * H * W;
-    const size_t lds = sizeof(int32_t) * 2 * ((size_t)W + 2 * (r[2] + 1));
+    const size_t lds = sizeof(int16_t) * 2 * (((size_t)W + 2 * (r[2] + 1) + 1) & ~(size_t)1);
     hipLaunchKernelGGL(k_box_rows, dim3(H, 2, n), dim3(kThreads), lds, s, seed, first, H, W, r[0], r[1], r[2], a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
