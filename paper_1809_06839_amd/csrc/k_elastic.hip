@@ -458,9 +458,10 @@ __global__ __launch_bounds__(kThreads) void k_box_cols(const int16_t *__restrict
     }
 }
 
-// The same column pass for even W, two adjacent columns per lane (32-bit loads
-// and stores of int16 pairs) and kBoxSeg2 rows per thread; reflected rows are
-// wave-uniform, and the loads of 8 rows are issued together.
+// The same column pass for even W, two or four adjacent columns per lane (one
+// 4- or 8-byte load and store per row) and kBoxSeg2 rows per thread; reflected
+// rows are wave-uniform, and the loads of 8 rows are issued together (rows past
+// the window or the segment repeat a valid row and are not used).
 constexpr int kBoxSeg2 = 256;
 
 __device__ __forceinline__ int box_row(int y, int H, bool near) {
@@ -471,53 +472,94 @@ __device__ __forceinline__ int box_row(int y, int H, bool near) {
     return reflect101(y, H);
 }
 
+// NC adjacent columns per lane (NC = 2 or 4; W % NC == 0): the NC int16 values
+// of a row move as one 4- or 8-byte word.
+template <int NC>
+struct BoxWord;
+template <>
+struct BoxWord<2> {
+    typedef int32_t T;
+    static __device__ __forceinline__ int get(T v, int j) { return j == 0 ? (v << 16) >> 16 : v >> 16; }
+};
+template <>
+struct BoxWord<4> {
+    typedef int2 T;
+    static __device__ __forceinline__ int get(T v, int j) {
+        const int h = j < 2 ? v.x : v.y;
+        return (j & 1) ? h >> 16 : (h << 16) >> 16;
+    }
+};
+
+template <int NC>
 __global__ __launch_bounds__(kThreads) void k_box_cols2(const int16_t *__restrict__ in, int H, int W, int r,
                                                         int alpha, int16_t *__restrict__ out16,
                                                         int32_t *__restrict__ off) {
-    const int x = 2 * ((int)blockIdx.x * 64 + ((int)threadIdx.x & 63));
+    typedef typename BoxWord<NC>::T T;
+    const int x = NC * ((int)blockIdx.x * 64 + ((int)threadIdx.x & 63));
     const int y0 = ((int)blockIdx.y * 4 + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) * kBoxSeg2;
     const size_t plane = ((size_t)blockIdx.z) * H * W;  // (image, field) plane
     if (x >= W || y0 >= H) return;
-    const int32_t *col = (const int32_t *)(in + plane + x);  // W even: every pair is word aligned
-    const int Wp = W / 2;                                    // words per row
+    const T *col = (const T *)(in + plane + x);  // W % NC == 0: every group is aligned to its size
+    const int Wp = W / NC;                       // words per row
     const int w = 2 * r + 1;
     const bool near = r <= H - 2;
     const float rw = __builtin_amdgcn_rcpf((float)w);
     const int ye = min(H, y0 + kBoxSeg2);
-    int s0 = 0, s1 = 0;
+    int sum[NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) sum[j] = 0;
     for (int k0 = -r; k0 <= r; k0 += 8) {
-        int v[8];
+        T v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = k0 + k <= r ? col[(size_t)box_row(y0 + k0 + k, H, near) * Wp] : 0;
+        for (int k = 0; k < 8; ++k) v[k] = col[(size_t)box_row(y0 + min(k0 + k, r), H, near) * Wp];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            s0 += (v[k] << 16) >> 16;
-            s1 += v[k] >> 16;
-        }
+        for (int k = 0; k < 8; ++k)
+            if (k0 + k <= r) {
+#pragma unroll
+                for (int j = 0; j < NC; ++j) sum[j] += BoxWord<NC>::get(v[k], j);
+            }
     }
     for (int y = y0; y < ye; y += 8) {
-        int av[8], sv[8];
+        T av[8], sv[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const bool in_seg = y + k < ye;
-            av[k] = in_seg ? col[(size_t)box_row(y + k + r + 1, H, near) * Wp] : 0;
-            sv[k] = in_seg ? col[(size_t)box_row(y + k - r, H, near) * Wp] : 0;
+            const int yy = min(y + k, ye - 1);
+            av[k] = col[(size_t)box_row(yy + r + 1, H, near) * Wp];
+            sv[k] = col[(size_t)box_row(yy - r, H, near) * Wp];
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if (y + k >= ye) break;
-            const int b0 = box_round(s0, w, rw), b1 = box_round(s1, w, rw);
+            int b[NC];
+#pragma unroll
+            for (int j = 0; j < NC; ++j) b[j] = box_round(sum[j], w, rw);
             const size_t o = plane + (size_t)(y + k) * W + x;
             if (alpha < 0) {
-                *(int32_t *)(out16 + o) = (b0 & 0xFFFF) | (b1 << 16);
+                if (NC == 2) {
+                    *(int32_t *)(out16 + o) = (b[0] & 0xFFFF) | (b[1] << 16);
+                } else {
+                    int2 q;
+                    q.x = (b[0] & 0xFFFF) | (b[1] << 16);
+                    q.y = (b[NC - 2] & 0xFFFF) | (b[NC - 1] << 16);
+                    *(int2 *)(out16 + o) = q;
+                }
             } else {
-                int2 q;
-                q.x = (int32_t)rshr_he64((int64_t)alpha * b0, 5);
-                q.y = (int32_t)rshr_he64((int64_t)alpha * b1, 5);
-                *(int2 *)(off + o) = q;
+                if (NC == 2) {
+                    int2 q;
+                    q.x = (int32_t)rshr_he64((int64_t)alpha * b[0], 5);
+                    q.y = (int32_t)rshr_he64((int64_t)alpha * b[1], 5);
+                    *(int2 *)(off + o) = q;
+                } else {
+                    int4 q;
+                    q.x = (int32_t)rshr_he64((int64_t)alpha * b[0], 5);
+                    q.y = (int32_t)rshr_he64((int64_t)alpha * b[1], 5);
+                    q.z = (int32_t)rshr_he64((int64_t)alpha * b[NC - 2], 5);
+                    q.w = (int32_t)rshr_he64((int64_t)alpha * b[NC - 1], 5);
+                    *(int4 *)(off + o) = q;
+                }
             }
-            s0 += ((av[k] << 16) >> 16) - ((sv[k] << 16) >> 16);
-            s1 += (av[k] >> 16) - (sv[k] >> 16);
+#pragma unroll
+            for (int j = 0; j < NC; ++j) sum[j] += BoxWord<NC>::get(av[k], j) - BoxWord<NC>::get(sv[k], j);
         }
     }
 }
@@ -1158,13 +1200,24 @@ hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H
     hipLaunchKernelGGL(k_box_rows, dim3(H, 2, n), dim3(kThreads), lds, s, seed, first, H, W, r[0], r[1], r[2], a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (W % 4 == 0) {  // four columns per lane
+        const dim3 grid4((W / 4 + 63) / 64, (H + 4 * kBoxSeg2 - 1) / (4 * kBoxSeg2), 2 * n);
+        hipLaunchKernelGGL(k_box_cols2<4>, grid4, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_box_cols2<4>, grid4, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_box_cols2<4>, grid4, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr,
+                           off);
+        return hipGetLastError();
+    }
     if (W % 2 == 0) {  // column pairs
         const dim3 grid2((W / 2 + 63) / 64, (H + 4 * kBoxSeg2 - 1) / (4 * kBoxSeg2), 2 * n);
-        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
+        hipLaunchKernelGGL(k_box_cols2<2>, grid2, dim3(kThreads), 0, s, a, H, W, r[0], -1, b, (int32_t *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
+        hipLaunchKernelGGL(k_box_cols2<2>, grid2, dim3(kThreads), 0, s, b, H, W, r[1], -1, a, (int32_t *)nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_box_cols2, grid2, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr, off);
+        hipLaunchKernelGGL(k_box_cols2<2>, grid2, dim3(kThreads), 0, s, a, H, W, r[2], alpha, (int16_t *)nullptr,
+                           off);
         return hipGetLastError();
     }
     const dim3 grid((W + 63) / 64, (H + 4 * kBoxSeg - 1) / (4 * kBoxSeg), 2 * n);
