@@ -412,7 +412,9 @@ int miaug_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, in
  * out = grid remap of e (source (mapx[x], mapy[y]), bilinear, reflect-101).
  * The mask (optional) takes the same two remaps with nearest sampling.
  *   img device u8 [n][H][W][C] (C in {1,3,4}); mask device u8 [n][H][W] or NULL
- *   out device u8 like img; out_mask like mask.
+ *   out device u8 like img; out_mask like mask.  The image is read in the
+ *   aligned 4-byte words that hold its bytes (at most 3 bytes on either side
+ *   of it, inside those words; device allocations are word granular).
  * per_image != 0 launches the kernel once per image (comparison form). */
 int miaug_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
                           const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,
