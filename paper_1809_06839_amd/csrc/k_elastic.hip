@@ -589,7 +589,6 @@ constexpr int kRE = 44;  // max side of the e-block held in LDS (grid factors up
 constexpr int kRS = 56;  // max side of the source block the e-block's displaced taps read
 // (about 25 KB of LDS: three workgroups in each half of a CU's LDS)
 constexpr int kREPer = (kRE * kRE + kThreads - 1) / kThreads;  // e-block entries per thread
-constexpr int kRSPer = (kRS * kRS + kThreads - 1) / kThreads;  // source-block entries per thread
 
 // reflect-101 with the in-range case inline and the rest out of line
 __device__ __noinline__ int reflect101_far(int i, int n) { return reflect101(i, n); }
