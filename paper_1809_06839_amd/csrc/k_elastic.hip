@@ -75,9 +75,29 @@ __device__ __forceinline__ void row_noise(uint64_t seed, uint64_t g, int field, 
             if (e >= e0 && e < e1) noise[radius + (int)(e - e0)] = (T)((int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768);
         }
     }
+    // halo columns of other segments that need no reflection (x in [0, W)): the
+    // ranges [x0 - radius, x0) and [x0 + m, x0 + m + radius), in aligned blocks of 16
+    const int la = max(0, x0 - radius), lb = x0, ra = x0 + m, rb = min(W, x0 + m + radius);
+    const int64_t gl0 = ((int64_t)y * W + la) >> 4, gl1 = ((int64_t)y * W + lb - 1) >> 4;
+    const int64_t gr0 = ((int64_t)y * W + ra) >> 4, gr1 = ((int64_t)y * W + rb - 1) >> 4;
+    const int nl = lb > la ? (int)(gl1 - gl0 + 1) : 0, nr = rb > ra ? (int)(gr1 - gr0 + 1) : 0;
+    for (int t = threadIdx.x; t < nl + nr; t += kThreads) {
+        const int64_t grp = t < nl ? gl0 + t : gr0 + (t - nl);
+        const int64_t lo = (int64_t)y * W + (t < nl ? la : ra), hi = (int64_t)y * W + (t < nl ? lb : rb);
+        uint64_t c[4] = {(uint64_t)grp, g, (uint64_t)field, 4};
+        philox4x64_10(c, seed, 0);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t e = grp * 16 + k;
+            if (e >= lo && e < hi)
+                noise[(int)(e - e0) + radius] = (T)((int32_t)((c[k >> 2] >> (16 * (k & 3))) & 0xFFFFu) - 32768);
+        }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < n_need; i += kThreads) {
         if (i >= radius && i < radius + m) continue;  // own column, generated above
+        const int xi = x0 - radius + i;
+        if (xi >= 0 && xi < W) continue;               // another segment's column, generated above
         const int xs = reflect101(x0 - radius + i, W);
         if (xs >= x0 && xs < x0 + m) {
             noise[i] = noise[radius + (xs - x0)];
