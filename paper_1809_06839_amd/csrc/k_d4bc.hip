@@ -63,27 +63,60 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
     const bool to_gray = !FROM_AB && C == 3 && gray && gray[img];
     __syncthreads();
 
+    // four output pixels per item: the Dih4 map, the staged row's phase and the
+    // pixel (one LDS word) once per pixel, the LUTs per channel, and C words
+    // stored when the four pixels start on a word
     uint8_t *obase = out + (size_t)img * plane;
-    constexpr int kItems = (kT * C) / 4 + 8;
-    for (int it = tid; it < th * kItems; it += kThreads) {
-        int r = it / kItems, j = it - r * kItems;
-        uint8_t *g = obase + ((size_t)(r0 + r) * Wo + c0) * C;
-        int len = tw * C;
-        if (j >= span_items(g, len)) continue;
-        const int orow = r0 + r;
-        auto byte_at = [&](int b) -> uint8_t {
-            int px = b / C, chn = b - px * C;
-            int c = c0 + px;
-            int sy = m.sy(orow, c), sx = m.sx(orow, c);
-            const uint8_t *grow = base + ((size_t)sy * W + sc0) * C;
-            const uint8_t *p = &src[(sy - sr0) * kStride + span_phase(grow) + (sx - sc0) * C];
-            if (FROM_AB) return lut[0][p[chn]];
-            if (!to_gray) return lut[chn][p[chn]];
-            // BT.601 luma in Q14 (4899, 9617, 1868), rounded half up, on the LUT'd channels
-            const int r = lut[0][p[0]], g = lut[C > 1 ? 1 : 0][p[C > 1 ? 1 : 0]], bl = lut[C > 2 ? 2 : 0][p[C > 2 ? 2 : 0]];
-            return (uint8_t)((4899 * r + 9617 * g + 1868 * bl + 8192) >> 14);
-        };
-        store_span_item(g, len, j, byte_at);
+    constexpr int kQ = kT / 4;
+    const uint32_t bphase = (uint32_t)(uintptr_t)base;
+    for (int it = tid; it < th * kQ; it += kThreads) {
+        const int r = it / kQ, q4 = (it - r * kQ) * 4;
+        if (q4 >= tw) continue;
+        const int orow = r0 + r, np = min(4, tw - q4);
+        uint32_t v[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= np) break;
+            const int c = c0 + q4 + j;
+            const int sy = m.sy(orow, c), sx = m.sx(orow, c);
+            const int o = (sy - sr0) * kStride + (int)((bphase + (uint32_t)(sy * W + sc0) * C) & 15) + (sx - sc0) * C;
+            const uint32_t *w = (const uint32_t *)(src + (o & ~3));
+            const uint32_t pw = __builtin_amdgcn_alignbyte(w[1], w[0], o & 3);
+            uint32_t q = 0;
+            if (FROM_AB) {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) q |= (uint32_t)lut[0][(pw >> (8 * ch)) & 255] << (8 * ch);
+            } else if (!to_gray) {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) q |= (uint32_t)lut[ch][(pw >> (8 * ch)) & 255] << (8 * ch);
+            } else {
+                // BT.601 luma in Q14 (4899, 9617, 1868), rounded half up, on the LUT'd channels
+                const int rr = lut[0][pw & 255], gg = lut[C > 1 ? 1 : 0][(pw >> 8) & 255];
+                const int bb = lut[C > 2 ? 2 : 0][(pw >> 16) & 255];
+                const uint32_t y = (uint32_t)((4899 * rr + 9617 * gg + 1868 * bb + 8192) >> 14);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) q |= y << (8 * ch);
+            }
+            v[j] = q;
+        }
+        uint8_t *g = obase + ((size_t)orow * Wo + c0 + q4) * C;
+        if (np == 4 && ((uintptr_t)g & 3) == 0) {
+            uint32_t *gw = (uint32_t *)g;
+            if (C == 1) {
+                gw[0] = v[0] | v[1] << 8 | v[2] << 16 | v[3] << 24;
+            } else if (C == 3) {
+                gw[0] = v[0] | v[1] << 24;
+                gw[1] = v[1] >> 8 | v[2] << 16;
+                gw[2] = v[2] >> 16 | v[3] << 8;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) gw[j] = v[j];
+            }
+        } else {
+            for (int j = 0; j < np; ++j)
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) g[j * C + ch] = (uint8_t)(v[j] >> (8 * ch));
+        }
     }
 }
 
