@@ -5,8 +5,9 @@
 // One workgroup per (image, 64x64 output tile).  The tile's source block is
 // an axis-aligned rectangle (a Dih4 element maps rectangles to rectangles);
 // its rows are staged into LDS with 16-byte vector loads, the 256-entry LUT
-// is built in LDS in IEEE double, and output rows are written as aligned
-// dwords assembled from LDS byte reads (flips and transposes become LDS
+// is built in LDS in IEEE double, and each thread forms four output pixels
+// (each one LDS word read at the Dih4-mapped position, then the LUTs) and
+// writes them as C aligned words (flips and transposes become LDS
 // addressing).  HBM traffic is one read and one write of every byte.
 #include "dev_common.h"
 #include "internal.h"
