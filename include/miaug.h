@@ -162,7 +162,8 @@ int miaug_hsv_shift_u8(const uint8_t *in, int n, int H, int W, const int32_t *dh
  * the rest after; out[y][x] = in[y - top][x - left] inside, else the
  * reflect-101 image of that index (border MIAUG_BORDER_REFLECT101) or value
  * (MIAUG_BORDER_CONSTANT).  in device u8 [n][H][W][C]; out device u8
- * [n][Ho][Wo][C].  Errors: EINVAL bad sizes, border or value; ESHAPE C. */
+ * [n][Ho][Wo][C]; in is read in the aligned 4-byte words that hold its bytes.
+ * Errors: EINVAL bad sizes, border or value; ESHAPE C. */
 int miaug_pad_u8(const uint8_t *in, int n, int H, int W, int C, int min_h, int min_w, int border, int value,
                  uint8_t *out, void *stream);
 

@@ -30,19 +30,42 @@ __device__ __forceinline__ int64_t border_index(int64_t i, int n, int border) {
     return reflect101_64(i, n);
 }
 
+constexpr int kPadThreads = 128;  // k_pad: 512 output pixels of one row per block and step
+
 template <int C>
-__global__ __launch_bounds__(kThreads) void k_pad(const uint8_t *__restrict__ in, int H, int W, int Ho, int Wo,
-                                                  int top, int left, int border, int value,
-                                                  uint8_t *__restrict__ out) {
-    const int img = blockIdx.y;
-    const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (e >= (int64_t)Ho * Wo) return;
-    const int y = (int)(e / Wo), x = (int)(e - (int64_t)y * Wo);
-    const int64_t sy = border_index(y - top, H, border), sx = border_index(x - left, W, border);
-    const uint8_t *p = in + (size_t)img * H * W * C + ((size_t)sy * W + sx) * C;
-    uint8_t *o = out + (size_t)img * Ho * Wo * C + (size_t)e * C;
+__global__ __launch_bounds__(kPadThreads) void k_pad(const uint8_t *__restrict__ in, int H, int W, int Ho, int Wo,
+                                                     int top, int left, int border, int value,
+                                                     uint8_t *__restrict__ out) {
+    // block (image row, column block): one output row, four pixels per thread
+    const int img = (int)(blockIdx.x / (unsigned)Ho), y = (int)(blockIdx.x - (unsigned)img * Ho);
+    const int64_t sy = border_index(y - top, H, border);  // the same for the whole block
+    uint8_t *orow = out + ((size_t)img * Ho + y) * Wo * C;
+    const uint8_t *srow = in + ((size_t)img * H + (sy < 0 ? 0 : sy)) * W * C;
+    for (int xb = blockIdx.y; (int64_t)xb * 4 * kPadThreads < Wo; xb += gridDim.y) {
+        const int x = (xb * kPadThreads + (int)threadIdx.x) * 4;
+        if (x >= Wo) break;
+        const int sx0 = x - left, np = min(4, Wo - x);
+        uint8_t *o = orow + (size_t)x * C;
+        if (sy >= 0 && np == 4 && sx0 >= 0 && sx0 + 4 <= W && ((uintptr_t)o & 3) == 0) {
+            // four contiguous source pixels: C words (C + 1 when they do not start on a
+            // word, the last one holding their last bytes), shifted into C output words
+            const uint8_t *p = srow + (size_t)sx0 * C;
+            const int sh = (int)((uintptr_t)p & 3);
+            const uint32_t *w = (const uint32_t *)(p - sh);
+            uint32_t d[C + 1];
 #pragma unroll
-    for (int c = 0; c < C; ++c) o[c] = (sy < 0 || sx < 0) ? (uint8_t)value : p[c];
+            for (int k = 0; k < C; ++k) d[k] = w[k];
+            d[C] = sh ? w[C] : 0u;
+#pragma unroll
+            for (int k = 0; k < C; ++k) ((uint32_t *)o)[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
+            continue;
+        }
+        for (int j = 0; j < np; ++j) {
+            const int64_t sx = border_index(sx0 + j, W, border);
+#pragma unroll
+            for (int c = 0; c < C; ++c) o[j * C + c] = (sy < 0 || sx < 0) ? (uint8_t)value : srow[sx * C + c];
+        }
+    }
 }
 
 // Output (x, y) samples the source at the Q10 position rshr_he(A (x, y, 1), 22)
@@ -227,10 +250,11 @@ hipError_t launch_pad_u8(const uint8_t *in, int n, int H, int W, int C, int Ho, 
                          uint8_t *out, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const int top = (Ho - H) / 2, left = (Wo - W) / 2;
-    dim3 grid((unsigned)(((int64_t)Ho * Wo + kThreads - 1) / kThreads), n);
-    if (C == 1) hipLaunchKernelGGL(k_pad<1>, grid, dim3(kThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
-    else if (C == 3) hipLaunchKernelGGL(k_pad<3>, grid, dim3(kThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
-    else hipLaunchKernelGGL(k_pad<4>, grid, dim3(kThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
+    const int64_t cb = ((int64_t)Wo + 4 * kPadThreads - 1) / (4 * kPadThreads);
+    dim3 grid((unsigned)((int64_t)Ho * n), (unsigned)(cb < 65535 ? cb : 65535));
+    if (C == 1) hipLaunchKernelGGL(k_pad<1>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
+    else if (C == 3) hipLaunchKernelGGL(k_pad<3>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
+    else hipLaunchKernelGGL(k_pad<4>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
     return hipGetLastError();
 }
 

@@ -53,7 +53,9 @@ def test_d4_luts_and_gray_bit_exact(m, C):
 
 
 @pytest.mark.parametrize("H,W,Hm,Wm,C", [(500, 380, 512, 512, 3), (512, 512, 512, 512, 3), (7, 600, 512, 512, 1),
-                                         (1, 1, 5, 9, 4), (300, 700, 512, 512, 3)])
+                                         (1, 1, 5, 9, 4), (300, 700, 512, 512, 3),
+                                         # output rows of 123 bytes: most pixel groups start off a word
+                                         (5, 37, 9, 41, 3)])
 def test_pad_bit_exact_both_borders(m, H, W, Hm, Wm, C):
     import torch
     rng = np.random.default_rng(H + W)
