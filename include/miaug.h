@@ -266,6 +266,11 @@ int miaug_boxes_ssr_crop_resize(const float *boxes, const int32_t *box_off, int 
  * [0, h]: a box outside the window keeps its slot with zero width or height)
  * and the scale (out_w/w', out_h/h') of the window (or the whole Dih4 image),
  * in double, stored as float.
+ * Images and masks may start at any byte offset.  The kernels stage source
+ * rows in the 16-byte aligned blocks that hold their bytes, so they may read
+ * (never write) up to 15 bytes before an image's or mask's first byte and
+ * after its last; those bytes share a 16-byte block with the image's own, so
+ * they lie in mapped memory, and they never enter a result.
  */
 typedef struct {
     int32_t n;               /* number of images (0 allowed)                      */

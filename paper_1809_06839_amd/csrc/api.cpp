@@ -338,15 +338,43 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
         return MIAUG_OK;
     }
     hipStream_t s = as_stream(stream);
-    const size_t out_bytes = (size_t)a->n * 3 * a->out_h * a->out_w * sizeof(float);
+    const size_t out_words = (size_t)a->n * 3 * a->out_h * a->out_w;
+    const size_t out_bytes = out_words * sizeof(float);
     const size_t mask_bytes = a->mask ? (size_t)a->n * a->out_h * a->out_w : 0;
-    std::vector<char> ref(out_bytes), got(out_bytes), mref(mask_bytes), mgot(mask_bytes);
+    int nbox = 0;
+    int st = MIAUG_OK;
+    if (a->boxes) {
+        st = hip_status(hipMemcpyAsync(&nbox, a->box_off + a->n, sizeof(int), hipMemcpyDeviceToHost, s), "copy");
+        if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+        if (st) return st;
+        if (nbox < 0) return set_error(MIAUG_EINVAL, "autotune: box_off[n] = %d", nbox);
+    }
+    const size_t box_bytes = (size_t)nbox * 4 * sizeof(float);
+    std::vector<char> ref(out_bytes), got(out_bytes), mref(mask_bytes), mgot(mask_bytes), bref(box_bytes),
+        bgot(box_bytes);
+    // Every run starts from the same sentinel in all three outputs, so images
+    // a launch skips (their outputs stay untouched) compare equal, and a form
+    // that leaves a mask or box unwritten does not.
+    auto fill = [&]() {
+        int e = hip_status(launch_fill_u32((uint32_t *)a->out, out_words, 0x7fc0a5a5u, s), "autotune fill");
+        if (!e && mask_bytes) e = hip_status(launch_fill_u8(a->out_mask, mask_bytes, 0xa5, s), "autotune fill");
+        if (!e && box_bytes)
+            e = hip_status(launch_fill_u32((uint32_t *)a->out_boxes, (size_t)nbox * 4, 0x7fc0a5a5u, s), "autotune fill");
+        return e;
+    };
+    auto fetch = [&](std::vector<char> &o, std::vector<char> &mo, std::vector<char> &bo) {
+        int e = hip_status(hipMemcpyAsync(o.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
+        if (!e && mask_bytes)
+            e = hip_status(hipMemcpyAsync(mo.data(), a->out_mask, mask_bytes, hipMemcpyDeviceToHost, s), "copy");
+        if (!e && box_bytes)
+            e = hip_status(hipMemcpyAsync(bo.data(), a->out_boxes, box_bytes, hipMemcpyDeviceToHost, s), "copy");
+        if (!e) e = hip_status(hipStreamSynchronize(s), "sync");
+        return e;
+    };
     RaggedLaunch L{0, ctx->num_cu, ctx->counters};
-    int st = hip_status(launch_ragged(a, L, 1, s), "autotune reference");
-    if (!st) st = hip_status(hipMemcpyAsync(ref.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
-    if (!st && mask_bytes)
-        st = hip_status(hipMemcpyAsync(mref.data(), a->out_mask, mask_bytes, hipMemcpyDeviceToHost, s), "copy");
-    if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+    st = fill();
+    if (!st) st = hip_status(launch_ragged(a, L, 1, s), "autotune reference");
+    if (!st) st = fetch(ref, mref, bref);
     if (st) return st;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
@@ -356,14 +384,12 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
     for (int v = 0; v < ragged_variant_count() && !st; ++v) {
         L.variant = v;
         if (times) times[v] = -1.f;
-        st = hip_status(hipMemsetAsync(a->out, 0, out_bytes, s), "clear");
+        st = fill();
         if (!st) st = hip_status(launch_ragged(a, L, 0, s), "autotune candidate");
-        if (!st) st = hip_status(hipMemcpyAsync(got.data(), a->out, out_bytes, hipMemcpyDeviceToHost, s), "copy");
-        if (!st && mask_bytes)
-            st = hip_status(hipMemcpyAsync(mgot.data(), a->out_mask, mask_bytes, hipMemcpyDeviceToHost, s), "copy");
-        if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+        if (!st) st = fetch(got, mgot, bgot);
         if (st) break;
-        if (memcmp(ref.data(), got.data(), out_bytes) != 0 || memcmp(mref.data(), mgot.data(), mask_bytes) != 0)
+        if (memcmp(ref.data(), got.data(), out_bytes) != 0 || memcmp(mref.data(), mgot.data(), mask_bytes) != 0 ||
+            memcmp(bref.data(), bgot.data(), box_bytes) != 0)
             continue;  // parity gate: only variants identical to the per-image form compete
         // untimed launches first: the parity copy above leaves the GPU idle, and
         // its clocks need some back-to-back work to come up again

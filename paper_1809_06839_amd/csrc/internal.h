@@ -68,6 +68,7 @@ size_t box_workspace_bytes(int n, int H, int W);
 hipError_t launch_elastic_fields_box(uint64_t seed, uint64_t first, int n, int H, int W, double sigma, int alpha,
                                      int32_t *off, void *ws, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s);
 hipError_t launch_grid_tables(const double *grid, int n, int H, int W, int32_t *mapx, int32_t *mapy, hipStream_t s);
 hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n, int H, int W, int C,
                                   const int32_t *off, const int32_t *mapx, const int32_t *mapy, uint8_t *out,

@@ -939,6 +939,10 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+__global__ void k_fill_u8(uint8_t *__restrict__ p, size_t n, uint8_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
 __global__ void k_fill_zero(float *__restrict__ p, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
@@ -1194,6 +1198,12 @@ hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, con
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, size_t n, uint8_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

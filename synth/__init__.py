@@ -101,14 +101,16 @@ class RaggedBatch:
 
 
 def ragged_batch(seed: int, n: int, lo: int = 128, hi: int = 1024, K: int = 21, mask_spacing: int = 128,
-                 max_boxes: int = 16, device="cpu", sizes=None, canvases: int = 16) -> RaggedBatch:
+                 max_boxes: int = 16, device="cpu", sizes=None, canvases: int = 16, phases=None) -> RaggedBatch:
     """n RGB images with H, W ~ U{lo..hi}, blob masks with K labels, 0..max_boxes boxes.
 
     Content: `canvases` smooth-noise canvases (and blob-mask canvases) of the
     largest size are drawn once; image i is the H x W window of canvas i mod
     `canvases` at a random offset, so every image is smooth noise with the same
-    statistics while generation costs a few kernel launches.  Returns host-side
-    (numpy) buffers."""
+    statistics while generation costs a few kernel launches.  Image and mask
+    starts are 256-byte aligned, or, with `phases` (a list of byte offsets),
+    image i and its mask start phases[i % len(phases)] bytes after a 256-byte
+    boundary.  Returns host-side (numpy) buffers."""
     rng = np.random.default_rng(seed)
     hw = np.asarray(sizes, np.int32) if sizes is not None else rng.integers(lo, hi + 1, size=(n, 2)).astype(np.int32)
     CH, CW = int(hw[:, 0].max()), int(hw[:, 1].max())
@@ -119,9 +121,10 @@ def ragged_batch(seed: int, n: int, lo: int = 128, hi: int = 1024, K: int = 21, 
     img_off = np.zeros(n, np.int64); mask_off = np.zeros(n, np.int64)
     io = mo = 0
     for i, (H, W) in enumerate(hw):
-        img_off[i] = io; mask_off[i] = mo
-        io += -(-int(H) * int(W) * 3 // align) * align
-        mo += -(-int(H) * int(W) // align) * align
+        ph = int(phases[i % len(phases)]) if phases else 0
+        img_off[i] = io + ph; mask_off[i] = mo + ph
+        io += -(-(int(H) * int(W) * 3 + ph) // align) * align
+        mo += -(-(int(H) * int(W) + ph) // align) * align
     img = np.zeros(io, np.uint8); mask = np.zeros(mo, np.uint8)
     boxes, box_off = [], [0]
     for i, (H, W) in enumerate(hw):

@@ -97,6 +97,53 @@ def test_graph_replays_match_eager(m, ctx, small):
     g.close()
 
 
+# ---------------------------------------------------------------- image and mask starts at any byte offset
+@pytest.fixture(scope="module")
+def unaligned(m):
+    # image and mask i start 1, 7 or 13 bytes past a 256-byte boundary, so the
+    # 16-byte chunks the kernels stage straddle each image's first and last byte
+    b = synth.ragged_batch(13, len(SMALL_SIZES), sizes=SMALL_SIZES, phases=(1, 7, 13))
+    assert set(int(o) % 16 for o in b.img_off) == {1, 7, 13}
+    assert set(int(o) % 16 for o in b.mask_off) == {1, 7, 13}
+    flags, ab = m.sample_d4bc(13, 0, len(SMALL_SIZES))
+    flags[:8] = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 2, 0), (0, 0, 3, 0), (0, 0, 0, 1),
+                 (1, 1, 1, 1)]
+    return b, flags, ab
+
+
+@pytest.mark.parametrize("variant", range(16))
+def test_unaligned_starts_all_variants_bit_exact(m, ctx, unaligned, variant):
+    if variant >= len(m.ragged_variants()):
+        pytest.skip("the library has fewer variants")
+    b, flags, ab = unaligned
+    ctx.set_variant(variant)
+    r = m.Ragged.from_host(b, flags, ab)
+    m.ragged_apply(ctx, r)
+    check_outputs(m, b, r, flags, ab, range(b.n))
+    win = crop_windows(b, flags, 79)
+    rc = m.Ragged.from_host(b, flags, ab, crop=win)
+    m.ragged_apply(ctx, rc)
+    check_crop_outputs(b, rc, flags, ab, win, range(b.n))
+    ctx.set_variant(-1)
+
+
+def test_unaligned_starts_per_image_and_graph(m, ctx, unaligned):
+    import torch
+    b, flags, ab = unaligned
+    r = m.Ragged.from_host(b, flags, ab)
+    m.ragged_apply_per_image(ctx, r)
+    check_outputs(m, b, r, flags, ab, range(b.n))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = m.Graph(ctx, r, s)
+        for rep in range(3):
+            r.out.zero_(); r.out_mask.zero_()
+            g.launch(s)
+            s.synchronize()
+            check_outputs(m, b, r, flags, ab, range(b.n))
+    g.close()
+
+
 def test_empty_ragged_batch(m, ctx):
     import torch
     z = lambda *s, dt=torch.int32: torch.zeros(s, dtype=dt, device="cuda")
@@ -183,6 +230,23 @@ def test_crop_window_per_image_form_and_skips(m, ctx, small):
     out, om = r.out.cpu().numpy(), r.out_mask.cpu().numpy()
     for i in bad:  # skipped images: outputs untouched
         assert np.all(out[i] == 7.0) and np.all(om[i] == 9), i
+
+
+def test_autotune_gate_with_skipped_images(m, small):
+    # images whose window is invalid are skipped (outputs untouched) by every
+    # form alike, so every variant passes the parity gate
+    b, flags, ab = small
+    win = crop_windows(b, flags, 78, scale=(0.3, 0.9))
+    win[1] = (0, 0, 2, 400)
+    win[6] = (-1, 0, 1, 1)
+    c2 = m.Context(0)
+    r = m.Ragged.from_host(b, flags, ab, crop=win)
+    v, ms, times = m.ragged_autotune(c2, r, reps=1, return_times=True)
+    assert all(t > 0 for t in times), times
+    full = [i for i in range(b.n) if i not in (1, 6)]
+    m.ragged_apply(c2, r)
+    check_crop_outputs(b, r, flags, ab, win, full)
+    c2.close()
 
 
 def test_full_size_batch_with_crop_windows_sampled_against_oracle(m, ctx):
