@@ -343,6 +343,29 @@ const char *miaug_ragged_variant_name(int v);
 /* Forces a variant (-1 restores the default). */
 int miaug_ragged_set_variant(miaug_ctx *ctx, int v);
 
+/* No-allocation form of miaug_ragged_apply, for callers that cannot allocate
+ * device memory: code under hipGraph stream capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  It needs no context and calls no
+ * hipMalloc, hipFree or other allocating routine: the queue counters the
+ * persistent kernel uses live in a static device array of the library
+ * (MIAUG_NOALLOC_SCRATCH_BYTES bytes on each GPU, held until the process ends),
+ * whose address is looked up once per device on the first call made with that
+ * device current.  Runs on the calling thread's current HIP device.
+ *   args     as miaug_ragged_apply (all device pointers, caller-owned)
+ *   variant  launch variant (miaug_ragged_variant_count; the index the
+ *            autotuner chose), -1 for the default
+ * Output is bit-identical to miaug_ragged_apply with the same variant.  The
+ * counters are cleared by a fill kernel enqueued before each launch, so each
+ * call starts from zero; calls that overlap in time on one GPU (different
+ * streams, or threads without ordering) share the one array and race, and
+ * must be serialised by the caller.  The counters do not grow with the
+ * batch, so every batch miaug_ragged_apply accepts is accepted.
+ * Errors: as miaug_ragged_apply; EINVAL variant out of range; ECAPACITY if a
+ * launch form needs more counter memory than the static array holds;
+ * EUNSUPPORTED device index >= 64; EDEVICE symbol lookup or launch failure. */
+#define MIAUG_NOALLOC_SCRATCH_BYTES 1024
+int miaug_ragged_apply_noalloc(const miaug_ragged_args *args, int variant, void *stream);
+
 /* ---------------------------------------------------------------- differentiable warp + colour
  * Float32 form for training-time augmentation with gradients.  Per image i
  * and channel c, with p_i = {angle_deg, scale, tx, ty, alpha, beta, gamma}:

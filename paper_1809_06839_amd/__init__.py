@@ -115,6 +115,7 @@ _SIGS = {
     "miaug_ragged_variant_count": (_i, []),
     "miaug_ragged_variant_name": (ctypes.c_char_p, [_i]),
     "miaug_ragged_set_variant": (_i, [_vp, _i]),
+    "miaug_ragged_apply_noalloc": (_i, [ctypes.POINTER(RaggedArgs), _i, _vp]),
     "miaug_warpcolor_fwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp]),
     "miaug_warpcolor_workspace_bytes": (_sz, [_i, _i, _i, _i]),
     "miaug_warpcolor_bwd": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -455,6 +456,12 @@ class Ragged:
 
 def ragged_apply(ctx: Context, r: Ragged, stream=None):
     _check(lib().miaug_ragged_apply(ctx.handle, ctypes.byref(r.args), _stream(stream)))
+    return r
+
+
+def ragged_apply_noalloc(r: Ragged, variant: int = -1, stream=None):
+    """ragged_apply without a context or any device allocation (static counters)."""
+    _check(lib().miaug_ragged_apply_noalloc(ctypes.byref(r.args), variant, _stream(stream)))
     return r
 
 

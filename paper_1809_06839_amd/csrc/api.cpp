@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -313,6 +314,70 @@ int miaug_graph_destroy(miaug_graph *g) {
     hipGraphDestroy(g->graph);
     delete g;
     return MIAUG_OK;
+}
+
+// Device scratch of miaug_ragged_apply_noalloc: the queue counters of the
+// persistent ragged kernel, one copy per GPU (the runtime loads the array into
+// every device the library runs on; each copy lives until the process ends).
+// Host code never passes `scratch` itself to a kernel or a copy: on the host
+// the name stands for a host-side shadow, not a device address.  It resolves
+// the device address once per device with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) int scratch[MIAUG_NOALLOC_SCRATCH_BYTES / sizeof(int)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+struct NoAllocSlot {
+    std::once_flag once;
+    int status = MIAUG_OK;
+    int *ptr = nullptr;  // device address of this device's `scratch`
+    int num_cu = 0;
+    char err[256] = "";
+};
+NoAllocSlot g_noalloc[kMaxDevices];
+
+// Set-up of device `dev` (current at the call): the address of its copy of
+// `scratch` and its compute-unit count.  Runs once per device.
+void noalloc_setup(NoAllocSlot &S, int dev) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        S.status = MIAUG_EDEVICE;
+        snprintf(S.err, sizeof(S.err), "ragged_apply_noalloc: hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                 hipGetErrorString(e));
+        return;
+    }
+    int cu = 0;
+    e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cu < 1) {
+        S.status = MIAUG_EDEVICE;
+        snprintf(S.err, sizeof(S.err), "ragged_apply_noalloc: compute-unit count of device %d: %s", dev,
+                 hipGetErrorString(e));
+        return;
+    }
+    S.ptr = (int *)p;
+    S.num_cu = cu;
+}
+}  // namespace
+
+int miaug_ragged_apply_noalloc(const miaug_ragged_args *a, int variant, void *stream) {
+    begin_call();
+    if (int st = ragged_check(a)) return st;
+    if (variant < -1 || variant >= ragged_variant_count())
+        return set_error(MIAUG_EINVAL, "ragged_apply_noalloc: variant %d out of range", variant);
+    const size_t need = (size_t)ragged_counter_ints() * sizeof(int);
+    if (need > MIAUG_NOALLOC_SCRATCH_BYTES)
+        return set_error(MIAUG_ECAPACITY, "ragged_apply_noalloc: needs %zu bytes of scratch, the static array holds %d",
+                         need, MIAUG_NOALLOC_SCRATCH_BYTES);
+    if (a->n == 0) return MIAUG_OK;
+    int dev = -1;
+    if (int st = hip_status(hipGetDevice(&dev), "hipGetDevice")) return st;
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(MIAUG_EUNSUPPORTED, "ragged_apply_noalloc: device %d (at most %d devices)", dev, kMaxDevices);
+    NoAllocSlot &S = g_noalloc[dev];
+    std::call_once(S.once, noalloc_setup, std::ref(S), dev);
+    if (S.status != MIAUG_OK) return set_error(S.status, "%s", S.err);
+    RaggedLaunch L{variant < 0 ? ragged_default_variant() : variant, S.num_cu, S.ptr};
+    return hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply_noalloc launch");
 }
 
 int miaug_ragged_variant_count(void) { return ragged_variant_count(); }

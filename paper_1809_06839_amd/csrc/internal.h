@@ -44,6 +44,8 @@ hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int 
 int ragged_variant_count();
 const char *ragged_variant_name(int v);
 int ragged_default_variant();
+// Ints of queue-counter memory launch_ragged uses (RaggedLaunch::counters).
+int ragged_counter_ints();
 
 hipError_t launch_c2(const uint8_t *in, int n, int H, int W, const miaug_c2_record *rec, int crop, int outsz,
                      uint8_t *out, hipStream_t s);

@@ -1388,6 +1388,7 @@ hipError_t launch_pipe5_only(const miaug_ragged_args *a, const Variant &v, const
 int ragged_variant_count() { return kNumVariants; }
 const char *ragged_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : nullptr; }
 int ragged_default_variant() { return 0; }
+int ragged_counter_ints() { return kQueues * kCounterStride; }
 
 hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s) {
     if (a->n == 0) return hipSuccess;
