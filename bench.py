@@ -63,7 +63,7 @@ def profiled_traffic(profile: str, variant_name: str):
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1809_06839_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("k_ragged.hip", "dev_common.h"):
+    for f in ("k_ragged.hip", "k_rows.hip", "k_gather.hip", "ragged_common.h", "dev_common.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     if fields.get("kernel_source_sha256_16", "").strip() != h.hexdigest()[:16]:
         return None
@@ -110,6 +110,10 @@ def ragged_algorithmic_bytes(hw, nboxes, out=224):
 
 def ragged_kernel_name(variant_name: str) -> str:
     """Kernel that a ragged launch variant runs."""
+    if "row bands" in variant_name:
+        return "k_rows"
+    if "row gathers" in variant_name:
+        return "k_gather"
     if "double-buffered" in variant_name:
         return "k_ragged_pipe6"
     if "planning wave" in variant_name:

@@ -90,13 +90,53 @@ int miaug_sample_grid(uint64_t seed, uint64_t first_index, int n, double limit, 
 
 /* ---------------------------------------------------------------- context
  * A context holds per-device state: queue counters of the persistent ragged
- * kernel, the tuned launch choice and device properties.  One context per
- * host thread/stream; calls on one context must not overlap in time on
- * different streams. */
+ * kernel, the tuned launch choice, the autotuner's cache file, counters of
+ * its use and device properties.  One context per host thread/stream; calls
+ * on one context must not overlap in time on different streams. */
 typedef struct miaug_ctx miaug_ctx;
-/* Creates a context on HIP device `device` (allocates 4 KiB of device memory). */
-int miaug_ctx_create(int device, miaug_ctx **out);
+/* Creates a context on HIP device `device` (allocates 1 KiB of device
+ * memory).  tune_cache_path: JSON file in which miaug_ragged_autotune keeps its
+ * choice per (GPU architecture, chain, batch-shape bucket) and from which later
+ * processes take it without timing; NULL = the MIAUG_TUNE_CACHE environment
+ * variable, or no cache when that is unset too.  The file is created on the
+ * first autotuner run; a file that is not a cache is ignored and replaced.
+ * Errors: EINVAL null out or device out of range; EDEVICE no HIP device;
+ * ENOMEM allocation failure. */
+int miaug_ctx_create(int device, const char *tune_cache_path, miaug_ctx **out);
 int miaug_ctx_destroy(miaug_ctx *ctx);
+
+/* Counters of a context since its creation. */
+typedef struct {
+    uint64_t calls;           /* calls with this context whose arguments were accepted   */
+    uint64_t launches;        /* batched or per-image ragged launches enqueued           */
+    uint64_t tune_runs;       /* autotuner runs that timed the variants                  */
+    uint64_t tune_cache_hits; /* autotuner runs answered from the cache file             */
+    uint64_t errors;          /* of those, calls that failed (device, launch, memory)    */
+    int32_t variant;          /* ragged launch variant the next launch uses              */
+    int32_t last_status;      /* status of the last call                                 */
+} miaug_stats;
+/* Copies the counters to *out.  Errors: EINVAL null pointer. */
+int miaug_ctx_stats(const miaug_ctx *ctx, miaug_stats *out);
+
+/* The autotuner's cache file, for tools and tests (host only, no GPU needed).
+ * lookup: the entry stored under `key` -> *variant, *ms and the variant's name
+ * (copied into name[0..name_len-1], NUL-terminated; name may be NULL); returns
+ * MIAUG_EUNSUPPORTED when the file has no such key (or does not exist) and
+ * MIAUG_EINVAL when it is not a cache file.  store: adds or replaces the entry
+ * (written to a temporary file renamed over the cache).  Errors: EINVAL null
+ * path or key, or the file cannot be written. */
+int miaug_tune_cache_lookup(const char *path, const char *key, int *variant, float *ms, char *name, size_t name_len);
+int miaug_tune_cache_store(const char *path, const char *key, int variant, const char *name, float ms);
+
+/* Failure injection for tests of the error paths: the library's allocation
+ * number `after` (0 = the next one; device or pinned host memory, counted
+ * across the process) fails with MIAUG_ENOMEM, once; -1 disarms.  The same
+ * as setting MIAUG_FAIL_ALLOC_AFTER before the first call. */
+int miaug_debug_fail_alloc_after(long after);
+/* Allocates `bytes` of device memory through the library's allocator (the one
+ * the injector above intercepts) and frees it; returns the allocation status
+ * (MIAUG_ENOMEM when injected, MIAUG_EDEVICE without a usable device). */
+int miaug_debug_alloc_probe(size_t bytes);
 
 /* ---------------------------------------------------------------- plain Dih4 + brightness/contrast
  * Sec. II-B (random transformation from Dih4) and Table I (HorizontalFlip,

@@ -28,7 +28,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 builds and loads an AddressSanitizer + UndefinedBehaviorSanitizer
+# copy instead (the process must preload the sanitizer runtimes)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 
 BILINEAR, NEAREST = 0, 1
 REFLECT101, CONSTANT, REPLICATE = 0, 1, 2
@@ -42,8 +45,9 @@ def build(force: bool = False) -> str:
     """Compile ``oracle.c`` into ``liboracle.so`` with gcc (no GPU involved)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        san = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"] if _SANITIZE else []
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-Wextra"] + san + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

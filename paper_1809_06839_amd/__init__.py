@@ -89,7 +89,13 @@ _SIGS = {
     "miaug_sample_c2": (_i, [_u64, _u64, _i, _i, _vp, _vp]),
     "miaug_sample_wc": (_i, [_u64, _u64, _i, _vp]),
     "miaug_sample_grid": (_i, [_u64, _u64, _i, _d, _vp]),
-    "miaug_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
+    "miaug_ctx_create": (_i, [_i, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    "miaug_ctx_stats": (_i, [_vp, ctypes.c_void_p]),
+    "miaug_tune_cache_lookup": (_i, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(_i), ctypes.POINTER(ctypes.c_float),
+                                     ctypes.c_char_p, _sz]),
+    "miaug_tune_cache_store": (_i, [ctypes.c_char_p, ctypes.c_char_p, _i, ctypes.c_char_p, ctypes.c_float]),
+    "miaug_debug_fail_alloc_after": (_i, [ctypes.c_long]),
+    "miaug_debug_alloc_probe": (_i, [_sz]),
     "miaug_ctx_destroy": (_i, [_vp]),
     "miaug_d4_bc_u8": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, _vp]),
     "miaug_ssr_crop_resize_hsv_gamma_blur_u8": (_i, [_vp, _i, _i, _i, _vp, _i, _i, _vp, _vp]),
@@ -220,13 +226,24 @@ def sample_grid(seed: int, first: int, n: int, limit: float = 0.3):
 
 
 # ---------------------------------------------------------------- context
-class Context:
-    """Per-device state (queue counters, tuned variant) of the ragged kernels."""
+class Stats(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_uint64), ("launches", ctypes.c_uint64), ("tune_runs", ctypes.c_uint64),
+                ("tune_cache_hits", ctypes.c_uint64), ("errors", ctypes.c_uint64), ("variant", ctypes.c_int32),
+                ("last_status", ctypes.c_int32)]
 
-    def __init__(self, device: int = 0):
+
+class Context:
+    """Per-device state (queue counters, tuned variant, autotuner cache file) of the ragged kernels."""
+
+    def __init__(self, device: int = 0, tune_cache: str | None = None):
         h = ctypes.c_void_p()
-        _check(lib().miaug_ctx_create(device, ctypes.byref(h)))
+        _check(lib().miaug_ctx_create(device, tune_cache.encode() if tune_cache else None, ctypes.byref(h)))
         self.handle = h
+
+    def stats(self) -> dict:
+        st = Stats()
+        _check(lib().miaug_ctx_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in Stats._fields_}
 
     def close(self):
         if self.handle:
@@ -241,6 +258,25 @@ class Context:
 
     def set_variant(self, v: int):
         _check(lib().miaug_ragged_set_variant(self.handle, v))
+
+
+def tune_cache_lookup(path: str, key: str):
+    """(variant, ms, name) stored under key in an autotuner cache file, or None."""
+    v, ms, name = ctypes.c_int(), ctypes.c_float(), ctypes.create_string_buffer(256)
+    st = lib().miaug_tune_cache_lookup(path.encode(), key.encode(), ctypes.byref(v), ctypes.byref(ms), name, 256)
+    if st == EUNSUPPORTED:
+        return None
+    _check(st)
+    return v.value, ms.value, name.value.decode()
+
+
+def tune_cache_store(path: str, key: str, variant: int, name: str, ms: float):
+    _check(lib().miaug_tune_cache_store(path.encode(), key.encode(), variant, name.encode(), ms))
+
+
+def debug_fail_alloc_after(after: int):
+    """The library's allocation number `after` from now fails with MIAUG_ENOMEM, once (-1 disarms)."""
+    _check(lib().miaug_debug_fail_alloc_after(after))
 
 
 def ragged_variants():

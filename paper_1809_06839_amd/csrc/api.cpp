@@ -1,5 +1,5 @@
-// api.cpp -- the C ABI of libmiaug: argument validation, error reporting,
-// contexts, graphs and the ragged-batch autotuner.  Every image operation is
+// api.cpp -- the C ABI of libmiaug: argument validation, contexts, graphs
+// and the ragged-batch autotuner.  Every image operation is
 // executed by the HIP kernels behind the launch_* functions.
 #include <hip/hip_runtime.h>
 #include <stdarg.h>
@@ -12,28 +12,6 @@
 
 #include "internal.h"
 
-namespace miaug {
-namespace {
-thread_local char g_err[512] = "";
-}
-
-int set_error(int status, const char *fmt, ...) {
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_err, sizeof(g_err), fmt, ap);
-    va_end(ap);
-    return status;
-}
-
-void clear_error() { g_err[0] = 0; }
-
-int hip_status(hipError_t e, const char *what) {
-    if (e == hipSuccess) return MIAUG_OK;
-    return set_error(e == hipErrorOutOfMemory ? MIAUG_ENOMEM : MIAUG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-}  // namespace miaug
-
 using namespace miaug;
 
 struct miaug_graph {
@@ -44,8 +22,27 @@ struct miaug_graph {
 namespace {
 
 int begin_call() {
-    g_err[0] = 0;
+    clear_error();
     return MIAUG_OK;
+}
+
+// Launch variant of a context: MIAUG_FORCE_VARIANT when set and in range.
+int ctx_variant(const miaug_ctx *c) {
+    const int f = env().force_variant;
+    return (f >= 0 && f < ragged_variant_count()) ? f : c->variant;
+}
+
+// Bookkeeping of a context call whose arguments were accepted; returns st.
+// (Argument errors return before it: a context pointer is only trusted once
+// the rest of the call checks out.)
+int ctx_done(miaug_ctx *c, int st) {
+    if (c) {
+        c->stats.calls++;
+        c->stats.last_status = st;
+        if (st < 0) c->stats.errors++;
+    }
+    if (st < 0) log_msg(1, "error %d: %s", st, miaug_last_error());
+    return st;
 }
 
 // Status of a ragged argument block (sizes of each image are validated on
@@ -69,24 +66,8 @@ int ragged_check(const miaug_ragged_args *a) {
 
 extern "C" {
 
-int miaug_version(void) { return 10000; }
 
-const char *miaug_status_str(int s) {
-    switch (s) {
-    case MIAUG_OK: return "ok";
-    case MIAUG_EINVAL: return "invalid argument";
-    case MIAUG_ESHAPE: return "invalid or unsupported shape";
-    case MIAUG_EUNSUPPORTED: return "unsupported";
-    case MIAUG_EDEVICE: return "device error";
-    case MIAUG_ENOMEM: return "out of memory";
-    case MIAUG_ECAPACITY: return "workspace too small";
-    default: return "unknown status";
-    }
-}
-
-const char *miaug_last_error(void) { return g_err; }
-
-int miaug_ctx_create(int device, miaug_ctx **out) {
+int miaug_ctx_create(int device, const char *tune_cache_path, miaug_ctx **out) {
     begin_call();
     if (!out) return set_error(MIAUG_EINVAL, "ctx_create: out is NULL");
     *out = nullptr;
@@ -101,11 +82,18 @@ int miaug_ctx_create(int device, miaug_ctx **out) {
     st = hip_status(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     miaug_ctx *c = nullptr;
     if (!st) {
-        c = new (std::nothrow) miaug_ctx{device, prop.multiProcessorCount, ragged_default_variant(), nullptr};
+        c = new (std::nothrow) miaug_ctx();
         if (!c) st = set_error(MIAUG_ENOMEM, "ctx_create: host allocation");
     }
     if (!st) {
-        st = hip_status(hipMalloc((void **)&c->counters, 256 * sizeof(int)), "hipMalloc counters");
+        c->device = device;
+        c->num_cu = prop.multiProcessorCount;
+        c->variant = ragged_default_variant();
+        c->counters = nullptr;
+        c->arch = prop.gcnArchName;
+        c->tune_cache = tune_cache_path ? tune_cache_path : env().tune_cache;
+        memset(&c->stats, 0, sizeof(c->stats));
+        st = dev_alloc((void **)&c->counters, 256 * sizeof(int), "ctx_create: queue counters");
         if (!st) st = hip_status(hipMemset(c->counters, 0, 256 * sizeof(int)), "hipMemset counters");
     }
     hipSetDevice(prev);
@@ -114,6 +102,8 @@ int miaug_ctx_create(int device, miaug_ctx **out) {
         delete c;
         return st;
     }
+    log_msg(2, "context on device %d (%s, %d CUs), tune cache %s", device, c->arch.c_str(), c->num_cu,
+         c->tune_cache.empty() ? "(none)" : c->tune_cache.c_str());
     *out = c;
     return MIAUG_OK;
 }
@@ -124,6 +114,55 @@ int miaug_ctx_destroy(miaug_ctx *c) {
     if (c->counters) hipFree(c->counters);
     delete c;
     return MIAUG_OK;
+}
+
+int miaug_ctx_stats(const miaug_ctx *c, miaug_stats *out) {
+    begin_call();
+    if (!c || !out) return set_error(MIAUG_EINVAL, "ctx_stats: NULL pointer");
+    *out = c->stats;
+    out->variant = ctx_variant(c);
+    return MIAUG_OK;
+}
+
+int miaug_tune_cache_lookup(const char *path, const char *key, int *variant, float *ms, char *name, size_t name_len) {
+    begin_call();
+    if (!path || !key) return set_error(MIAUG_EINVAL, "tune_cache_lookup: NULL path or key");
+    TuneEntry e;
+    const int st = tune_cache_get(path, key, &e);
+    if (st == MIAUG_EUNSUPPORTED) return set_error(st, "tune_cache_lookup: %s has no entry %s", path, key);
+    if (st) return st;
+    if (variant) *variant = e.variant;
+    if (ms) *ms = e.ms;
+    if (name && name_len) {
+        strncpy(name, e.name.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    return MIAUG_OK;
+}
+
+int miaug_tune_cache_store(const char *path, const char *key, int variant, const char *name, float ms) {
+    begin_call();
+    if (!path || !key) return set_error(MIAUG_EINVAL, "tune_cache_store: NULL path or key");
+    TuneEntry e;
+    e.key = key;
+    e.variant = variant;
+    e.name = name ? name : "";
+    e.ms = ms;
+    return tune_cache_put(path, e);
+}
+
+int miaug_debug_fail_alloc_after(long after) {
+    begin_call();
+    arm_alloc_failure(after);
+    return MIAUG_OK;
+}
+
+int miaug_debug_alloc_probe(size_t bytes) {
+    begin_call();
+    void *p = nullptr;
+    const int st = dev_alloc(&p, bytes, "alloc_probe");
+    if (p) hipFree(p);
+    return st;
 }
 
 int miaug_d4_bc_u8(const uint8_t *in, int n, int H, int W, int C, const int32_t *flags, const float *ab,
@@ -243,8 +282,11 @@ int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream)
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply: ctx is NULL");
     if (int st = ragged_check(a)) return st;
-    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
-    return hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply launch");
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
+    log_msg(3, "ragged_apply: %d images, variant %d (%s)", a->n, L.variant, ragged_variant_name(L.variant));
+    const int st = hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply launch");
+    if (!st && a->n > 0) ctx->stats.launches++;
+    return ctx_done(ctx, st);
 }
 
 int miaug_ragged_masks_u8(const miaug_ragged_args *a, int channels, uint8_t *out, void *stream) {
@@ -264,8 +306,10 @@ int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *a, voi
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply_per_image: ctx is NULL");
     if (int st = ragged_check(a)) return st;
-    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
-    return hip_status(launch_ragged(a, L, 1, as_stream(stream)), "ragged_apply_per_image launch");
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
+    const int st = hip_status(launch_ragged(a, L, 1, as_stream(stream)), "ragged_apply_per_image launch");
+    if (!st && a->n > 0) ctx->stats.launches++;
+    return ctx_done(ctx, st);
 }
 
 int miaug_ragged_graph_create(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream, miaug_graph **out) {
@@ -276,8 +320,9 @@ int miaug_ragged_graph_create(miaug_ctx *ctx, const miaug_ragged_args *a, void *
     if (!stream) return set_error(MIAUG_EINVAL, "graph_create: capture needs a non-null stream");
     hipStream_t s = as_stream(stream);
     int st = hip_status(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    if (st) return st;
-    RaggedLaunch L{ctx->variant, ctx->num_cu, ctx->counters};
+    if (st) return ctx_done(ctx, st);
+    ctx->stats.calls++;
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
     hipError_t le = launch_ragged(a, L, 0, s);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(s, &g);
@@ -388,21 +433,38 @@ int miaug_ragged_set_variant(miaug_ctx *ctx, int v) {
     if (!ctx) return set_error(MIAUG_EINVAL, "set_variant: NULL ctx");
     if (v < -1 || v >= ragged_variant_count()) return set_error(MIAUG_EINVAL, "set_variant: %d out of range", v);
     ctx->variant = v < 0 ? ragged_default_variant() : v;
+    return ctx_done(ctx, MIAUG_OK);
+}
+
+namespace {
+
+// Cache key of a ragged batch: GPU architecture, chain options, output size
+// and buckets (powers of two) of the image count, the mean image area and the
+// longest side, plus the size of the variant table.
+int ragged_tune_key(const miaug_ctx *ctx, const miaug_ragged_args *a, hipStream_t s, std::string &key) {
+    std::vector<int32_t> hw((size_t)2 * a->n);
+    int st = hip_status(hipMemcpyAsync(hw.data(), a->hw, hw.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                        "autotune: copy sizes");
+    if (!st) st = hip_status(hipStreamSynchronize(s), "sync");
+    if (st) return st;
+    double area = 0;
+    int side = 1;
+    for (int i = 0; i < a->n; ++i) {
+        area += (double)hw[2 * i] * hw[2 * i + 1];
+        side = hw[2 * i] > side ? hw[2 * i] : side;
+        side = hw[2 * i + 1] > side ? hw[2 * i + 1] : side;
+    }
+    auto lg = [](double v) { int k = 0; while (v > 1.5 && k < 62) { v /= 2; ++k; } return k; };
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|ragged|o%dx%d|m%db%dc%d|n%d|p%d|s%d|v%d", ctx->arch.c_str(), a->out_h, a->out_w,
+             a->mask != nullptr, a->boxes != nullptr, a->crop != nullptr, lg((double)a->n), lg(area / a->n),
+             lg((double)side), ragged_variant_count());
+    key = buf;
     return MIAUG_OK;
 }
 
-int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, void *stream, int *chosen, float *ms,
-                          float *times) {
-    begin_call();
-    if (!ctx) return set_error(MIAUG_EINVAL, "autotune: NULL ctx");
-    if (int st = ragged_check(a)) return st;
-    if (reps < 1) return set_error(MIAUG_EINVAL, "autotune: reps < 1");
-    if (a->n == 0) {
-        if (chosen) *chosen = ctx->variant;
-        if (ms) *ms = 0.f;
-        return MIAUG_OK;
-    }
-    hipStream_t s = as_stream(stream);
+int ragged_autotune_run(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, hipStream_t s, int *chosen, float *ms,
+                        float *times) {
     const size_t out_words = (size_t)a->n * 3 * a->out_h * a->out_w;
     const size_t out_bytes = out_words * sizeof(float);
     const size_t mask_bytes = a->mask ? (size_t)a->n * a->out_h * a->out_w : 0;
@@ -480,6 +542,60 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
     if (chosen) *chosen = best;
     if (ms) *ms = best_ms;
     return MIAUG_OK;
+}
+
+}  // namespace
+
+int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, void *stream, int *chosen, float *ms,
+                          float *times) {
+    begin_call();
+    if (!ctx) return set_error(MIAUG_EINVAL, "autotune: NULL ctx");
+    if (int st = ragged_check(a)) return st;
+    if (reps < 1) return set_error(MIAUG_EINVAL, "autotune: reps < 1");
+    if (a->n == 0) {
+        if (chosen) *chosen = ctx->variant;
+        if (ms) *ms = 0.f;
+        return ctx_done(ctx, MIAUG_OK);
+    }
+    hipStream_t s = as_stream(stream);
+    std::string key;
+    if (!ctx->tune_cache.empty()) {
+        if (int st = ragged_tune_key(ctx, a, s, key)) return ctx_done(ctx, st);
+        TuneEntry e;
+        const int cst = tune_cache_get(ctx->tune_cache, key, &e);
+        const char *nm = ragged_variant_name(e.variant);
+        if (cst == MIAUG_OK && nm && e.name == nm) {
+            ctx->variant = e.variant;
+            if (chosen) *chosen = e.variant;
+            if (ms) *ms = e.ms;
+            if (times)
+                for (int v = 0; v < ragged_variant_count(); ++v) times[v] = v == e.variant ? e.ms : -1.f;
+            ctx->stats.tune_cache_hits++;
+            log_msg(2, "autotune: %s from the cache: variant %d (%s), %.4f ms", key.c_str(), e.variant, nm, (double)e.ms);
+            clear_error();
+            return ctx_done(ctx, MIAUG_OK);
+        }
+        clear_error();  // a missing or stale entry is not an error
+    }
+    int v = -1;
+    float t = 0.f;
+    int st = ragged_autotune_run(ctx, a, reps, s, &v, &t, times);
+    if (st) return ctx_done(ctx, st);
+    ctx->stats.tune_runs++;
+    log_msg(2, "autotune: variant %d (%s), %.4f ms", v, ragged_variant_name(v), (double)t);
+    if (!key.empty()) {
+        TuneEntry e;
+        e.key = key;
+        e.variant = v;
+        e.name = ragged_variant_name(v);
+        e.ms = t;
+        st = tune_cache_put(ctx->tune_cache, e);  // the choice stands even if the file cannot be written
+        if (st) log_msg(1, "autotune: %s", miaug_last_error());
+        clear_error();
+    }
+    if (chosen) *chosen = v;
+    if (ms) *ms = t;
+    return ctx_done(ctx, MIAUG_OK);
 }
 
 int miaug_warpcolor_fwd(const float *x, int n, int C, int H, int W, const float *params, float *y, void *stream) {

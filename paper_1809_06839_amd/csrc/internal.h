@@ -5,16 +5,47 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "../../include/miaug.h"
 
 struct miaug_ctx {
     int device;
     int num_cu;
     int variant;
-    int *counters;  // device, 256 ints
+    int *counters;           // device, 256 ints
+    std::string arch;        // gcnArchName of the device (tune-cache keys)
+    std::string tune_cache;  // autotuner cache file ("" = none)
+    miaug_stats stats;
 };
 
 namespace miaug {
+
+// ---- runtime.cpp: environment, logging, allocations, tune cache
+struct EnvConfig {
+    int log_level = 0;
+    int force_variant = -1;
+    std::string tune_cache;
+    long fail_alloc_after = -1;
+};
+const EnvConfig &env();
+// Message to stderr when MIAUG_LOG >= level.
+void log_msg(int level, const char *fmt, ...);
+// hipMalloc / hipHostMalloc through the failure injector; status as hip_status.
+int dev_alloc(void **p, size_t bytes, const char *what);
+int pinned_alloc(void **p, size_t bytes, const char *what);
+// Arms the injector: the library's allocation number `after` from now fails once (-1 disarms).
+void arm_alloc_failure(long after);
+struct TuneEntry {
+    std::string key, name;
+    int variant = -1;
+    float ms = 0.f;
+};
+int tune_cache_read(const std::string &path, std::vector<TuneEntry> &out);
+// MIAUG_OK with *hit filled, MIAUG_EUNSUPPORTED when the key is absent.
+int tune_cache_get(const std::string &path, const std::string &key, TuneEntry *hit);
+int tune_cache_put(const std::string &path, const TuneEntry &e);
 
 // Records a formatted message as the calling thread's last error; returns status.
 int set_error(int status, const char *fmt, ...);
@@ -41,6 +72,12 @@ struct RaggedLaunch {
     int *counters;    // device: queue counters (8 + 8 padding ints)
 };
 hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s);
+// Row-band form of the batched launch (k_rows.hip); cap_kind 0/1/2 picks the stage size.
+hipError_t launch_ragged_rows(const miaug_ragged_args *a, int cap_kind, int wg_per_cu, const RaggedLaunch &L,
+                              hipStream_t s);
+// Wave-independent row-gather form of the batched launch (k_gather.hip).
+hipError_t launch_ragged_gather(const miaug_ragged_args *a, int band, int wg_per_cu, const RaggedLaunch &L,
+                                hipStream_t s);
 int ragged_variant_count();
 const char *ragged_variant_name(int v);
 int ragged_default_variant();

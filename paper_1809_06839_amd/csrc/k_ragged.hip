@@ -1278,9 +1278,10 @@ struct Variant {
     int tl, ts;
     int mode;       // 0 streaming pipeline, 1 persistent one pass at a time, 2 flat grid, 3 persistent with
                     // the next pass planned during the current pass's DMA, 4 the same with a planning wave,
-                    // 5 double-buffered stage with the planning wave two passes ahead, 6 register-staged loads
+                    // 5 double-buffered stage with the planning wave two passes ahead, 6 register-staged loads,
+                    // 7 row bands (k_rows.hip), 8 wave-independent row gathers (k_gather.hip)
     int wg_per_cu;  // workgroups per CU of the persistent modes
-    int chunk;      // tiles claimed per atomic (persistent mode)
+    int chunk;      // tiles claimed per atomic (persistent mode); stage size of the row-band form
     const char *name;
 };
 // Variant 0 is the default.  Workgroups per CU are chosen against the LDS as
@@ -1302,6 +1303,14 @@ const Variant kVariants[] = {
     {32, 32, 0, 2, 1, "tile 32x32, streaming pipeline 8+1 waves, 2 wg/CU"},
     {16, 64, 4, 4, 1, "tile 16x64, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {8, 128, 4, 4, 1, "tile 8x128, persistent 4 wg/CU, 4 worker waves + a planning wave"},
+    {0, 0, 7, 3, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 3 wg/CU"},
+    {0, 0, 7, 4, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 4 wg/CU"},
+    {0, 0, 7, 6, 1, "row bands of 16 lines, whole source rows, 9 KB stages x 2, 6 wg/CU"},
+    {0, 0, 7, 2, 2, "row bands of 16 lines, whole source rows, 36 KB stages x 2, 2 wg/CU"},
+    {0, 0, 8, 4, 32, "wave row gathers, 32 lines x 64 per item, 4 wg/CU"},
+    {0, 0, 8, 4, 16 + 64, "wave row gathers, 16 lines x 64 per item, band per workgroup, 4 wg/CU"},
+    {0, 0, 8, 4, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 4 wg/CU"},
+    {0, 0, 8, 6, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 6 wg/CU"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -1393,6 +1402,8 @@ int ragged_counter_ints() { return kQueues * kCounterStride; }
 hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s) {
     if (a->n == 0) return hipSuccess;
     const Variant &v = kVariants[(L.variant >= 0 && L.variant < kNumVariants) ? L.variant : 0];
+    if (!per_image && v.mode == 7) return launch_ragged_rows(a, v.chunk, v.wg_per_cu, L, s);
+    if (!per_image && v.mode == 8) return launch_ragged_gather(a, v.chunk, v.wg_per_cu, L, s);
     if (per_image || v.tl == 32) return launch_t<32, 32>(a, v, L, per_image, s);
     if (v.ts == 64) return launch_pipe5_only<16, 64>(a, v, L, s);
     if (v.ts == 128) return launch_pipe5_only<8, 128>(a, v, L, s);

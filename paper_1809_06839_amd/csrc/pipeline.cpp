@@ -248,7 +248,7 @@ int grow_pinned(miaug_pipeline *p, size_t bytes) {
         p->pinned = nullptr;
         p->pinned_cap = 0;
     }
-    int st = hip_status(hipHostMalloc(&p->pinned, bytes, hipHostMallocDefault), "pipeline: pinned staging");
+    int st = pinned_alloc(&p->pinned, bytes, "pipeline: pinned staging");
     if (!st) p->pinned_cap = bytes;
     return st;
 }
@@ -261,7 +261,7 @@ int grow_device(void **ptr, size_t *cap, size_t bytes, const char *what) {
         *ptr = nullptr;
         *cap = 0;
     }
-    int st = hip_status(hipMalloc(ptr, bytes), what);
+    int st = dev_alloc(ptr, bytes, what);
     if (!st) *cap = bytes;
     return st;
 }
@@ -916,7 +916,7 @@ int miaug_pipeline_graph_capture(miaug_pipeline *p, const miaug_batch_in *in, co
                                                                        0, nullptr, nullptr, nullptr};
     if (!G) return set_error(MIAUG_ENOMEM, "graph_capture: host allocation");
     G->packed = staged_bytes(p, in->n, in->channels);
-    st = hip_status(hipHostMalloc(&G->pinned, G->packed, hipHostMallocDefault), "graph_capture: pinned staging");
+    st = pinned_alloc(&G->pinned, G->packed, "graph_capture: pinned staging");
     if (!st) st = hip_status(hipEventCreateWithFlags(&G->done, hipEventDisableTiming), "event");
     // every record the chains read comes from the staging buffer at replay time; run_chain only
     // reads seed and index of the first record, for the elastic field, which is rejected above

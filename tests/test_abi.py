@@ -93,7 +93,7 @@ def test_ctx_create_reports_a_missing_device(miaug):
     if torch.cuda.is_available():
         pytest.skip("a GPU is visible")
     h = ctypes.c_void_p()
-    st = miaug.lib().miaug_ctx_create(0, ctypes.byref(h))
+    st = miaug.lib().miaug_ctx_create(0, None, ctypes.byref(h))
     assert st == miaug.EDEVICE and not h.value
 
 

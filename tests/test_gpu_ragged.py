@@ -54,7 +54,7 @@ def small(m):
     return b, flags, ab
 
 
-@pytest.mark.parametrize("variant", range(13))
+@pytest.mark.parametrize("variant", range(24))
 def test_small_ragged_all_variants_bit_exact(m, ctx, small, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
@@ -111,7 +111,7 @@ def unaligned(m):
     return b, flags, ab
 
 
-@pytest.mark.parametrize("variant", range(16))
+@pytest.mark.parametrize("variant", range(24))
 def test_unaligned_starts_all_variants_bit_exact(m, ctx, unaligned, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
@@ -198,7 +198,7 @@ def check_crop_outputs(b, r, flags, ab, win, idx, OH=224, OW=224):
             assert np.all(np.abs(got - rb) <= 1e-5 * np.maximum(1.0, np.abs(rb))), ("boxes", i)
 
 
-@pytest.mark.parametrize("variant", range(13))
+@pytest.mark.parametrize("variant", range(24))
 def test_crop_windows_all_variants_bit_exact(m, ctx, small, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
