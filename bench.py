@@ -205,7 +205,7 @@ def bench_ragged(args, torch, m):
                                "batched_speedup": ms_pi / ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic("k_ragged_2048img_ragged_to_224_f32.md", variants[variant]),
+                     "traffic": profiled_traffic("k_gather_2048img_ragged_to_224_f32.md", variants[variant]),
                      "kernel": ragged_kernel_name(variants[variant]), "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:

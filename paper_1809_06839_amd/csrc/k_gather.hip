@@ -17,11 +17,11 @@
 // tables live in LDS: the normalisation LUT per workgroup and one
 // brightness/contrast LUT per wave (rebuilt when its image changes).
 //
-// Keep-axes elements store each blended line at once (64 consecutive floats
-// per plane).  Swapping elements keep the band's pixels of each of their
-// output rows in a per-wave LDS tile (packed R | G << 8 | B << 16 |
-// mask << 24), written a line at a time, and at the band's end read it back
-// row-wise so that the stores write whole row runs.
+// Keep-axes elements pass every four blended lines through a per-wave LDS
+// tile and store them 16 bytes per lane.  Swapping elements keep the band's
+// pixels of each of their output rows in that tile (packed R | G << 8 |
+// B << 16 | mask << 24), written a line at a time, and at the band's end read
+// it back row-wise so that the stores write whole row runs.
 //
 // Work items are dealt to the eight per-XCD queues of k_ragged.hip; every wave
 // claims its own items, four at a time (the span segments of one band), one
@@ -213,6 +213,15 @@ __device__ __forceinline__ void gather_blend(const GLoads &L, const GLine &g, co
     }
 }
 
+// Word of tile row r, column k: rows of BAND words; the groups of four
+// columns are permuted by the row (group g of row r sits at g ^ (r mod 8)), so
+// that the 64 lanes' writes of one column spread over the LDS banks while a
+// group stays four aligned words for the 16-byte read back.
+template <int BAND>
+__device__ __forceinline__ int tile_word(int r, int k) {
+    return r * BAND + (k ^ ((r & 7 & (BAND / 4 - 1)) << 2));
+}
+
 // Band-end store of a swapping element: tile row j holds output row s0 + j,
 // columns l0 .. l0 + BAND - 1 (written one line at a time by gather_item).
 // The wave reads the tile back as runs of four columns, so that each store
@@ -221,7 +230,6 @@ __device__ __forceinline__ void gather_blend(const GLoads &L, const GLine &g, co
 template <int BAND>
 __device__ __forceinline__ void gather_store_swap(const miaug_ragged_args &a, const GItem &it,
                                                   const float (&nlut)[3][256], const uint32_t *tile) {
-    constexpr int RS = BAND + 4;   // tile row stride in words
     constexpr int LPR = BAND / 4;  // lanes per output row
     constexpr int RPI = 64 / LPR;  // output rows per store
     const int plane = a.out_h * a.out_w;
@@ -236,7 +244,7 @@ __device__ __forceinline__ void gather_store_swap(const miaug_ragged_args &a, co
 #pragma unroll
     for (int r0 = 0; r0 < 64; r0 += RPI) {
         const int r = r0 + lane / LPR;  // row of the tile (output row s0 + r)
-        const u32x4 w = *(const u32x4 *)(tile + r * RS + 4 * g);
+        const u32x4 w = *(const u32x4 *)(tile + tile_word<BAND>(r, 4 * g));
         // rows past the segment, and columns past the item, store past the
         // image's outputs (element 3 plane), where the range check drops them
         const int base = r < it.ns ? (it.s0 + r) * a.out_w + it.l0 : 3 * plane;
@@ -269,6 +277,51 @@ __device__ __forceinline__ void gather_store_swap(const miaug_ragged_args &a, co
         }
     }
     __builtin_amdgcn_wave_barrier();  // the tile is rewritten by this wave's next item
+}
+
+// Store of four keep-axes lines lf .. lf + 3 of the band from the tile (row
+// r = line lf + r, 64 packed pixels): lane j writes line lf + j / 16, span
+// positions 4 (j mod 16) .. + 3 -- 16 bytes per plane and 4 mask bytes -- when
+// the output rows take 16-byte stores, else one element at a time.  Lines past
+// the item and positions past the segment store past the image's outputs
+// (element 3 plane), where the buffer range check drops them.
+__device__ __forceinline__ void keep_flush(const miaug_ragged_args &a, const GItem &it, const float (&nlut)[3][256],
+                                           const uint32_t *tile, int lf, __amdgpu_buffer_rsrc_t ro,
+                                           __amdgpu_buffer_rsrc_t rmo) {
+    const int plane = a.out_h * a.out_w;
+    const bool has_mask = a.mask != nullptr;
+    const int lane = (int)(threadIdx.x & 63);
+    const int r = lane >> 4, g = lane & 15;
+    const u32x4 w = *(const u32x4 *)(tile + r * 64 + 4 * g);
+    const int l = lf + r, k = 4 * g;
+    const int base = (it.l0 + l) * a.out_w + it.s0;
+    if ((a.out_w & 3) == 0 && (it.ns & 3) == 0) {
+        const int off = (l < it.nl && k < it.ns) ? base + k : 3 * plane;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u32x4 v;
+            v.x = __float_as_uint(nlut[c][byte_of(w.x, c)]);
+            v.y = __float_as_uint(nlut[c][byte_of(w.y, c)]);
+            v.z = __float_as_uint(nlut[c][byte_of(w.z, c)]);
+            v.w = __float_as_uint(nlut[c][byte_of(w.w, c)]);
+            __builtin_amdgcn_raw_buffer_store_b128(v, ro, 4 * off, 4 * c * plane, 0);
+        }
+        if (has_mask) {
+            const uint32_t mv = (w.x >> 24) | ((w.y >> 24) << 8) | ((w.z >> 24) << 16) | (w.w & 0xff000000u);
+            __builtin_amdgcn_raw_buffer_store_b32(mv, rmo, off, 0, 0);
+        }
+    } else {
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int off = (l < it.nl && k + e < it.ns) ? base + k + e : 3 * plane;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(nlut[c][byte_of(ws[e], c)]), ro, 4 * off,
+                                                      4 * c * plane, 0);
+            if (has_mask) __builtin_amdgcn_raw_buffer_store_b8(ws[e] >> 24, rmo, off, 0, 0);
+        }
+    }
 }
 
 // Boxes of one image by one wave (lane-strided).
@@ -352,17 +405,14 @@ __device__ __forceinline__ void gather_item(const miaug_ragged_args &a, const GI
             gather_blend(ring[u], lines[u], tp, it.ks, bc, px);
             if constexpr (SWAP) {
                 // line l of the band is tile column l (lines past the item are never read back)
-                tile[(int)(threadIdx.x & 63) * (BAND + 4) + (l & (BAND - 1))] =
+                tile[tile_word<BAND>((int)(threadIdx.x & 63), l & (BAND - 1))] =
                     px[0] | (px[1] << 8) | (px[2] << 16) | (ring[u].m << 24);
             } else {
-                // a lane past the segment, or a line past the item, stores past
-                // the image's outputs, where the buffer range check drops it
-                const int off = (tp.on && l < it.nl) ? (it.l0 + l) * a.out_w + it.s0 + (int)(threadIdx.x & 63) : 3 * plane;
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(nlut[c][px[c]]), ro, 4 * off, 4 * c * plane,
-                                                          0);
-                __builtin_amdgcn_raw_buffer_store_b8(ring[u].m, rmo, off, 0, 0);
+                // four lines collect in the tile (row l mod 4) and leave in one
+                // store per plane: lane j takes line j / 16, columns 4 (j mod 16) .. + 3
+                const int lane = (int)(threadIdx.x & 63);
+                tile[(l & 3) * 64 + lane] = px[0] | (px[1] << 8) | (px[2] << 16) | (ring[u].m << 24);
+                if ((u & 3) == 3) keep_flush(a, it, nlut, tile, l - 3, ro, rmo);
             }
         }
     }
@@ -403,7 +453,7 @@ __global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4))) 
     miaug_ragged_args a, int *__restrict__ counters) {
     __shared__ float nlut[3][256];
     __shared__ uint8_t bcl[kGWaves][256];
-    __shared__ __align__(16) uint32_t tiles[kGWaves][64 * (BAND + 4)];  // per-wave transpose tile
+    __shared__ __align__(16) uint32_t tiles[kGWaves][64 * BAND];  // per-wave transpose tile
     __shared__ int3 claim_s;
     build_norm_lut(a, nlut);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);

@@ -17,12 +17,14 @@
 // passes over the halves of its span positions; a half that still does not
 // fit reads its taps straight from global memory.
 //
-// The default form is a persistent launch in which four worker waves of a
-// workgroup stream and blend pass k while a fifth wave claims items and plans
-// pass k+1 into a second table set.  Other launch forms are kept as autotuner
-// candidates: the same pipeline with the planning done by a rotating worker
-// wave, one pass at a time with chunked claims, a flat grid, and a streaming
-// form.
+// The best tile-pass form is a persistent launch in which four worker waves of
+// a workgroup stream and blend pass k while a fifth wave claims items and
+// plans pass k+1 into a second table set.  Other launch forms are kept as
+// autotuner candidates: the same pipeline with the planning done by a rotating
+// worker wave, one pass at a time with chunked claims, a flat grid, and a
+// streaming form.  This file also holds the launcher and the variant table of
+// every batched form, including the row bands of k_rows.hip and the wave
+// gathers of k_gather.hip (the default).
 //
 // The streaming form is a persistent launch in which every workgroup runs a
 // three-stage software pipeline over its passes: in one iteration it builds
@@ -1284,12 +1286,18 @@ struct Variant {
     int chunk;      // tiles claimed per atomic (persistent mode); stage size of the row-band form
     const char *name;
 };
-// Variant 0 is the default.  Workgroups per CU are chosen against the LDS as
-// measured on gfx950: a workgroup above about 40 KB runs as if only one fits
-// in each 80 KB half of the 160 KB (three 42.5 KB workgroups per CU run like
-// two), so the staged forms keep a workgroup at or under 40 KB.  The default
-// runs three per CU (four measured the same).
+// Variant 0 is the default: the wave-gather form of k_gather.hip with one
+// band per workgroup (0.66-0.68 ms per 2048-image batch against 0.76 ms for
+// the best tile-pass form, which follows it).  Workgroups per CU are chosen
+// against the LDS as measured on gfx950: a workgroup above about 40 KB runs as
+// if only one fits in each 80 KB half of the 160 KB (three 42.5 KB workgroups
+// per CU run like two), so the staged forms keep a workgroup at or under
+// 40 KB; the tile passes run three per CU (four measured the same).
 const Variant kVariants[] = {
+    {0, 0, 8, 4, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 4 wg/CU"},
+    {0, 0, 8, 6, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 6 wg/CU"},
+    {0, 0, 8, 4, 16 + 64, "wave row gathers, 16 lines x 64 per item, band per workgroup, 4 wg/CU"},
+    {0, 0, 8, 4, 32, "wave row gathers, 32 lines x 64 per item, 4 wg/CU"},
     {32, 32, 4, 3, 1, "tile 32x32, persistent 3 wg/CU, 4 worker waves + a planning wave"},
     {32, 32, 3, 4, 1, "tile 32x32, persistent 4 wg/CU, next pass planned during the DMA"},
     {32, 32, 5, 2, 1, "tile 32x32, persistent 2 wg/CU, double-buffered stage, planning wave two passes ahead"},
@@ -1307,10 +1315,6 @@ const Variant kVariants[] = {
     {0, 0, 7, 4, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 4 wg/CU"},
     {0, 0, 7, 6, 1, "row bands of 16 lines, whole source rows, 9 KB stages x 2, 6 wg/CU"},
     {0, 0, 7, 2, 2, "row bands of 16 lines, whole source rows, 36 KB stages x 2, 2 wg/CU"},
-    {0, 0, 8, 4, 32, "wave row gathers, 32 lines x 64 per item, 4 wg/CU"},
-    {0, 0, 8, 4, 16 + 64, "wave row gathers, 16 lines x 64 per item, band per workgroup, 4 wg/CU"},
-    {0, 0, 8, 4, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 4 wg/CU"},
-    {0, 0, 8, 6, 32 + 64, "wave row gathers, 32 lines x 64 per item, band per workgroup, 6 wg/CU"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
