@@ -8,22 +8,34 @@
 //   w = bilinear(x_ic, sx, sy) (taps outside the image read 0),
 //   z = alpha w + beta, y1 = clamp(z, 0, 1), y = y1^gamma (0^gamma = 0).
 // Sample positions are evaluated in double, pixel values and the colour ops
-// in float32 (no contraction); the forward and the backward evaluate the
-// positions with the same function, so both see the same bilinear cells.
+// in float32 (no contraction).
 //
-// Backward:
-//   k_wc_bwd_pix  one thread per output pixel: dL/dw per channel (stored in
-//                 the workspace) and the pixel's contributions to the 7
-//                 parameter gradients, reduced over the wavefront (shuffles)
-//                 and the workgroup (LDS) into one partial per workgroup;
-//   k_wc_bwd_img  the adjoint of the bilinear warp, owned per source tile: a
-//                 workgroup scans the output pixels whose sample point can
-//                 reach its tile (the forward image of the tile, plus a
-//                 margin), accumulates their weighted dL/dw in LDS and stores
-//                 the tile once -- every grad_x element has exactly one
-//                 writer, so no global atomics and no zero-fill are needed;
-//   k_wc_reduce   sums the per-workgroup partials of each image in a fixed
-//                 order (double accumulators).
+// Layout of the work:
+//   k_wc_fwd      one workgroup per 32 x 32 output tile, four pixels per
+//                 thread down a column (rows 8 apart): the fp64 position is
+//                 evaluated once per thread and stepped by the constant row
+//                 increment.  The tile's source footprint (its bounding box,
+//                 all channels) is staged in LDS with zeros outside the
+//                 image; a footprint too large for the box (zoom-out well
+//                 below 1) gathers its taps from global memory instead, as
+//                 32-bit buffer offsets where a tap outside the image gets an
+//                 offset past the end of the plane, which reads as 0;
+//   k_wc_bwd      one workgroup per 32 x 32 source tile: the adjoint of the
+//                 bilinear warp as a gather over the output pixels whose cell
+//                 has a tap in the tile (grad_x has one writer per element: no
+//                 global atomics, no zero-fill, no dL/dw buffer), with the
+//                 parameter-gradient terms of the output pixels the tile owns
+//                 reduced into one record per workgroup;
+//   k_wc_reduce   sums the records of each image in a fixed order (double
+//                 accumulators, one wave per image), plus the share of the
+//                 output pixels whose cell lies wholly outside the image.
+// The parameter gradients are bit-identical across runs.  grad_x is too,
+// except where three or more output pixels share one bilinear cell (a
+// zoom): the LDS slot order of those entries, and so their summation order,
+// follows the order of the count atomics.
+// y1^gamma is evaluated as exp2(gamma log2 y1) with the hardware base-2
+// exponential and logarithm (a few float32 ulp, well inside the 1e-5
+// forward and 1e-4 gradient tolerances).
 #include "dev_common.h"
 #include "internal.h"
 
@@ -31,9 +43,13 @@ namespace miaug {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTile = 16;                // output tile of the per-pixel kernels is 16 x 16
+constexpr int kTile = 32;                // output tile of the per-pixel kernels
+constexpr int kRowStep = 8;              // rows between a thread's four pixels
+constexpr int kPix = kTile * kTile / kThreads;
 constexpr int kSrcTile = 32;             // source tile of the adjoint kernel
+constexpr int kCells = kSrcTile + 1;     // cells with a tap in the tile, per axis
 constexpr int kMaxC = 4;
+constexpr uint32_t kOOB = 0x80000000u;   // byte offset past every plane (planes are at most 2^30 bytes)
 
 // Per-image geometry in double.  Sample positions are evaluated in double
 // because a float32 position alone carries up to 2^-17 relative error (about
@@ -57,56 +73,340 @@ __device__ __forceinline__ Geo make_geo(const float *p, int H, int W) {
     return g;
 }
 
-// Bilinear cell and weights of output pixel (x, y); X, Y are its offsets
-// from the shifted centre (used by the parameter chain rule).
-struct Cell {
-    int x0, y0;
-    float fx, fy;
-    double X, Y;
-};
-
-__device__ __forceinline__ Cell cell_of(const Geo &g, int x, int y) {
-    Cell k;
-    k.X = (double)x - g.ux;
-    k.Y = (double)y - g.uy;
-    const double sx = (g.c * k.X - g.s_ * k.Y) * g.inv_s + g.cx;
-    const double sy = (g.s_ * k.X + g.c * k.Y) * g.inv_s + g.cy;
-    const double fx0 = floor(sx), fy0 = floor(sy);
-    k.x0 = (int)fx0;
-    k.y0 = (int)fy0;
-    k.fx = (float)(sx - fx0);
-    k.fy = (float)(sy - fy0);
-    return k;
+__device__ __forceinline__ void sample_pos(const Geo &g, int x, int y, double &sx, double &sy) {
+    const double X = (double)x - g.ux, Y = (double)y - g.uy;
+    sx = (g.c * X - g.s_ * Y) * g.inv_s + g.cx;
+    sy = (g.s_ * X + g.c * Y) * g.inv_s + g.cy;
 }
 
-__device__ __forceinline__ float ztap(const float *img, int H, int W, int yy, int xx) {
-    return (yy >= 0 && yy < H && xx >= 0 && xx < W) ? img[(size_t)yy * W + xx] : 0.0f;
+// Bilinear cell of a sample point as four tap byte offsets into a plane
+// (kOOB for a tap outside the image) and the float32 fractions.
+struct Taps {
+    uint32_t o00, o01, o10, o11;
+    float fx, fy;
+};
+
+__device__ __forceinline__ Taps taps_of(double sx, double sy, int H, int W) {
+    const double fx0 = floor(sx), fy0 = floor(sy);
+    Taps t;
+    t.fx = (float)(sx - fx0);
+    t.fy = (float)(sy - fy0);
+    // corners beyond the image read as outside; clamping first keeps the
+    // integer conversion in range
+    const uint32_t ux = (uint32_t)(int)fmin(fmax(fx0, -2.0), (double)W);
+    const uint32_t uy = (uint32_t)(int)fmin(fmax(fy0, -2.0), (double)H);
+    const bool vx0 = ux < (uint32_t)W, vx1 = ux + 1u < (uint32_t)W;
+    const bool vy0 = uy < (uint32_t)H, vy1 = uy + 1u < (uint32_t)H;
+    const uint32_t b = (uy * (uint32_t)W + ux) * 4u, bw = 4u * (uint32_t)W;  // wraps when unused
+    t.o00 = (vx0 && vy0) ? b : kOOB;
+    t.o01 = (vx1 && vy0) ? b + 4u : kOOB;
+    t.o10 = (vx0 && vy1) ? b + bw : kOOB;
+    t.o11 = (vx1 && vy1) ? b + bw + 4u : kOOB;
+    return t;
+}
+
+__device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void stf(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float *base, size_t plane, int H, int W) {
+    return buffer_rsrc(const_cast<float *>(base) + plane * (size_t)H * W, (uint32_t)H * (uint32_t)W * 4u);
+}
+
+struct Quad {
+    float p00, p01, p10, p11;
+};
+
+__device__ __forceinline__ Quad load_quad(__amdgpu_buffer_rsrc_t r, const Taps &t) {
+    return Quad{ldf(r, t.o00), ldf(r, t.o01), ldf(r, t.o10), ldf(r, t.o11)};
+}
+
+__device__ __forceinline__ float bilerp(const Quad &q, float fx, float fy) {
+    return (1.0f - fy) * ((1.0f - fx) * q.p00 + fx * q.p01) + fy * ((1.0f - fx) * q.p10 + fx * q.p11);
+}
+
+// y1^gamma for y1 > 0 (exactly y1 when gamma is 1), given l2 = log2(y1).
+__device__ __forceinline__ float pow_pos(float y1, float gamma, float l2) {
+    return gamma == 1.0f ? y1 : __builtin_amdgcn_exp2f(gamma * l2);
+}
+
+constexpr int kBoxFloats = 9216;  // 36 KB of LDS: the source footprint of an output tile, all channels
+
+// Source box staged in LDS: [c][h][w] floats from (x0, y0); w = 0 when the
+// footprint does not fit (the per-pixel kernels then gather from global memory).
+struct Box {
+    int x0, y0, w, h;
+};
+
+// Footprint of the 32 x 32 output tile at (X0, Y0): the cells of its sample
+// points, their +1 taps and one pixel of margin on each side for the rounding
+// of the stepped per-pixel positions.
+__device__ __forceinline__ Box tile_box(const Geo &g, int X0, int Y0, int C) {
+    double xl = 1e300, xh = -1e300, yl = 1e300, yh = -1e300;
+    for (int k = 0; k < 4; ++k) {
+        double sx, sy;
+        sample_pos(g, X0 + ((k & 1) ? kTile - 1 : 0), Y0 + ((k & 2) ? kTile - 1 : 0), sx, sy);
+        xl = fmin(xl, sx);
+        xh = fmax(xh, sx);
+        yl = fmin(yl, sy);
+        yh = fmax(yh, sy);
+    }
+    Box b{0, 0, 0, 0};
+    const double x0 = floor(xl) - 1.0, y0 = floor(yl) - 1.0;
+    const double w = floor(xh) + 3.0 - x0, h = floor(yh) + 3.0 - y0;
+    if (!(fabs(x0) < 1e9 && fabs(y0) < 1e9 && w <= 64.0 && w * h * C <= (double)kBoxFloats)) return b;
+    b.x0 = (int)x0;
+    b.y0 = (int)y0;
+    b.w = (int)w;
+    b.h = (int)h;
+    return b;
+}
+
+// Stages box b of planes plane0 .. plane0 + C - 1 of x into lds ([c][h][w]);
+// pixels outside the image are 0.  Wave w takes rows w, w + 4, ..., a lane
+// one column; a row or column outside the image loads through an offset past
+// the end of the plane.
+__device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, int H, int W, const Box &b,
+                                          float *lds) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int col = b.x0 + lane;
+    const uint32_t voff = (lane < b.w && col >= 0 && col < W) ? (uint32_t)col * 4u : kOOB;
+    for (int c = 0; c < C; ++c) {
+        const __amdgpu_buffer_rsrc_t r = plane_rsrc(x, plane0 + c, H, W);
+        float *dst = lds + c * b.h * b.w;
+#pragma unroll 4
+        for (int row = wave; row < b.h; row += kThreads / 64) {
+            const int sy = b.y0 + row;
+            const bool ok = sy >= 0 && sy < H;
+            const float v = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(r, ok ? voff : kOOB, ok ? sy * W * 4 : 0, 0));
+            if (lane < b.w) dst[row * b.w + lane] = v;
+        }
+    }
+}
+
+// This thread's four pixels of the 32 x 32 output tile (column ox, rows oy0
+// + 8k): bilinear fractions, the pixel's byte offset in a plane (kOOB outside
+// the image), and the taps -- LDS box index of tap (0, 0), or global offsets.
+struct PixSet {
+    int ox, oy0;
+    float fx[kPix], fy[kPix];
+    uint32_t off[kPix];
+    int bi[kPix];
+    Taps t[kPix];
+};
+
+template <bool LDS>
+__device__ __forceinline__ void pix_set(const Geo &g, int H, int W, const Box &b, PixSet &ps) {
+    const int tiles_x = (W + kTile - 1) / kTile;
+    const int X0 = (blockIdx.x % tiles_x) * kTile, Y0 = (blockIdx.x / tiles_x) * kTile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    ps.ox = X0 + (lane & 31);
+    ps.oy0 = Y0 + 2 * wave + (lane >> 5);
+    double sx0, sy0;
+    sample_pos(g, ps.ox, ps.oy0, sx0, sy0);
+    // one row of output moves the sample point by (-sin, cos) / s
+    const double dsx = -g.s_ * g.inv_s * kRowStep, dsy = g.c * g.inv_s * kRowStep;
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) {
+        const int oy = ps.oy0 + k * kRowStep;
+        const double sx = sx0 + (double)k * dsx, sy = sy0 + (double)k * dsy;
+        ps.off[k] = (ps.ox < W && oy < H) ? ((uint32_t)oy * (uint32_t)W + (uint32_t)ps.ox) * 4u : kOOB;
+        if (LDS) {
+            const double fx0 = floor(sx), fy0 = floor(sy);
+            ps.fx[k] = (float)(sx - fx0);
+            ps.fy[k] = (float)(sy - fy0);
+            // inside the box by construction; the clamp only guards the LDS range
+            const int lx = (int)fmin(fmax(fx0 - (double)b.x0, 0.0), (double)(b.w - 2));
+            const int ly = (int)fmin(fmax(fy0 - (double)b.y0, 0.0), (double)(b.h - 2));
+            ps.bi[k] = ly * b.w + lx;
+        } else {
+            ps.t[k] = taps_of(sx, sy, H, W);
+            ps.fx[k] = ps.t[k].fx;
+            ps.fy[k] = ps.t[k].fy;
+        }
+    }
+}
+
+template <bool LDS>
+__device__ __forceinline__ Quad quad_at(const PixSet &ps, int k, const float *box, int bw,
+                                        __amdgpu_buffer_rsrc_t xr) {
+    if (LDS) {
+        const float *q = box + ps.bi[k];
+        return Quad{q[0], q[1], q[bw], q[bw + 1]};
+    }
+    return load_quad(xr, ps.t[k]);
+}
+
+template <bool LDS>
+__device__ __forceinline__ void fwd_tile(const float *x, int img, int C, int H, int W, const float *p, const Geo &g,
+                                         const Box &b, const float *box, float *y) {
+    PixSet ps;
+    pix_set<LDS>(g, H, W, b, ps);
+    const float alpha = p[4], beta = p[5], gamma = p[6];
+    for (int c = 0; c < C; ++c) {
+        const size_t plane = (size_t)img * C + c;
+        const __amdgpu_buffer_rsrc_t xr = plane_rsrc(x, plane, H, W), yr = plane_rsrc(y, plane, H, W);
+        Quad q[kPix];
+#pragma unroll
+        for (int k = 0; k < kPix; ++k) q[k] = quad_at<LDS>(ps, k, box + c * b.h * b.w, b.w, xr);
+#pragma unroll
+        for (int k = 0; k < kPix; ++k) {
+            const float w = bilerp(q[k], ps.fx[k], ps.fy[k]);
+            const float z = alpha * w + beta;
+            const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
+            stf(yr, ps.off[k], y1 > 0.0f ? pow_pos(y1, gamma, __builtin_amdgcn_logf(y1)) : 0.0f);
+        }
+    }
+}
+
+// Geometry and source box of this workgroup's output tile, in LDS.
+__device__ __forceinline__ void tile_setup(const float *p, int C, int H, int W, Geo &sg, Box &sb) {
+    if (threadIdx.x == 0) {
+        const int tiles_x = (W + kTile - 1) / kTile;
+        sg = make_geo(p, H, W);
+        sb = tile_box(sg, (blockIdx.x % tiles_x) * kTile, (blockIdx.x / tiles_x) * kTile, C);
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(kThreads) void k_wc_fwd(const float *__restrict__ x, int C, int H, int W,
                                                      const float *__restrict__ params, float *__restrict__ y) {
-    const int img = blockIdx.z;
-    const int tiles_x = (W + kTile - 1) / kTile;
-    const int ox = (blockIdx.x % tiles_x) * kTile + (threadIdx.x & (kTile - 1));
-    const int oy = (blockIdx.x / tiles_x) * kTile + (threadIdx.x / kTile);
-    const float *p = params + 7 * img;
+    __shared__ float box[kBoxFloats];
     __shared__ Geo sg;
-    if (threadIdx.x == 0) sg = make_geo(p, H, W);
-    __syncthreads();
-    if (ox >= W || oy >= H) return;
-    const Cell k = cell_of(sg, ox, oy);
-    const int x0 = k.x0, y0 = k.y0;
-    const float fx = k.fx, fy = k.fy;
-    const float alpha = p[4], beta = p[5], gamma = p[6];
-    for (int c = 0; c < C; ++c) {
-        const float *xc = x + ((size_t)img * C + c) * H * W;
-        const float p00 = ztap(xc, H, W, y0, x0), p01 = ztap(xc, H, W, y0, x0 + 1);
-        const float p10 = ztap(xc, H, W, y0 + 1, x0), p11 = ztap(xc, H, W, y0 + 1, x0 + 1);
-        const float w = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
+    __shared__ Box sb;
+    const int img = blockIdx.y;
+    const float *p = params + 7 * img;
+    tile_setup(p, C, H, W, sg, sb);
+    const Box b = sb;
+    if (b.w > 0) {
+        stage_box(x, (size_t)img * C, C, H, W, b, box);
+        __syncthreads();
+        fwd_tile<true>(x, img, C, H, W, p, sg, b, box, y);
+    } else {
+        fwd_tile<false>(x, img, C, H, W, p, sg, b, box, y);
+    }
+}
+
+// Integer span [lo, hi] of t for which a t + b lies in [v0, v1), given
+// ia = 1 / a, widened by a hair (1e-6 px: the bounds are rounded products,
+// the callers confirm every pixel with its cell) and clamped to [0, n - 1]
+// (empty: lo > hi).
+__device__ __forceinline__ int2 affine_span(double a, double ia, double b, double v0, double v1, int n) {
+    double lo, hi;
+    if (a > 0.0) {
+        lo = (v0 - b) * ia;
+        hi = (v1 - b) * ia;
+    } else if (a < 0.0) {
+        lo = (v1 - b) * ia;
+        hi = (v0 - b) * ia;
+    } else {
+        if (b < v0 || b >= v1) return make_int2(1, 0);
+        return make_int2(0, n - 1);
+    }
+    const double l = fmax(ceil(lo - 1e-6), 0.0), h = fmin(floor(hi + 1e-6), (double)(n - 1));
+    return l > h ? make_int2(1, 0) : make_int2((int)l, (int)h);
+}
+
+// Along output row oy the sample point is (A ox + B, Cc ox + D).
+struct RowMap {
+    double A, iA, Cc, iC;
+};
+
+__device__ __forceinline__ RowMap row_map(const Geo &g) {
+    RowMap r;
+    r.A = g.c * g.inv_s;
+    r.Cc = g.s_ * g.inv_s;
+    r.iA = r.A != 0.0 ? 1.0 / r.A : 0.0;
+    r.iC = r.Cc != 0.0 ? 1.0 / r.Cc : 0.0;
+    return r;
+}
+
+// Output pixels of row oy whose sample point lies in [x0, x1) x [y0, y1)
+// (a hair wider), clamped to the image (empty: .x > .y).
+__device__ __forceinline__ int2 row_span(const Geo &g, const RowMap &m, int oy, double x0, double x1, double y0,
+                                         double y1, int W) {
+    const double Y = (double)oy - g.uy;
+    const double B = (-g.c * g.ux - g.s_ * Y) * g.inv_s + g.cx;
+    const double D = (-g.s_ * g.ux + g.c * Y) * g.inv_s + g.cy;
+    const int2 a = affine_span(m.A, m.iA, B, x0, x1, W);
+    const int2 b = affine_span(m.Cc, m.iC, D, y0, y1, W);
+    return make_int2(max(a.x, b.x), min(a.y, b.y));
+}
+
+// Per-thread sums for the parameter gradients over the pixels a workgroup
+// owns: v = {sum (g_sy rx - g_sx ry), sum (g_sx rx + g_sy ry), sum g_sx,
+// sum g_sy, dL/dalpha, dL/dbeta, dL/dgamma}, (rx, ry) = (sx - cx, sy - cy);
+// own[c] = sum of dL/dy over the owned pixels, channel c.
+struct ParAcc {
+    float v[7];
+    float own[kMaxC];
+};
+
+// One output pixel of the region: dL/dw per channel into gw and, when the
+// pixel is owned, its parameter-gradient terms into a.  With g_y = dL/dy and
+// y1 in (0, 1]: dL/dgamma += g_y y ln y1; where z lies in (0, 1), with
+// g_z = g_y gamma y / y1: dL/dw = g_z alpha, dL/dalpha += g_z w,
+// dL/dbeta += g_z, (g_sx, g_sy) += dL/dw (dw/dsx, dw/dsy).
+// quad(c) gives the pixel's taps in channel c, gvf(c) its dL/dy.
+template <class QuadF, class GyF>
+__device__ __forceinline__ void pixel_adjoint(int C, float fx, float fy, double sx, double sy, const Geo &g,
+                                              float alpha, float beta, float gamma, bool owned, QuadF quad, GyF gvf,
+                                              float (&gw)[kMaxC], ParAcc &a) {
+    float gsx = 0.0f, gsy = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c) {
+        gw[c] = 0.0f;
+        if (c >= C) continue;
+        const Quad q = quad(c);
+        const float gv = gvf(c);
+        const float w = bilerp(q, fx, fy);
         const float z = alpha * w + beta;
         const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
-        y[(((size_t)img * C + c) * H + oy) * W + ox] = y1 > 0.0f ? (gamma == 1.0f ? y1 : powf(y1, gamma)) : 0.0f;
+        if (owned) a.own[c] += gv;
+        if (y1 > 0.0f) {
+            const float l2 = __builtin_amdgcn_logf(y1);
+            const float yv = pow_pos(y1, gamma, l2);
+            if (owned) a.v[6] += gv * yv * (l2 * 0.6931471805599453f);
+            if (z < 1.0f) {
+                const float gz = gv * gamma * (yv / y1);  // d(y1^gamma)/dy1 = gamma y1^(gamma-1)
+                gw[c] = gz * alpha;
+                if (owned) {
+                    a.v[4] += gz * w;
+                    a.v[5] += gz;
+                    gsx += gw[c] * ((1.0f - fy) * (q.p01 - q.p00) + fy * (q.p11 - q.p10));
+                    gsy += gw[c] * ((1.0f - fx) * (q.p10 - q.p00) + fx * (q.p11 - q.p01));
+                }
+            }
+        }
     }
+    if (owned) {
+        const float rx = (float)(sx - g.cx), ry = (float)(sy - g.cy);
+        a.v[0] += gsy * rx - gsx * ry;
+        a.v[1] += gsx * rx + gsy * ry;
+        a.v[2] += gsx;
+        a.v[3] += gsy;
+    }
+}
+
+constexpr int kEPT = 6;                         // region pixels per thread in the gather form
+constexpr int kPoolFloats = 7936;               // 31 KB of sorted entries
+constexpr int kMaxRows = 64;                    // region rows of the gather form (one wave scans them)
+constexpr int kCellN = kCells * kCells;
+constexpr int kScanPT = (kCellN + 1 + kThreads - 1) / kThreads;
+constexpr int kRec = 12;                        // floats per workgroup record: 7 parameters, then kMaxC sums, pad
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -115,170 +415,363 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_wc_bwd_pix(const float *__restrict__ x, int C, int H, int W,
-                                                         const float *__restrict__ params,
-                                                         const float *__restrict__ gy, float *__restrict__ gw,
-                                                         float *__restrict__ partial) {
-    __shared__ float red[kThreads / 64][8];
-    const int img = blockIdx.z;
-    const int tiles_x = (W + kTile - 1) / kTile;
-    const int ox = (blockIdx.x % tiles_x) * kTile + (threadIdx.x & (kTile - 1));
-    const int oy = (blockIdx.x / tiles_x) * kTile + (threadIdx.x / kTile);
-    const float *p = params + 7 * img;
+// The backward, one workgroup per 32 x 32 source tile T at (X0, Y0):
+//   0. the sum of dL/dy over the output tile at (X0, Y0) (the same grid);
+//   1. the region -- output pixels whose bilinear cell has a tap in T, i.e.
+//      cell corner in [X0-1, X0+31] x [Y0-1, Y0+31] -- row by row from the
+//      affine map, flattened over the workgroup;
+//   2. per region pixel, from T's taps staged in LDS ([X0-1, X0+32]^2): its
+//      cell, fractions and dL/dw (recomputed in registers), counted per cell;
+//      and, for the pixels T owns (cell corner in T, the first tile row and
+//      column also owning corner -1), the parameter-gradient terms;
+//   3. an exclusive scan of the 33 x 33 cell counts, the entries stored in
+//      LDS sorted by cell;
+//   4. each source pixel sums the entries of the four cells that have it as
+//      a tap: two contiguous runs (the two cells of a row are adjacent in
+//      the sorted order).  Every grad_x element has one writer: no global
+//      atomics, no zero-fill, no dL/dw buffer.
+// Output pixels whose cell has no tap in the image (w = 0, z = beta) belong
+// to no tile; their share of dL/dbeta and dL/dgamma depends only on the sum
+// of their dL/dy, which the record carries as (sum over the output tile) -
+// (sum over the owned pixels) and k_wc_reduce applies.
+// A region larger than the LDS pool (scale well above 1) takes its taps from
+// global memory and scatters into an LDS accumulator with float atomics.
+// With gx NULL only the parameter gradients are formed.
+__global__ __launch_bounds__(kThreads) void k_wc_bwd(const float *__restrict__ x, int C, int H, int W,
+                                                     const float *__restrict__ params,
+                                                     const float *__restrict__ gy, float *__restrict__ gx,
+                                                     float *__restrict__ rec) {
+    // pool: T's taps [c][34][34] during step 2; then entries sorted by cell,
+    // g[c][cap], fx[cap], fy[cap]; or the scatter form's accumulator [c][32][33]
+    __shared__ float pool[kPoolFloats];
+    __shared__ int off[kCellN + 1];  // per cell: entry count, then exclusive start
+    __shared__ int rxa[kMaxRows], roff[kMaxRows + 1];
+    __shared__ int wsum[kThreads / 64];
+    __shared__ float red[kThreads / 64][kRec];
     __shared__ Geo sg;
-    if (threadIdx.x == 0) sg = make_geo(p, H, W);
-    __syncthreads();
-    const Geo &g = sg;
-    float acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (ox < W && oy < H) {
-        const Cell k = cell_of(g, ox, oy);
-        const int x0 = k.x0, y0 = k.y0;
-        const float fx = k.fx, fy = k.fy;
-        const float alpha = p[4], beta = p[5], gamma = p[6];
-        float gsx = 0.0f, gsy = 0.0f;  // dL/dsx, dL/dsy summed over channels
-        for (int c = 0; c < C; ++c) {
-            const size_t plane = ((size_t)img * C + c) * H * W;
-            const float *xc = x + plane;
-            const float p00 = ztap(xc, H, W, y0, x0), p01 = ztap(xc, H, W, y0, x0 + 1);
-            const float p10 = ztap(xc, H, W, y0 + 1, x0), p11 = ztap(xc, H, W, y0 + 1, x0 + 1);
-            const float w = (1.0f - fy) * ((1.0f - fx) * p00 + fx * p01) + fy * ((1.0f - fx) * p10 + fx * p11);
-            const float z = alpha * w + beta;
-            const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
-            const float gv = gy[plane + (size_t)oy * W + ox];
-            float gwv = 0.0f;
-            if (y1 > 0.0f) {
-                const float yv = gamma == 1.0f ? y1 : powf(y1, gamma);
-                acc[6] += gv * yv * logf(y1);
-                if (z > 0.0f && z < 1.0f) {
-                    const float gz = gv * gamma * (gamma == 1.0f ? 1.0f : powf(y1, gamma - 1.0f));
-                    acc[4] += gz * w;
-                    acc[5] += gz;
-                    gwv = gz * alpha;
-                    gsx += gwv * ((1.0f - fy) * (p01 - p00) + fy * (p11 - p10));
-                    gsy += gwv * ((1.0f - fx) * (p10 - p00) + fx * (p11 - p01));
-                }
-            }
-            gw[plane + (size_t)oy * W + ox] = gwv;
-        }
-        // chain through (sx, sy)(angle_deg, scale, tx, ty)
-        const float is = (float)g.inv_s, d2r = 0.017453292519943295f, c = (float)g.c, sn = (float)g.s_;
-        const float rx = (float)((g.c * k.X - g.s_ * k.Y) * g.inv_s);  // rotated, scaled offsets
-        const float ry = (float)((g.s_ * k.X + g.c * k.Y) * g.inv_s);
-        acc[0] += (gsx * (-ry) + gsy * rx) * d2r;
-        acc[1] += (gsx * (-rx) + gsy * (-ry)) * is;
-        acc[2] += (gsx * (-c) + gsy * (-sn)) * is * (float)W;
-        acc[3] += (gsx * sn + gsy * (-c)) * is * (float)H;
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-        const float v = wave_sum(acc[k]);
-        if (lane == 0) red[wave][k] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 7) {
-        float v = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
-        partial[((size_t)img * gridDim.x + blockIdx.x) * 8 + threadIdx.x] = v;
-    }
-}
-
-// Adjoint of the bilinear warp, one source tile per workgroup (all channels).
-__global__ __launch_bounds__(kThreads) void k_wc_bwd_img(int C, int H, int W, const float *__restrict__ params,
-                                                         const float *__restrict__ gw, float *__restrict__ gx) {
-    __shared__ float acc[kMaxC][kSrcTile][kSrcTile + 1];
-    const int img = blockIdx.z;
+    __shared__ int s_r0, s_nrows, s_total;
+    const int img = blockIdx.y;
     const int tiles_x = (W + kSrcTile - 1) / kSrcTile;
     const int X0 = (blockIdx.x % tiles_x) * kSrcTile, Y0 = (blockIdx.x / tiles_x) * kSrcTile;
     const float *p = params + 7 * img;
-    __shared__ Geo sg;
-    if (threadIdx.x == 0) sg = make_geo(p, H, W);
-    for (int e = threadIdx.x; e < kMaxC * kSrcTile * (kSrcTile + 1); e += kThreads) (&acc[0][0][0])[e] = 0.0f;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // 0. dL/dy summed over the output tile
+    float s_all[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < kSrcTile * kSrcTile / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        const int u = X0 + (e & (kSrcTile - 1)), v = Y0 + e / kSrcTile;
+        const uint32_t o = (u < W && v < H) ? ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u : kOOB;
+#pragma unroll
+        for (int c = 0; c < kMaxC; ++c)
+            if (c < C) s_all[c] += ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), o);
+    }
+    if (threadIdx.x == 0) {
+        const Geo g = make_geo(p, H, W);
+        sg = g;
+        // rows of the forward image of the cell square [X0-1, X0+32] x [Y0-1, Y0+32],
+        // p_out = s R (p_src - c) + c + t, plus a margin
+        double yl = 1e300, yh = -1e300;
+        for (int k = 0; k < 4; ++k) {
+            const double px = ((k & 1) ? (double)(X0 + kSrcTile) : (double)(X0 - 1)) - g.cx;
+            const double py = ((k & 2) ? (double)(Y0 + kSrcTile) : (double)(Y0 - 1)) - g.cy;
+            const double qy = g.scale * (-g.s_ * px + g.c * py) + g.uy;
+            yl = fmin(yl, qy);
+            yh = fmax(yh, qy);
+        }
+        const int r0 = (int)fmin(fmax(floor(yl) - 1.0, 0.0), (double)H);
+        const int r1 = (int)fmax(fmin(ceil(yh) + 1.0, (double)(H - 1)), -1.0);
+        s_r0 = r0;
+        s_nrows = max(0, r1 - r0 + 1);
+    }
+    for (int i = threadIdx.x; i < kCellN + 1; i += kThreads) off[i] = 0;
     __syncthreads();
     const Geo &g = sg;
-    // Output pixels that can sample this tile: the forward image of the tile
-    // grown by one pixel (bilinear footprint), mapped with the forward map
-    // p_out = s R (p_src - c) + c + t, plus a 2-pixel margin for float rounding.
-    float bx0 = 1e30f, bx1 = -1e30f, by0 = 1e30f, by1 = -1e30f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float px = (k & 1) ? (float)(X0 + kSrcTile) : (float)(X0 - 1);
-        const float py = (k & 2) ? (float)(Y0 + kSrcTile) : (float)(Y0 - 1);
-        const float dx = px - (float)g.cx, dy = py - (float)g.cy;
-        const float c = (float)g.c, sn = (float)g.s_, sc = (float)g.scale;
-        const float qx = sc * (c * dx + sn * dy) + (float)g.ux;
-        const float qy = sc * (-sn * dx + c * dy) + (float)g.uy;
-        bx0 = fminf(bx0, qx); bx1 = fmaxf(bx1, qx);
-        by0 = fminf(by0, qy); by1 = fmaxf(by1, qy);
+    const RowMap rm = row_map(g);
+    const int r0 = s_r0, nrows = s_nrows;
+    const double tx0 = (double)(X0 - 1), tx1 = (double)(X0 + kSrcTile);
+    const double ty0 = (double)(Y0 - 1), ty1 = (double)(Y0 + kSrcTile);
+    if (wave == 0) {
+        int xa = 0, len = 0;
+        if (lane < nrows) {
+            const int2 sp = row_span(g, rm, r0 + lane, tx0, tx1, ty0, ty1, W);
+            xa = sp.x;
+            len = max(0, sp.y - sp.x + 1);
+        }
+        const int inc = wave_incl_scan(len, lane);
+        rxa[lane] = xa;
+        roff[lane + 1] = inc;
+        if (lane == 0) roff[0] = 0;
+        if (lane == 63) s_total = nrows > kMaxRows ? INT_MAX : inc;
     }
-    const int ox0 = max(0, (int)floorf(bx0) - 2), ox1 = min(W - 1, (int)ceilf(bx1) + 2);
-    const int oy0 = max(0, (int)floorf(by0) - 2), oy1 = min(H - 1, (int)ceilf(by1) + 2);
     __syncthreads();
-    const int bw = ox1 - ox0 + 1;
-    const int cnt = (ox1 >= ox0 && oy1 >= oy0) ? bw * (oy1 - oy0 + 1) : 0;
-    for (int e = threadIdx.x; e < cnt; e += kThreads) {
-        const int oy = oy0 + e / bw, ox = ox0 + e % bw;
-        const Cell k = cell_of(g, ox, oy);
-        const int x0 = k.x0 - X0, y0 = k.y0 - Y0;
-        if (x0 < -1 || x0 >= kSrcTile || y0 < -1 || y0 >= kSrcTile) continue;
-        const float fx = k.fx, fy = k.fy;
-        const float wt[4] = {(1.0f - fy) * (1.0f - fx), (1.0f - fy) * fx, fy * (1.0f - fx), fy * fx};
-        for (int c = 0; c < C; ++c) {
-            const float gv = gw[(((size_t)img * C + c) * H + oy) * W + ox];
-            if (gv == 0.0f) continue;
+    const float alpha = p[4], beta = p[5], gamma = p[6];
+    const int total = s_total;
+    const int cap = min(kEPT * kThreads, kPoolFloats / (C + 2));
+    // owned cell corners, relative to the cell square: [own_x0, own_x1] x [own_y0, own_y1]
+    const int own_x0 = X0 == 0 ? 0 : 1, own_x1 = min(kCells - 1, W - X0);
+    const int own_y0 = Y0 == 0 ? 0 : 1, own_y1 = min(kCells - 1, H - Y0);
+    ParAcc acc;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int ty = y0 + (k >> 1), tx = x0 + (k & 1);
-                if (ty >= 0 && ty < kSrcTile && tx >= 0 && tx < kSrcTile && Y0 + ty < H && X0 + tx < W)
-                    atomicAdd(&acc[c][ty][tx], gv * wt[k]);
+    for (int k = 0; k < 7; ++k) acc.v[k] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c) acc.own[c] = 0.0f;
+    if (total <= cap) {
+        constexpr int kXT = kCells + 1;
+        stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT}, pool);
+        __syncthreads();
+        // 2. region pixels
+        float eg[kEPT][kMaxC], efx[kEPT], efy[kEPT];
+        int ecs[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            const int e = threadIdx.x + k * kThreads;
+            ecs[k] = -1;
+            efx[k] = efy[k] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) eg[k][c] = 0.0f;
+            if (e >= total) continue;
+            int r = 0;  // the last row whose start is at or before e
+#pragma unroll
+            for (int st = kMaxRows / 2; st > 0; st >>= 1)
+                if (r + st < nrows && roff[r + st] <= e) r += st;
+            const int oy = r0 + r, ox = rxa[r] + (e - roff[r]);
+            double sx, sy;
+            sample_pos(g, ox, oy, sx, sy);
+            const double fx0 = floor(sx), fy0 = floor(sy);
+            const double dcx = fx0 - tx0, dcy = fy0 - ty0;  // cell relative to the cell square
+            if (!(dcx >= 0.0 && dcx < (double)kCells && dcy >= 0.0 && dcy < (double)kCells)) continue;
+            const int cx = (int)dcx, cy = (int)dcy;
+            const float fx = (float)(sx - fx0), fy = (float)(sy - fy0);
+            const bool owned = cx >= own_x0 && cx <= own_x1 && cy >= own_y0 && cy <= own_y1;
+            const int bi = cy * kXT + cx;
+            const uint32_t opix = ((uint32_t)oy * (uint32_t)W + (uint32_t)ox) * 4u;
+            float gw[kMaxC];
+            pixel_adjoint(
+                C, fx, fy, sx, sy, g, alpha, beta, gamma, owned,
+                [&](int c) {
+                    const float *q = pool + c * kXT * kXT + bi;
+                    return Quad{q[0], q[1], q[kXT], q[kXT + 1]};
+                },
+                [&](int c) { return ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), opix); }, gw, acc);
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) eg[k][c] = gw[c];
+            efx[k] = fx;
+            efy[k] = fy;
+            if (gx) {
+                const int ci = cy * kCells + cx;
+                ecs[k] = (atomicAdd(&off[ci], 1) << 11) | ci;
             }
         }
+        if (gx) {
+            __syncthreads();
+            // 3. exclusive scan of the cell counts (off[kCellN] becomes the entry count)
+            {
+                int v[kScanPT], s = 0;
+#pragma unroll
+                for (int j = 0; j < kScanPT; ++j) {
+                    const int i = threadIdx.x * kScanPT + j;
+                    v[j] = i < kCellN ? off[i] : 0;
+                    s += v[j];
+                }
+                const int inc = wave_incl_scan(s, lane);
+                if (lane == 63) wsum[wave] = inc;
+                __syncthreads();
+                int base = inc - s;
+                for (int w = 0; w < wave; ++w) base += wsum[w];
+#pragma unroll
+                for (int j = 0; j < kScanPT; ++j) {
+                    const int i = threadIdx.x * kScanPT + j;
+                    if (i <= kCellN) off[i] = base;
+                    base += v[j];
+                }
+            }
+            __syncthreads();
+            float *pg = pool, *pfx = pool + C * cap, *pfy = pool + (C + 1) * cap;
+#pragma unroll
+            for (int k = 0; k < kEPT; ++k) {
+                if (ecs[k] < 0) continue;
+                const int pos = off[ecs[k] & 2047] + (ecs[k] >> 11);
+#pragma unroll
+                for (int c = 0; c < kMaxC; ++c)
+                    if (c < C) pg[c * cap + pos] = eg[k][c];
+                pfx[pos] = efx[k];
+                pfy[pos] = efy[k];
+            }
+            __syncthreads();
+            // 4. every source pixel sums the entries of its four cells
+#pragma unroll
+            for (int j = 0; j < kSrcTile * kSrcTile / kThreads; ++j) {
+                const int e = threadIdx.x + j * kThreads;
+                const int lu = e & (kSrcTile - 1), lv = e / kSrcTile;
+                const int u = X0 + lu, v = Y0 + lv;
+                float sum[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy) {
+                    // cell row lv + dy has corner y0 = v - 1 + dy: the pixel is its tap row 1 - dy
+                    const int ci = (lv + dy) * kCells + lu;
+                    const int a0 = off[ci], mid = off[ci + 1], b0 = off[ci + 2];
+                    for (int q = a0; q < b0; ++q) {
+                        const float fx = pfx[q], fy = pfy[q];
+                        const float wx = q < mid ? fx : 1.0f - fx;  // left cell: corner x0 = u - 1
+                        const float wy = dy == 0 ? fy : 1.0f - fy;
+                        const float wt = wy * wx;
+#pragma unroll
+                        for (int c = 0; c < kMaxC; ++c)
+                            if (c < C) sum[c] += pg[c * cap + q] * wt;
+                    }
+                }
+                const uint32_t o = (u < W && v < H) ? ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u : kOOB;
+#pragma unroll
+                for (int c = 0; c < kMaxC; ++c)
+                    if (c < C) stf(plane_rsrc(gx, (size_t)img * C + c, H, W), o, sum[c]);
+            }
+        }
+    } else {
+        // a region beyond the pool: taps from global memory, scatter with LDS float atomics
+        float(*accs)[kSrcTile][kSrcTile + 1] = reinterpret_cast<float(*)[kSrcTile][kSrcTile + 1]>(pool);
+        if (gx)
+            for (int e = threadIdx.x; e < kMaxC * kSrcTile * (kSrcTile + 1); e += kThreads) pool[e] = 0.0f;
+        __syncthreads();
+        for (int oy = r0 + wave; oy < r0 + nrows; oy += kThreads / 64) {
+            const int2 sp = row_span(g, rm, oy, tx0, tx1, ty0, ty1, W);
+            for (int ox = sp.x + lane; ox <= sp.y; ox += 64) {
+                double sx, sy;
+                sample_pos(g, ox, oy, sx, sy);
+                const double fx0 = floor(sx), fy0 = floor(sy);
+                if (!(fx0 >= tx0 && fx0 < tx1 && fy0 >= ty0 && fy0 < ty1)) continue;
+                const int cx = (int)(fx0 - tx0), cy = (int)(fy0 - ty0);
+                const bool owned = cx >= own_x0 && cx <= own_x1 && cy >= own_y0 && cy <= own_y1;
+                const Taps t = taps_of(sx, sy, H, W);
+                const uint32_t opix = ((uint32_t)oy * (uint32_t)W + (uint32_t)ox) * 4u;
+                float gw[kMaxC];
+                pixel_adjoint(
+                    C, t.fx, t.fy, sx, sy, g, alpha, beta, gamma, owned,
+                    [&](int c) { return load_quad(plane_rsrc(x, (size_t)img * C + c, H, W), t); },
+                    [&](int c) { return ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), opix); }, gw, acc);
+                if (!gx) continue;
+                const float wt[4] = {(1.0f - t.fy) * (1.0f - t.fx), (1.0f - t.fy) * t.fx, t.fy * (1.0f - t.fx),
+                                     t.fy * t.fx};
+#pragma unroll
+                for (int c = 0; c < kMaxC; ++c) {
+                    if (c >= C || gw[c] == 0.0f) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int yy = cy - 1 + (q >> 1), xx = cx - 1 + (q & 1);
+                        if (yy >= 0 && yy < kSrcTile && xx >= 0 && xx < kSrcTile)
+                            atomicAdd(&accs[c][yy][xx], gw[c] * wt[q]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (gx)
+            for (int e = threadIdx.x; e < C * kSrcTile * kSrcTile; e += kThreads) {
+                const int c = e / (kSrcTile * kSrcTile), r = (e / kSrcTile) % kSrcTile, q = e % kSrcTile;
+                if (Y0 + r < H && X0 + q < W) gx[(((size_t)img * C + c) * H + Y0 + r) * W + X0 + q] = accs[c][r][q];
+            }
+    }
+    // the workgroup's record: parameter partials, and per channel the dL/dy sum
+    // of the output tile minus that of the owned pixels
+#pragma unroll
+    for (int k = 0; k < kRec; ++k) {
+        float v = 0.0f;
+        if (k < 7) v = acc.v[k];
+#pragma unroll
+        for (int c = 0; c < kMaxC; ++c)
+            if (k == 7 + c) v = s_all[c] - acc.own[c];
+        const float t = wave_sum(v);
+        if (lane == 0) red[wave][k] = t;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < C * kSrcTile * kSrcTile; e += kThreads) {
-        const int c = e / (kSrcTile * kSrcTile), r = (e / kSrcTile) % kSrcTile, q = e % kSrcTile;
-        if (Y0 + r < H && X0 + q < W) gx[(((size_t)img * C + c) * H + Y0 + r) * W + X0 + q] = acc[c][r][q];
+    if (threadIdx.x < kRec) {
+        const int t = threadIdx.x;
+        auto sum = [&](int k) { return red[0][k] + red[1][k] + red[2][k] + red[3][k]; };
+        const float is = (float)g.inv_s, c = (float)g.c, sn = (float)g.s_;
+        float o;
+        if (t == 0) o = sum(0) * 0.017453292519943295f;                     // angle (degrees)
+        else if (t == 1) o = -sum(1) * is;                                 // scale
+        else if (t == 2) o = -(c * sum(2) + sn * sum(3)) * is * (float)W;  // tx
+        else if (t == 3) o = (sn * sum(2) - c * sum(3)) * is * (float)H;   // ty
+        else o = sum(t);                                                   // alpha, beta, gamma, dL/dy sums
+        rec[((size_t)img * gridDim.x + blockIdx.x) * kRec + t] = o;
     }
 }
 
-__global__ void k_wc_reduce(const float *__restrict__ partial, int blocks, float *__restrict__ gp) {
-    const int img = blockIdx.x, k = threadIdx.x;
-    if (k >= 7) return;
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += (double)partial[((size_t)img * blocks + b) * 8 + k];
-    gp[img * 7 + k] = (float)s;
+// Sums the workgroup records of one image (lane l takes records l, l + 64,
+// ... in order, then a fixed butterfly over the wave, in double) and adds
+// the share of the output pixels whose cell has no tap in the image: w = 0,
+// z = beta, so with S their dL/dy sum over channels, dL/dgamma gains
+// S y ln y1 and, for beta in (0, 1), dL/dbeta gains S gamma y / y1.
+__global__ __launch_bounds__(64) void k_wc_reduce(const float *__restrict__ rec, int blocks, int C,
+                                                  const float *__restrict__ params, float *__restrict__ gp) {
+    const int img = blockIdx.x, lane = threadIdx.x;
+    double s[kRec];
+#pragma unroll
+    for (int k = 0; k < kRec; ++k) s[k] = 0.0;
+    for (int b = lane; b < blocks; b += 64) {
+        const float *q = rec + ((size_t)img * blocks + b) * kRec;
+#pragma unroll
+        for (int k = 0; k < kRec; ++k) s[k] += (double)q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kRec; ++k)
+        for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, 64);
+    if (lane == 0) {
+        double off = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxC; ++c)
+            if (c < C) off += s[7 + c];
+        const float *p = params + 7 * img;
+        const float beta = p[5], gamma = p[6];
+        const float y1 = fminf(fmaxf(beta, 0.0f), 1.0f);
+        if (y1 > 0.0f) {
+            const float l2 = __builtin_amdgcn_logf(y1);
+            const float yv = pow_pos(y1, gamma, l2);
+            s[6] += off * (double)(yv * (l2 * 0.6931471805599453f));
+            if (beta < 1.0f) s[5] += off * (double)(gamma * (yv / y1));
+        }
+#pragma unroll
+        for (int k = 0; k < 7; ++k) gp[img * 7 + k] = (float)s[k];
+    }
 }
+
+constexpr int kMaxGridY = 65535;
 
 }  // namespace
 
 hipError_t launch_wc_fwd(const float *x, int n, int C, int H, int W, const float *p, float *y, hipStream_t s) {
     const int tiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_wc_fwd, dim3(tiles, 1, n), dim3(kThreads), 0, s, x, C, H, W, p, y);
-    return hipGetLastError();
+    const size_t img = (size_t)C * H * W;
+    for (int i0 = 0; i0 < n; i0 += kMaxGridY) {
+        const int m = min(n - i0, kMaxGridY);
+        hipLaunchKernelGGL(k_wc_fwd, dim3(tiles, m), dim3(kThreads), 0, s, x + i0 * img, C, H, W, p + 7 * (size_t)i0,
+                           y + i0 * img);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 size_t wc_workspace_bytes(int n, int C, int H, int W) {
-    const size_t tiles = (size_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
-    return (size_t)n * C * H * W * sizeof(float) + (size_t)n * tiles * 8 * sizeof(float);
+    (void)C;
+    const size_t tiles = (size_t)((W + kSrcTile - 1) / kSrcTile) * ((H + kSrcTile - 1) / kSrcTile);
+    return (size_t)n * tiles * kRec * sizeof(float);
 }
 
 hipError_t launch_wc_bwd(const float *x, int n, int C, int H, int W, const float *p, const float *gy, float *gx,
                          float *gp, void *ws, hipStream_t s) {
     if (C > kMaxC) return hipErrorInvalidValue;
-    const int tiles = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
-    float *gw = (float *)ws;
-    float *partial = gw + (size_t)n * C * H * W;
-    hipLaunchKernelGGL(k_wc_bwd_pix, dim3(tiles, 1, n), dim3(kThreads), 0, s, x, C, H, W, p, gy, gw, partial);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (gx) {
-        const int st = ((W + kSrcTile - 1) / kSrcTile) * ((H + kSrcTile - 1) / kSrcTile);
-        hipLaunchKernelGGL(k_wc_bwd_img, dim3(st, 1, n), dim3(kThreads), 0, s, C, H, W, p, gw, gx);
-        e = hipGetLastError();
+    const int st = ((W + kSrcTile - 1) / kSrcTile) * ((H + kSrcTile - 1) / kSrcTile);
+    const size_t img = (size_t)C * H * W;
+    for (int i0 = 0; i0 < n; i0 += kMaxGridY) {
+        const int m = min(n - i0, kMaxGridY);
+        hipLaunchKernelGGL(k_wc_bwd, dim3(st, m), dim3(kThreads), 0, s, x + i0 * img, C, H, W, p + 7 * (size_t)i0,
+                           gy + i0 * img, gx ? gx + i0 * img : nullptr, (float *)ws + (size_t)i0 * st * kRec);
+        const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_wc_reduce, dim3(n), dim3(64), 0, s, partial, tiles, gp);
+    hipLaunchKernelGGL(k_wc_reduce, dim3(n), dim3(64), 0, s, (const float *)ws, st, C, p, gp);
     return hipGetLastError();
 }
 

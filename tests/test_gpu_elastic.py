@@ -150,6 +150,36 @@ def test_large_tile_sampled_pixels_against_the_definition(m):
         acc = (1024 - ay) * ((1024 - ax) * e[(0, 0)] + ax * e[(0, 1)]) + ay * ((1024 - ax) * e[(1, 0)] + ax * e[(1, 1)])
         ref = np.array([oracle.rshr_he(int(v), 20) for v in acc], np.uint8)
         assert np.array_equal(outn[yy, xx], ref), (yy, xx)
+    # masks: the nearest grid tap of the elastic result, whose pixel is the
+    # mask's nearest displaced tap; the field at that pixel from the oracle
+    omn, maskn = om.cpu().numpy()[0], mask.cpu().numpy()[0]
+    for (yy, xx) in [tuple(v) for v in rng.integers(0, H, (200, 2))] + [(0, 0), (H - 1, W - 1)]:
+        Y = oracle.reflect101((int(myn[yy]) + 512) >> 10, H)
+        X = oracle.reflect101((int(mxn[xx]) + 512) >> 10, W)
+        ox, oy = oracle.elastic_field_at(1809068395, 0, H, W, Y, X)
+        sy = oracle.reflect101(((Y << 10) + oy + 512) >> 10, H)
+        sx = oracle.reflect101(((X << 10) + ox + 512) >> 10, W)
+        assert omn[yy, xx] == maskn[sy, sx], (yy, xx)
+
+
+def test_f32_chain_at_1024_against_the_oracle(m):
+    # one 3 x 1024 x 1024 float image through the elastic (sigma 50, alpha 1000)
+    # and grid maps the oracle computes; forward and adjoint against its fp64 chain
+    import torch
+    H = W = 1024
+    x = synth.smooth_noise(9, 1, H, W, 3)
+    ox, oy = oracle.elastic_field(9, 0, H, W)
+    g = oracle.sample_grid(9, 0, 1)
+    mx, my = oracle.grid_table(g[0, :5], W), oracle.grid_table(g[0, 5:], H)
+    off = torch.from_numpy(np.stack([ox, oy])[None].copy()).cuda()
+    mxt, myt = torch.from_numpy(mx[None].copy()).cuda(), torch.from_numpy(my[None].copy()).cuda()
+    y = m.elastic_grid_f32_fwd(x.cuda(), off, mxt, myt).cpu().numpy()[0]
+    yr = oracle.chain_f_forward(x[0].numpy(), ox, oy, mx, my)
+    assert np.abs(y - yr).max() <= 1e-6
+    gy = np.random.default_rng(4).uniform(-1, 1, (1, 3, H, W)).astype(np.float32)
+    gx = m.elastic_grid_f32_bwd(torch.from_numpy(gy).cuda(), off, mxt, myt).cpu().numpy()[0]
+    gr = oracle.chain_f_backward(gy[0].astype(np.float64), ox, oy, mx, my)
+    assert np.abs(gx - gr).max() <= 1e-5 * np.abs(gr).max()
 
 
 def test_image_stats_match_oracle(m):

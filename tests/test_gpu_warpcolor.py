@@ -61,6 +61,18 @@ def test_odd_shapes_and_channel_counts(m, C, H, W):
     compare(m, x, p, w)
 
 
+def test_far_scales_take_the_other_kernel_forms(m):
+    # a zoom-out whose source footprint is too wide for the LDS box (the forward
+    # and parameter kernels then gather from global memory) and zoom-ins whose
+    # adjoint region exceeds the sorted LDS entries (scatter form)
+    n, C, H, W = 4, 3, 80, 72
+    x = synth.smooth_noise(21, n, H, W, C).numpy()
+    p = m.sample_wc(21, 0, n)
+    p[:, 1] = [0.4, 0.6, 1.7, 2.5]
+    w = np.random.default_rng(3).uniform(-1, 1, (n, C, H, W)).astype(np.float32)
+    compare(m, x, p, w)
+
+
 def test_identity_forward_is_exact(m):
     import torch
     x = synth.smooth_noise(3, 2, 20, 24, 3).cuda()
