@@ -15,8 +15,8 @@
 //                 thread down a column (rows 8 apart): the fp64 position is
 //                 evaluated once per thread and stepped by the constant row
 //                 increment.  The tile's source footprint (its bounding box,
-//                 all channels) is staged in LDS with zeros outside the
-//                 image; a footprint too large for the box (zoom-out well
+//                 all channels) is staged in LDS by LDS-DMA with zeros
+//                 outside the image; a footprint too large for the box (zoom-out well
 //                 below 1) gathers its taps from global memory instead, as
 //                 32-bit buffer offsets where a tap outside the image gets an
 //                 offset past the end of the plane, which reads as 0;
@@ -166,27 +166,31 @@ __device__ __forceinline__ Box tile_box(const Geo &g, int X0, int Y0, int C) {
     return b;
 }
 
-// Stages box b of planes plane0 .. plane0 + C - 1 of x into lds ([c][h][w]);
-// pixels outside the image are 0.  Wave w takes rows w, w + 4, ..., a lane
-// one column; a row or column outside the image loads through an offset past
-// the end of the plane.
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Stages box b of planes plane0 .. plane0 + C - 1 of x into lds ([c][h][w])
+// through LDS-DMA (buffer loads that write LDS directly, so a wave has every
+// row of its share in flight at once); pixels outside the image are 0.  Wave
+// w takes rows w, w + 4, ..., lane i column i of the row; a row or column
+// outside the image loads through an offset past the end of the plane.
+// Returns after this wave's rows have landed; the caller's barrier publishes them.
 __device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, int H, int W, const Box &b,
                                           float *lds) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int col = b.x0 + lane;
-    const uint32_t voff = (lane < b.w && col >= 0 && col < W) ? (uint32_t)col * 4u : kOOB;
+    const uint32_t voff = (col >= 0 && col < W) ? (uint32_t)col * 4u : kOOB;
     for (int c = 0; c < C; ++c) {
         const __amdgpu_buffer_rsrc_t r = plane_rsrc(x, plane0 + c, H, W);
         float *dst = lds + c * b.h * b.w;
-#pragma unroll 4
         for (int row = wave; row < b.h; row += kThreads / 64) {
             const int sy = b.y0 + row;
             const bool ok = sy >= 0 && sy < H;
-            const float v = __uint_as_float(
-                __builtin_amdgcn_raw_buffer_load_b32(r, ok ? voff : kOOB, ok ? sy * W * 4 : 0, 0));
-            if (lane < b.w) dst[row * b.w + lane] = v;
+            if (lane < b.w)  // lane i lands at dst + row w + 4 i bytes
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)(dst + row * b.w), 4, ok ? voff : kOOB,
+                                                         ok ? sy * W * 4 : 0, 0, 0);
         }
     }
+    __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
 }
 
 // This thread's four pixels of the 32 x 32 output tile (column ox, rows oy0
@@ -352,11 +356,12 @@ struct ParAcc {
 // y1 in (0, 1]: dL/dgamma += g_y y ln y1; where z lies in (0, 1), with
 // g_z = g_y gamma y / y1: dL/dw = g_z alpha, dL/dalpha += g_z w,
 // dL/dbeta += g_z, (g_sx, g_sy) += dL/dw (dw/dsx, dw/dsy).
-// quad(c) gives the pixel's taps in channel c, gvf(c) its dL/dy.
+// quad(c) gives the pixel's taps in channel c, gvf(c) its dL/dy; (rx, ry) is
+// its sample point relative to the image centre.
 template <class QuadF, class GyF>
-__device__ __forceinline__ void pixel_adjoint(int C, float fx, float fy, double sx, double sy, const Geo &g,
-                                              float alpha, float beta, float gamma, bool owned, QuadF quad, GyF gvf,
-                                              float (&gw)[kMaxC], ParAcc &a) {
+__device__ __forceinline__ void pixel_adjoint(int C, float fx, float fy, float rx, float ry, float alpha, float beta,
+                                              float gamma, bool owned, QuadF quad, GyF gvf, float (&gw)[kMaxC],
+                                              ParAcc &a) {
     float gsx = 0.0f, gsy = 0.0f;
 #pragma unroll
     for (int c = 0; c < kMaxC; ++c) {
@@ -385,7 +390,6 @@ __device__ __forceinline__ void pixel_adjoint(int C, float fx, float fy, double 
         }
     }
     if (owned) {
-        const float rx = (float)(sx - g.cx), ry = (float)(sy - g.cy);
         a.v[0] += gsy * rx - gsx * ry;
         a.v[1] += gsx * rx + gsy * ry;
         a.v[2] += gsx;
@@ -437,7 +441,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // A region larger than the LDS pool (scale well above 1) takes its taps from
 // global memory and scatters into an LDS accumulator with float atomics.
 // With gx NULL only the parameter gradients are formed.
-__global__ __launch_bounds__(kThreads) void k_wc_bwd(const float *__restrict__ x, int C, int H, int W,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_wc_bwd(const float *__restrict__ x, int C, int H, int W,
                                                      const float *__restrict__ params,
                                                      const float *__restrict__ gy, float *__restrict__ gx,
                                                      float *__restrict__ rec) {
@@ -520,16 +524,17 @@ __global__ __launch_bounds__(kThreads) void k_wc_bwd(const float *__restrict__ x
         constexpr int kXT = kCells + 1;
         stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT}, pool);
         __syncthreads();
-        // 2. region pixels
-        float eg[kEPT][kMaxC], efx[kEPT], efy[kEPT];
-        int ecs[kEPT];
+        // 2. region pixels: positions and cells first, then every dL/dy load of
+        // the thread's pixels in flight together, then the arithmetic
+        uint32_t eop[kEPT];  // the pixel's byte offset in a plane; kOOB: no pixel, or a cell outside the square
+        int einf[kEPT];      // tap index in the staged tile | cell index << 11 | owned << 22
+        float efx[kEPT], efy[kEPT], erx[kEPT], ery[kEPT];
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             const int e = threadIdx.x + k * kThreads;
-            ecs[k] = -1;
-            efx[k] = efy[k] = 0.0f;
-#pragma unroll
-            for (int c = 0; c < kMaxC; ++c) eg[k][c] = 0.0f;
+            eop[k] = kOOB;
+            einf[k] = 0;
+            efx[k] = efy[k] = erx[k] = ery[k] = 0.0f;
             if (e >= total) continue;
             int r = 0;  // the last row whose start is at or before e
 #pragma unroll
@@ -542,24 +547,38 @@ __global__ __launch_bounds__(kThreads) void k_wc_bwd(const float *__restrict__ x
             const double dcx = fx0 - tx0, dcy = fy0 - ty0;  // cell relative to the cell square
             if (!(dcx >= 0.0 && dcx < (double)kCells && dcy >= 0.0 && dcy < (double)kCells)) continue;
             const int cx = (int)dcx, cy = (int)dcy;
-            const float fx = (float)(sx - fx0), fy = (float)(sy - fy0);
             const bool owned = cx >= own_x0 && cx <= own_x1 && cy >= own_y0 && cy <= own_y1;
-            const int bi = cy * kXT + cx;
-            const uint32_t opix = ((uint32_t)oy * (uint32_t)W + (uint32_t)ox) * 4u;
-            float gw[kMaxC];
+            eop[k] = ((uint32_t)oy * (uint32_t)W + (uint32_t)ox) * 4u;
+            einf[k] = (cy * kXT + cx) | ((cy * kCells + cx) << 11) | ((int)owned << 22);
+            efx[k] = (float)(sx - fx0);
+            efy[k] = (float)(sy - fy0);
+            erx[k] = (float)(sx - g.cx);
+            ery[k] = (float)(sy - g.cy);
+        }
+        float egv[kEPT][kMaxC];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k)
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c)
+                egv[k][c] = c < C ? ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), eop[k]) : 0.0f;
+        float eg[kEPT][kMaxC];
+        int ecs[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            ecs[k] = -1;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) eg[k][c] = 0.0f;
+            if (eop[k] == kOOB) continue;
+            const int bi = einf[k] & 2047;
             pixel_adjoint(
-                C, fx, fy, sx, sy, g, alpha, beta, gamma, owned,
+                C, efx[k], efy[k], erx[k], ery[k], alpha, beta, gamma, (einf[k] >> 22) != 0,
                 [&](int c) {
                     const float *q = pool + c * kXT * kXT + bi;
                     return Quad{q[0], q[1], q[kXT], q[kXT + 1]};
                 },
-                [&](int c) { return ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), opix); }, gw, acc);
-#pragma unroll
-            for (int c = 0; c < kMaxC; ++c) eg[k][c] = gw[c];
-            efx[k] = fx;
-            efy[k] = fy;
+                [&](int c) { return egv[k][c]; }, eg[k], acc);
             if (gx) {
-                const int ci = cy * kCells + cx;
+                const int ci = (einf[k] >> 11) & 2047;
                 ecs[k] = (atomicAdd(&off[ci], 1) << 11) | ci;
             }
         }
@@ -646,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void k_wc_bwd(const float *__restrict__ x
                 const uint32_t opix = ((uint32_t)oy * (uint32_t)W + (uint32_t)ox) * 4u;
                 float gw[kMaxC];
                 pixel_adjoint(
-                    C, t.fx, t.fy, sx, sy, g, alpha, beta, gamma, owned,
+                    C, t.fx, t.fy, (float)(sx - g.cx), (float)(sy - g.cy), alpha, beta, gamma, owned,
                     [&](int c) { return load_quad(plane_rsrc(x, (size_t)img * C + c, H, W), t); },
                     [&](int c) { return ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), opix); }, gw, acc);
                 if (!gx) continue;

@@ -1,8 +1,11 @@
 """GPU parity of the differentiable warp + colour op: the float32 forward
 against the fp64 oracle (|y - y_ref| <= 1e-5 max(1, |y_ref|)), the HIP backward
 against the oracle's analytic fp64 adjoint (image gradient within 1e-4 of
-max|g_ref|; each parameter gradient within 1e-4 (|g_ref| + median |g_ref|)),
-and torch.autograd plumbing."""
+max|g_ref|; each parameter gradient within 1e-4 (|g_ref| + median |g_ref|)
+over the batch: a float32 sum of ~150 K terms that nearly cancel has no
+relative bound, the median sets its scale), and torch.autograd plumbing.  The
+full-size test checks all 128 images and prints the errors reached, pure
+relative ones included."""
 import numpy as np
 import pytest
 
@@ -20,6 +23,11 @@ def m(dev):
 
 
 def compare(m, x, p, w, check_gx=True, n_check=None):
+    """Checks the HIP forward and backward against the oracle on images n_check
+    (default all) and returns the errors reached: forward max |dy| and max
+    |dy| / |y_ref| over |y_ref| >= 1e-3; grad_x max |dg| / max |g_ref| per
+    image; parameter gradients max |dg| / |g_ref| (pure relative) and max of
+    |dg| / (|g_ref| + median |g_ref|) (the mixed bar)."""
     import torch
     xt, pt, wt = (torch.from_numpy(a).cuda() for a in (x, p, w))
     y = m.warpcolor_fwd(xt, pt)
@@ -29,18 +37,29 @@ def compare(m, x, p, w, check_gx=True, n_check=None):
     n = x.shape[0]
     idx = range(n) if n_check is None else n_check
     ref_gp = np.zeros((n, 7))
+    st = {"fwd_abs": 0.0, "fwd_rel": 0.0, "gx_rel_to_max": 0.0}
     for i in idx:
         yr = oracle.wc_forward(x[i], p[i].astype(np.float64))
-        assert np.all(np.abs(y[i] - yr) <= 1e-5 * np.maximum(1.0, np.abs(yr))), ("forward", i)
+        d = np.abs(y[i] - yr)
+        assert np.all(d <= 1e-5 * np.maximum(1.0, np.abs(yr))), ("forward", i)
+        big = np.abs(yr) >= 1e-3
+        st["fwd_abs"] = max(st["fwd_abs"], float(d.max()))
+        st["fwd_rel"] = max(st["fwd_rel"], float((d[big] / np.abs(yr[big])).max()) if big.any() else 0.0)
         gxr, gpr = oracle.wc_backward(x[i], p[i].astype(np.float64), w[i].astype(np.float64), want_gx=check_gx)
         ref_gp[i] = gpr
         if check_gx:
-            assert np.abs(gx[i] - gxr).max() <= 1e-4 * np.abs(gxr).max(), ("grad_x", i, np.abs(gx[i] - gxr).max())
+            e = np.abs(gx[i] - gxr).max() / max(np.abs(gxr).max(), 1e-300)
+            st["gx_rel_to_max"] = max(st["gx_rel_to_max"], float(e))
+            assert e <= 1e-4, ("grad_x", i, e)
     idx = list(idx)
     med = np.median(np.abs(ref_gp[idx]), axis=0)
     err = np.abs(gp[idx] - ref_gp[idx])
     tol = 1e-4 * (np.abs(ref_gp[idx]) + med)
+    st["gp_mixed"] = float((err / np.maximum(tol, 1e-300)).max()) * 1e-4
+    st["gp_rel"] = float((err / np.maximum(np.abs(ref_gp[idx]), 1e-300)).max())
+    st["gp_rel_over_1e-4"] = int((err > 1e-4 * np.abs(ref_gp[idx])).sum())
     assert np.all(err <= tol), (err / np.maximum(tol, 1e-30)).max()
+    return st
 
 
 def test_small_batch_matches_oracle(m):
@@ -80,7 +99,7 @@ def test_identity_forward_is_exact(m):
     assert torch.equal(m.warpcolor_fwd(x, p), x)
 
 
-def test_full_size_batch_sampled(m):
+def test_full_size_batch_all_images(m):
     # 128 x 3 x 224 x 224 float32 in [0, 1], loss weights U[-1, 1]
     import torch
     n, C, H, W = 128, 3, 224, 224
@@ -88,7 +107,8 @@ def test_full_size_batch_sampled(m):
     p = m.sample_wc(1809068394, 0, n)
     g = torch.Generator().manual_seed(5)
     w = (torch.rand((n, C, H, W), generator=g) * 2 - 1)
-    compare(m, x.cpu().numpy(), p, w.numpy(), check_gx=True, n_check=list(range(0, 128, 16)))
+    st = compare(m, x.cpu().numpy(), p, w.numpy(), check_gx=True)
+    print("\nwarpcolor parity, 128 x 3 x 224 x 224: " + ", ".join("%s=%.3g" % kv for kv in st.items()))
 
 
 def test_autograd_function(m):
