@@ -93,8 +93,8 @@ int miaug_ctx_create(int device, const char *tune_cache_path, miaug_ctx **out) {
         c->arch = prop.gcnArchName;
         c->tune_cache = tune_cache_path ? tune_cache_path : env().tune_cache;
         memset(&c->stats, 0, sizeof(c->stats));
-        st = dev_alloc((void **)&c->counters, 256 * sizeof(int), "ctx_create: queue counters");
-        if (!st) st = hip_status(hipMemset(c->counters, 0, 256 * sizeof(int)), "hipMemset counters");
+        st = dev_alloc((void **)&c->counters, (256 + kLptMax) * sizeof(int), "ctx_create: queue counters");
+        if (!st) st = hip_status(hipMemset(c->counters, 0, (256 + kLptMax) * sizeof(int)), "hipMemset counters");
     }
     hipSetDevice(prev);
     if (st) {
@@ -282,7 +282,7 @@ int miaug_ragged_apply(miaug_ctx *ctx, const miaug_ragged_args *a, void *stream)
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply: ctx is NULL");
     if (int st = ragged_check(a)) return st;
-    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters, ctx->counters + 256};
     log_msg(3, "ragged_apply: %d images, variant %d (%s)", a->n, L.variant, ragged_variant_name(L.variant));
     const int st = hip_status(launch_ragged(a, L, 0, as_stream(stream)), "ragged_apply launch");
     if (!st && a->n > 0) ctx->stats.launches++;
@@ -306,7 +306,7 @@ int miaug_ragged_apply_per_image(miaug_ctx *ctx, const miaug_ragged_args *a, voi
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "ragged_apply_per_image: ctx is NULL");
     if (int st = ragged_check(a)) return st;
-    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters, ctx->counters + 256};
     const int st = hip_status(launch_ragged(a, L, 1, as_stream(stream)), "ragged_apply_per_image launch");
     if (!st && a->n > 0) ctx->stats.launches++;
     return ctx_done(ctx, st);
@@ -322,7 +322,7 @@ int miaug_ragged_graph_create(miaug_ctx *ctx, const miaug_ragged_args *a, void *
     int st = hip_status(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     if (st) return ctx_done(ctx, st);
     ctx->stats.calls++;
-    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters};
+    RaggedLaunch L{ctx_variant(ctx), ctx->num_cu, ctx->counters, ctx->counters + 256};
     hipError_t le = launch_ragged(a, L, 0, s);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(s, &g);
@@ -498,7 +498,7 @@ int ragged_autotune_run(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, hi
         if (!e) e = hip_status(hipStreamSynchronize(s), "sync");
         return e;
     };
-    RaggedLaunch L{0, ctx->num_cu, ctx->counters};
+    RaggedLaunch L{0, ctx->num_cu, ctx->counters, ctx->counters + 256};
     st = fill();
     if (!st) st = hip_status(launch_ragged(a, L, 1, s), "autotune reference");
     if (!st) st = fetch(ref, mref, bref);

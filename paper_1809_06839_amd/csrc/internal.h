@@ -14,7 +14,7 @@ struct miaug_ctx {
     int device;
     int num_cu;
     int variant;
-    int *counters;           // device, 256 ints
+    int *counters;           // device, 256 ints of queue counters, then kLptMax ints of work order
     std::string arch;        // gcnArchName of the device (tune-cache keys)
     std::string tune_cache;  // autotuner cache file ("" = none)
     miaug_stats stats;
@@ -66,10 +66,12 @@ hipError_t launch_pad_u8(const uint8_t *in, int n, int H, int W, int C, int Ho, 
 hipError_t launch_warp_u8(const uint8_t *in, int n, int H, int W, int C, const int64_t *aq, int interp, int border,
                           uint8_t *out, hipStream_t s);
 
+constexpr int kLptMax = 4096;  // largest batch the largest-first work order sorts (larger: index order)
 struct RaggedLaunch {
     int variant;      // index into the variant table
     int num_cu;       // compute units of the device
     int *counters;    // device: queue counters (8 + 8 padding ints)
+    int *order = nullptr;  // device, kLptMax ints: the largest-first work order (NULL: index order)
 };
 hipError_t launch_ragged(const miaug_ragged_args *a, const RaggedLaunch &L, int per_image, hipStream_t s);
 // Row-band form of the batched launch (k_rows.hip); cap_kind 0/1/2 picks the stage size.

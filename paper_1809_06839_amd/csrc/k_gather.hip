@@ -450,7 +450,7 @@ __device__ __forceinline__ void gather_run(const miaug_ragged_args &a, int img, 
 // barrier per band keeps them together.
 template <int BAND, bool SYNC>
 __global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_gather(
-    miaug_ragged_args a, int *__restrict__ counters) {
+    miaug_ragged_args a, int *__restrict__ counters, const int *__restrict__ order) {
     __shared__ float nlut[3][256];
     __shared__ uint8_t bcl[kGWaves][256];
     __shared__ __align__(16) uint32_t tiles[kGWaves][64 * BAND];  // per-wave transpose tile
@@ -475,7 +475,8 @@ __global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             if (cn == 0) break;
             if (wave < cn) {
                 int tile;
-                const int img = udiv_small(cbase + wave, per, tile) * kQueues + cq;
+                const int slot = udiv_small(cbase + wave, per, tile) * kQueues + cq;
+                const int img = order ? ldc(order + slot) : slot;
                 gather_run<BAND>(a, img, tile, bc_img, bc, nlut, tiles[wave]);
             }
             __syncthreads();  // every wave has read claim_s
@@ -500,11 +501,62 @@ __global__ __launch_bounds__(kGThreads) __attribute__((amdgpu_waves_per_eu(4))) 
             if (cn == 0) break;
             for (int k = 0; k < cn; ++k) {
                 int tile;
-                const int img = udiv_small(cbase + k, per, tile) * kQueues + cq;
+                const int slot = udiv_small(cbase + k, per, tile) * kQueues + cq;
+                const int img = order ? ldc(order + slot) : slot;
                 gather_run<BAND>(a, img, tile, bc_img, bc, nlut, tiles[wave]);
             }
         }
     }
+}
+
+// Largest-first work order (longest processing time first): image slots
+// sorted by an estimate of the source bytes the image's items read --
+// min(h, 2 out_h) rows of w pixels (4 bytes with a mask, 3 without) for the
+// window (h, w) of its Dih4 image -- in descending order, ties by index, by
+// a bitonic sort of (estimate << 32 | ~index) keys in LDS.  Slot j of the
+// queues (queue j mod 8, position j / 8) then takes image order[j], so every
+// queue starts with its largest images and the last items of the launch are
+// small ones.  n <= kLptMax; one workgroup.
+__global__ __launch_bounds__(1024) void k_lpt_order(miaug_ragged_args a, int *__restrict__ order) {
+    __shared__ uint64_t key[kLptMax];
+    const int n = a.n;
+    int N = 1;
+    while (N < n) N <<= 1;
+    for (int i = threadIdx.x; i < N; i += 1024) {
+        uint64_t k = 0;
+        if (i < n) {
+            const bool swap = ((a.flags[4 * i + 2] & 1) ^ (a.flags[4 * i + 3] & 1)) != 0;
+            int h = a.hw[2 * i], w = a.hw[2 * i + 1];
+            if (swap) {
+                const int t = h;
+                h = w;
+                w = t;
+            }
+            if (a.crop && a.crop[4 * i + 2] > 0) {
+                h = a.crop[4 * i + 2];
+                w = a.crop[4 * i + 3];
+            }
+            const uint64_t rows = (uint64_t)min(max(h, 0), 2 * a.out_h);
+            const uint64_t est = min(rows * (uint64_t)max(w, 0) * (a.mask ? 4u : 3u), (uint64_t)0xFFFFFFFFu);
+            k = est << 32 | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= N; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < N / 2; t += 1024) {
+                const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+                const bool desc = (lo & size) == 0;  // the last merge (size N) is descending throughout
+                const uint64_t x = key[lo], y = key[hi];
+                if (desc ? x < y : x > y) {
+                    key[lo] = y;
+                    key[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = threadIdx.x; i < n; i += 1024) order[i] = (int)(0xFFFFFFFFu - (uint32_t)key[i]);
 }
 
 }  // namespace
@@ -516,16 +568,25 @@ hipError_t launch_ragged_gather(const miaug_ragged_args *a, int band, int wg_per
     if (e != hipSuccess) return e;
     const int b = band & 63;
     const bool sync = (band & 64) != 0;
+    // bit 128: largest images first (index order without a context's order
+    // buffer or beyond kLptMax images)
+    const int *order = nullptr;
+    if ((band & 128) && L.order && a->n <= kLptMax) {
+        hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, s, *a, L.order);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        order = L.order;
+    }
     const int per = b == 32 ? gather_items_per_image<32>(a->out_h, a->out_w)
                             : gather_items_per_image<16>(a->out_h, a->out_w);
     int grid = L.num_cu * wg_per_cu;
     const long waves = ((long)a->n * per + kGWaves - 1) / kGWaves;
     if (grid > waves) grid = (int)waves;
     grid = ((grid + kQueues - 1) / kQueues) * kQueues;
-    if (b == 32 && sync) hipLaunchKernelGGL((k_gather<32, true>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters);
-    else if (b == 32) hipLaunchKernelGGL((k_gather<32, false>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters);
-    else if (sync) hipLaunchKernelGGL((k_gather<16, true>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters);
-    else hipLaunchKernelGGL((k_gather<16, false>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters);
+    if (b == 32 && sync) hipLaunchKernelGGL((k_gather<32, true>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters, order);
+    else if (b == 32) hipLaunchKernelGGL((k_gather<32, false>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters, order);
+    else if (sync) hipLaunchKernelGGL((k_gather<16, true>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters, order);
+    else hipLaunchKernelGGL((k_gather<16, false>), dim3(grid), dim3(kGThreads), 0, s, *a, L.counters, order);
     return hipGetLastError();
 }
 

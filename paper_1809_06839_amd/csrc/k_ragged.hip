@@ -1315,6 +1315,8 @@ const Variant kVariants[] = {
     {0, 0, 7, 4, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 4 wg/CU"},
     {0, 0, 7, 6, 1, "row bands of 16 lines, whole source rows, 9 KB stages x 2, 6 wg/CU"},
     {0, 0, 7, 2, 2, "row bands of 16 lines, whole source rows, 36 KB stages x 2, 2 wg/CU"},
+    {0, 0, 8, 4, 32 + 64 + 128, "wave row gathers, 32 lines x 64 per item, band per workgroup, 4 wg/CU, largest images first"},
+    {0, 0, 8, 6, 32 + 64 + 128, "wave row gathers, 32 lines x 64 per item, band per workgroup, 6 wg/CU, largest images first"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
