@@ -130,16 +130,10 @@ def ragged_kernel_name(variant_name: str) -> str:
 def cpu_baseline_ragged(b, flags, ab, seconds):
     import oracle
     oracle.lib()
-    t0 = time.perf_counter()
-    done = 0
-    while done < b.n:
-        oracle.pipe_ragged_one(b.image(done), b.mask_of(done), flags[done], ab[done], b.boxes_of(done), 224, 224)
-        done += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d images of the same 2048-image batch, single-threaded C oracle, %.1f s" % (done, dt)}
+
+    def one(i):
+        oracle.pipe_ragged_one(b.image(i), b.mask_of(i), flags[i], ab[i], b.boxes_of(i), 224, 224)
+    return cpu_oracle_rates(one, b.n, seconds, "images of the same 2048-image batch, C oracle")
 
 
 def bench_ragged(args, torch, m):
@@ -188,6 +182,25 @@ def bench_ragged(args, torch, m):
         e1.record(s)
         s.synchronize()
         ms_pi = e0.elapsed_time(e1) / pe_steps
+        # the op-list form: the same chain compiled from an op list, replayed through
+        # miaug_pipeline_graph_launch with fresh records every step (sampled on the
+        # host while the previous step runs)
+        pipe = m.Pipeline(ctx, [m.op("HFLIP", 0.5), m.op("VFLIP", 0.5), m.op("ROT90", 1, (0,), (3,)),
+                                m.op("TRANSPOSE", 0.5), m.op("BRIGHT_CONTRAST", 1, (0.8, -51), (1.2, 51)),
+                                m.op("RESIZE", out=(224, 224)), m.op("NORMALIZE", 1, m.IMAGENET_MEAN, m.IMAGENET_STD)])
+        bi, bo, _ = pipe.batch(ragged=r)
+        pg = pipe.graph(bi, bo, s)
+        for j in range(max(2, args.warmup)):
+            pg.launch(pipe.sample(1809068393, j * n, n), s)
+        s.synchronize()
+        e0.record(s)
+        for j in range(args.steps):
+            pg.launch(pipe.sample(1809068393, (j + 1000) * n, n), s)
+        e1.record(s)
+        s.synchronize()
+        ms_pg = e0.elapsed_time(e1) / args.steps
+        pg.close()
+        pipe.close()
     g.close()
     alg = ragged_algorithmic_bytes(b.hw, len(b.boxes))
     achieved = alg / (ms * 1e-3) / 1e9
@@ -203,6 +216,8 @@ def bench_ragged(args, torch, m):
                    "parallelism": "single GPU"},
         "per_image_launches": {"value": n / (ms_pi * 1e-3), "unit": "images/s", "ms_per_step": ms_pi,
                                "batched_speedup": ms_pi / ms},
+        "pipeline_graph": {"value": n / (ms_pg * 1e-3), "unit": "images/s", "ms_per_step": ms_pg,
+                           "form": "op-list pipeline, miaug_pipeline_graph_launch, fresh records per step"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": profiled_traffic("k_gather_2048img_ragged_to_224_f32.md", variants[variant]),
@@ -261,6 +276,74 @@ def line(metric, n, ms, args, dtype, config, roofline, extra=None):
     return res
 
 
+ROTATE_BYTES = 1 << 30  # inputs + outputs cycled per step, so no step finds its data in the 256 MB MALL
+
+
+def n_sets(set_bytes):
+    """Copies of a workload's buffers that together reach ROTATE_BYTES."""
+    return max(1, -(-ROTATE_BYTES // int(set_bytes)))
+
+
+def time_rotating(torch, fn, sets, steps, warmup, s):
+    """time_on_stream over fn(st, k): call i uses buffer set i mod `sets`."""
+    i = [0]
+
+    def call(st):
+        fn(st, i[0] % sets)
+        i[0] += 1
+    return time_on_stream(torch, call, steps, warmup, s)
+
+
+def host_cpu():
+    """Model name and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def pool_threads():
+    """Threads for the all-core oracle timing: the host's CPUs, at most the 16
+    that a one-GPU share of the machine gets (OMP_NUM_THREADS when set)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    n = int(env) if env.isdigit() and int(env) > 0 else (os.cpu_count() or 1)
+    return max(1, min(n, os.cpu_count() or 1, 16))
+
+
+def cpu_oracle_rates(one, n_items, seconds, what):
+    """The oracle's throughput on a bounded sample: one(i) processes item i
+    (a call into the C oracle, which releases the GIL); items cycle through
+    0 .. n_items - 1.  First single-threaded for about seconds / 2, then on a
+    thread pool for about seconds / 2; returns the cpu_baseline record
+    (value: all cores)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    done1 = 0
+    while time.perf_counter() - t0 < seconds / 2:
+        one(done1 % n_items)
+        done1 += 1
+    dt1 = time.perf_counter() - t0
+    th = pool_threads()
+    t0 = time.perf_counter()
+    doneN = 0
+    with ThreadPoolExecutor(th) as ex:
+        while time.perf_counter() - t0 < seconds / 2:
+            list(ex.map(lambda i: one(i % n_items), range(doneN, doneN + 4 * th)))
+            doneN += 4 * th
+    dtN = time.perf_counter() - t0
+    model, nproc = host_cpu()
+    return {"value": doneN / dtN, "unit": "images/s", "cores": th, "kind": "oracle",
+            "sample": "%s, cycled: %d on %d threads in %.1f s (single thread: %d in %.1f s)"
+                      % (what, doneN, th, dtN, done1, dt1),
+            "single_thread": {"value": done1 / dt1, "unit": "images/s", "cores": 1},
+            "cpu_model": model, "nproc": nproc}
+
+
 def hbm_roof(alg_bytes, ms, kernel):
     a = alg_bytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a / HBM_PEAK_GBS,
@@ -268,27 +351,43 @@ def hbm_roof(alg_bytes, ms, kernel):
 
 
 def bench_d4bc(args, torch, m):
-    """64 RGB 256x256 u8 images: random Dih4 element + brightness/contrast."""
+    """64 RGB 256x256 u8 images: random Dih4 element + brightness/contrast.  The
+    batch is 25 MB, so a step replays a hipGraph of 40 batch launches, each on
+    its own copy of the buffers (41 copies, 1 GiB, cycled)."""
     import synth
     n, H, W = 64, 256, 256
     img = synth.uniform_u8(1809068391, n, H, W).cuda()
     flags, ab = m.sample_d4bc(1809068391, 0, n)
     fl, abt = torch.from_numpy(flags).cuda(), torch.from_numpy(ab).cuda()
-    out = torch.empty_like(img)
-    s = torch.cuda.Stream()
-    ms = time_on_stream(torch, lambda st: m.d4_bc_u8(img, fl, abt, out, st), args.steps, args.warmup, s)
     alg = 2 * n * H * W * 3
+    K = n_sets(alg)
+    imgs = [img] + [img.clone() for _ in range(K - 1)]
+    outs = [torch.empty_like(img) for _ in range(K)]
+    per_graph = 40
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for k in range(K):
+            m.d4_bc_u8(imgs[k], fl, abt, outs[k], s)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for j in range(per_graph):
+            m.d4_bc_u8(imgs[j % K], fl, abt, outs[j % K], torch.cuda.current_stream())
+    ms_graph = time_on_stream(torch, lambda st: g.replay(), args.steps, args.warmup, s)
+    ms = ms_graph / per_graph
+    ms_eager = time_rotating(torch, lambda st, k: m.d4_bc_u8(imgs[k], fl, abt, outs[k], st), K, args.steps,
+                             args.warmup, s)
     res = line("images/sec and HBM GB/s (% peak), plain Dih4 + brightness/contrast", n, ms, args, "u8",
-               {"workload": "d4_brightness_contrast_64x256x256x3"}, hbm_roof(alg, ms, "k_d4_bc<3>"))
+               {"workload": "d4_brightness_contrast_64x256x256x3",
+                "timing": "%d batch launches per hipGraph replay, %d buffer copies (%.2f GB) cycled"
+                          % (per_graph, K, K * alg / 1e9)},
+               hbm_roof(alg, ms, "k_d4_bc<3>"), {"eager_ms_per_batch": ms_eager})
     if not args.no_cpu_baseline:
-        import oracle, time as _t
+        import oracle
         x = img.cpu().numpy()
-        t0 = _t.perf_counter(); done = 0
-        while done < n and _t.perf_counter() - t0 < args.cpu_seconds:
-            oracle.pipe_d4bc(x[done:done + 1], flags[done:done + 1], ab[done:done + 1]); done += 1
-        dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": done / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d of the 64 images, single-threaded C oracle" % done}
+        res["cpu_baseline"] = cpu_oracle_rates(
+            lambda i: oracle.pipe_d4bc(x[i:i + 1], flags[i:i + 1], ab[i:i + 1]), n, args.cpu_seconds,
+            "images of the 64-image batch, C oracle")
     return res
 
 
@@ -299,22 +398,21 @@ def bench_c2(args, torch, m):
     img = synth.smooth_u8_hwc(1809068392, n, 512, 512, device="cuda")
     f, k = m.sample_c2(1809068392, 0, n)
     rec = torch.from_numpy(m.compile_c2(f, k, 512, 512, 448)).cuda()
-    out = torch.empty((n, 224, 224, 3), dtype=torch.uint8, device="cuda")
-    s = torch.cuda.Stream()
-    ms = time_on_stream(torch, lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec, 448, 224, out, st),
-                        args.steps, args.warmup, s)
     alg = n * (512 * 512 * 3 + 224 * 224 * 3)
+    K = n_sets(alg)
+    imgs = [img] + [img.clone() for _ in range(K - 1)]
+    outs = [torch.empty((n, 224, 224, 3), dtype=torch.uint8, device="cuda") for _ in range(K)]
+    s = torch.cuda.Stream()
+    ms = time_rotating(torch, lambda st, j: m.ssr_crop_resize_hsv_gamma_blur_u8(imgs[j], rec, 448, 224, outs[j], st),
+                       K, args.steps, args.warmup, s)
     res = line("images/sec and HBM GB/s (% peak), full u8 pipeline", n, ms, args, "u8",
-               {"workload": "ssr_crop448_resize224_hsv_gamma_blur_256x512x512x3"}, hbm_roof(alg, ms, "k_c2"))
+               {"workload": "ssr_crop448_resize224_hsv_gamma_blur_256x512x512x3",
+                "timing": "%d buffer copies (%.2f GB) cycled" % (K, K * alg / 1e9)}, hbm_roof(alg, ms, "k_c2"))
     if not args.no_cpu_baseline:
-        import oracle, time as _t
+        import oracle
         x = img.cpu().numpy()
-        t0 = _t.perf_counter(); done = 0
-        while done < n and _t.perf_counter() - t0 < args.cpu_seconds:
-            oracle.pipe_c2_one(x[done], f[done], k[done]); done += 1
-        dt = _t.perf_counter() - t0
-        res["cpu_baseline"] = {"value": done / dt, "unit": "images/s", "cores": 1, "kind": "oracle",
-                               "sample": "%d of the 256 images, single-threaded C oracle" % done}
+        res["cpu_baseline"] = cpu_oracle_rates(lambda i: oracle.pipe_c2_one(x[i], f[i], k[i]), n, args.cpu_seconds,
+                                               "images of the 256-image batch, C oracle")
     return res
 
 
@@ -326,23 +424,47 @@ def bench_wc(args, torch, m):
     p = torch.from_numpy(m.sample_wc(1809068394, 0, n)).cuda()
     g = torch.Generator().manual_seed(5)
     w = (torch.rand((n, C, H, W), generator=g) * 2 - 1).cuda()
-    y = torch.empty_like(x)
-    gx = torch.empty_like(x)
+    plane = n * C * H * W * 4
+    K = n_sets(4 * plane)  # x, y, dL/dy, grad_x per copy
+    xs = [x] + [x.clone() for _ in range(K - 1)]
+    ws_ = [w] + [w.clone() for _ in range(K - 1)]
+    ys = [torch.empty_like(x) for _ in range(K)]
+    gxs = [torch.empty_like(x) for _ in range(K)]
     gp = torch.empty_like(p)
     ws = torch.empty(m.lib().miaug_warpcolor_workspace_bytes(n, C, H, W), dtype=torch.uint8, device="cuda")
     L = m.lib()
 
-    def step(st):
-        m._check(L.miaug_warpcolor_fwd(m._p(x), n, C, H, W, m._p(p), m._p(y), m._stream(st)))
-        m._check(L.miaug_warpcolor_bwd(m._p(x), n, C, H, W, m._p(p), m._p(w), m._p(gx), m._p(gp), m._p(ws),
-                                       ws.numel(), m._stream(st)))
+    def fwd(st, k):
+        m._check(L.miaug_warpcolor_fwd(m._p(xs[k]), n, C, H, W, m._p(p), m._p(ys[k]), m._stream(st)))
+
+    def bwd(st, k):
+        m._check(L.miaug_warpcolor_bwd(m._p(xs[k]), n, C, H, W, m._p(p), m._p(ws_[k]), m._p(gxs[k]), m._p(gp),
+                                       m._p(ws), ws.numel(), m._stream(st)))
 
     s = torch.cuda.Stream()
-    ms = time_on_stream(torch, step, args.steps, args.warmup, s)
-    plane = n * C * H * W * 4
+    ms = time_rotating(torch, lambda st, k: (fwd(st, k), bwd(st, k)), K, args.steps, args.warmup, s)
+    ms_f = time_rotating(torch, fwd, K, args.steps, args.warmup, s)
+    ms_b = time_rotating(torch, bwd, K, args.steps, args.warmup, s)
     alg = 2 * plane + 3 * plane  # forward x, y; backward gy, x, grad_x
-    return line("images/sec and HBM GB/s (% peak), differentiable warp + colour fwd+bwd", n, ms, args, "f32",
-                {"workload": "warpcolor_fwd_bwd_128x3x224x224_f32"}, hbm_roof(alg, ms, "k_wc_* (fwd + bwd)"))
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        xh, ph, wh = x.cpu().numpy(), p.cpu().numpy().astype(np.float64), w.cpu().numpy().astype(np.float64)
+
+        def one(i):
+            oracle.wc_forward(xh[i], ph[i])
+            oracle.wc_backward(xh[i], ph[i], wh[i])
+        cpu = cpu_oracle_rates(one, n, args.cpu_seconds, "images of the 128-image batch, fp64 C oracle forward + "
+                                                          "backward")
+    res = line("images/sec and HBM GB/s (% peak), differentiable warp + colour fwd+bwd", n, ms, args, "f32",
+                {"workload": "warpcolor_fwd_bwd_128x3x224x224_f32",
+                 "timing": "%d buffer copies (%.2f GB) cycled" % (K, K * 4 * plane / 1e9)},
+                hbm_roof(alg, ms, "k_wc_* (fwd + bwd)"),
+                {"forward_ms": ms_f, "forward_roofline": hbm_roof(2 * plane, ms_f, "k_wc_fwd"),
+                 "backward_ms": ms_b, "backward_roofline": hbm_roof(3 * plane, ms_b, "k_wc_bwd + k_wc_reduce")})
+    if cpu:
+        res["cpu_baseline"] = cpu
+    return res
 
 
 def bench_elastic(args, torch, m):
@@ -416,7 +538,10 @@ def bench_table1(args, torch, m):
     n, S = 256, 512
     img = synth.smooth_u8_hwc(1809068397, n, S, S, device="cuda")
     small = synth.smooth_u8_hwc(1809068398, n, 448, 448, device="cuda")
-    out = torch.empty_like(img)
+    K = n_sets(2 * img.numel())  # every op reads and writes about one batch per step
+    imgs = [img] + [img.clone() for _ in range(K - 1)]
+    smalls = [small] + [small.clone() for _ in range(K - 1)]
+    outs = [torch.empty_like(img) for _ in range(K)]
     s = torch.cuda.Stream()
     rng = np.random.default_rng(1809068397)
     zero_fl = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
@@ -444,44 +569,50 @@ def bench_table1(args, torch, m):
     rec_crop = c2_rec(ident_f, [[int(rng.integers(0, S - 63)), int(rng.integers(0, S - 63)), 0, 0, 0]
                                 for _ in range(n)], 64)
     out64 = torch.empty((n, 64, 64, 3), dtype=torch.uint8, device="cuda")
-    pad_out = torch.empty_like(img)
     px = n * S * S * 3
+    # each op is fn(stream, k): buffer copy k of the K cycled ones
     ops = [
-        ("RandomCrop64", lambda st: m.ssr_crop_resize_hsv_gamma_blur_u8(img, rec_crop, 64, 64, out64, st),
+        ("RandomCrop64", lambda st, k: m.ssr_crop_resize_hsv_gamma_blur_u8(imgs[k], rec_crop, 64, 64, out64, st),
          2 * n * 64 * 64 * 3, "k_c2 (identity warp, 64x64 crop)"),
-        ("PadToSize512", lambda st: m.pad_u8(small, S, S, 0, 0, pad_out, st), n * (448 * 448 * 3) + px,
+        ("PadToSize512", lambda st, k: m.pad_u8(smalls[k], S, S, 0, 0, outs[k], st), n * (448 * 448 * 3) + px,
          "k_pad<3>"),
-        ("HorizontalFlip", lambda st: m.d4_bc_u8(img, fl_h, ident_ab, out, st), 2 * px, "k_d4_bc<3>"),
-        ("VerticalFlip", lambda st: m.d4_bc_u8(img, fl_v, ident_ab, out, st), 2 * px, "k_d4_bc<3>"),
-        ("Rotate", lambda st: m.warp_affine_u8(img, aq_rot, 0, 0, out, st), 2 * px, "k_warp<3>"),
-        ("ShiftScaleRotate", lambda st: m.warp_affine_u8(img, aq_ssr, 0, 0, out, st), 2 * px, "k_warp<3>"),
-        ("Brightness", lambda st: m.d4_bc_u8(img, zero_fl, ab, out, st), 2 * px, "k_d4_bc<3>"),
-        ("ShiftHSV", lambda st: m.hsv_shift_u8(img, dhsv, out, st), 2 * px, "k_hsv_u8"),
-        ("ShiftRGB", lambda st: m.d4_lut_u8(img, zero_fl, luts_rgb, None, out, st), 2 * px, "k_d4_bc<3, LUTs>"),
-        ("Gamma", lambda st: m.d4_lut_u8(img, zero_fl, luts_gam, None, out, st), 2 * px, "k_d4_bc<3, LUTs>"),
-        ("Grayscale", lambda st: m.d4_lut_u8(img, zero_fl, luts_id, gray, out, st), 2 * px, "k_d4_bc<3, gray>"),
+        ("HorizontalFlip", lambda st, k: m.d4_bc_u8(imgs[k], fl_h, ident_ab, outs[k], st), 2 * px, "k_d4_bc<3>"),
+        ("VerticalFlip", lambda st, k: m.d4_bc_u8(imgs[k], fl_v, ident_ab, outs[k], st), 2 * px, "k_d4_bc<3>"),
+        ("Rotate", lambda st, k: m.warp_affine_u8(imgs[k], aq_rot, 0, 0, outs[k], st), 2 * px, "k_warp<3>"),
+        ("ShiftScaleRotate", lambda st, k: m.warp_affine_u8(imgs[k], aq_ssr, 0, 0, outs[k], st), 2 * px,
+         "k_warp<3>"),
+        ("Brightness", lambda st, k: m.d4_bc_u8(imgs[k], zero_fl, ab, outs[k], st), 2 * px, "k_d4_bc<3>"),
+        ("ShiftHSV", lambda st, k: m.hsv_shift_u8(imgs[k], dhsv, outs[k], st), 2 * px, "k_hsv_u8"),
+        ("ShiftRGB", lambda st, k: m.d4_lut_u8(imgs[k], zero_fl, luts_rgb, None, outs[k], st), 2 * px,
+         "k_d4_bc<3, LUTs>"),
+        ("Gamma", lambda st, k: m.d4_lut_u8(imgs[k], zero_fl, luts_gam, None, outs[k], st), 2 * px,
+         "k_d4_bc<3, LUTs>"),
+        ("Grayscale", lambda st, k: m.d4_lut_u8(imgs[k], zero_fl, luts_id, gray, outs[k], st), 2 * px,
+         "k_d4_bc<3, gray>"),
     ]
     extra = [  # not Table I rows: the blur of the u8 chain, alone, on the same batch
-        ("Blur3x3", lambda st: m.blur_u8(img, 3, None, out, st), 2 * px, "k_blur<3, 1>"),
-        ("Blur5x5", lambda st: m.blur_u8(img, 5, None, out, st), 2 * px, "k_blur<3, 2>"),
+        ("Blur3x3", lambda st, k: m.blur_u8(imgs[k], 3, None, outs[k], st), 2 * px, "k_blur<3, 1>"),
+        ("Blur5x5", lambda st, k: m.blur_u8(imgs[k], 5, None, outs[k], st), 2 * px, "k_blur<3, 2>"),
     ]
     extra_rows = {}
     for name, fn, alg, kernel in extra:
-        ms = time_on_stream(torch, fn, args.steps, args.warmup, s)
+        ms = time_rotating(torch, fn, K, args.steps, args.warmup, s)
         extra_rows[name] = {"ms_per_batch": ms, "images_per_s": n / (ms * 1e-3), "gb_per_s": alg / (ms * 1e-3) / 1e9,
                             "kernel": kernel}
         print("# %-16s %8.3f ms  %10.0f img/s  %7.0f GB/s (not a Table I row)" % (name, ms, n / (ms * 1e-3),
               extra_rows[name]["gb_per_s"]), file=sys.stderr, flush=True)
     rows = {}
     for name, fn, alg, kernel in ops:
-        ms = time_on_stream(torch, fn, args.steps, args.warmup, s)
+        ms = time_rotating(torch, fn, K, args.steps, args.warmup, s)
         rows[name] = {"ms_per_batch": ms, "images_per_s": n / (ms * 1e-3), "gb_per_s": alg / (ms * 1e-3) / 1e9,
                       "hbm_frac": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "kernel": kernel}
         print("# %-16s %8.3f ms  %10.0f img/s  %7.0f GB/s" % (name, ms, n / (ms * 1e-3), rows[name]["gb_per_s"]),
               file=sys.stderr, flush=True)
     total = sum(r["ms_per_batch"] for r in rows.values())
     res = line("images/sec per Table I op (one launch per op), 256 x 512x512x3 u8", n * len(rows), total, args, "u8",
-               {"workload": "table1_single_ops_256x512x512x3"}, None, {"ops": rows, "other_ops": extra_rows})
+               {"workload": "table1_single_ops_256x512x512x3",
+                "timing": "%d buffer copies (%.2f GB) cycled" % (K, K * 2 * px / 1e9)}, None,
+               {"ops": rows, "other_ops": extra_rows})
     res["value"] = n / (total * 1e-3) * len(rows)
     res["unit"] = "op-images/s"
     return res
