@@ -14,7 +14,7 @@ launch form for comparison, the roofline of the dominant kernel (algorithmic
 bytes per launch / average launch time, HIP events on the launch stream), and
 the oracle's CPU throughput on a bounded sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged|d4bc|c2|wc|elastic|table1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ragged|d4bc|c2|wc|elastic|elastic_f32|table1]
 """
 from __future__ import annotations
 
@@ -518,6 +518,56 @@ def bench_elastic(args, torch, m):
     return res
 
 
+def bench_elastic_f32(args, torch, m):
+    """Float copy of the elastic + grid chain (the training-time form, backward on a
+    float32 copy): 16 x 3 x 4096 x 4096 float32, fields sigma 50 / alpha 1000 and a
+    5x5 grid (0.3), forward and backward timed apart."""
+    import synth
+    n, C, H, W = 16, 3, 4096, 4096
+    x = torch.cat([synth.smooth_noise(1809068395 + i, 1, H, W, C, device="cuda") for i in range(n)])
+    g = torch.Generator(device="cuda").manual_seed(1809068399)
+    gy = torch.rand((n, C, H, W), generator=g, device="cuda") * 2 - 1
+    grid = torch.from_numpy(m.sample_grid(1809068395, 0, n)).cuda()
+    off = torch.empty((n, 2, H, W), dtype=torch.int32, device="cuda")
+    wsf = torch.empty(m.lib().miaug_elastic_workspace_bytes(n, H, W), dtype=torch.uint8, device="cuda")
+    mapx = torch.empty((n, W), dtype=torch.int32, device="cuda")
+    mapy = torch.empty((n, H), dtype=torch.int32, device="cuda")
+    L = m.lib()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        m._check(L.miaug_elastic_fields(1809068395, 0, n, H, W, 50.0, 1000, 150, m._p(off), m._p(wsf), wsf.numel(),
+                                         m._stream(s)))
+        m._check(L.miaug_grid_tables(m._p(grid), n, H, W, m._p(mapx), m._p(mapy), m._stream(s)))
+    s.synchronize()
+    del wsf
+    y = torch.empty_like(x)
+    gx = torch.empty_like(x)
+    ws = torch.empty(L.miaug_chain_f32_workspace_bytes(n, C, H, W), dtype=torch.uint8, device="cuda")
+
+    def fwd(st):
+        m._check(L.miaug_elastic_grid_f32_fwd(m._p(x), n, C, H, W, m._p(off), m._p(mapx), m._p(mapy), m._p(y),
+                                               m._p(ws), ws.numel(), m._stream(st)))
+
+    def bwd(st):
+        m._check(L.miaug_elastic_grid_f32_bwd(m._p(gy), n, C, H, W, m._p(off), m._p(mapx), m._p(mapy), m._p(gx),
+                                               m._p(ws), ws.numel(), m._stream(st)))
+
+    steps = max(2, args.steps // 4)
+    ms_f = time_on_stream(torch, fwd, steps, 1, s)
+    ms_b = time_on_stream(torch, bwd, steps, 1, s)
+    plane = n * C * H * W * 4
+    offb = n * 2 * H * W * 4
+    alg = plane + offb + plane  # per direction: image in, the elastic offsets, image out (maps are KB)
+    res = line("images/sec and HBM GB/s (% peak), float32 elastic + grid chain forward + backward", n, ms_f + ms_b,
+               args, "f32", {"workload": "elastic_grid_f32_16x3x4096x4096"},
+               hbm_roof(2 * alg, ms_f + ms_b, "k_chain_f_* (forward + backward)"),
+               {"forward_ms": ms_f, "forward_roofline": hbm_roof(alg, ms_f, "k_chain_f_elastic + k_chain_f_grid"),
+                "backward_ms": ms_b,
+                "backward_roofline": hbm_roof(alg, ms_b, "k_chain_f_grid_adj + k_chain_f_elastic_adj")})
+    res["steps"] = steps
+    return res
+
+
 def bench_copy(args, torch, m):
     """Plain device-to-device copy of 1 GiB: the reference for scaling the HBM
     byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
@@ -618,7 +668,8 @@ def bench_table1(args, torch, m):
     return res
 
 
-WORKLOADS = {"table1": bench_table1, "copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic}
+WORKLOADS = {"table1": bench_table1, "copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic,
+             "elastic_f32": bench_elastic_f32}
 
 
 def main():

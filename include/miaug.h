@@ -505,9 +505,15 @@ int miaug_boxes_elastic_grid(const float *boxes, const int32_t *box_off, int n, 
 
 /* Float copy of the chain without u8 rounding (same Q10 positions, dyadic
  * weights), CHW float32, and its adjoint w.r.t. the image (fields and grid
- * are random draws, not parameters).  The backward accumulates with float
- * atomics into grad_x, which it zeroes first; workspace holds the
- * intermediate gradient (miaug_chain_f32_workspace_bytes). */
+ * are random draws, not parameters; the training-time form of Sec. II-C's
+ * distortions).  The backward has one writer per element and no global
+ * float atomics: dL/de of the grid step as a gather over the grid's inverse
+ * ranges, then dL/dx of the elastic step per source tile over the window
+ * the field's largest displacement allows, summed in LDS (the order of
+ * those sums may vary between runs).  workspace (contents need not be
+ * initialised): dL/de and small tables, miaug_chain_f32_workspace_bytes.
+ * Errors: EINVAL null pointers; ESHAPE n > 65535, H or W >= 2^20 or
+ * H W > 2^30; ECAPACITY workspace too small. */
 int miaug_elastic_grid_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off,
                                const int32_t *mapx, const int32_t *mapy, float *y, void *workspace,
                                size_t workspace_bytes, void *stream);

@@ -720,7 +720,8 @@ int miaug_elastic_grid_f32_fwd(const float *x, int n, int C, int H, int W, const
     if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "chain_f32_fwd: negative size");
     if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
     if (!x || !off || !mapx || !mapy || !y) return set_error(MIAUG_EINVAL, "chain_f32_fwd: NULL pointer");
-    if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "chain_f32_fwd: image too large");
+    if ((long long)H * W > (1ll << 30) || H >= (1 << 20) || W >= (1 << 20) || n > 65535)
+        return set_error(MIAUG_ESHAPE, "chain_f32_fwd: n=%d, %dx%d out of range", n, H, W);
     size_t need = chain_f32_workspace_bytes(n, C, H, W);
     if (!ws || ws_bytes < need)
         return set_error(MIAUG_ECAPACITY, "chain_f32_fwd: workspace %zu < %zu bytes", ws_bytes, need);
@@ -734,7 +735,8 @@ int miaug_elastic_grid_f32_bwd(const float *gy, int n, int C, int H, int W, cons
     if (n < 0 || C < 0 || H < 0 || W < 0) return set_error(MIAUG_EINVAL, "chain_f32_bwd: negative size");
     if (n == 0 || C == 0 || H == 0 || W == 0) return MIAUG_OK;
     if (!gy || !off || !mapx || !mapy || !gx) return set_error(MIAUG_EINVAL, "chain_f32_bwd: NULL pointer");
-    if ((long long)H * W > (1ll << 30)) return set_error(MIAUG_ESHAPE, "chain_f32_bwd: image too large");
+    if ((long long)H * W > (1ll << 30) || H >= (1 << 20) || W >= (1 << 20) || n > 65535)
+        return set_error(MIAUG_ESHAPE, "chain_f32_bwd: n=%d, %dx%d out of range", n, H, W);
     size_t need = chain_f32_workspace_bytes(n, C, H, W);
     if (!ws || ws_bytes < need)
         return set_error(MIAUG_ECAPACITY, "chain_f32_bwd: workspace %zu < %zu bytes", ws_bytes, need);

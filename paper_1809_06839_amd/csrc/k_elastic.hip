@@ -25,8 +25,10 @@
 // reflect-101), and the output from the e-block.  Tiles whose blocks do not
 // fit, or reach past one reflection of the image, gather their taps from
 // global memory instead.  The mask takes the same two maps with nearest
-// sampling.  Float copy: the same maps without rounding; its adjoint scatters
-// with float atomics.
+// sampling.  Float copy: the same maps without rounding; its adjoint is
+// owner-computes: the grid step as a gather over the inverse grid ranges,
+// the elastic step per source tile over the window its largest displacement
+// allows, accumulated in LDS (no global float atomics).
 #include "dev_common.h"
 #include "q10_blend.h"
 #include "internal.h"
@@ -943,46 +945,368 @@ __global__ void k_fill_u8(uint8_t *__restrict__ p, size_t n, uint8_t v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ void k_fill_zero(float *__restrict__ p, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0f;
+
+// ---- adjoint of the float copy, owner-computes (every element has one writer)
+// Workspace: ge [n][C][H][W] (dL/de); dmax [n] (the largest |offset| of the
+// elastic field, Q10); wide [n]; the inverse grid tables: per source column j
+// (row i) the count of output columns (rows) whose nonzero taps land on it,
+// then up to kInvK of them with their weights, sorted by output index and
+// padded with weight 0.
+constexpr int kInvK = 8;
+
+struct ChainWs {
+    float *ge;
+    int32_t *dmax, *wide, *cx, *cy;  // cx [n][W], cy [n][H]: entry counts
+    int32_t *xc, *yc;                // [n][W][kInvK] / [n][H][kInvK] output index of each entry
+    float *xw, *yw;                  // its weight
+};
+
+__host__ __device__ inline ChainWs chain_ws(void *ws, int n, int C, int H, int W) {
+    ChainWs w;
+    w.ge = (float *)ws;
+    w.dmax = (int32_t *)(w.ge + (size_t)n * C * H * W);
+    w.wide = w.dmax + n;
+    w.cx = w.wide + n;
+    w.cy = w.cx + (size_t)n * W;
+    w.xc = w.cy + (size_t)n * H;
+    w.yc = w.xc + (size_t)n * W * kInvK;
+    w.xw = (float *)(w.yc + (size_t)n * H * kInvK);
+    w.yw = w.xw + (size_t)n * W * kInvK;
+    return w;
 }
 
-// adjoint of the grid step: ge += w * gy (scatter)
-__global__ void k_chain_f_grid_adj(const float *__restrict__ gy, int C, int H, int W, const int32_t *__restrict__ mapx,
-                                   const int32_t *__restrict__ mapy, float *__restrict__ ge) {
-    const size_t plane = (size_t)H * W;
-    const int im = blockIdx.y;
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= plane) return;
-    const int r = (int)(p / W), c0 = (int)(p % W);
-    int xs[2], ys[2];
-    float wx[2], wy[2];
-    taps_q(mapx[(size_t)im * W + c0], mapy[(size_t)im * H + r], H, W, xs, ys, wx, wy);
-    for (int c = 0; c < C; ++c) {
-        const float g = gy[((size_t)im * C + c) * plane + p];
-        float *gc = ge + ((size_t)im * C + c) * plane;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) atomicAdd(&gc[(size_t)ys[k >> 1] * W + xs[k & 1]], wy[k >> 1] * wx[k & 1] * g);
+__device__ __forceinline__ int reflect_fast(int i, int n) { return (unsigned)i < (unsigned)n ? i : reflect101(i, n); }
+
+// Inverse grid tables, step 1: output column c (row r) appends itself, with
+// the weight, to the entries of each source index its nonzero taps land on.
+// More than kInvK entries for one index (a map that folds many outputs onto
+// one source index) marks the image wide.
+__global__ void k_chain_inv(const int32_t *__restrict__ mapx, const int32_t *__restrict__ mapy, int H, int W,
+                            ChainWs w) {
+    const int im = blockIdx.y, t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = axis ? H : W;
+        if (t >= n) continue;
+        const int q = (axis ? mapy : mapx)[(size_t)im * n + t];
+        const int x0 = q >> kFBits, ax = q & (kFOne - 1);
+        const int js[2] = {reflect101(x0, n), reflect101(x0 + 1, n)};
+        const float ws[2] = {(float)(kFOne - ax) * (1.0f / kFOne), (float)ax * (1.0f / kFOne)};
+        int32_t *cnt = (axis ? w.cy : w.cx) + (size_t)im * n;
+        int32_t *oc = (axis ? w.yc : w.xc) + (size_t)im * n * kInvK;
+        float *ow = (axis ? w.yw : w.xw) + (size_t)im * n * kInvK;
+        for (int k = 0; k < 2; ++k) {
+            if (ws[k] == 0.0f) continue;
+            const int slot = atomicAdd(cnt + js[k], 1);
+            if (slot < kInvK) {
+                oc[(size_t)js[k] * kInvK + slot] = t;
+                ow[(size_t)js[k] * kInvK + slot] = ws[k];
+            } else {
+                w.wide[im] = 1;
+            }
+        }
     }
 }
 
-// adjoint of the elastic step: gx += w * ge (scatter)
-__global__ void k_chain_f_elastic_adj(const float *__restrict__ ge, int C, int H, int W,
-                                      const int32_t *__restrict__ off, float *__restrict__ gx) {
-    const size_t plane = (size_t)H * W;
-    const int im = blockIdx.y;
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= plane) return;
-    const int Y = (int)(p / W), X = (int)(p % W);
-    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
-    int xs[2], ys[2];
-    float wx[2], wy[2];
-    taps_q((X << kFBits) + ox[p], (Y << kFBits) + oy[p], H, W, xs, ys, wx, wy);
-    for (int c = 0; c < C; ++c) {
-        const float g = ge[((size_t)im * C + c) * plane + p];
-        float *gc = gx + ((size_t)im * C + c) * plane;
+// Step 2: each source index sorts its entries by output index (so sums run
+// in a fixed order) and pads the rest with weight 0.
+__global__ void k_chain_inv_sort(int H, int W, ChainWs w) {
+    const int im = blockIdx.y, t = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int axis = 0; axis < 2; ++axis) {
+        const int n = axis ? H : W;
+        if (t >= n) continue;
+        const size_t e = (size_t)im * n + t;
+        const int m = min((axis ? w.cy : w.cx)[e], kInvK);
+        int32_t *oc = (axis ? w.yc : w.xc) + e * kInvK;
+        float *ow = (axis ? w.yw : w.xw) + e * kInvK;
+        int c[kInvK];
+        float v[kInvK];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) atomicAdd(&gc[(size_t)ys[k >> 1] * W + xs[k & 1]], wy[k >> 1] * wx[k & 1] * g);
+        for (int k = 0; k < kInvK; ++k) {
+            c[k] = k < m ? oc[k] : INT_MAX;
+            v[k] = k < m ? ow[k] : 0.0f;
+        }
+#pragma unroll
+        for (int a = 1; a < kInvK; ++a)  // insertion sort as a fixed network of compare-exchanges
+#pragma unroll
+            for (int b = a; b > 0; --b)
+                if (c[b] < c[b - 1]) {
+                    const int tc = c[b];
+                    c[b] = c[b - 1];
+                    c[b - 1] = tc;
+                    const float tv = v[b];
+                    v[b] = v[b - 1];
+                    v[b - 1] = tv;
+                }
+#pragma unroll
+        for (int k = 0; k < kInvK; ++k) {
+            oc[k] = k < m ? c[k] : t;  // pads: weight 0 at a valid index
+            ow[k] = k < m ? v[k] : 0.0f;
+        }
+    }
+}
+
+// dL/de of one pixel of the grid step from the tables: sum over the entries
+// (r, wy) of row i and (c, wx) of column j of wy wx gy(r, c).
+__device__ __forceinline__ void ge_pixel_tab(const float *__restrict__ gy, int C, int H, int W, int im, int i, int j,
+                                             const ChainWs &w) {
+    const size_t plane = (size_t)H * W;
+    const size_t ey = ((size_t)im * H + i) * kInvK, ex = ((size_t)im * W + j) * kInvK;
+    for (int cb = 0; cb < C; cb += 4) {
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int a = 0; a < kInvK; ++a) {
+            const float wy = w.yw[ey + a];
+            if (wy == 0.0f) break;  // sorted: the pads come last
+            const int r = w.yc[ey + a];
+            for (int b = 0; b < kInvK; ++b) {
+                const float wx = w.xw[ex + b];
+                if (wx == 0.0f) break;
+                const float wt = wy * wx;
+                const float *g = gy + ((size_t)im * C + cb) * plane + (size_t)r * W + w.xc[ex + b];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (cb + k < C) acc[k] += wt * g[k * plane];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (cb + k < C) w.ge[((size_t)im * C + cb + k) * plane + (size_t)i * W + j] = acc[k];
+    }
+}
+
+// Folds the largest |offset| of a workgroup's pixels into dmax (integer max;
+// the atomic only when it raises the value, so the workgroups of an image do
+// not serialise on the one word).
+__device__ __forceinline__ void fold_dmax(int dm, int32_t *dmax, int *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = max(dm, __shfl_xor(dm, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int v = max(max(red[0], red[1]), max(red[2], red[3]));
+        if (v > __hip_atomic_load(dmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dmax, v);
+    }
+}
+
+// dL/de of the grid step, separable: one workgroup per 16 rows x 256 columns
+// of ge.  Pass x: for each output row r the tile's rows draw on (at most
+// kSepR of them, contiguous), t(r, j) = sum_k xw(j, k) gy(r, xc(j, k)) into
+// LDS; pass y: ge(i, j) = sum_k yw(i, k) t(yc(i, k), j).  One channel at a
+// time.  A tile whose rows draw on a wider span (a fold at a border) does
+// its pixels from the tables one by one; images marked wide are left to the
+// scatter form.  Also folds |offset| of its pixels into dmax.
+constexpr int kSepI = 16, kSepR = 32;
+
+__global__ __launch_bounds__(256) void k_chain_grid_adj_sep(const float *__restrict__ gy, int C, int H, int W,
+                                                            const int32_t *__restrict__ off, ChainWs w) {
+    __shared__ float tl[kSepR][256];
+    __shared__ int red[4], s_r0, s_r1;
+    const int im = blockIdx.z, I0 = blockIdx.y * kSepI, j = blockIdx.x * 256 + threadIdx.x;
+    const size_t plane = (size_t)H * W;
+    const int I1 = min(H, I0 + kSepI);
+    int dm = 0;
+    if (j < W)
+        for (int i = I0; i < I1; ++i) {
+            const int32_t *o = off + (size_t)im * 2 * plane + (size_t)i * W + j;
+            dm = max(dm, max(abs(o[0]), abs(o[plane])));
+        }
+    fold_dmax(dm, w.dmax + im, red);
+    if (w.wide[im]) return;
+    if (threadIdx.x < 64) {  // output rows the tile draws on (entries of weight != 0)
+        int lo = INT_MAX, hi = -1;
+        const int i = I0 + (threadIdx.x >> 2);
+        if (i < I1)
+            for (int k = (threadIdx.x & 3); k < kInvK; k += 4) {
+                const size_t e = ((size_t)im * H + i) * kInvK + k;
+                if (w.yw[e] != 0.0f) {
+                    lo = min(lo, w.yc[e]);
+                    hi = max(hi, w.yc[e]);
+                }
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+        }
+        if (threadIdx.x == 0) {
+            s_r0 = lo;
+            s_r1 = hi;
+        }
+    }
+    __syncthreads();
+    const int r0 = s_r0;
+    const long nr = (long)s_r1 - (long)s_r0 + 1;  // <= 0: no entries
+    if (nr > kSepR) {
+        if (j < W)
+            for (int i = I0; i < I1; ++i) ge_pixel_tab(gy, C, H, W, im, i, j, w);
+        return;
+    }
+    int xc[kInvK];
+    float xw[kInvK];
+#pragma unroll
+    for (int k = 0; k < kInvK; ++k) {
+        const size_t e = ((size_t)im * W + min(j, W - 1)) * kInvK + k;
+        xc[k] = w.xc[e];
+        xw[k] = j < W ? w.xw[e] : 0.0f;
+    }
+    for (int ch = 0; ch < C; ++ch) {
+        const float *g = gy + ((size_t)im * C + ch) * plane;
+        // pass x, four rows' loads in flight at a time
+        for (int q = 0; q < nr; q += 4) {
+            float v[4][kInvK];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < kInvK; ++k)
+                    v[u][k] = q + u < nr && xw[k] != 0.0f ? g[(size_t)(r0 + q + u) * W + xc[k]] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float t = 0.0f;
+#pragma unroll
+                for (int k = 0; k < kInvK; ++k)
+                    if (xw[k] != 0.0f) t += xw[k] * v[u][k];
+                if (q + u < nr) tl[q + u][threadIdx.x] = t;
+            }
+        }
+        __syncthreads();
+        // pass y
+        if (j < W)
+            for (int i = I0; i < I1; ++i) {
+                float a = 0.0f;
+#pragma unroll
+                for (int k = 0; k < kInvK; ++k) {
+                    const size_t e = ((size_t)im * H + i) * kInvK + k;
+                    const float yw = w.yw[e];
+                    if (yw != 0.0f) a += yw * tl[w.yc[e] - r0][threadIdx.x];
+                }
+                w.ge[((size_t)im * C + ch) * plane + (size_t)i * W + j] = a;
+            }
+        __syncthreads();
+    }
+}
+
+// Scatter form of dL/de for images marked wide: zero, then each gy element
+// adds its four weighted taps with float atomics (maps that fold more than
+// kInvK output indices onto one source index; grid distortions never do).
+__global__ void k_chain_ge_zero_wide(int C, int H, int W, ChainWs w) {
+    const int im = blockIdx.y;
+    if (!w.wide[im]) return;
+    const size_t total = (size_t)C * H * W;
+    float *g = w.ge + (size_t)im * total;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x)
+        g[e] = 0.0f;
+}
+
+__global__ void k_chain_grid_scatter_wide(const float *__restrict__ gy, int C, int H, int W,
+                                          const int32_t *__restrict__ mapx, const int32_t *__restrict__ mapy,
+                                          ChainWs w) {
+    const int im = blockIdx.y;
+    if (!w.wide[im]) return;
+    const size_t plane = (size_t)H * W;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < plane; p += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(p / W), c0 = (int)(p % W);
+        int xs[2], ys[2];
+        float wx[2], wy[2];
+        taps_q(mapx[(size_t)im * W + c0], mapy[(size_t)im * H + r], H, W, xs, ys, wx, wy);
+        for (int c = 0; c < C; ++c) {
+            const float g = gy[((size_t)im * C + c) * plane + p];
+            float *gc = w.ge + ((size_t)im * C + c) * plane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) atomicAdd(&gc[(size_t)ys[k >> 1] * W + xs[k & 1]], wy[k >> 1] * wx[k & 1] * g);
+        }
+    }
+}
+
+// dL/dx of the elastic step, owned per 64 x 32 source tile T: every output
+// pixel P whose four taps (reflect-101) can reach T lies within
+// m = ceil(dmax / 2^10) + 1 of T (or of T's mirror image at a border, which
+// the window clipped to the image already holds), so the workgroup scans
+// that window, accumulates w dL/de(P) of the taps inside T in LDS and stores
+// the tile once.  Channels in groups of four.
+constexpr int kAdjTX = 64, kAdjTY = 32;
+constexpr int kAdjU = 4;  // window elements per thread per round
+
+__global__ __launch_bounds__(256) void k_chain_elastic_adj(int C, int H, int W, const int32_t *__restrict__ off,
+                                                           ChainWs w, float *__restrict__ gx) {
+    __shared__ float acc[4][kAdjTY][kAdjTX + 1];
+    const int im = blockIdx.y;
+    const int tiles_x = (W + kAdjTX - 1) / kAdjTX;
+    const int X0 = (blockIdx.x % tiles_x) * kAdjTX, Y0 = (blockIdx.x / tiles_x) * kAdjTY;
+    const size_t plane = (size_t)H * W;
+    const int m = (int)min(((long)w.dmax[im] + kFOne - 1) >> kFBits, (long)(H + W)) + 1;
+    const int wx0 = max(0, X0 - m), wx1 = min(W - 1, X0 + kAdjTX - 1 + m);
+    const int wy0 = max(0, Y0 - m), wy1 = min(H - 1, Y0 + kAdjTY - 1 + m);
+    const int ww = wx1 - wx0 + 1, total = ww * (wy1 - wy0 + 1);
+    const int dq = 256 / ww, dr = 256 % ww;
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    for (int cb = 0; cb < C; cb += 4) {
+        for (int e = threadIdx.x; e < 4 * kAdjTY * (kAdjTX + 1); e += 256) (&acc[0][0][0])[e] = 0.0f;
+        __syncthreads();
+        // window element e = tid + 256 k -> row e / ww, column e mod ww, stepped
+        // incrementally; kAdjU elements per thread per round with their loads
+        // issued together
+        int row = threadIdx.x / ww, col = threadIdx.x % ww;
+        for (int base = 0; base < total; base += 256 * kAdjU) {
+            size_t pp[kAdjU];
+            int qx[kAdjU], qy[kAdjU];
+#pragma unroll
+            for (int u = 0; u < kAdjU; ++u) {
+                const bool ok = base + (int)threadIdx.x + 256 * u < total;
+                const int Y = wy0 + row, X = wx0 + col;
+                pp[u] = ok ? (size_t)Y * W + X : 0;
+                qx[u] = ok ? (X << kFBits) + ox[pp[u]] : INT_MIN;  // INT_MIN: no element
+                qy[u] = ok ? (Y << kFBits) + oy[pp[u]] : 0;
+                col += dr;
+                row += dq;
+                if (col >= ww) {
+                    col -= ww;
+                    ++row;
+                }
+            }
+            int xs[kAdjU][2], ys[kAdjU][2];
+            bool hit[kAdjU];
+#pragma unroll
+            for (int u = 0; u < kAdjU; ++u) {
+                const int x0 = qx[u] >> kFBits, y0 = qy[u] >> kFBits;
+                xs[u][0] = reflect_fast(x0, W) - X0;
+                xs[u][1] = reflect_fast(x0 + 1, W) - X0;
+                ys[u][0] = reflect_fast(y0, H) - Y0;
+                ys[u][1] = reflect_fast(y0 + 1, H) - Y0;
+                const bool inx = (unsigned)xs[u][0] < (unsigned)kAdjTX || (unsigned)xs[u][1] < (unsigned)kAdjTX;
+                const bool iny = (unsigned)ys[u][0] < (unsigned)kAdjTY || (unsigned)ys[u][1] < (unsigned)kAdjTY;
+                hit[u] = qx[u] != INT_MIN && inx && iny;
+            }
+            float g[kAdjU][4];
+#pragma unroll
+            for (int u = 0; u < kAdjU; ++u)
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    g[u][k] = hit[u] && cb + k < C ? w.ge[((size_t)im * C + cb + k) * plane + pp[u]] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < kAdjU; ++u) {
+                if (!hit[u]) continue;
+                const int ax = qx[u] & (kFOne - 1), ay = qy[u] & (kFOne - 1);
+                const float wx[2] = {(float)(kFOne - ax) * (1.0f / kFOne), (float)ax * (1.0f / kFOne)};
+                const float wy[2] = {(float)(kFOne - ay) * (1.0f / kFOne), (float)ay * (1.0f / kFOne)};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int tx = xs[u][t & 1], ty = ys[u][t >> 1];
+                    if ((unsigned)tx >= (unsigned)kAdjTX || (unsigned)ty >= (unsigned)kAdjTY) continue;
+                    const float wt = wy[t >> 1] * wx[t & 1];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (cb + k < C) atomicAdd(&acc[k][ty][tx], wt * g[u][k]);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kAdjTY * kAdjTX; e += 256) {
+            const int r = e / kAdjTX, c = e % kAdjTX;
+            if (Y0 + r >= H || X0 + c >= W) continue;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (cb + k < C) gx[((size_t)im * C + cb + k) * plane + (size_t)(Y0 + r) * W + X0 + c] = acc[k][r][c];
+        }
+        __syncthreads();
     }
 }
 
@@ -1166,7 +1490,10 @@ hipError_t launch_elastic_grid_u8(const uint8_t *img, const uint8_t *mask, int n
     return go(dim3(tiles, n), -1);
 }
 
-size_t chain_f32_workspace_bytes(int n, int C, int H, int W) { return (size_t)n * C * H * W * sizeof(float); }
+size_t chain_f32_workspace_bytes(int n, int C, int H, int W) {
+    return (size_t)n * C * H * W * sizeof(float) +
+           (2 * (size_t)n + (size_t)n * (W + H) * (1 + 2 * kInvK)) * sizeof(int32_t);
+}
 
 hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
                                 const int32_t *mapy, float *y, void *ws, hipStream_t s) {
@@ -1180,17 +1507,28 @@ hipError_t launch_chain_f32_fwd(const float *x, int n, int C, int H, int W, cons
     return hipGetLastError();
 }
 
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+
 hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, const int32_t *off, const int32_t *mapx,
                                 const int32_t *mapy, float *gx, void *ws, hipStream_t s) {
-    const size_t plane = (size_t)H * W, total = (size_t)n * C * plane;
-    const dim3 grid((unsigned)((plane + 255) / 256), n);
-    float *ge = (float *)ws;
-    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, ge, total);
-    hipLaunchKernelGGL(k_fill_zero, dim3(2048), dim3(256), 0, s, gx, total);
-    hipLaunchKernelGGL(k_chain_f_grid_adj, grid, dim3(256), 0, s, gy, C, H, W, mapx, mapy, ge);
-    hipError_t err = hipGetLastError();
+    const ChainWs w = chain_ws(ws, n, C, H, W);
+    // dmax, wide and the entry counts are contiguous: one zero fill
+    hipError_t err = launch_fill_u32((uint32_t *)w.dmax, 2 * (size_t)n + (size_t)n * (W + H), 0u, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_chain_f_elastic_adj, grid, dim3(256), 0, s, ge, C, H, W, off, gx);
+    const dim3 g1((unsigned)((max(H, W) + 255) / 256), n);
+    hipLaunchKernelGGL(k_chain_inv, g1, dim3(256), 0, s, mapx, mapy, H, W, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_inv_sort, g1, dim3(256), 0, s, H, W, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_grid_adj_sep, dim3((unsigned)((W + 255) / 256), (unsigned)((H + kSepI - 1) / kSepI), n),
+                       dim3(256), 0, s, gy, C, H, W, off, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_ge_zero_wide, dim3(1024, n), dim3(256), 0, s, C, H, W, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_chain_grid_scatter_wide, dim3(1024, n), dim3(256), 0, s, gy, C, H, W, mapx, mapy, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int tiles = ((W + kAdjTX - 1) / kAdjTX) * ((H + kAdjTY - 1) / kAdjTY);
+    hipLaunchKernelGGL(k_chain_elastic_adj, dim3(tiles, n), dim3(256), 0, s, C, H, W, off, w, gx);
     return hipGetLastError();
 }
 

@@ -114,6 +114,28 @@ def test_f32_chain_forward_and_adjoint(m):
         assert np.abs(gx[i] - gr).max() <= 1e-5 * np.abs(gr).max()
 
 
+def test_f32_adjoint_with_arbitrary_maps_and_far_offsets(m):
+    # maps that are not monotonic and reach outside the image, offsets beyond
+    # the image size (several reflect-101 folds), five channels (two channel
+    # groups): the owner-computes adjoint against the oracle's scatter
+    import torch
+    n, C, H, W = 2, 5, 37, 53
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0, 1, (n, C, H, W)).astype(np.float32)
+    o = rng.integers(-70 * 1024, 70 * 1024, (n, 2, H, W)).astype(np.int32)
+    mxx = rng.integers(-W * 1024, 2 * W * 1024, (n, W)).astype(np.int32)
+    myy = rng.integers(-H * 1024, 2 * H * 1024, (n, H)).astype(np.int32)
+    off, mx, my = (torch.from_numpy(a).cuda() for a in (o, mxx, myy))
+    y = m.elastic_grid_f32_fwd(torch.from_numpy(x).cuda(), off, mx, my).cpu().numpy()
+    gy = rng.uniform(-1, 1, (n, C, H, W)).astype(np.float32)
+    gx = m.elastic_grid_f32_bwd(torch.from_numpy(gy).cuda(), off, mx, my).cpu().numpy()
+    for i in range(n):
+        yr = oracle.chain_f_forward(x[i], o[i, 0], o[i, 1], mxx[i], myy[i])
+        assert np.abs(y[i] - yr).max() <= 1e-6
+        gr = oracle.chain_f_backward(gy[i].astype(np.float64), o[i, 0], o[i, 1], mxx[i], myy[i])
+        assert np.abs(gx[i] - gr).max() <= 1e-5 * np.abs(gr).max(), i
+
+
 def test_large_tile_sampled_pixels_against_the_definition(m):
     # one 4096 x 4096 image (sigma 50, alpha 1000, radius 150, 5x5 grid with limit 0.3):
     # sampled field values and output pixels recomputed by the oracle one by one
