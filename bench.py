@@ -568,6 +568,31 @@ def bench_elastic_f32(args, torch, m):
     return res
 
 
+def bench_stats(args, torch, m):
+    """Per-image statistics (sum, min, max, 256-bin histogram per channel) of 256
+    smooth-noise RGB 512x512 u8 images, buffers cycled over >= 1 GiB."""
+    import synth
+    n, S = 256, 512
+    img = synth.smooth_u8_hwc(1809068397, n, S, S, device="cuda")
+    alg = img.numel()
+    K = n_sets(alg)
+    imgs = [img] + [img.clone() for _ in range(K - 1)]
+    L = m.lib()
+    sm = torch.empty((n, 3), dtype=torch.int64, device="cuda")
+    mn = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    mx = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    h = torch.empty((n, 3, 256), dtype=torch.int32, device="cuda")
+
+    def fn(st, k):
+        m._check(L.miaug_image_stats_u8(m._p(imgs[k]), n, S * S, 3, m._p(sm), m._p(mn), m._p(mx), m._p(h),
+                                         m._stream(st)))
+    s = torch.cuda.Stream()
+    ms = time_rotating(torch, fn, K, args.steps, args.warmup, s)
+    return line("images/sec and HBM GB/s (% peak), per-image statistics", n, ms, args, "u8",
+                {"workload": "image_stats_256x512x512x3",
+                 "timing": "%d buffer copies (%.2f GB) cycled" % (K, K * alg / 1e9)}, hbm_roof(alg, ms, "k_stats"))
+
+
 def bench_copy(args, torch, m):
     """Plain device-to-device copy of 1 GiB: the reference for scaling the HBM
     byte counters (FETCH_SIZE, WRITE_SIZE) of the other kernels."""
@@ -669,7 +694,7 @@ def bench_table1(args, torch, m):
 
 
 WORKLOADS = {"table1": bench_table1, "copy": bench_copy, "ragged": bench_ragged, "d4bc": bench_d4bc, "c2": bench_c2, "wc": bench_wc, "elastic": bench_elastic,
-             "elastic_f32": bench_elastic_f32}
+             "elastic_f32": bench_elastic_f32, "stats": bench_stats}
 
 
 def main():

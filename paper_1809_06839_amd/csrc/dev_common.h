@@ -57,6 +57,19 @@ __device__ __forceinline__ uint32_t umad24(uint32_t a, uint32_t b, uint32_t c) {
     return d;
 }
 
+// Logical workgroup (x, y) of a 2-D grid (x fastest), remapped for L2
+// locality: the hardware deals consecutive workgroups to the 8 XCDs
+// round-robin, each XCD with its own L2, so the logical range is cut into 8
+// contiguous runs and XCD k takes run k; neighbouring logical workgroups (tiles
+// that share source rows) then meet in one L2.  A bijection on the grid.
+__device__ __forceinline__ int2 xcd_block() {
+    const int gx = gridDim.x, nb = gx * gridDim.y;
+    const int b = blockIdx.x + gx * blockIdx.y;
+    const int per = nb >> 3, rem = nb & 7, x = b & 7, k = b >> 3;
+    const int L = x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+    return make_int2(L % gx, L / gx);
+}
+
 // Buffer resource over [base, base + bytes) for raw buffer stores: 32-bit byte
 // offsets, stores outside the range are dropped by the hardware.  Word 3 is
 // the gfx9-family default descriptor (32-bit data, no swizzle).

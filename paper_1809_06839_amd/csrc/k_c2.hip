@@ -141,10 +141,11 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
     __shared__ int32_t box[6];                                 // bx, by, bw, bh, nch, staged
     __shared__ uint8_t lut[256];
 
-    const int img = blockIdx.y, tid = threadIdx.x;
+    const int2 lb = xcd_block();  // (output tile, image): an image's tiles share one XCD's L2
+    const int img = lb.y, tid = threadIdx.x;
     const miaug_c2_record &R = recs[img];
     const int tiles_x = (outsz + kT - 1) / kT;
-    const int y0 = (blockIdx.x / tiles_x) * kT, x0 = (blockIdx.x % tiles_x) * kT;
+    const int y0 = (lb.x / tiles_x) * kT, x0 = (lb.x % tiles_x) * kT;
     const int th = min(kT, outsz - y0), tw = min(kT, outsz - x0);
     const uint8_t *src = in + (size_t)img * H * W * 3;
     const int gh = 2 * (th + 2), gw = 2 * (tw + 2);

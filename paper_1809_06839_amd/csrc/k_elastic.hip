@@ -1228,9 +1228,10 @@ constexpr int kAdjU = 4;  // window elements per thread per round
 __global__ __launch_bounds__(256) void k_chain_elastic_adj(int C, int H, int W, const int32_t *__restrict__ off,
                                                            ChainWs w, float *__restrict__ gx) {
     __shared__ float acc[4][kAdjTY][kAdjTX + 1];
-    const int im = blockIdx.y;
+    const int2 lb = xcd_block();  // (source tile, image): an image's tiles share one XCD's L2
+    const int im = lb.y;
     const int tiles_x = (W + kAdjTX - 1) / kAdjTX;
-    const int X0 = (blockIdx.x % tiles_x) * kAdjTX, Y0 = (blockIdx.x / tiles_x) * kAdjTY;
+    const int X0 = (lb.x % tiles_x) * kAdjTX, Y0 = (lb.x / tiles_x) * kAdjTY;
     const size_t plane = (size_t)H * W;
     const int m = (int)min(((long)w.dmax[im] + kFOne - 1) >> kFBits, (long)(H + W)) + 1;
     const int wx0 = max(0, X0 - m), wx1 = min(W - 1, X0 + kAdjTX - 1 + m);

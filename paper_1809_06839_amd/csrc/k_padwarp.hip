@@ -141,9 +141,10 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
     __shared__ __align__(16) uint8_t box[kWarpStage];
     __shared__ int roff[kWarpRows];
     __shared__ __align__(4) uint8_t obuf[kWarpTile * kWarpTile * C];
-    const int img = blockIdx.y;
+    const int2 lb = xcd_block();  // (output tile, image): an image's tiles share one XCD's L2
+    const int img = lb.y;
     const int ntx = (W + kWarpTile - 1) / kWarpTile;
-    const int tx0 = (int)(blockIdx.x % ntx) * kWarpTile, ty0 = (int)(blockIdx.x / ntx) * kWarpTile;
+    const int tx0 = (lb.x % ntx) * kWarpTile, ty0 = (lb.x / ntx) * kWarpTile;
     const int tw = min(kWarpTile, W - tx0), th = min(kWarpTile, H - ty0);
     int64_t a[6];
 #pragma unroll

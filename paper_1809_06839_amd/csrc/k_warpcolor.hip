@@ -205,9 +205,9 @@ struct PixSet {
 };
 
 template <bool LDS>
-__device__ __forceinline__ void pix_set(const Geo &g, int H, int W, const Box &b, PixSet &ps) {
+__device__ __forceinline__ void pix_set(const Geo &g, int H, int W, int tile, const Box &b, PixSet &ps) {
     const int tiles_x = (W + kTile - 1) / kTile;
-    const int X0 = (blockIdx.x % tiles_x) * kTile, Y0 = (blockIdx.x / tiles_x) * kTile;
+    const int X0 = (tile % tiles_x) * kTile, Y0 = (tile / tiles_x) * kTile;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     ps.ox = X0 + (lane & 31);
     ps.oy0 = Y0 + 2 * wave + (lane >> 5);
@@ -247,10 +247,10 @@ __device__ __forceinline__ Quad quad_at(const PixSet &ps, int k, const float *bo
 }
 
 template <bool LDS>
-__device__ __forceinline__ void fwd_tile(const float *x, int img, int C, int H, int W, const float *p, const Geo &g,
-                                         const Box &b, const float *box, float *y) {
+__device__ __forceinline__ void fwd_tile(const float *x, int img, int tile, int C, int H, int W, const float *p,
+                                         const Geo &g, const Box &b, const float *box, float *y) {
     PixSet ps;
-    pix_set<LDS>(g, H, W, b, ps);
+    pix_set<LDS>(g, H, W, tile, b, ps);
     const float alpha = p[4], beta = p[5], gamma = p[6];
     for (int c = 0; c < C; ++c) {
         const size_t plane = (size_t)img * C + c;
@@ -268,12 +268,12 @@ __device__ __forceinline__ void fwd_tile(const float *x, int img, int C, int H, 
     }
 }
 
-// Geometry and source box of this workgroup's output tile, in LDS.
-__device__ __forceinline__ void tile_setup(const float *p, int C, int H, int W, Geo &sg, Box &sb) {
+// Geometry and source box of output tile `tile`, in LDS.
+__device__ __forceinline__ void tile_setup(const float *p, int tile, int C, int H, int W, Geo &sg, Box &sb) {
     if (threadIdx.x == 0) {
         const int tiles_x = (W + kTile - 1) / kTile;
         sg = make_geo(p, H, W);
-        sb = tile_box(sg, (blockIdx.x % tiles_x) * kTile, (blockIdx.x / tiles_x) * kTile, C);
+        sb = tile_box(sg, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, C);
     }
     __syncthreads();
 }
@@ -283,16 +283,17 @@ __global__ __launch_bounds__(kThreads) void k_wc_fwd(const float *__restrict__ x
     __shared__ float box[kBoxFloats];
     __shared__ Geo sg;
     __shared__ Box sb;
-    const int img = blockIdx.y;
+    const int2 lb = xcd_block();  // (output tile, image): an image's tiles share one XCD's L2
+    const int tile = lb.x, img = lb.y;
     const float *p = params + 7 * img;
-    tile_setup(p, C, H, W, sg, sb);
+    tile_setup(p, tile, C, H, W, sg, sb);
     const Box b = sb;
     if (b.w > 0) {
         stage_box(x, (size_t)img * C, C, H, W, b, box);
         __syncthreads();
-        fwd_tile<true>(x, img, C, H, W, p, sg, b, box, y);
+        fwd_tile<true>(x, img, tile, C, H, W, p, sg, b, box, y);
     } else {
-        fwd_tile<false>(x, img, C, H, W, p, sg, b, box, y);
+        fwd_tile<false>(x, img, tile, C, H, W, p, sg, b, box, y);
     }
 }
 
@@ -454,9 +455,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ float red[kThreads / 64][kRec];
     __shared__ Geo sg;
     __shared__ int s_r0, s_nrows, s_total;
-    const int img = blockIdx.y;
+    const int2 lb = xcd_block();  // (source tile, image): an image's tiles share one XCD's L2
+    const int tile = lb.x, img = lb.y;
     const int tiles_x = (W + kSrcTile - 1) / kSrcTile;
-    const int X0 = (blockIdx.x % tiles_x) * kSrcTile, Y0 = (blockIdx.x / tiles_x) * kSrcTile;
+    const int X0 = (tile % tiles_x) * kSrcTile, Y0 = (tile / tiles_x) * kSrcTile;
     const float *p = params + 7 * img;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     // 0. dL/dy summed over the output tile
@@ -713,7 +715,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         else if (t == 2) o = -(c * sum(2) + sn * sum(3)) * is * (float)W;  // tx
         else if (t == 3) o = (sn * sum(2) - c * sum(3)) * is * (float)H;   // ty
         else o = sum(t);                                                   // alpha, beta, gamma, dL/dy sums
-        rec[((size_t)img * gridDim.x + blockIdx.x) * kRec + t] = o;
+        rec[((size_t)img * gridDim.x + tile) * kRec + t] = o;
     }
 }
 

@@ -117,7 +117,8 @@ def test_f32_chain_forward_and_adjoint(m):
 def test_f32_adjoint_with_arbitrary_maps_and_far_offsets(m):
     # maps that are not monotonic and reach outside the image, offsets beyond
     # the image size (several reflect-101 folds), five channels (two channel
-    # groups): the owner-computes adjoint against the oracle's scatter
+    # groups), and in image 1 a column map that folds every output onto two
+    # source columns: the adjoint (table and scatter forms) against the oracle
     import torch
     n, C, H, W = 2, 5, 37, 53
     rng = np.random.default_rng(8)
@@ -125,6 +126,7 @@ def test_f32_adjoint_with_arbitrary_maps_and_far_offsets(m):
     o = rng.integers(-70 * 1024, 70 * 1024, (n, 2, H, W)).astype(np.int32)
     mxx = rng.integers(-W * 1024, 2 * W * 1024, (n, W)).astype(np.int32)
     myy = rng.integers(-H * 1024, 2 * H * 1024, (n, H)).astype(np.int32)
+    mxx[1] = 5 * 1024 + 512  # every output column samples x = 5.5: more than 8 outputs per source index (scatter form)
     off, mx, my = (torch.from_numpy(a).cuda() for a in (o, mxx, myy))
     y = m.elastic_grid_f32_fwd(torch.from_numpy(x).cuda(), off, mx, my).cpu().numpy()
     gy = rng.uniform(-1, 1, (n, C, H, W)).astype(np.float32)
