@@ -1148,6 +1148,13 @@ __global__ __launch_bounds__(256) void k_chain_grid_adj_sep(const float *__restr
         xc[k] = w.xc[e];
         xw[k] = j < W ? w.xw[e] : 0.0f;
     }
+    // entries are sorted with the weight-0 pads last: the wave needs only as many as its widest column
+    int kx = 0;
+#pragma unroll
+    for (int k = 0; k < kInvK; ++k) kx += xw[k] != 0.0f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) kx = max(kx, __shfl_xor(kx, o, 64));
+    kx = __builtin_amdgcn_readfirstlane(kx);
     for (int ch = 0; ch < C; ++ch) {
         const float *g = gy + ((size_t)im * C + ch) * plane;
         // pass x, four rows' loads in flight at a time
@@ -1157,7 +1164,7 @@ __global__ __launch_bounds__(256) void k_chain_grid_adj_sep(const float *__restr
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int k = 0; k < kInvK; ++k)
-                    v[u][k] = q + u < nr && xw[k] != 0.0f ? g[(size_t)(r0 + q + u) * W + xc[k]] : 0.0f;
+                    v[u][k] = k < kx && q + u < nr ? g[(size_t)(r0 + q + u) * W + xc[k]] : 0.0f;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 float t = 0.0f;
@@ -1172,11 +1179,11 @@ __global__ __launch_bounds__(256) void k_chain_grid_adj_sep(const float *__restr
         if (j < W)
             for (int i = I0; i < I1; ++i) {
                 float a = 0.0f;
-#pragma unroll
-                for (int k = 0; k < kInvK; ++k) {
+                for (int k = 0; k < kInvK; ++k) {  // row i is uniform: scalar loads, stop at the first pad
                     const size_t e = ((size_t)im * H + i) * kInvK + k;
                     const float yw = w.yw[e];
-                    if (yw != 0.0f) a += yw * tl[w.yc[e] - r0][threadIdx.x];
+                    if (yw == 0.0f) break;
+                    a += yw * tl[w.yc[e] - r0][threadIdx.x];
                 }
                 w.ge[((size_t)im * C + ch) * plane + (size_t)i * W + j] = a;
             }
@@ -1216,14 +1223,27 @@ __global__ void k_chain_grid_scatter_wide(const float *__restrict__ gy, int C, i
     }
 }
 
-// dL/dx of the elastic step, owned per 64 x 32 source tile T: every output
-// pixel P whose four taps (reflect-101) can reach T lies within
-// m = ceil(dmax / 2^10) + 1 of T (or of T's mirror image at a border, which
-// the window clipped to the image already holds), so the workgroup scans
-// that window, accumulates w dL/de(P) of the taps inside T in LDS and stores
-// the tile once.  Channels in groups of four.
+// dL/dx of the elastic step.  Every output pixel P whose four taps (reflect-
+// 101) reach a source tile T lies within m = ceil(dmax / 2^10) + 1 of T (or of
+// T's mirror image at a border, which the window clipped to the image already
+// holds).  A 32 x 32 tile is interior when it lies at least m + 2 from every
+// border: then no reflected tap reaches it and each contributor reaches it
+// through its own bilinear cell.  Interior tiles take the gather of
+// k_chain_elastic_gather; the others k_chain_elastic_adj, which owns a 64 x 32
+// tile, scans the window, sums w dL/de(P) of the taps inside it in LDS (float
+// adds) and stores the tile's pixels that no interior 32 x 32 tile owns.
+// Channels in groups of four.
 constexpr int kAdjTX = 64, kAdjTY = 32;
 constexpr int kAdjU = 4;  // window elements per thread per round
+constexpr int kEG = 32;   // tile of the gather form
+
+__device__ __forceinline__ int elastic_margin(const ChainWs &w, int im, int H, int W) {
+    return (int)min(((long)w.dmax[im] + kFOne - 1) >> kFBits, (long)(H + W)) + 1;
+}
+
+__device__ __forceinline__ bool interior_tile(int X0, int Y0, int m, int H, int W) {
+    return X0 >= m + 2 && X0 + kEG <= W - m - 2 && Y0 >= m + 2 && Y0 + kEG <= H - m - 2;
+}
 
 __global__ __launch_bounds__(256) void k_chain_elastic_adj(int C, int H, int W, const int32_t *__restrict__ off,
                                                            ChainWs w, float *__restrict__ gx) {
@@ -1233,7 +1253,9 @@ __global__ __launch_bounds__(256) void k_chain_elastic_adj(int C, int H, int W, 
     const int tiles_x = (W + kAdjTX - 1) / kAdjTX;
     const int X0 = (lb.x % tiles_x) * kAdjTX, Y0 = (lb.x / tiles_x) * kAdjTY;
     const size_t plane = (size_t)H * W;
-    const int m = (int)min(((long)w.dmax[im] + kFOne - 1) >> kFBits, (long)(H + W)) + 1;
+    const int m = elastic_margin(w, im, H, W);
+    const bool in0 = interior_tile(X0, Y0, m, H, W), in1 = interior_tile(X0 + kEG, Y0, m, H, W);
+    if (in0 && in1) return;  // both halves belong to the gather form
     const int wx0 = max(0, X0 - m), wx1 = min(W - 1, X0 + kAdjTX - 1 + m);
     const int wy0 = max(0, Y0 - m), wy1 = min(H - 1, Y0 + kAdjTY - 1 + m);
     const int ww = wx1 - wx0 + 1, total = ww * (wy1 - wy0 + 1);
@@ -1302,10 +1324,199 @@ __global__ __launch_bounds__(256) void k_chain_elastic_adj(int C, int H, int W, 
         __syncthreads();
         for (int e = threadIdx.x; e < kAdjTY * kAdjTX; e += 256) {
             const int r = e / kAdjTX, c = e % kAdjTX;
-            if (Y0 + r >= H || X0 + c >= W) continue;
+            if (Y0 + r >= H || X0 + c >= W || (c < kEG ? in0 : in1)) continue;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 if (cb + k < C) gx[((size_t)im * C + cb + k) * plane + (size_t)(Y0 + r) * W + X0 + c] = acc[k][r][c];
+        }
+        __syncthreads();
+    }
+}
+
+// Gather form for interior 32 x 32 tiles T: the window's output pixels whose
+// bilinear cell (x0, y0) lies in T's 33 x 33 cells [X0-1, X0+31] x [Y0-1, Y0+31]
+// are counted per cell (pass A), the counts scanned, and their dL/de values
+// and Q10 fractions stored in LDS sorted by cell (pass B, a second count per
+// cell giving each its slot); each source pixel then sums the entries of the
+// four cells that have it as a tap (two contiguous runs).  No float atomics:
+// one integer count per entry and pass.  A tile with more entries than the
+// pool takes the float-add form in LDS.
+constexpr int kEC = kEG + 1, kECN = kEC * kEC;
+constexpr int kEPool = 7168;  // words: kEPoolCap entries x (4 dL/de + packed fractions)
+constexpr int kEPoolCap = kEPool / 5;
+constexpr int kEScanPT = (kECN + 1 + 255) / 256;
+
+__device__ __forceinline__ int block_incl_scan_w(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_chain_elastic_gather(int C, int H, int W, const int32_t *__restrict__ off,
+                                                              ChainWs w, float *__restrict__ gx) {
+    __shared__ int cnt[kECN + 1], cnt2[kECN];
+    __shared__ float pool[kEPool];
+    __shared__ int wsum[4];
+    const int2 lb = xcd_block();
+    const int im = lb.y;
+    const int tiles_x = (W + kEG - 1) / kEG;
+    const int X0 = (lb.x % tiles_x) * kEG, Y0 = (lb.x / tiles_x) * kEG;
+    const int m = elastic_margin(w, im, H, W);
+    if (!interior_tile(X0, Y0, m, H, W)) return;
+    const size_t plane = (size_t)H * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wx0 = X0 - m, wx1 = X0 + kEG - 1 + m, wy0 = Y0 - m, wy1 = Y0 + kEG - 1 + m;  // inside the image
+    const int ww = wx1 - wx0 + 1, total = ww * (wy1 - wy0 + 1);
+    const int dq = 256 / ww, dr = 256 % ww;
+    const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
+    // cell index (-1: outside T's cells) and packed fractions of window element e
+    auto cell = [&](int Y, int X, int &frac) {
+        const size_t p = (size_t)Y * W + X;
+        const int qx = (X << kFBits) + ox[p], qy = (Y << kFBits) + oy[p];
+        const int cx = (qx >> kFBits) - (X0 - 1), cy = (qy >> kFBits) - (Y0 - 1);
+        frac = (qx & (kFOne - 1)) | (qy & (kFOne - 1)) << 16;
+        return ((unsigned)cx < (unsigned)kEC && (unsigned)cy < (unsigned)kEC) ? cy * kEC + cx : -1;
+    };
+    for (int cb = 0; cb < C; cb += 4) {
+        for (int i = threadIdx.x; i < kECN; i += 256) {
+            cnt[i] = 0;
+            cnt2[i] = 0;
+        }
+        __syncthreads();
+        // pass A: counts
+        {
+            int row = threadIdx.x / ww, col = threadIdx.x % ww;
+            for (int base = 0; base < total; base += 256 * kAdjU) {
+                int ci[kAdjU];
+#pragma unroll
+                for (int u = 0; u < kAdjU; ++u) {
+                    int fr;
+                    ci[u] = base + (int)threadIdx.x + 256 * u < total ? cell(wy0 + row, wx0 + col, fr) : -1;
+                    col += dr;
+                    row += dq;
+                    if (col >= ww) {
+                        col -= ww;
+                        ++row;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kAdjU; ++u)
+                    if (ci[u] >= 0) atomicAdd(&cnt[ci[u]], 1);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the counts (cnt[kECN] becomes the entry count)
+        {
+            int v[kEScanPT], sum = 0;
+#pragma unroll
+            for (int j = 0; j < kEScanPT; ++j) {
+                const int i = threadIdx.x * kEScanPT + j;
+                v[j] = i < kECN ? cnt[i] : 0;
+                sum += v[j];
+            }
+            const int inc = block_incl_scan_w(sum, lane);
+            if (lane == 63) wsum[wave] = inc;
+            __syncthreads();
+            int base = inc - sum;
+            for (int k = 0; k < wave; ++k) base += wsum[k];
+#pragma unroll
+            for (int j = 0; j < kEScanPT; ++j) {
+                const int i = threadIdx.x * kEScanPT + j;
+                if (i <= kECN) cnt[i] = base;
+                base += v[j];
+            }
+        }
+        __syncthreads();
+        const int entries = cnt[kECN];
+        float(*acc)[kEG][kEG + 1] = reinterpret_cast<float(*)[kEG][kEG + 1]>(pool);
+        const bool gather = entries <= kEPoolCap;
+        if (!gather) {
+            for (int e = threadIdx.x; e < 4 * kEG * (kEG + 1); e += 256) pool[e] = 0.0f;
+            __syncthreads();
+        }
+        // pass B: entries in cell order (or, past the pool, float adds into the tile)
+        {
+            int row = threadIdx.x / ww, col = threadIdx.x % ww;
+            for (int base = 0; base < total; base += 256 * kAdjU) {
+                int ci[kAdjU], fr[kAdjU];
+                size_t pp[kAdjU];
+#pragma unroll
+                for (int u = 0; u < kAdjU; ++u) {
+                    const int Y = wy0 + row, X = wx0 + col;
+                    pp[u] = (size_t)Y * W + X;
+                    ci[u] = base + (int)threadIdx.x + 256 * u < total ? cell(Y, X, fr[u]) : -1;
+                    col += dr;
+                    row += dq;
+                    if (col >= ww) {
+                        col -= ww;
+                        ++row;
+                    }
+                }
+                float g[kAdjU][4];
+#pragma unroll
+                for (int u = 0; u < kAdjU; ++u)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        g[u][k] = ci[u] >= 0 && cb + k < C ? w.ge[((size_t)im * C + cb + k) * plane + pp[u]] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < kAdjU; ++u) {
+                    if (ci[u] < 0) continue;
+                    if (gather) {
+                        const int pos = cnt[ci[u]] + atomicAdd(&cnt2[ci[u]], 1);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) pool[k * kEPoolCap + pos] = g[u][k];
+                        pool[4 * kEPoolCap + pos] = __int_as_float(fr[u]);
+                    } else {
+                        const int cx = ci[u] % kEC - 1, cy = ci[u] / kEC - 1;  // tap (0, 0) relative to T
+                        const int ax = fr[u] & 0xffff, ay = fr[u] >> 16;
+                        const float wxs[2] = {(float)(kFOne - ax) * (1.0f / kFOne), (float)ax * (1.0f / kFOne)};
+                        const float wys[2] = {(float)(kFOne - ay) * (1.0f / kFOne), (float)ay * (1.0f / kFOne)};
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int tx = cx + (t & 1), ty = cy + (t >> 1);
+                            if ((unsigned)tx >= (unsigned)kEG || (unsigned)ty >= (unsigned)kEG) continue;
+                            const float wt = wys[t >> 1] * wxs[t & 1];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k)
+                                if (cb + k < C) atomicAdd(&acc[k][ty][tx], wt * g[u][k]);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // every source pixel of T: the entries of its four cells, or the summed tile
+#pragma unroll
+        for (int j = 0; j < kEG * kEG / 256; ++j) {
+            const int e = threadIdx.x + j * 256;
+            const int lu = e % kEG, lv = e / kEG;
+            float sum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (gather) {
+#pragma unroll
+                for (int dy = 0; dy < 2; ++dy) {
+                    // cell row lv + dy has corner y0 = v - 1 + dy: the pixel is its tap row 1 - dy
+                    const int ci = (lv + dy) * kEC + lu;
+                    const int a0 = cnt[ci], mid = cnt[ci + 1], b0 = cnt[ci + 2];
+                    for (int q = a0; q < b0; ++q) {
+                        const int fr = __float_as_int(pool[4 * kEPoolCap + q]);
+                        const int ax = fr & 0xffff, ay = fr >> 16;
+                        const float wx = (float)(q < mid ? ax : kFOne - ax) * (1.0f / kFOne);  // left cell: x0 = u - 1
+                        const float wy = (float)(dy == 0 ? ay : kFOne - ay) * (1.0f / kFOne);
+                        const float wt = wy * wx;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) sum[k] += wt * pool[k * kEPoolCap + q];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) sum[k] = acc[k][lv][lu];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (cb + k < C) gx[((size_t)im * C + cb + k) * plane + (size_t)(Y0 + lv) * W + X0 + lu] = sum[k];
         }
         __syncthreads();
     }
@@ -1530,6 +1741,9 @@ hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, con
     if ((err = hipGetLastError()) != hipSuccess) return err;
     const int tiles = ((W + kAdjTX - 1) / kAdjTX) * ((H + kAdjTY - 1) / kAdjTY);
     hipLaunchKernelGGL(k_chain_elastic_adj, dim3(tiles, n), dim3(256), 0, s, C, H, W, off, w, gx);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int gtiles = ((W + kEG - 1) / kEG) * ((H + kEG - 1) / kEG);
+    hipLaunchKernelGGL(k_chain_elastic_gather, dim3(gtiles, n), dim3(256), 0, s, C, H, W, off, w, gx);
     return hipGetLastError();
 }
 
