@@ -345,11 +345,9 @@ __device__ __forceinline__ int2 row_span(const Geo &g, const RowMap &m, int oy, 
 
 // Per-thread sums for the parameter gradients over the pixels a workgroup
 // owns: v = {sum (g_sy rx - g_sx ry), sum (g_sx rx + g_sy ry), sum g_sx,
-// sum g_sy, dL/dalpha, dL/dbeta, dL/dgamma}, (rx, ry) = (sx - cx, sy - cy);
-// own[c] = sum of dL/dy over the owned pixels, channel c.
+// sum g_sy, dL/dalpha, dL/dbeta, dL/dgamma}, (rx, ry) = (sx - cx, sy - cy).
 struct ParAcc {
     float v[7];
-    float own[kMaxC];
 };
 
 // One output pixel of the region: dL/dw per channel into gw and, when the
@@ -373,7 +371,6 @@ __device__ __forceinline__ void pixel_adjoint(int C, float fx, float fy, float r
         const float w = bilerp(q, fx, fy);
         const float z = alpha * w + beta;
         const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
-        if (owned) a.own[c] += gv;
         if (y1 > 0.0f) {
             const float l2 = __builtin_amdgcn_logf(y1);
             const float yv = pow_pos(y1, gamma, l2);
@@ -421,7 +418,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // The backward, one workgroup per 32 x 32 source tile T at (X0, Y0):
-//   0. the sum of dL/dy over the output tile at (X0, Y0) (the same grid);
+//   0. the sum of dL/dy over the pixels of the output tile at (X0, Y0) (the
+//      same grid) whose cell lies wholly outside the image;
 //   1. the region -- output pixels whose bilinear cell has a tap in T, i.e.
 //      cell corner in [X0-1, X0+31] x [Y0-1, Y0+31] -- row by row from the
 //      affine map, flattened over the workgroup;
@@ -436,9 +434,9 @@ __device__ __forceinline__ float wave_sum(float v) {
 //      the sorted order).  Every grad_x element has one writer: no global
 //      atomics, no zero-fill, no dL/dw buffer.
 // Output pixels whose cell has no tap in the image (w = 0, z = beta) belong
-// to no tile; their share of dL/dbeta and dL/dgamma depends only on the sum
-// of their dL/dy, which the record carries as (sum over the output tile) -
-// (sum over the owned pixels) and k_wc_reduce applies.
+// to no source tile; their share of dL/dbeta and dL/dgamma depends only on
+// the sum of their dL/dy, which step 0 forms over the output tile at the
+// same grid position, the record carries, and k_wc_reduce applies.
 // A region larger than the LDS pool (scale well above 1) takes its taps from
 // global memory and scatters into an LDS accumulator with float atomics.
 // With gx NULL only the parameter gradients are formed.
@@ -461,17 +459,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const int X0 = (tile % tiles_x) * kSrcTile, Y0 = (tile / tiles_x) * kSrcTile;
     const float *p = params + 7 * img;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // 0. dL/dy summed over the output tile
-    float s_all[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int j = 0; j < kSrcTile * kSrcTile / kThreads; ++j) {
-        const int e = threadIdx.x + j * kThreads;
-        const int u = X0 + (e & (kSrcTile - 1)), v = Y0 + e / kSrcTile;
-        const uint32_t o = (u < W && v < H) ? ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u : kOOB;
-#pragma unroll
-        for (int c = 0; c < kMaxC; ++c)
-            if (c < C) s_all[c] += ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), o);
-    }
     if (threadIdx.x == 0) {
         const Geo g = make_geo(p, H, W);
         sg = g;
@@ -495,6 +482,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const Geo &g = sg;
     const RowMap rm = row_map(g);
     const int r0 = s_r0, nrows = s_nrows;
+    // 0. dL/dy summed over the pixels of the output tile at the same grid
+    // position whose bilinear cell lies wholly outside the image (most tiles
+    // have none, and their loads are skipped)
+    float s_off[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < kSrcTile * kSrcTile / kThreads; ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        const int u = X0 + (e & (kSrcTile - 1)), v = Y0 + e / kSrcTile;
+        double sx, sy;
+        sample_pos(g, u, v, sx, sy);
+        const double fx0 = floor(sx), fy0 = floor(sy);
+        const bool outside = fx0 < -1.0 || fx0 > (double)(W - 1) || fy0 < -1.0 || fy0 > (double)(H - 1);
+        if (u < W && v < H && outside) {
+            const uint32_t o = ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u;
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c)
+                if (c < C) s_off[c] += ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), o);
+        }
+    }
     const double tx0 = (double)(X0 - 1), tx1 = (double)(X0 + kSrcTile);
     const double ty0 = (double)(Y0 - 1), ty1 = (double)(Y0 + kSrcTile);
     if (wave == 0) {
@@ -520,8 +526,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     ParAcc acc;
 #pragma unroll
     for (int k = 0; k < 7; ++k) acc.v[k] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < kMaxC; ++c) acc.own[c] = 0.0f;
     if (total <= cap) {
         constexpr int kXT = kCells + 1;
         stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT}, pool);
@@ -693,14 +697,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             }
     }
     // the workgroup's record: parameter partials, and per channel the dL/dy sum
-    // of the output tile minus that of the owned pixels
+    // of its output tile's pixels whose cell lies outside the image
 #pragma unroll
     for (int k = 0; k < kRec; ++k) {
         float v = 0.0f;
         if (k < 7) v = acc.v[k];
 #pragma unroll
         for (int c = 0; c < kMaxC; ++c)
-            if (k == 7 + c) v = s_all[c] - acc.own[c];
+            if (k == 7 + c) v = s_off[c];
         const float t = wave_sum(v);
         if (lane == 0) red[wave][k] = t;
     }
