@@ -249,24 +249,48 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
     }
     __syncthreads();
 
-    // output rows: blur (or copy) from the pre-blur tile, aligned dword stores
+    // blur (or copy) per output pixel into LDS, all three channels at once: a
+    // pre-blur word c0 | c1 << 8 | c2 << 16 splits into c0 | c2 << 16 and c1,
+    // whose 16-bit lanes take the 3x3 binomial sums (at most 16 x 255) and the
+    // round-half-even shift without carrying into each other
     const bool blur = R.blur != 0;
+    uint8_t *ob = stage;  // the staged source is no longer read
+    for (int e = tid; e < th * tw; e += kThreads) {
+        const int r = e / tw, px = e - r * tw;
+        uint32_t v;
+        if (blur) {
+            uint32_t slo = 0, shi = 0;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const uint32_t *q = &pre[r + dy][px];
+                const uint32_t lo = (q[0] & 0x00FF00FFu) + 2 * (q[1] & 0x00FF00FFu) + (q[2] & 0x00FF00FFu);
+                const uint32_t hi = ((q[0] >> 8) & 0xFFu) + 2 * ((q[1] >> 8) & 0xFFu) + ((q[2] >> 8) & 0xFFu);
+                const uint32_t w = dy == 1 ? 2u : 1u;
+                slo += w * lo;
+                shi += w * hi;
+            }
+            slo = ((slo + 0x00070007u + ((slo >> 4) & 0x00010001u)) >> 4) & 0x00FF00FFu;
+            shi = ((shi + 7u + ((shi >> 4) & 1u)) >> 4) & 0xFFu;
+            v = slo | shi << 8;
+        } else {
+            v = pre[r + 1][px + 1];
+        }
+        uint8_t *o = ob + r * (kT * 3) + 3 * px;
+        o[0] = (uint8_t)v;
+        o[1] = (uint8_t)(v >> 8);
+        o[2] = (uint8_t)(v >> 16);
+    }
+    __syncthreads();
+
+    // output rows from LDS, aligned dword stores
     constexpr int kItems = (kT * 3) / 4 + 8;
     for (int it = tid; it < th * kItems; it += kThreads) {
         const int r = it / kItems, j = it - r * kItems;
         uint8_t *g = out + ((size_t)img * outsz * outsz + (size_t)(y0 + r) * outsz + x0) * 3;
         const int len = tw * 3;
         if (j >= span_items(g, len)) continue;
-        auto byte_at = [&](int b) -> uint8_t {
-            const int px = b / 3, c = b - 3 * px, sh = 8 * c;
-            if (!blur) return (uint8_t)(pre[r + 1][px + 1] >> sh);
-            const uint32_t *u = &pre[r][px], *m = &pre[r + 1][px], *d = &pre[r + 2][px];
-            const int s = (int)((u[0] >> sh) & 255) + 2 * (int)((u[1] >> sh) & 255) + (int)((u[2] >> sh) & 255) +
-                          2 * ((int)((m[0] >> sh) & 255) + 2 * (int)((m[1] >> sh) & 255) + (int)((m[2] >> sh) & 255)) +
-                          (int)((d[0] >> sh) & 255) + 2 * (int)((d[1] >> sh) & 255) + (int)((d[2] >> sh) & 255);
-            return (uint8_t)((s + 7 + ((s >> 4) & 1)) >> 4);
-        };
-        store_span_item(g, len, j, byte_at);
+        const uint8_t *orow = ob + r * (kT * 3);
+        store_span_item(g, len, j, [&](int b) -> uint8_t { return orow[b]; });
     }
 }
 
