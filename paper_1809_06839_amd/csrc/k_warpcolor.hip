@@ -61,9 +61,7 @@ struct Geo {
 
 __device__ __forceinline__ Geo make_geo(const float *p, int H, int W) {
     Geo g;
-    const double th = (double)p[0] * (3.14159265358979323846 / 180.0);
-    g.c = cos(th);
-    g.s_ = sin(th);
+    sincospi((double)p[0] / 180.0, &g.s_, &g.c);  // the angle is in degrees: no reduction by pi needed
     g.scale = (double)p[1];
     g.inv_s = 1.0 / g.scale;
     g.cx = 0.5 * (double)(W - 1);
