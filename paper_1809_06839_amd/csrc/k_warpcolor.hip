@@ -132,18 +132,22 @@ __device__ __forceinline__ float pow_pos(float y1, float gamma, float l2) {
     return gamma == 1.0f ? y1 : __builtin_amdgcn_exp2f(gamma * l2);
 }
 
-constexpr int kBoxFloats = 9216;  // 36 KB of LDS: the source footprint of an output tile, all channels
+constexpr int kSlotFloats = 3072;  // 12 KB of LDS: one channel of the source footprint of an output tile
 
-// Source box staged in LDS: [c][h][w] floats from (x0, y0); w = 0 when the
-// footprint does not fit (the per-pixel kernels then gather from global memory).
+// Source box staged in LDS: [h][w] floats per channel from (x0, y0); w = 0
+// when the footprint does not fit (the forward then gathers from global memory).
+// v4: x0 and w are multiples of 4 and the rows are staged as 16-byte chunks
+// (planes 16-byte aligned, W a multiple of 4, so a chunk never straddles the
+// image's edge).
 struct Box {
-    int x0, y0, w, h;
+    int x0, y0, w, h, v4;
 };
 
 // Footprint of the 32 x 32 output tile at (X0, Y0): the cells of its sample
 // points, their +1 taps and one pixel of margin on each side for the rounding
-// of the stepped per-pixel positions.
-__device__ __forceinline__ Box tile_box(const Geo &g, int X0, int Y0, int C) {
+// of the stepped per-pixel positions.  With al, widened to whole 16-byte
+// chunks when that still fits.
+__device__ __forceinline__ Box tile_box(const Geo &g, int X0, int Y0, bool al) {
     double xl = 1e300, xh = -1e300, yl = 1e300, yh = -1e300;
     for (int k = 0; k < 4; ++k) {
         double sx, sy;
@@ -153,33 +157,54 @@ __device__ __forceinline__ Box tile_box(const Geo &g, int X0, int Y0, int C) {
         yl = fmin(yl, sy);
         yh = fmax(yh, sy);
     }
-    Box b{0, 0, 0, 0};
+    Box b{0, 0, 0, 0, 0};
     const double x0 = floor(xl) - 1.0, y0 = floor(yl) - 1.0;
     const double w = floor(xh) + 3.0 - x0, h = floor(yh) + 3.0 - y0;
-    if (!(fabs(x0) < 1e9 && fabs(y0) < 1e9 && w <= 64.0 && w * h * C <= (double)kBoxFloats)) return b;
+    if (!(fabs(x0) < 1e9 && fabs(y0) < 1e9 && w <= 64.0 && w * h <= (double)kSlotFloats)) return b;
     b.x0 = (int)x0;
     b.y0 = (int)y0;
     b.w = (int)w;
     b.h = (int)h;
+    if (al) {
+        const int xa = (b.x0 >> 2) << 2, wa = (((b.x0 + b.w + 3) >> 2) << 2) - xa;  // floor / ceil to 4
+        if (wa <= 64 && wa * b.h <= kSlotFloats) {
+            b.x0 = xa;
+            b.w = wa;
+            b.v4 = 1;
+        }
+    }
     return b;
 }
 
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
-// Stages box b of planes plane0 .. plane0 + C - 1 of x into lds ([c][h][w])
-// through LDS-DMA (buffer loads that write LDS directly, so a wave has every
-// row of its share in flight at once); pixels outside the image are 0.  Wave
-// w takes rows w, w + 4, ..., lane i column i of the row; a row or column
-// outside the image loads through an offset past the end of the plane.
-// Returns after this wave's rows have landed; the caller's barrier publishes them.
-__device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, int H, int W, const Box &b,
-                                          float *lds) {
+// Stages box b of plane `plane` of x into lds ([h][w]) through LDS-DMA
+// (buffer loads that write LDS directly, so a wave has every row of its share
+// in flight at once); pixels outside the image are 0.  A row or column
+// outside the image loads through an offset past the end of the plane.  A v4
+// box moves 16 bytes per lane: one instruction covers 64 / (w / 4) whole rows
+// (the LDS destination of lane i is 16 i bytes on, so rows land w floats
+// apart), waves taking consecutive groups of rows in turn.  Otherwise 4 bytes
+// per lane: wave w takes rows w, w + 4, ..., lane i column i of the row.  The
+// wave issues stage_count(b) instructions and does not wait for them.
+__device__ __forceinline__ void stage_plane(const float *x, size_t plane, int H, int W, const Box &b, float *dst) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int col = b.x0 + lane;
-    const uint32_t voff = (col >= 0 && col < W) ? (uint32_t)col * 4u : kOOB;
-    for (int c = 0; c < C; ++c) {
-        const __amdgpu_buffer_rsrc_t r = plane_rsrc(x, plane0 + c, H, W);
-        float *dst = lds + c * b.h * b.w;
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(x, plane, H, W);
+    if (b.v4) {
+        const int lpr = b.w >> 2, rpi = 64 / lpr;  // lanes per row, rows per instruction
+        const int rl = lane / lpr, col = b.x0 + 4 * (lane - rl * lpr);
+        const bool cok = col >= 0 && col < W && rl < rpi;
+        for (int r0 = wave * rpi; r0 < b.h; r0 += (kThreads / 64) * rpi) {
+            const int row = r0 + rl, sy = b.y0 + row;
+            const bool ok = cok && sy >= 0 && sy < H;
+            if (rl < rpi && row < b.h)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr_t)(dst + r0 * b.w), 16,
+                                                         ok ? ((uint32_t)sy * (uint32_t)W + (uint32_t)col) * 4u : kOOB,
+                                                         0, 0, 0);
+        }
+    } else {
+        const int col = b.x0 + lane;
+        const uint32_t voff = (col >= 0 && col < W) ? (uint32_t)col * 4u : kOOB;
         for (int row = wave; row < b.h; row += kThreads / 64) {
             const int sy = b.y0 + row;
             const bool ok = sy >= 0 && sy < H;
@@ -188,6 +213,39 @@ __device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, 
                                                          ok ? sy * W * 4 : 0, 0, 0);
         }
     }
+}
+
+// Instructions stage_plane issues in this wave (uniform).
+__device__ __forceinline__ int stage_count(const Box &b) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int step = b.v4 ? 64 / (b.w >> 2) : 1, first = wave * step, stride = (kThreads / 64) * step;
+    return b.h > first ? (b.h - first + stride - 1) / stride : 0;
+}
+
+// Waits until at most n (uniform) of this wave's vector memory instructions
+// are outstanding (n rounded down to a bucket: waiting for fewer is safe).
+// Vector memory instructions complete in issue order, so the ones issued
+// before the last n have then completed.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+__device__ __forceinline__ void wait_vm_at_most(int n) {
+    if (n >= 48) wait_vm<48>();
+    else if (n >= 32) wait_vm<32>();
+    else if (n >= 24) wait_vm<24>();
+    else if (n >= 16) wait_vm<16>();
+    else if (n >= 12) wait_vm<12>();
+    else if (n >= 8) wait_vm<8>();
+    else if (n >= 4) wait_vm<4>();
+    else wait_vm<0>();
+}
+
+// Every channel of box b ([c][h][w]); returns after this wave's rows have
+// landed, the caller's barrier publishes them.
+__device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, int H, int W, const Box &b,
+                                          float *lds) {
+    for (int c = 0; c < C; ++c) stage_plane(x, plane0 + c, H, W, b, lds + c * b.h * b.w);
     __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
 }
 
@@ -234,64 +292,129 @@ __device__ __forceinline__ void pix_set(const Geo &g, int H, int W, int tile, co
     }
 }
 
-template <bool LDS>
-__device__ __forceinline__ Quad quad_at(const PixSet &ps, int k, const float *box, int bw,
-                                        __amdgpu_buffer_rsrc_t xr) {
-    if (LDS) {
-        const float *q = box + ps.bi[k];
-        return Quad{q[0], q[1], q[bw], q[bw + 1]};
+// Channel c of this thread's four pixels from taps q, written to y.
+__device__ __forceinline__ void fwd_store(float *y, size_t plane, int H, int W, const PixSet &ps, const Quad (&q)[kPix],
+                                          float alpha, float beta, float gamma) {
+    const __amdgpu_buffer_rsrc_t yr = plane_rsrc(y, plane, H, W);
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) {
+        const float w = bilerp(q[k], ps.fx[k], ps.fy[k]);
+        const float z = alpha * w + beta;
+        const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
+        stf(yr, ps.off[k], y1 > 0.0f ? pow_pos(y1, gamma, __builtin_amdgcn_logf(y1)) : 0.0f);
     }
-    return load_quad(xr, ps.t[k]);
 }
 
-template <bool LDS>
-__device__ __forceinline__ void fwd_tile(const float *x, int img, int tile, int C, int H, int W, const float *p,
-                                         const Geo &g, const Box &b, const float *box, float *y) {
+// One channel from a staged slot: the four taps of each pixel from LDS, kPix
+// stores.  The LDS reads sit in one asm block that waits for them itself: the
+// compiler cannot tell this slot's DMA from the other slot's (their issue
+// counts are data-dependent), and would otherwise wait for every DMA in
+// flight before the first read.
+__device__ __forceinline__ void fwd_slot(float *y, size_t plane, int H, int W, const PixSet &ps, const Box &b,
+                                         const float *slot, float alpha, float beta, float gamma) {
+    static_assert(kPix == 4, "one asm block reads the taps of four pixels");
+    uint32_t a[kPix], u[kPix];
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) {
+        a[k] = (uint32_t)(uintptr_t)(lds_ptr_t)(slot + ps.bi[k]);
+        u[k] = a[k] + 4u * (uint32_t)b.w;
+    }
+    float2 r0, r1, r2, r3, r4, r5, r6, r7;
+    asm volatile(
+        "ds_read2_b32 %0, %8 offset1:1\n\t"
+        "ds_read2_b32 %1, %9 offset1:1\n\t"
+        "ds_read2_b32 %2, %10 offset1:1\n\t"
+        "ds_read2_b32 %3, %11 offset1:1\n\t"
+        "ds_read2_b32 %4, %12 offset1:1\n\t"
+        "ds_read2_b32 %5, %13 offset1:1\n\t"
+        "ds_read2_b32 %6, %14 offset1:1\n\t"
+        "ds_read2_b32 %7, %15 offset1:1\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3), "=&v"(r4), "=&v"(r5), "=&v"(r6), "=&v"(r7)
+        : "v"(a[0]), "v"(u[0]), "v"(a[1]), "v"(u[1]), "v"(a[2]), "v"(u[2]), "v"(a[3]), "v"(u[3])
+        : "memory");
+    const Quad q[kPix] = {Quad{r0.x, r0.y, r1.x, r1.y}, Quad{r2.x, r2.y, r3.x, r3.y}, Quad{r4.x, r4.y, r5.x, r5.y},
+                          Quad{r6.x, r6.y, r7.x, r7.y}};
+    fwd_store(y, plane, H, W, ps, q, alpha, beta, gamma);
+}
+
+// Footprint too large for a slot: taps gathered from global memory.
+__device__ __forceinline__ void fwd_tile_global(const float *x, int img, int tile, int C, int H, int W, const float *p,
+                                                const Geo &g, float *y) {
     PixSet ps;
-    pix_set<LDS>(g, H, W, tile, b, ps);
+    pix_set<false>(g, H, W, tile, Box{0, 0, 0, 0, 0}, ps);
     const float alpha = p[4], beta = p[5], gamma = p[6];
     for (int c = 0; c < C; ++c) {
         const size_t plane = (size_t)img * C + c;
-        const __amdgpu_buffer_rsrc_t xr = plane_rsrc(x, plane, H, W), yr = plane_rsrc(y, plane, H, W);
+        const __amdgpu_buffer_rsrc_t xr = plane_rsrc(x, plane, H, W);
         Quad q[kPix];
 #pragma unroll
-        for (int k = 0; k < kPix; ++k) q[k] = quad_at<LDS>(ps, k, box + c * b.h * b.w, b.w, xr);
-#pragma unroll
-        for (int k = 0; k < kPix; ++k) {
-            const float w = bilerp(q[k], ps.fx[k], ps.fy[k]);
-            const float z = alpha * w + beta;
-            const float y1 = fminf(fmaxf(z, 0.0f), 1.0f);
-            stf(yr, ps.off[k], y1 > 0.0f ? pow_pos(y1, gamma, __builtin_amdgcn_logf(y1)) : 0.0f);
-        }
+        for (int k = 0; k < kPix; ++k) q[k] = load_quad(xr, ps.t[k]);
+        fwd_store(y, plane, H, W, ps, q, alpha, beta, gamma);
     }
 }
 
 // Geometry and source box of output tile `tile`, in LDS.
-__device__ __forceinline__ void tile_setup(const float *p, int tile, int C, int H, int W, Geo &sg, Box &sb) {
+__device__ __forceinline__ void tile_setup(const float *p, int tile, int H, int W, bool al, Geo &sg, Box &sb) {
     if (threadIdx.x == 0) {
         const int tiles_x = (W + kTile - 1) / kTile;
         sg = make_geo(p, H, W);
-        sb = tile_box(sg, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, C);
+        sb = tile_box(sg, (tile % tiles_x) * kTile, (tile / tiles_x) * kTile, al);
     }
     __syncthreads();
 }
 
+// Workgroup barrier without a memory fence (a fence would wait for every
+// LDS-DMA in flight): the callers have waited for their own DMA, and for their
+// LDS reads, themselves.  The memory clobber keeps the compiler from moving
+// memory operations across it.
+__device__ __forceinline__ void bare_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// Channels go through two LDS slots in turn: channel c + 1 (and, once its
+// slot is free, c + 2) is in flight while channel c is blended and stored.
+// The wait before channel c's blend lets the instructions issued after its
+// DMA stay outstanding: the stores of channel c - 1 (kPix per thread) and the
+// DMA of channel c + 1.  Two separate LDS arrays keep the compiler from
+// waiting on the other slot's DMA when it reads one.
 __global__ __launch_bounds__(kThreads) void k_wc_fwd(const float *__restrict__ x, int C, int H, int W,
                                                      const float *__restrict__ params, float *__restrict__ y) {
-    __shared__ float box[kBoxFloats];
+    __shared__ float slot0[kSlotFloats];
+    __shared__ float slot1[kSlotFloats];
     __shared__ Geo sg;
     __shared__ Box sb;
     const int2 lb = xcd_block();  // (output tile, image): an image's tiles share one XCD's L2
     const int tile = lb.x, img = lb.y;
     const float *p = params + 7 * img;
-    tile_setup(p, tile, C, H, W, sg, sb);
+    tile_setup(p, tile, H, W, (((uintptr_t)x & 15) | (W & 3)) == 0, sg, sb);
     const Box b = sb;
-    if (b.w > 0) {
-        stage_box(x, (size_t)img * C, C, H, W, b, box);
-        __syncthreads();
-        fwd_tile<true>(x, img, tile, C, H, W, p, sg, b, box, y);
-    } else {
-        fwd_tile<false>(x, img, tile, C, H, W, p, sg, b, box, y);
+    if (b.w == 0) {
+        fwd_tile_global(x, img, tile, C, H, W, p, sg, y);
+        return;
+    }
+    const size_t pl0 = (size_t)img * C;
+    stage_plane(x, pl0, H, W, b, slot0);
+    if (C > 1) stage_plane(x, pl0 + 1, H, W, b, slot1);
+    PixSet ps;
+    pix_set<true>(sg, H, W, tile, b, ps);
+    const float alpha = p[4], beta = p[5], gamma = p[6];
+    const int n = stage_count(b);
+    for (int c = 0; c < C; c += 2) {
+        wait_vm_at_most((c > 0 ? kPix : 0) + (c + 1 < C ? n : 0));
+        bare_barrier();
+        fwd_slot(y, pl0 + c, H, W, ps, b, slot0, alpha, beta, gamma);
+        if (c + 2 < C) {
+            bare_barrier();  // every wave has read slot 0
+            stage_plane(x, pl0 + c + 2, H, W, b, slot0);
+        }
+        if (c + 1 < C) {
+            wait_vm_at_most(kPix + (c + 2 < C ? n : 0));
+            bare_barrier();
+            fwd_slot(y, pl0 + c + 1, H, W, ps, b, slot1, alpha, beta, gamma);
+            if (c + 3 < C) {
+                bare_barrier();
+                stage_plane(x, pl0 + c + 3, H, W, b, slot1);
+            }
+        }
     }
 }
 
@@ -526,7 +649,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int k = 0; k < 7; ++k) acc.v[k] = 0.0f;
     if (total <= cap) {
         constexpr int kXT = kCells + 1;
-        stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT}, pool);
+        stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT, 0}, pool);
         __syncthreads();
         // 2. region pixels: positions and cells first, then every dL/dy load of
         // the thread's pixels in flight together, then the arithmetic

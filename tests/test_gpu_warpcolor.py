@@ -70,7 +70,8 @@ def test_small_batch_matches_oracle(m):
     compare(m, x, p, w)
 
 
-@pytest.mark.parametrize("C,H,W", [(1, 17, 29), (4, 33, 8), (3, 1, 5), (2, 64, 65)])
+@pytest.mark.parametrize("C,H,W", [(1, 17, 29), (4, 33, 8), (3, 1, 5), (2, 64, 65), (4, 31, 45), (1, 48, 64),
+                                   (3, 50, 52)])
 def test_odd_shapes_and_channel_counts(m, C, H, W):
     n = 3
     x = synth.smooth_noise(C * H * W, n, H, W, C).numpy()
@@ -90,6 +91,21 @@ def test_far_scales_take_the_other_kernel_forms(m):
     p[:, 1] = [0.4, 0.6, 1.7, 2.5]
     w = np.random.default_rng(3).uniform(-1, 1, (n, C, H, W)).astype(np.float32)
     compare(m, x, p, w)
+
+
+def test_forward_same_from_an_unaligned_base(m):
+    # rows are staged as 16-byte chunks only when the planes start 16-byte
+    # aligned and W is a multiple of 4; a base 4 bytes off takes the 4-byte
+    # form, which must give the same bits
+    import torch
+    n, C, H, W = 5, 3, 96, 100
+    x = synth.smooth_noise(31, n, H, W, C).cuda()
+    p = torch.from_numpy(m.sample_wc(31, 0, n)).cuda()
+    buf = torch.empty(x.numel() + 1, device="cuda")
+    xu = buf[1:].view(n, C, H, W)
+    xu.copy_(x)
+    assert xu.data_ptr() % 16 != 0
+    assert torch.equal(m.warpcolor_fwd(xu, p), m.warpcolor_fwd(x, p))
 
 
 def test_identity_forward_is_exact(m):
