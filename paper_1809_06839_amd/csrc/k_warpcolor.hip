@@ -241,14 +241,6 @@ __device__ __forceinline__ void wait_vm_at_most(int n) {
     else wait_vm<0>();
 }
 
-// Every channel of box b ([c][h][w]); returns after this wave's rows have
-// landed, the caller's barrier publishes them.
-__device__ __forceinline__ void stage_box(const float *x, size_t plane0, int C, int H, int W, const Box &b,
-                                          float *lds) {
-    for (int c = 0; c < C; ++c) stage_plane(x, plane0 + c, H, W, b, lds + c * b.h * b.w);
-    __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
-}
-
 // This thread's four pixels of the 32 x 32 output tile (column ox, rows oy0
 // + 8k): bilinear fractions, the pixel's byte offset in a plane (kOOB outside
 // the image), and the taps -- LDS box index of tap (0, 0), or global offsets.
@@ -369,6 +361,10 @@ __device__ __forceinline__ void tile_setup(const float *p, int tile, int H, int 
 // LDS reads, themselves.  The memory clobber keeps the compiler from moving
 // memory operations across it.
 __device__ __forceinline__ void bare_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// Workgroup barrier for LDS written with ordinary stores, without the fence
+// that would also wait for every LDS-DMA in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Channels go through two LDS slots in turn: channel c + 1 (and, once its
 // slot is free, c + 2) is in flight while channel c is blended and stored.
@@ -604,23 +600,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const RowMap rm = row_map(g);
     const int r0 = s_r0, nrows = s_nrows;
     // 0. dL/dy summed over the pixels of the output tile at the same grid
-    // position whose bilinear cell lies wholly outside the image (most tiles
-    // have none, and their loads are skipped)
-    float s_off[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
+    // position whose bilinear cell lies wholly outside the image.  Most tiles
+    // have none, and their waves load nothing; a wave that has some loads
+    // every channel of its four pixels at once (an offset past the plane reads
+    // 0), before the tap DMA is issued, so that waiting for these loads does
+    // not wait for the DMA.
+    constexpr int kOwnPix = kSrcTile * kSrcTile / kThreads;
+    uint32_t oo[kOwnPix];  // byte offset of such a pixel in a plane, else kOOB
+    bool any_off = false;
 #pragma unroll
-    for (int j = 0; j < kSrcTile * kSrcTile / kThreads; ++j) {
+    for (int j = 0; j < kOwnPix; ++j) {
         const int e = threadIdx.x + j * kThreads;
         const int u = X0 + (e & (kSrcTile - 1)), v = Y0 + e / kSrcTile;
         double sx, sy;
         sample_pos(g, u, v, sx, sy);
         const double fx0 = floor(sx), fy0 = floor(sy);
         const bool outside = fx0 < -1.0 || fx0 > (double)(W - 1) || fy0 < -1.0 || fy0 > (double)(H - 1);
-        if (u < W && v < H && outside) {
-            const uint32_t o = ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u;
+        oo[j] = (u < W && v < H && outside) ? ((uint32_t)v * (uint32_t)W + (uint32_t)u) * 4u : kOOB;
+        any_off |= oo[j] != kOOB;
+    }
+    float s_off[kMaxC] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (__builtin_amdgcn_ballot_w64(any_off) != 0) {  // uniform in the wave
+        float ov[kOwnPix][kMaxC];
+#pragma unroll
+        for (int j = 0; j < kOwnPix; ++j)
 #pragma unroll
             for (int c = 0; c < kMaxC; ++c)
-                if (c < C) s_off[c] += ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), o);
-        }
+                ov[j][c] = ldf(plane_rsrc(gy, (size_t)img * C + min(c, C - 1), H, W), c < C ? oo[j] : kOOB);
+#pragma unroll
+        for (int j = 0; j < kOwnPix; ++j)
+#pragma unroll
+            for (int c = 0; c < kMaxC; ++c) s_off[c] += ov[j][c];
+    }
+    // the tile's taps (34 x 34 per channel around it): their DMA is in flight
+    // through step 1 and the region's positions and dL/dy loads, and waited
+    // for before the first tap is read (or before the scatter form reuses the
+    // pool); the barriers until then wait for LDS stores only
+    constexpr int kXT = kCells + 1;
+    {
+        const Box tb{X0 - 1, Y0 - 1, kXT, kXT, 0};
+        for (int c = 0; c < C; ++c) stage_plane(x, (size_t)img * C + c, H, W, tb, pool + c * kXT * kXT);
     }
     const double tx0 = (double)(X0 - 1), tx1 = (double)(X0 + kSrcTile);
     const double ty0 = (double)(Y0 - 1), ty1 = (double)(Y0 + kSrcTile);
@@ -637,7 +656,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (lane == 0) roff[0] = 0;
         if (lane == 63) s_total = nrows > kMaxRows ? INT_MAX : inc;
     }
-    __syncthreads();
+    lds_barrier();
     const float alpha = p[4], beta = p[5], gamma = p[6];
     const int total = s_total;
     const int cap = min(kEPT * kThreads, kPoolFloats / (C + 2));
@@ -648,9 +667,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
     for (int k = 0; k < 7; ++k) acc.v[k] = 0.0f;
     if (total <= cap) {
-        constexpr int kXT = kCells + 1;
-        stage_box(x, (size_t)img * C, C, H, W, Box{X0 - 1, Y0 - 1, kXT, kXT, 0}, pool);
-        __syncthreads();
         // 2. region pixels: positions and cells first, then every dL/dy load of
         // the thread's pixels in flight together, then the arithmetic
         uint32_t eop[kEPT];  // the pixel's byte offset in a plane; kOOB: no pixel, or a cell outside the square
@@ -688,6 +704,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
             for (int c = 0; c < kMaxC; ++c)
                 egv[k][c] = c < C ? ldf(plane_rsrc(gy, (size_t)img * C + c, H, W), eop[k]) : 0.0f;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's tap DMA and dL/dy loads
+        lds_barrier();                  // every wave's taps
         float eg[kEPT][kMaxC];
         int ecs[kEPT];
 #pragma unroll
@@ -776,6 +794,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     } else {
         // a region beyond the pool: taps from global memory, scatter with LDS float atomics
         float(*accs)[kSrcTile][kSrcTile + 1] = reinterpret_cast<float(*)[kSrcTile][kSrcTile + 1]>(pool);
+        __builtin_amdgcn_s_waitcnt(0);  // the tap DMA has landed before the pool is reused
+        lds_barrier();
         if (gx)
             for (int e = threadIdx.x; e < kMaxC * kSrcTile * (kSrcTile + 1); e += kThreads) pool[e] = 0.0f;
         __syncthreads();
