@@ -104,6 +104,9 @@ __device__ __forceinline__ uint32_t hsv_shift(uint32_t rgb, int dh, int ds, int 
     return o0 | (o1 << 8) | (o2 << 16);
 }
 
+// Reflect-101 of an index within one reflection of [0, n): -(n - 1) <= i <= 2n - 2, n >= 2.
+__device__ __forceinline__ int refl1(int i, int n) { return i < 0 ? -i : (i >= n ? 2 * n - 2 - i : i); }
+
 typedef __attribute__((address_space(3))) void *lds_ptr_t;
 constexpr int kStageMax = 40 * 1024;  // bytes of staged source per tile
 constexpr int kMaxRows = 160;          // staged source rows per tile
@@ -187,15 +190,31 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
         const int xmax = (int)(rshr_he64(hi[0] + hi[1], 32 - kFBits) >> kFBits) + 1;
         const int ymin = (int)(rshr_he64(lo[2] + lo[3], 32 - kFBits) >> kFBits);
         const int ymax = (int)(rshr_he64(hi[2] + hi[3], 32 - kFBits) >> kFBits) + 1;
-        const int bw = xmax - xmin + 1, bh = ymax - ymin + 1;
-        const int nch = (3 * bw + 30) >> 4;
         const bool inside = xmin >= 0 && xmax <= W - 1 && ymin >= 0 && ymax <= H - 1;
-        box[0] = xmin; box[1] = ymin; box[2] = bw; box[3] = bh; box[4] = nch;
-        box[5] = inside && bh <= kMaxRows && bh * nch * 16 <= kStageMax;
+        // a box that crosses the border by less than the image size: stage the
+        // range of image pixels its reflected taps read (form 2)
+        const bool once = W >= 2 && H >= 2 && xmin >= 1 - W && xmax <= 2 * W - 2 && ymin >= 1 - H && ymax <= 2 * H - 2;
+        int xl = xmin, xh = xmax, yl = ymin, yh = ymax;
+        if (!inside && once) {
+            xl = min(refl1(xmin, W), refl1(xmax, W));
+            xh = max(refl1(xmin, W), refl1(xmax, W));
+            if (xmin <= 0 && xmax >= 0) xl = 0;
+            if (xmin <= W - 1 && xmax >= W - 1) xh = W - 1;
+            yl = min(refl1(ymin, H), refl1(ymax, H));
+            yh = max(refl1(ymin, H), refl1(ymax, H));
+            if (ymin <= 0 && ymax >= 0) yl = 0;
+            if (ymin <= H - 1 && ymax >= H - 1) yh = H - 1;
+        }
+        const int bw = xh - xl + 1, bh = yh - yl + 1;
+        const int nch = (3 * bw + 30) >> 4;
+        const bool fits = bh <= kMaxRows && bh * nch * 16 <= kStageMax;
+        box[0] = xl; box[1] = yl; box[2] = bw; box[3] = bh; box[4] = nch;
+        box[5] = fits ? (inside ? 1 : (once ? 2 : 0)) : 0;
     }
     __syncthreads();
     const int bx = box[0], by = box[1], bh = box[3], nch = box[4];
-    const bool staged = box[5] != 0;
+    const int form = box[5];
+    const bool staged = form != 0;
     if (staged) {
         const int bw = box[2];
         if (tid < bh) {
@@ -232,12 +251,20 @@ __global__ __launch_bounds__(kThreads) void k_c2(const uint8_t *__restrict__ in,
                 const int r = 2 * pi + u, c = 2 * pj + v;
                 const int64_t qx = rshr_he64(txx[c] + tyx[r], 32 - kFBits);
                 const int64_t qy = rshr_he64(txy[c] + tyy[r], 32 - kFBits);
-                if (staged) {
+                if (form == 1) {
                     const int sx = (int)(qx >> kFBits) - bx, sy = (int)(qy >> kFBits) - by;
                     const int ax = (int)(qx & (kFOne - 1)), ay = (int)(qy & (kFOne - 1));
                     const int o0 = rowoff[sy] + 3 * sx, o1 = rowoff[sy + 1] + 3 * sx;
                     g[u][v] = blend4(lds_rgb(stage, o0), lds_rgb(stage, o0 + 3), lds_rgb(stage, o1),
                                      lds_rgb(stage, o1 + 3), ax, ay);
+                } else if (form == 2) {
+                    // every tap reflected on its own (a reflected pair need not be adjacent)
+                    const int x0 = (int)(qx >> kFBits), y0 = (int)(qy >> kFBits);
+                    const int ax = (int)(qx & (kFOne - 1)), ay = (int)(qy & (kFOne - 1));
+                    const int c0 = 3 * (refl1(x0, W) - bx), c1 = 3 * (refl1(x0 + 1, W) - bx);
+                    const int r0 = rowoff[refl1(y0, H) - by], r1 = rowoff[refl1(y0 + 1, H) - by];
+                    g[u][v] = blend4(lds_rgb(stage, r0 + c0), lds_rgb(stage, r0 + c1), lds_rgb(stage, r1 + c0),
+                                     lds_rgb(stage, r1 + c1), ax, ay);
                 } else {
                     g[u][v] = warp_sample(src, H, W, qx, qy);
                 }
