@@ -1087,29 +1087,57 @@ __device__ __forceinline__ void fold_dmax(int dm, int32_t *dmax, int *red) {
     }
 }
 
+// The largest |offset| of each image (both planes, Q10) into dmax, for the
+// elastic adjoint's window: a streaming pass over the offsets, 16 bytes per
+// lane when the image's offsets start 16-byte aligned, four loads of a thread
+// in flight at a time.
+constexpr int kDmaxBlocks = 256;  // workgroups per image
+
+__global__ __launch_bounds__(256) void k_chain_dmax(const int32_t *__restrict__ off, int H, int W, ChainWs w) {
+    __shared__ int red[4];
+    const int im = blockIdx.y;
+    const size_t cnt = 2 * (size_t)H * W, stride = (size_t)gridDim.x * 256;
+    const int32_t *o = off + (size_t)im * cnt;
+    const size_t first = (size_t)blockIdx.x * 256 + threadIdx.x;
+    int dm = 0;
+    size_t t0 = 0;  // elements from here on go one at a time
+    if (((uintptr_t)o & 15) == 0) {
+        const int4 *v = (const int4 *)o;
+        const size_t n4 = cnt / 4;
+        size_t i = first;
+        for (; i + 3 * stride < n4; i += 4 * stride) {
+            int4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = v[i + u * stride];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dm = max(dm, max(max(abs(a[u].x), abs(a[u].y)), max(abs(a[u].z), abs(a[u].w))));
+        }
+        for (; i < n4; i += stride) {
+            const int4 a = v[i];
+            dm = max(dm, max(max(abs(a.x), abs(a.y)), max(abs(a.z), abs(a.w))));
+        }
+        t0 = n4 * 4;
+    }
+    for (size_t t = t0 + first; t < cnt; t += stride) dm = max(dm, abs(o[t]));
+    fold_dmax(dm, w.dmax + im, red);
+}
+
 // dL/de of the grid step, separable: one workgroup per 16 rows x 256 columns
 // of ge.  Pass x: for each output row r the tile's rows draw on (at most
 // kSepR of them, contiguous), t(r, j) = sum_k xw(j, k) gy(r, xc(j, k)) into
 // LDS; pass y: ge(i, j) = sum_k yw(i, k) t(yc(i, k), j).  One channel at a
 // time.  A tile whose rows draw on a wider span (a fold at a border) does
 // its pixels from the tables one by one; images marked wide are left to the
-// scatter form.  Also folds |offset| of its pixels into dmax.
+// scatter form.
 constexpr int kSepI = 16, kSepR = 32;
 
 __global__ __launch_bounds__(256) void k_chain_grid_adj_sep(const float *__restrict__ gy, int C, int H, int W,
-                                                            const int32_t *__restrict__ off, ChainWs w) {
+                                                            ChainWs w) {
     __shared__ float tl[kSepR][256];
-    __shared__ int red[4], s_r0, s_r1;
+    __shared__ int s_r0, s_r1;
     const int im = blockIdx.z, I0 = blockIdx.y * kSepI, j = blockIdx.x * 256 + threadIdx.x;
     const size_t plane = (size_t)H * W;
     const int I1 = min(H, I0 + kSepI);
-    int dm = 0;
-    if (j < W)
-        for (int i = I0; i < I1; ++i) {
-            const int32_t *o = off + (size_t)im * 2 * plane + (size_t)i * W + j;
-            dm = max(dm, max(abs(o[0]), abs(o[plane])));
-        }
-    fold_dmax(dm, w.dmax + im, red);
     if (w.wide[im]) return;
     if (threadIdx.x < 64) {  // output rows the tile draws on (entries of weight != 0)
         int lo = INT_MAX, hi = -1;
@@ -1728,12 +1756,14 @@ hipError_t launch_chain_f32_bwd(const float *gy, int n, int C, int H, int W, con
     hipError_t err = launch_fill_u32((uint32_t *)w.dmax, 2 * (size_t)n + (size_t)n * (W + H), 0u, s);
     if (err != hipSuccess) return err;
     const dim3 g1((unsigned)((max(H, W) + 255) / 256), n);
+    hipLaunchKernelGGL(k_chain_dmax, dim3(kDmaxBlocks, n), dim3(256), 0, s, off, H, W, w);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_chain_inv, g1, dim3(256), 0, s, mapx, mapy, H, W, w);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_chain_inv_sort, g1, dim3(256), 0, s, H, W, w);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_chain_grid_adj_sep, dim3((unsigned)((W + 255) / 256), (unsigned)((H + kSepI - 1) / kSepI), n),
-                       dim3(256), 0, s, gy, C, H, W, off, w);
+                       dim3(256), 0, s, gy, C, H, W, w);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_chain_ge_zero_wide, dim3(1024, n), dim3(256), 0, s, C, H, W, w);
     if ((err = hipGetLastError()) != hipSuccess) return err;
