@@ -890,11 +890,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) v
 }
 
 // ---------------------------------------------------------------- float copy of the chain
+__device__ __forceinline__ int reflect_fast(int i, int n) { return (unsigned)i < (unsigned)n ? i : reflect101(i, n); }
+
 __device__ __forceinline__ void taps_q(int qx, int qy, int H, int W, int xs[2], int ys[2], float wx[2], float wy[2]) {
     const int x0 = qx >> kFBits, y0 = qy >> kFBits;
     const int ax = qx & (kFOne - 1), ay = qy & (kFOne - 1);
-    xs[0] = reflect101(x0, W); xs[1] = reflect101(x0 + 1, W);
-    ys[0] = reflect101(y0, H); ys[1] = reflect101(y0 + 1, H);
+    xs[0] = reflect_fast(x0, W); xs[1] = reflect_fast(x0 + 1, W);
+    ys[0] = reflect_fast(y0, H); ys[1] = reflect_fast(y0 + 1, H);
     wx[0] = (float)(kFOne - ax) * (1.0f / kFOne); wx[1] = (float)ax * (1.0f / kFOne);
     wy[0] = (float)(kFOne - ay) * (1.0f / kFOne); wy[1] = (float)ay * (1.0f / kFOne);
 }
@@ -906,7 +908,9 @@ __global__ void k_chain_f_elastic(const float *__restrict__ x, int C, int H, int
     const int im = blockIdx.y;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= plane) return;
-    const int Y = (int)(p / W), X = (int)(p % W);
+    // pixel index to (row, column): 32-bit division while the plane fits 32 bits
+    const int Y = plane <= 0xFFFFFFFFu ? (int)((uint32_t)p / (uint32_t)W) : (int)(p / W);
+    const int X = (int)(p - (size_t)Y * W);
     const int32_t *ox = off + (size_t)im * 2 * plane, *oy = ox + plane;
     int xs[2], ys[2];
     float wx[2], wy[2];
@@ -925,7 +929,8 @@ __global__ void k_chain_f_grid(const float *__restrict__ e, int C, int H, int W,
     const int im = blockIdx.y;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= plane) return;
-    const int r = (int)(p / W), c0 = (int)(p % W);
+    const int r = plane <= 0xFFFFFFFFu ? (int)((uint32_t)p / (uint32_t)W) : (int)(p / W);
+    const int c0 = (int)(p - (size_t)r * W);
     int xs[2], ys[2];
     float wx[2], wy[2];
     taps_q(mapx[(size_t)im * W + c0], mapy[(size_t)im * H + r], H, W, xs, ys, wx, wy);
@@ -975,7 +980,6 @@ __host__ __device__ inline ChainWs chain_ws(void *ws, int n, int C, int H, int W
     return w;
 }
 
-__device__ __forceinline__ int reflect_fast(int i, int n) { return (unsigned)i < (unsigned)n ? i : reflect101(i, n); }
 
 // Inverse grid tables, step 1: output column c (row r) appends itself, with
 // the weight, to the entries of each source index its nonzero taps land on.
