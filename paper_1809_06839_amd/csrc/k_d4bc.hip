@@ -4,7 +4,9 @@
 //
 // One workgroup per (image, 64x64 output tile).  The tile's source block is
 // an axis-aligned rectangle (a Dih4 element maps rectangles to rectangles);
-// its rows are staged into LDS with 16-byte vector loads, the 256-entry LUT
+// its rows are staged into LDS with 16-byte LDS-DMA loads (all of a thread's
+// chunks in flight at once; rows contiguous in LDS, so the lane-ordered DMA
+// destinations tile them), the 256-entry LUT
 // is built in LDS in IEEE double, and each thread forms four output pixels
 // (each one LDS word read at the Dih4-mapped position, then the LUTs) and
 // writes them as C aligned words (flips and transposes become LDS
@@ -17,6 +19,7 @@ namespace {
 
 constexpr int kT = 64;
 constexpr int kThreads = 256;
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
 
 // FROM_AB: one LUT per image built from (alpha, beta); otherwise C LUTs per
 // image read from `luts` ([n][C][256], composed on the host) and, for C = 3,
@@ -27,9 +30,9 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
                                                    const uint8_t *__restrict__ luts, const int32_t *__restrict__ gray,
                                                    uint8_t *__restrict__ out) {
     constexpr int kChunks = (kT * C + 30) / 16;          // 16-byte chunks per staged row (phase included)
-    constexpr int kStride = kChunks * 16 + 16;           // LDS bytes per row (+16 against bank conflicts)
+    constexpr int kStride = kChunks * 16;                // LDS bytes per row
     constexpr int kLuts = FROM_AB ? 1 : C;
-    __shared__ __align__(16) uint8_t src[kT * kStride];
+    __shared__ __align__(16) uint8_t src[kT * kStride + 16];  // + the word past the last pixel a read takes
     __shared__ uint8_t lut[kLuts][256];
 
     const int img = blockIdx.y;
@@ -49,11 +52,21 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
     const size_t plane = (size_t)H * W * C;
     const uint8_t *base = in + (size_t)img * plane;
 
-    // stage source rows [sr0, sr0 + nsr), columns [sc0, sc0 + nsc)
-    for (int it = tid; it < nsr * kChunks; it += kThreads) {
-        int row = it / kChunks, ch = it - row * kChunks;
-        const uint8_t *g = base + ((size_t)(sr0 + row) * W + sc0) * C;
-        if (ch < span_chunks(g, nsc * C)) load_span16_chunk(g, ch, src + row * kStride);
+    // stage source rows [sr0, sr0 + nsr), columns [sc0, sc0 + nsc): chunk it
+    // (row it / kChunks of the row's 16-byte aligned span) lands at 16 it
+    {
+        const int total = nsr * kChunks, lane = tid & 63;
+        for (int b = tid - lane; b < total; b += kThreads) {  // b is uniform in the wave
+            const int it = b + lane;
+            const uint8_t *g = nullptr;
+            if (it < total) {
+                const int row = it / kChunks, ch = it - row * kChunks;
+                const uint8_t *r = base + ((size_t)(sr0 + row) * W + sc0) * C;
+                if (ch < span_chunks(r, nsc * C)) g = (const uint8_t *)((uintptr_t)r & ~(uintptr_t)15) + 16 * ch;
+            }
+            if (g) __builtin_amdgcn_global_load_lds((const void *)g, (lds_ptr_t)(src + 16 * b), 16, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
     }
     if (FROM_AB) {
         double t = (double)ab[2 * img] * (double)tid + (double)ab[2 * img + 1];
