@@ -114,6 +114,8 @@ __device__ __forceinline__ void warp_px_direct(const uint8_t *src, int H, int W,
     }
 }
 
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
 constexpr int kWarpTile = 32;            // output tile side
 constexpr int kWarpStage = 16 * 1024;    // bytes of staged source box per workgroup
 constexpr int kWarpRows = 128;           // rows of a box staged in dwords
@@ -184,12 +186,19 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
                     ((by0 + bh - 1) * (int64_t)W + bx0) * C + P <= (int64_t)H * W * C;
     if (dw) {
         if ((int)threadIdx.x < bh) roff[threadIdx.x] = threadIdx.x * P + (int)(((by0 + threadIdx.x) * W + bx0) * C & 3);
+        // dword e = r nd + j of the box lands at box + 4 e: the LDS-DMA's
+        // lane-ordered destinations, every dword of a thread in flight at once
         const float rnd = 1.0f / (float)nd;
-        for (int e = threadIdx.x; e < bh * nd; e += kThreads) {
-            const int r = small_div(e, nd, rnd), j = e - r * nd;
-            const size_t g4 = (size_t)(((by0 + r) * W + bx0) * C) & ~(size_t)3;
-            *(uint32_t *)(box + r * P + 4 * j) = *(const uint32_t *)(src + g4 + 4 * j);
+        const int lane = threadIdx.x & 63;
+        for (int b = threadIdx.x - lane; b < bh * nd; b += kThreads) {  // b is uniform in the wave
+            const int e = b + lane;
+            if (e < bh * nd) {
+                const int r = small_div(e, nd, rnd), j = e - r * nd;
+                const size_t g4 = (size_t)(((by0 + r) * W + bx0) * C) & ~(size_t)3;
+                __builtin_amdgcn_global_load_lds((const void *)(src + g4 + 4 * j), (lds_ptr_t)(box + 4 * b), 4, 0, 0);
+            }
         }
+        __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
     } else {
         const float rbw = 1.0f / (float)bw;
         for (int e = threadIdx.x; e < bw * bh; e += kThreads) {
