@@ -200,13 +200,29 @@ __global__ __launch_bounds__(kThreads) void k_warp(const uint8_t *__restrict__ i
         }
         __builtin_amdgcn_s_waitcnt(0);  // LDS-DMA writes are counted by vmcnt
     } else {
+        // pixel by pixel with the border rule, kBatch pixels of a thread loaded
+        // before any is stored (their loads in flight together)
+        constexpr int kBatch = 4;
         const float rbw = 1.0f / (float)bw;
-        for (int e = threadIdx.x; e < bw * bh; e += kThreads) {
-            const int r = small_div(e, bw, rbw), c = e - r * bw;
-            const int64_t sy = border_index(by0 + r, H, border), sx = border_index(bx0 + c, W, border);
-            const uint8_t *p = src + ((size_t)sy * W + sx) * C;
+        for (int e0 = threadIdx.x; e0 < bw * bh; e0 += kBatch * kThreads) {
+            uint8_t v[kBatch][C];
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch) box[e * C + ch] = (sy < 0 || sx < 0) ? 0 : p[ch];
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + u * kThreads;
+                const int r = small_div(min(e, bw * bh - 1), bw, rbw), c = min(e, bw * bh - 1) - r * bw;
+                const int64_t sy = border_index(by0 + r, H, border), sx = border_index(bx0 + c, W, border);
+                const bool in = sy >= 0 && sx >= 0;
+                const uint8_t *p = src + (in ? ((size_t)sy * W + sx) * C : 0);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) v[u][ch] = in ? p[ch] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + u * kThreads;
+                if (e < bw * bh)
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch) box[e * C + ch] = v[u][ch];
+            }
         }
     }
     __syncthreads();
