@@ -30,40 +30,61 @@ __device__ __forceinline__ int64_t border_index(int64_t i, int n, int border) {
     return reflect101_64(i, n);
 }
 
-constexpr int kPadThreads = 128;  // k_pad: 512 output pixels of one row per block and step
+constexpr int kPadThreads = 128;  // k_pad: 512 output pixels of a row per block and step
+constexpr int kPadRows = 4;       // output rows per block: their loads are in flight together
 
 template <int C>
 __global__ __launch_bounds__(kPadThreads) void k_pad(const uint8_t *__restrict__ in, int H, int W, int Ho, int Wo,
                                                      int top, int left, int border, int value,
                                                      uint8_t *__restrict__ out) {
-    // block (image row, column block): one output row, four pixels per thread
-    const int img = (int)(blockIdx.x / (unsigned)Ho), y = (int)(blockIdx.x - (unsigned)img * Ho);
-    const int64_t sy = border_index(y - top, H, border);  // the same for the whole block
-    uint8_t *orow = out + ((size_t)img * Ho + y) * Wo * C;
-    const uint8_t *srow = in + ((size_t)img * H + (sy < 0 ? 0 : sy)) * W * C;
+    // block (image, group of kPadRows output rows, column block): four pixels
+    // of each row per thread, every row's source words loaded before any is stored
+    const int groups = (Ho + kPadRows - 1) / kPadRows;
+    const int img = (int)(blockIdx.x / (unsigned)groups), y0 = (int)(blockIdx.x - (unsigned)img * groups) * kPadRows;
+    int64_t sy[kPadRows];  // source row of each output row (the same for the whole block), -1: constant
+#pragma unroll
+    for (int r = 0; r < kPadRows; ++r) sy[r] = y0 + r < Ho ? border_index(y0 + r - top, H, border) : -1;
     for (int xb = blockIdx.y; (int64_t)xb * 4 * kPadThreads < Wo; xb += gridDim.y) {
         const int x = (xb * kPadThreads + (int)threadIdx.x) * 4;
         if (x >= Wo) break;
         const int sx0 = x - left, np = min(4, Wo - x);
-        uint8_t *o = orow + (size_t)x * C;
-        if (sy >= 0 && np == 4 && sx0 >= 0 && sx0 + 4 <= W && ((uintptr_t)o & 3) == 0) {
-            // four contiguous source pixels: C words (C + 1 when they do not start on a
-            // word, the last one holding their last bytes), shifted into C output words
-            const uint8_t *p = srow + (size_t)sx0 * C;
-            const int sh = (int)((uintptr_t)p & 3);
-            const uint32_t *w = (const uint32_t *)(p - sh);
-            uint32_t d[C + 1];
+        const bool cols = np == 4 && sx0 >= 0 && sx0 + 4 <= W;
+        uint32_t d[kPadRows][C + 1];
+        bool fast[kPadRows];
+        int sh[kPadRows];
 #pragma unroll
-            for (int k = 0; k < C; ++k) d[k] = w[k];
-            d[C] = sh ? w[C] : 0u;
+        for (int r = 0; r < kPadRows; ++r) {
+            uint8_t *o = out + (((size_t)img * Ho + y0 + r) * Wo + x) * C;
+            // four contiguous source pixels: C words (C + 1 when they do not start on
+            // a word, the last one holding their last bytes), shifted into C output words
+            fast[r] = cols && sy[r] >= 0 && ((uintptr_t)o & 3) == 0;
+            sh[r] = 0;
 #pragma unroll
-            for (int k = 0; k < C; ++k) ((uint32_t *)o)[k] = __builtin_amdgcn_alignbyte(d[k + 1], d[k], sh);
-            continue;
+            for (int k = 0; k <= C; ++k) d[r][k] = 0u;
+            if (fast[r]) {  // only then are the words inside the source row
+                const uint8_t *p = in + (((size_t)img * H + sy[r]) * W + sx0) * C;
+                sh[r] = (int)((uintptr_t)p & 3);
+                const uint32_t *w = (const uint32_t *)(p - sh[r]);
+#pragma unroll
+                for (int k = 0; k < C; ++k) d[r][k] = w[k];
+                if (sh[r]) d[r][C] = w[C];
+            }
         }
-        for (int j = 0; j < np; ++j) {
-            const int64_t sx = border_index(sx0 + j, W, border);
 #pragma unroll
-            for (int c = 0; c < C; ++c) o[j * C + c] = (sy < 0 || sx < 0) ? (uint8_t)value : srow[sx * C + c];
+        for (int r = 0; r < kPadRows; ++r) {
+            if (y0 + r >= Ho) break;
+            uint8_t *o = out + (((size_t)img * Ho + y0 + r) * Wo + x) * C;
+            if (fast[r]) {
+#pragma unroll
+                for (int k = 0; k < C; ++k) ((uint32_t *)o)[k] = __builtin_amdgcn_alignbyte(d[r][k + 1], d[r][k], sh[r]);
+                continue;
+            }
+            const uint8_t *srow = in + ((size_t)img * H + (sy[r] < 0 ? 0 : sy[r])) * W * C;
+            for (int j = 0; j < np; ++j) {
+                const int64_t sx = border_index(sx0 + j, W, border);
+#pragma unroll
+                for (int c = 0; c < C; ++c) o[j * C + c] = (sy[r] < 0 || sx < 0) ? (uint8_t)value : srow[sx * C + c];
+            }
         }
     }
 }
@@ -277,7 +298,7 @@ hipError_t launch_pad_u8(const uint8_t *in, int n, int H, int W, int C, int Ho, 
     if (n == 0) return hipSuccess;
     const int top = (Ho - H) / 2, left = (Wo - W) / 2;
     const int64_t cb = ((int64_t)Wo + 4 * kPadThreads - 1) / (4 * kPadThreads);
-    dim3 grid((unsigned)((int64_t)Ho * n), (unsigned)(cb < 65535 ? cb : 65535));
+    dim3 grid((unsigned)((int64_t)((Ho + kPadRows - 1) / kPadRows) * n), (unsigned)(cb < 65535 ? cb : 65535));
     if (C == 1) hipLaunchKernelGGL(k_pad<1>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
     else if (C == 3) hipLaunchKernelGGL(k_pad<3>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
     else hipLaunchKernelGGL(k_pad<4>, grid, dim3(kPadThreads), 0, s, in, H, W, Ho, Wo, top, left, border, value, out);
