@@ -71,8 +71,13 @@ __global__ __launch_bounds__(kThreads) void k_d4_bc(const uint8_t *__restrict__ 
     if (FROM_AB) {
         double t = (double)ab[2 * img] * (double)tid + (double)ab[2 * img + 1];
         lut[0][tid] = (uint8_t)sat8((int)rint(t));
-    } else {
-        for (int e = tid; e < C * 256; e += kThreads) lut[e >> 8][e & 255] = luts[(size_t)img * C * 256 + e];
+    } else {  // every channel's entry loaded before any is stored
+        static_assert(kThreads == 256, "one LUT entry per thread and channel");
+        uint8_t lv[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) lv[c] = luts[((size_t)img * C + c) * 256 + tid];
+#pragma unroll
+        for (int c = 0; c < C; ++c) lut[c][tid] = lv[c];
     }
     const bool to_gray = !FROM_AB && C == 3 && gray && gray[img];
     __syncthreads();
