@@ -206,6 +206,20 @@ def test_f32_chain_at_1024_against_the_oracle(m):
     assert np.abs(gx - gr).max() <= 1e-5 * np.abs(gr).max()
 
 
+@pytest.mark.parametrize("n,H,W,C,smooth", [(3, 33, 17, 1, False), (2, 64, 64, 4, True), (2, 31, 31, 3, False),
+                                            (2, 128, 128, 2, False), (3, 96, 80, 3, True), (2, 1, 6, 4, False)])
+def test_image_stats_shapes_and_smooth_images(m, n, H, W, C, smooth):
+    # four-pixel groups (npix a multiple of 4) and single pixels, 1-4 channels;
+    # smooth images put many equal values in one group and on one histogram bin
+    img = synth.smooth_u8_hwc(5 + H, n, H, W, C) if smooth else synth.uniform_u8(7 + H, n, H, W, C)
+    s, mn, mx, h = m.image_stats_u8(img.cuda())
+    for i in range(n):
+        rs, rmn, rmx, rh = oracle.image_stats(img[i].cpu().numpy(), C)
+        assert s[i].cpu().numpy().astype(np.uint64).tolist() == rs.tolist()
+        assert mn[i].tolist() == rmn.tolist() and mx[i].tolist() == rmx.tolist()
+        assert np.array_equal(h[i].cpu().numpy().astype(np.uint32), rh)
+
+
 def test_image_stats_match_oracle(m):
     import torch
     img = synth.uniform_u8(3, 5, 70, 90, 3)
