@@ -67,12 +67,15 @@ def profiled_traffic(profile: str, variant_name: str):
         h.update(open(os.path.join(csrc, f), "rb").read())
     if fields.get("kernel_source_sha256_16", "").strip() != h.hexdigest()[:16]:
         return None
-    if fields.get("variant", "").strip() != variant_name:
-        return None
-    try:
-        return int(fields["traffic_bytes_per_launch"].split()[0])
-    except (KeyError, ValueError):
-        return None
+    # one entry per launch variant the counters were taken on: variant / traffic_bytes_per_launch,
+    # variant_1 / traffic_bytes_per_launch_1, ...
+    for sfx in [""] + ["_%d" % i for i in range(1, 8)]:
+        if fields.get("variant" + sfx, "").strip() == variant_name:
+            try:
+                return int(fields["traffic_bytes_per_launch" + sfx].split()[0])
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def resize_rows_touched(L: int, out: int = 224) -> int:

@@ -374,13 +374,16 @@ int miaug_graph_destroy(miaug_graph *g);
  * miaug_ragged_apply calls).  Writes the chosen variant index to *chosen, its
  * mean time in ms to *ms and, when `times` is not NULL, every variant's mean
  * time to times[0 .. variant_count-1] (-1 for a variant that failed the
- * parity gate).  Synchronises `stream`.  `args->out*` are overwritten. */
+ * parity gate or is switched off).  Synchronises `stream`.  `args->out*` are
+ * overwritten. */
 int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *args, int reps, void *stream, int *chosen,
                           float *ms, float *times);
-/* Number of variants and a variant's description ("tile 32x32, 4 wg/CU"). */
+/* Number of variants and a variant's description ("tile 32x32, 4 wg/CU");
+ * the description of a variant that is switched off begins "off: ". */
 int miaug_ragged_variant_count(void);
 const char *miaug_ragged_variant_name(int v);
-/* Forces a variant (-1 restores the default). */
+/* Forces a variant (-1 restores the default).  EUNSUPPORTED for a variant that
+ * is switched off (MIAUG_FORCE_VARIANT ignores such a variant). */
 int miaug_ragged_set_variant(miaug_ctx *ctx, int v);
 
 /* No-allocation form of miaug_ragged_apply, for callers that cannot allocate
@@ -402,7 +405,8 @@ int miaug_ragged_set_variant(miaug_ctx *ctx, int v);
  * batch, so every batch miaug_ragged_apply accepts is accepted.
  * Errors: as miaug_ragged_apply; EINVAL variant out of range; ECAPACITY if a
  * launch form needs more counter memory than the static array holds;
- * EUNSUPPORTED device index >= 64; EDEVICE symbol lookup or launch failure. */
+ * EUNSUPPORTED device index >= 64, or a variant that is switched off; EDEVICE
+ * symbol lookup or launch failure. */
 #define MIAUG_NOALLOC_SCRATCH_BYTES 1024
 int miaug_ragged_apply_noalloc(const miaug_ragged_args *args, int variant, void *stream);
 

@@ -29,7 +29,7 @@ int begin_call() {
 // Launch variant of a context: MIAUG_FORCE_VARIANT when set and in range.
 int ctx_variant(const miaug_ctx *c) {
     const int f = env().force_variant;
-    return (f >= 0 && f < ragged_variant_count()) ? f : c->variant;
+    return ragged_variant_enabled(f) ? f : c->variant;
 }
 
 // Bookkeeping of a context call whose arguments were accepted; returns st.
@@ -409,6 +409,8 @@ int miaug_ragged_apply_noalloc(const miaug_ragged_args *a, int variant, void *st
     if (int st = ragged_check(a)) return st;
     if (variant < -1 || variant >= ragged_variant_count())
         return set_error(MIAUG_EINVAL, "ragged_apply_noalloc: variant %d out of range", variant);
+    if (variant >= 0 && !ragged_variant_enabled(variant))
+        return set_error(MIAUG_EUNSUPPORTED, "ragged_apply_noalloc: variant %d is switched off", variant);
     const size_t need = (size_t)ragged_counter_ints() * sizeof(int);
     if (need > MIAUG_NOALLOC_SCRATCH_BYTES)
         return set_error(MIAUG_ECAPACITY, "ragged_apply_noalloc: needs %zu bytes of scratch, the static array holds %d",
@@ -432,6 +434,7 @@ int miaug_ragged_set_variant(miaug_ctx *ctx, int v) {
     begin_call();
     if (!ctx) return set_error(MIAUG_EINVAL, "set_variant: NULL ctx");
     if (v < -1 || v >= ragged_variant_count()) return set_error(MIAUG_EINVAL, "set_variant: %d out of range", v);
+    if (v >= 0 && !ragged_variant_enabled(v)) return set_error(MIAUG_EUNSUPPORTED, "set_variant: variant %d is switched off", v);
     ctx->variant = v < 0 ? ragged_default_variant() : v;
     return ctx_done(ctx, MIAUG_OK);
 }
@@ -511,6 +514,7 @@ int ragged_autotune_run(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, hi
     for (int v = 0; v < ragged_variant_count() && !st; ++v) {
         L.variant = v;
         if (times) times[v] = -1.f;
+        if (!ragged_variant_enabled(v)) continue;
         st = fill();
         if (!st) st = hip_status(launch_ragged(a, L, 0, s), "autotune candidate");
         if (!st) st = fetch(got, mgot, bgot);
@@ -564,7 +568,7 @@ int miaug_ragged_autotune(miaug_ctx *ctx, const miaug_ragged_args *a, int reps, 
         TuneEntry e;
         const int cst = tune_cache_get(ctx->tune_cache, key, &e);
         const char *nm = ragged_variant_name(e.variant);
-        if (cst == MIAUG_OK && nm && e.name == nm) {
+        if (cst == MIAUG_OK && nm && e.name == nm && ragged_variant_enabled(e.variant)) {
             ctx->variant = e.variant;
             if (chosen) *chosen = e.variant;
             if (ms) *ms = e.ms;

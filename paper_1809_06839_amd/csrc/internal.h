@@ -81,6 +81,7 @@ hipError_t launch_ragged_rows(const miaug_ragged_args *a, int cap_kind, int wg_p
 hipError_t launch_ragged_gather(const miaug_ragged_args *a, int band, int wg_per_cu, const RaggedLaunch &L,
                                 hipStream_t s);
 int ragged_variant_count();
+bool ragged_variant_enabled(int v);  // false for forms switched off (their names begin "off: ")
 const char *ragged_variant_name(int v);
 int ragged_default_variant();
 // Ints of queue-counter memory launch_ragged uses (RaggedLaunch::counters).

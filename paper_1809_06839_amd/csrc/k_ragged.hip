@@ -1311,10 +1311,10 @@ const Variant kVariants[] = {
     {32, 32, 0, 2, 1, "tile 32x32, streaming pipeline 8+1 waves, 2 wg/CU"},
     {16, 64, 4, 4, 1, "tile 16x64, persistent 4 wg/CU, 4 worker waves + a planning wave"},
     {8, 128, 4, 4, 1, "tile 8x128, persistent 4 wg/CU, 4 worker waves + a planning wave"},
-    {0, 0, 7, 3, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 3 wg/CU"},
-    {0, 0, 7, 4, 0, "row bands of 16 lines, whole source rows, 17 KB stages x 2, 4 wg/CU"},
-    {0, 0, 7, 6, 1, "row bands of 16 lines, whole source rows, 9 KB stages x 2, 6 wg/CU"},
-    {0, 0, 7, 2, 2, "row bands of 16 lines, whole source rows, 36 KB stages x 2, 2 wg/CU"},
+    {0, 0, 7, 3, 0, "off: row bands of 16 lines, whole source rows, 17 KB stages x 2, 3 wg/CU"},
+    {0, 0, 7, 4, 0, "off: row bands of 16 lines, whole source rows, 17 KB stages x 2, 4 wg/CU"},
+    {0, 0, 7, 6, 1, "off: row bands of 16 lines, whole source rows, 9 KB stages x 2, 6 wg/CU"},
+    {0, 0, 7, 2, 2, "off: row bands of 16 lines, whole source rows, 36 KB stages x 2, 2 wg/CU"},
     {0, 0, 8, 4, 32 + 64 + 128, "wave row gathers, 32 lines x 64 per item, band per workgroup, 4 wg/CU, largest images first"},
     {0, 0, 8, 6, 32 + 64 + 128, "wave row gathers, 32 lines x 64 per item, band per workgroup, 6 wg/CU, largest images first"},
 };
@@ -1401,6 +1401,11 @@ hipError_t launch_pipe5_only(const miaug_ragged_args *a, const Variant &v, const
 }  // namespace
 
 int ragged_variant_count() { return kNumVariants; }
+// The row-band forms (k_rows.hip) are switched off: in one run of the parity
+// tests one of them wrote a wrong image for one batch with unaligned starts,
+// while a rerun and every earlier run were exact; the cause is not found.
+// They were never the fastest form.  Their indices stay (names "off: ...").
+bool ragged_variant_enabled(int v) { return v >= 0 && v < kNumVariants && kVariants[v].mode != 7; }
 const char *ragged_variant_name(int v) { return (v >= 0 && v < kNumVariants) ? kVariants[v].name : nullptr; }
 int ragged_default_variant() { return 0; }
 int ragged_counter_ints() { return kQueues * kCounterStride; }

@@ -86,6 +86,11 @@ def test_validation_errors_without_a_gpu(miaug):
     assert L.miaug_image_stats_u8(None, 1, 10, 5, None, None, None, None, None) == miaug.ESHAPE
     assert L.miaug_ragged_variant_count() >= 4
     assert L.miaug_ragged_variant_name(0)
+    # launch forms switched off are named "off: ..." and cannot be forced
+    off = [v for v in range(L.miaug_ragged_variant_count()) if L.miaug_ragged_variant_name(v).startswith(b"off: ")]
+    assert off and 0 not in off
+    assert L.miaug_ragged_set_variant(dummy, off[0]) == miaug.EUNSUPPORTED
+    assert b"switched off" in L.miaug_last_error()
 
 
 def test_ctx_create_reports_a_missing_device(miaug):

@@ -58,6 +58,8 @@ def small(m):
 def test_small_ragged_all_variants_bit_exact(m, ctx, small, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
+    if m.ragged_variants()[variant].startswith("off: "):
+        pytest.skip("launch form switched off in the library: an intermittent wrong image, cause not found")
     b, flags, ab = small
     ctx.set_variant(variant)
     r = m.Ragged.from_host(b, flags, ab)
@@ -115,6 +117,8 @@ def unaligned(m):
 def test_unaligned_starts_all_variants_bit_exact(m, ctx, unaligned, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
+    if m.ragged_variants()[variant].startswith("off: "):
+        pytest.skip("launch form switched off in the library: an intermittent wrong image, cause not found")
     b, flags, ab = unaligned
     ctx.set_variant(variant)
     r = m.Ragged.from_host(b, flags, ab)
@@ -202,6 +206,8 @@ def check_crop_outputs(b, r, flags, ab, win, idx, OH=224, OW=224):
 def test_crop_windows_all_variants_bit_exact(m, ctx, small, variant):
     if variant >= len(m.ragged_variants()):
         pytest.skip("the library has fewer variants")
+    if m.ragged_variants()[variant].startswith("off: "):
+        pytest.skip("launch form switched off in the library: an intermittent wrong image, cause not found")
     b, flags, ab = small
     win = crop_windows(b, flags, 77)
     win[3] = (0, 0, *d4_shape(int(b.hw[3][0]), int(b.hw[3][1]), flags[3]))  # the whole image
@@ -242,7 +248,8 @@ def test_autotune_gate_with_skipped_images(m, small):
     c2 = m.Context(0)
     r = m.Ragged.from_host(b, flags, ab, crop=win)
     v, ms, times = m.ragged_autotune(c2, r, reps=1, return_times=True)
-    assert all(t > 0 for t in times), times
+    names = m.ragged_variants()
+    assert all((t > 0) != names[i].startswith("off: ") for i, t in enumerate(times)), times  # off: -1
     full = [i for i in range(b.n) if i not in (1, 6)]
     m.ragged_apply(c2, r)
     check_crop_outputs(b, r, flags, ab, win, full)
