@@ -1,8 +1,9 @@
 // k_padwarp.hip -- the remaining geometric rows of Table I as single ops on a
 // dense u8 batch: PadToSize (identity map plus a border) and a standalone
 // affine warp (Rotate; ShiftScaleRotate without crop or resize), both with a
-// reflect-101 or constant border.  The pad is one thread per output pixel (no
-// reuse to stage); the warp stages each output tile's source box in LDS.
+// reflect-101 or constant border.  The pad takes four pixels of four output
+// rows per thread (no reuse to stage); the warp stages each output tile's
+// source box in LDS.
 #include "dev_common.h"
 #include "internal.h"
 

@@ -14,12 +14,14 @@
 //   k_wc_fwd      one workgroup per 32 x 32 output tile, four pixels per
 //                 thread down a column (rows 8 apart): the fp64 position is
 //                 evaluated once per thread and stepped by the constant row
-//                 increment.  The tile's source footprint (its bounding box,
-//                 all channels) is staged in LDS by LDS-DMA with zeros
-//                 outside the image; a footprint too large for the box (zoom-out well
-//                 below 1) gathers its taps from global memory instead, as
-//                 32-bit buffer offsets where a tap outside the image gets an
-//                 offset past the end of the plane, which reads as 0;
+//                 increment.  The tile's source footprint (its bounding box)
+//                 is staged in LDS by LDS-DMA with zeros outside the image,
+//                 one channel at a time through two slots, the next channel's
+//                 DMA in flight while a channel is blended; a footprint too
+//                 large for a slot (zoom-out well below 1) gathers its taps
+//                 from global memory instead, as 32-bit buffer offsets where a
+//                 tap outside the image gets an offset past the end of the
+//                 plane, which reads as 0;
 //   k_wc_bwd      one workgroup per 32 x 32 source tile: the adjoint of the
 //                 bilinear warp as a gather over the output pixels whose cell
 //                 has a tap in the tile (grad_x has one writer per element: no
